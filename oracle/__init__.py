@@ -1,0 +1,254 @@
+"""CPU FP64 oracle for reduce / scan / reduce-by-index and their adjoints.
+
+TEST INFRASTRUCTURE ONLY.  Only the test-suite, ``__graft_entry__.smoke()``
+and the CPU-baseline leg of ``bench.py`` may import this package.  It shares
+no code with the GPU library and never imports it.
+
+The arithmetic lives in ``oracle.c`` (plain single-threaded float64, built
+with gcc, no fast-math, no FMA contraction); this module only marshals numpy
+arrays through ctypes and composes the C calls for the chained segmented
+workload.  Every function widens its float32 inputs exactly to float64.
+
+Operators (names used throughout): ``add``, ``mul``, ``min``, ``max``,
+``linrec`` (linear-function composition, Section 5.1 operator figure, with
+multiplier a and offset b, y_i = a_i*y_{i-1} + b_i) and ``mat2`` (row-major
+2x2 matrix product, Section 5.1 operator figure).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+OPS = {"add": 0, "mul": 1, "min": 2, "max": 3, "linrec": 4, "mat2": 5}
+DIM = {"add": 1, "mul": 1, "min": 1, "max": 1, "linrec": 2, "mat2": 4}
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c into liboracle.so with gcc (plain -O2, no contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call([
+            "gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+            "-shared", _SRC, "-o", tmp, "-lm",
+        ])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build(force=False)
+        L = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        I = ctypes.c_int
+        I64 = ctypes.c_int64
+        L.orc_scan_fwd.argtypes = [I, I64, P, P, P]
+        L.orc_scan_vjp.argtypes = [I, I64, P, P, P, P, P]
+        L.orc_reduce_fwd.argtypes = [I, I64, P, P, P, P, P, P]
+        L.orc_reduce_vjp.argtypes = [I, I64, P, P, P, P]
+        L.orc_rbi_fwd.argtypes = [I, I64, I64, P, P, P, P, P, P, P, P]
+        L.orc_rbi_vjp.argtypes = [I, I64, I64, P, P, P, P, P]
+        for f in (L.orc_scan_fwd, L.orc_scan_vjp, L.orc_reduce_fwd, L.orc_reduce_vjp,
+                  L.orc_rbi_fwd, L.orc_rbi_vjp):
+            f.restype = I
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a), dtype=np.float64)
+
+
+def pack(op: str, x0, x1=None) -> np.ndarray:
+    """Element array (n, d) float64.  linrec: x0 = a (multiplier), x1 = b
+    (offset).  mat2: x0 has shape (n, 4).  Scalar ops: x0 has shape (n,)."""
+    d = DIM[op]
+    if op == "linrec":
+        a, b = _f64(x0).reshape(-1), _f64(x1).reshape(-1)
+        return np.ascontiguousarray(np.stack([a, b], axis=1))
+    if d == 4:
+        return _f64(x0).reshape(-1, 4)
+    return _f64(x0).reshape(-1, 1)
+
+
+def _check(rc):
+    if rc != 0:
+        raise RuntimeError(f"oracle error {rc}")
+
+
+# -------------------------------------------------------------------------
+# scan
+# -------------------------------------------------------------------------
+def scan_fwd(op: str, x0, x1=None):
+    """Inclusive scan.  Returns (rs, c), both (n, d) float64.  For linrec
+    the columns are (A, y): the cumulative multiplier and the recurrence."""
+    X = pack(op, x0, x1)
+    n, d = X.shape
+    rs = np.empty((n, d))
+    c = np.empty((n, d))
+    _check(lib().orc_scan_fwd(OPS[op], n, _p(X), _p(rs), _p(c)))
+    return rs, c
+
+
+def scan_vjp(op: str, ybar, x0, x1=None, cybar=None):
+    """Adjoint of the inclusive scan.  ``ybar`` is (n, d) (for linrec the
+    columns are (A_bar, y_bar)).  ``cybar`` optionally seeds the companion
+    of the output adjoint (default |ybar|).  Returns (xbar, c), (n, d)
+    float64; for linrec the columns are (a_bar, b_bar)."""
+    X = pack(op, x0, x1)
+    n, d = X.shape
+    Y = _f64(ybar).reshape(n, d)
+    CY = None if cybar is None else _f64(cybar).reshape(n, d)
+    xb = np.empty((n, d))
+    c = np.empty((n, d))
+    _check(lib().orc_scan_vjp(OPS[op], n, _p(X), _p(Y), _p(CY), _p(xb), _p(c)))
+    return xb, c
+
+
+# -------------------------------------------------------------------------
+# reduce
+# -------------------------------------------------------------------------
+def reduce_fwd(op: str, x0, x1=None):
+    """Left fold.  Returns dict(y (d,), c (d,), k, n0, ypos)."""
+    X = pack(op, x0, x1)
+    n, d = X.shape
+    y = np.empty(d)
+    c = np.empty(d)
+    k = np.zeros(1, np.int64)
+    n0 = np.zeros(1, np.int64)
+    yp = np.zeros(1)
+    _check(lib().orc_reduce_fwd(OPS[op], n, _p(X), _p(y), _p(c), _p(k), _p(n0), _p(yp)))
+    return dict(y=y, c=c, k=int(k[0]), n0=int(n0[0]), ypos=float(yp[0]))
+
+
+def reduce_vjp(op: str, ybar, x0, x1=None):
+    X = pack(op, x0, x1)
+    n, d = X.shape
+    Y = _f64(ybar).reshape(d)
+    xb = np.empty((n, d))
+    c = np.empty((n, d))
+    _check(lib().orc_reduce_vjp(OPS[op], n, _p(X), _p(Y), _p(xb), _p(c)))
+    return xb, c
+
+
+# -------------------------------------------------------------------------
+# reduce-by-index
+# -------------------------------------------------------------------------
+def rbi_fwd(op: str, idx, m: int, v0, v1=None):
+    """Sequential histogram.  Returns dict(hist (m,d), c, count, argk, n0, ypos)."""
+    V = pack(op, v0, v1)
+    n, d = V.shape
+    ix = np.ascontiguousarray(np.asarray(idx, dtype=np.int32).reshape(-1))
+    assert ix.shape[0] == n
+    mm = max(int(m), 0)
+    h = np.empty((mm, d))
+    c = np.empty((mm, d))
+    cnt = np.empty(mm, np.int64)
+    ak = np.empty(mm, np.int64)
+    n0 = np.empty(mm, np.int64)
+    yp = np.empty(mm)
+    _check(lib().orc_rbi_fwd(OPS[op], n, mm, _p(ix), _p(V), _p(h), _p(c), _p(cnt), _p(ak),
+                             _p(n0), _p(yp)))
+    return dict(hist=h, c=c, count=cnt, argk=ak, n0=n0, ypos=yp)
+
+
+def rbi_vjp(op: str, idx, m: int, hbar, v0, v1=None):
+    V = pack(op, v0, v1)
+    n, d = V.shape
+    ix = np.ascontiguousarray(np.asarray(idx, dtype=np.int32).reshape(-1))
+    H = _f64(hbar).reshape(max(int(m), 0), d)
+    vb = np.empty((n, d))
+    c = np.empty((n, d))
+    _check(lib().orc_rbi_vjp(OPS[op], n, int(m), _p(ix), _p(V), _p(H), _p(vb), _p(c)))
+    return vb, c
+
+
+# -------------------------------------------------------------------------
+# chained segmented workload: per instance s,
+#   y_s = linrec scan of (a_s, b_s);  (h_s, argk_s) = min-by-index(y_s, idx_s, m)
+# and the adjoint of both given y_bar (per element) and h_bar (per bin).
+# -------------------------------------------------------------------------
+def segmented_fwd(offsets, a, b, idx, m: int):
+    """Returns dict(y, cy, h, ch, argk, count) with argk relative to the
+    instance start (sentinel = instance length for an empty bin).
+
+    The min-by-index decision is taken on the float32 rounding of the
+    float64 recurrence (the precision of the paper's evaluation), with the
+    lowest index winning among equal float32 values; h is then the float64
+    value at that position."""
+    off = np.asarray(offsets, dtype=np.int64)
+    S = off.shape[0] - 1
+    N = int(off[-1])
+    y = np.empty(N)
+    cy = np.empty(N)
+    h = np.empty((S, m))
+    ch = np.empty((S, m))
+    argk = np.empty((S, m), np.int64)
+    for s in range(S):
+        lo, hi = int(off[s]), int(off[s + 1])
+        rs, c = scan_fwd("linrec", a[lo:hi], b[lo:hi])
+        y[lo:hi] = rs[:, 1]
+        cy[lo:hi] = c[:, 1]
+        y32 = rs[:, 1].astype(np.float32).astype(np.float64)
+        r = rbi_fwd("min", idx[lo:hi], m, y32)
+        ak = r["argk"]
+        argk[s] = ak
+        L = hi - lo
+        ok = ak < L
+        hs = np.full(m, np.inf)
+        chs = np.full(m, np.inf)
+        hs[ok] = rs[ak[ok], 1]
+        chs[ok] = c[ak[ok], 1]
+        h[s] = hs
+        ch[s] = chs
+    return dict(y=y, cy=cy, h=h, ch=ch, argk=argk)
+
+
+def segmented_vjp(offsets, a, b, idx, m: int, ybar, hbar, argk):
+    """Adjoint of the chained workload for a given per-bin decision
+    ``argk`` (S, m) (instance-relative, >= length means empty).  The
+    min-by-index adjoint adds h_bar[s,k] at position argk[s,k]; that sum is
+    the adjoint of y fed to the linrec scan adjoint.  Returns (abar, bbar,
+    cabar, cbbar) float64 arrays of length N."""
+    off = np.asarray(offsets, dtype=np.int64)
+    S = off.shape[0] - 1
+    N = int(off[-1])
+    hb = np.asarray(hbar, dtype=np.float64).reshape(S, m)
+    ab = np.empty(N)
+    bb = np.empty(N)
+    cab = np.empty(N)
+    cbb = np.empty(N)
+    for s in range(S):
+        lo, hi = int(off[s]), int(off[s + 1])
+        L = hi - lo
+        yt = np.zeros((L, 2))
+        yt[:, 1] = ybar[lo:hi]
+        ak = np.asarray(argk[s], dtype=np.int64)
+        ok = ak < L
+        # each element is the argmin of at most one bin, so no collisions
+        yt[ak[ok], 1] += hb[s][ok]
+        # companion of the summed adjoint: |y_bar| + |h_bar|
+        yc = np.zeros((L, 2))
+        yc[:, 1] = np.abs(ybar[lo:hi])
+        yc[ak[ok], 1] += np.abs(hb[s][ok])
+        xb, c = scan_vjp("linrec", yt, a[lo:hi], b[lo:hi], cybar=yc)
+        ab[lo:hi] = xb[:, 0]
+        bb[lo:hi] = xb[:, 1]
+        cab[lo:hi] = c[:, 0]
+        cbb[lo:hi] = c[:, 1]
+    return ab, bb, cab, cbb

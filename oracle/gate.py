@@ -1,0 +1,69 @@
+"""Comparison gate between a float32 result and the float64 oracle.
+
+TEST INFRASTRUCTURE ONLY (used by the tests and the benchmark's parity leg).
+
+For each float output g (float32) against the oracle value r (float64) with
+companion c >= |r| (the same multilinear expression on absolute values):
+
+    |g - r| <= rtol * c + 2^-126
+
+* If |r| > FLT_MAX the float32 result must be the same-signed infinity.
+* If c > FLT_MAX (or r, c are not finite) while r is in range, the element is
+  "range-exceeded": no float32 method can be held to it; it is excluded and
+  counted, and the caller decides how many are acceptable.
+* A NaN where the oracle is finite fails.
+
+The tolerance is relative to the companion rather than to |r| because plain
+element-wise relative error is unattainable for any float32 method where
+cancellation makes |r| much smaller than the terms that produce it (suffix
+sums of N(0,1) adjoints, linear recurrences crossing zero).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+FLT_MAX = float(np.finfo(np.float32).max)
+TINY = 2.0 ** -126
+
+RTOL = {"add": 1e-5, "min": 1e-5, "max": 1e-5, "mul": 1e-4, "linrec": 1e-4, "mat2": 1e-4}
+
+
+def gate(g, r, c, rtol: float):
+    g = np.asarray(g, dtype=np.float64).reshape(-1)
+    r = np.asarray(r, dtype=np.float64).reshape(-1)
+    c = np.asarray(c, dtype=np.float64).reshape(-1)
+    assert g.shape == r.shape == c.shape, (g.shape, r.shape, c.shape)
+    over = np.isfinite(r) & (np.abs(r) > FLT_MAX)
+    rng_ex = (~over) & (~np.isfinite(r) | ~np.isfinite(c) | (c > FLT_MAX))
+    normal = ~over & ~rng_ex
+    ok = np.ones(g.shape, dtype=bool)
+    ok[over] = np.isinf(g[over]) & (np.sign(g[over]) == np.sign(r[over]))
+    with np.errstate(invalid="ignore", over="ignore"):
+        err = np.abs(g - r)
+        bound = rtol * c + TINY
+        ok[normal] = np.isfinite(g[normal]) & (err[normal] <= bound[normal])
+        sel = normal & (np.abs(r) >= 1e-3 * c) & (np.abs(r) > 0)
+        max_rel = float(np.max(err[sel] / np.abs(r[sel]))) if sel.any() else 0.0
+        rn = np.linalg.norm(r[normal])
+        normwise = float(np.linalg.norm((g - r)[normal]) / rn) if rn > 0 else 0.0
+        ratio = np.where(normal, err / bound, 0.0)
+    bad = np.flatnonzero(~ok)
+    worst = int(np.argmax(ratio)) if ratio.size else -1
+    return dict(
+        ok=bool(bad.size == 0), n=int(g.size), n_fail=int(bad.size),
+        first_fail=[int(i) for i in bad[:8]], n_range_exceeded=int(rng_ex.sum()),
+        max_rel=max_rel, normwise=normwise,
+        worst=worst, worst_ratio=float(ratio[worst]) if worst >= 0 else 0.0,
+    )
+
+
+def assert_gate(g, r, c, rtol: float, max_range_exceeded: int = 0, what: str = ""):
+    res = gate(g, r, c, rtol)
+    gg = np.asarray(g, dtype=np.float64).reshape(-1)
+    rr = np.asarray(r, dtype=np.float64).reshape(-1)
+    cc = np.asarray(c, dtype=np.float64).reshape(-1)
+    detail = ", ".join(f"[{i}] g={gg[i]!r} r={rr[i]!r} c={cc[i]!r}" for i in res["first_fail"][:4])
+    assert res["ok"], f"{what}: {res['n_fail']}/{res['n']} outside the gate: {detail}"
+    assert res["n_range_exceeded"] <= max_range_exceeded, (
+        f"{what}: {res['n_range_exceeded']} range-exceeded elements")
+    return res

@@ -1,0 +1,723 @@
+"""Pins of the CPU oracle against things other than itself.
+
+Each check is chosen so that a plausible mistake in the oracle (a dropped
+term, a wrong sign or index, a transposed operand, a wrong tie rule) fails at
+least one of them:
+
+* hand-derived worked examples under ``tests/golden`` (each cites the rule it
+  follows);
+* library primitives for the forward (numpy cumsum / cumprod / accumulate /
+  matmul / bincount / ufunc.at / argmin);
+* closed forms for the adjoints (broadcast, suffix sums, the three zero cases
+  of multiplication, one-hot at the lowest-index argmin, the linear-recurrence
+  sums, the matrix embedding of the linear recurrence, determinants);
+* forward-mode dual numbers over independently written operator definitions
+  (a brute-force Jacobian, so x_bar = J^T y_bar is checked without any
+  reverse sweep) for n <= 16;
+* central finite differences of the oracle forward;
+* the paper's alternative rules for the same adjoint: the general reduce rule
+  (exclusive scans l and r, then the local vjp of l (.) x (.) r), the general
+  scan rule (Jacobians cs, a scan with linear-function composition, then a
+  map), PPAD's scan rule (appendix figure) and the sort-based
+  reduce-by-index rule (its rule figure).
+"""
+from __future__ import annotations
+
+import glob
+import itertools
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+OPS = ["add", "mul", "min", "max", "linrec", "mat2"]
+D = oracle.DIM
+
+
+# ---------------------------------------------------------------------------
+# independent operator definitions (Section 5.1 operator figure) and duals
+# ---------------------------------------------------------------------------
+class Dual:
+    __slots__ = ("v", "t")
+
+    def __init__(self, v, t):
+        self.v = v
+        self.t = t
+
+    @staticmethod
+    def lift(o, N):
+        return o if isinstance(o, Dual) else Dual(float(o), np.zeros(N))
+
+    def __add__(self, o):
+        o = Dual.lift(o, self.t.size)
+        return Dual(self.v + o.v, self.t + o.t)
+
+    __radd__ = __add__
+
+    def __mul__(self, o):
+        o = Dual.lift(o, self.t.size)
+        return Dual(self.v * o.v, self.v * o.t + o.v * self.t)
+
+    __rmul__ = __mul__
+
+    def __le__(self, o):
+        return self.v <= (o.v if isinstance(o, Dual) else o)
+
+    def __ge__(self, o):
+        return self.v >= (o.v if isinstance(o, Dual) else o)
+
+
+def py_op(op, p, q):
+    """p (.) q on lists of components; min/max keep the left operand on ties."""
+    if op == "add":
+        return [p[0] + q[0]]
+    if op == "mul":
+        return [p[0] * q[0]]
+    if op == "min":
+        return [p[0] if p[0] <= q[0] else q[0]]
+    if op == "max":
+        return [p[0] if p[0] >= q[0] else q[0]]
+    if op == "linrec":
+        # linFnComp (b1,c1) (b2,c2) = (b2 + c2*b1, c2*c1); stored as (c, b)
+        c1, b1 = p
+        c2, b2 = q
+        return [c2 * c1, b2 + c2 * b1]
+    if op == "mat2":
+        a1, b1, c1, d1 = p
+        a2, b2, c2, d2 = q
+        return [a1 * a2 + b1 * c2, a1 * b2 + b1 * d2, c1 * a2 + d1 * c2, c1 * b2 + d1 * d2]
+    raise ValueError(op)
+
+
+def py_neutral(op):
+    return {"add": [0.0], "mul": [1.0], "min": [np.inf], "max": [-np.inf],
+            "linrec": [1.0, 0.0], "mat2": [1.0, 0.0, 0.0, 1.0]}[op]
+
+
+def dual_inputs(X):
+    n, d = X.shape
+    N = n * d
+    out = []
+    for i in range(n):
+        row = []
+        for t in range(d):
+            tan = np.zeros(N)
+            tan[i * d + t] = 1.0
+            row.append(Dual(float(X[i, t]), tan))
+        out.append(row)
+    return out
+
+
+def jac_rows(elems, N):
+    return np.array([[e.t if isinstance(e, Dual) else np.zeros(N) for e in el] for el in elems])
+
+
+def dual_scan(op, X):
+    xs = dual_inputs(X)
+    rs = [xs[0]]
+    for i in range(1, len(xs)):
+        rs.append(py_op(op, rs[-1], xs[i]))
+    N = X.size
+    J = jac_rows(rs, N).reshape(-1, N)
+    vals = np.array([[e.v for e in el] for el in rs])
+    return vals, J
+
+
+def dual_reduce(op, X):
+    xs = dual_inputs(X)
+    acc = xs[0]
+    for i in range(1, len(xs)):
+        acc = py_op(op, acc, xs[i])
+    N = X.size
+    return np.array([e.v for e in acc]), np.array([e.t for e in acc]).reshape(-1, N)
+
+
+def dual_rbi(op, idx, m, V):
+    xs = dual_inputs(V)
+    N = V.size
+    d = V.shape[1]
+    hist = [None] * m
+    for i, k in enumerate(idx):
+        if 0 <= k < m:
+            hist[k] = xs[i] if hist[k] is None else py_op(op, hist[k], xs[i])
+    J = np.zeros((m * d, N))
+    for k in range(m):
+        if hist[k] is not None:
+            for t in range(d):
+                J[k * d + t] = hist[k][t].t
+    return J
+
+
+def rand_elems(op, n, rng, nonneg=False):
+    d = D[op]
+    if op == "linrec":
+        a = rng.uniform(0.5, 1.5, n)
+        b = rng.standard_normal(n)
+        return np.stack([a, b], 1).astype(np.float32).astype(np.float64)
+    X = rng.standard_normal((n, d))
+    if op == "mul":
+        X = rng.uniform(0.5, 2.0, (n, 1)) * rng.choice([-1.0, 1.0], (n, 1))
+    return X.astype(np.float32).astype(np.float64)
+
+
+def as_args(op, X):
+    if op == "linrec":
+        return (X[:, 0], X[:, 1])
+    if op == "mat2":
+        return (X,)
+    return (X[:, 0],)
+
+
+# ---------------------------------------------------------------------------
+# golden worked examples
+# ---------------------------------------------------------------------------
+def _golden():
+    return [json.load(open(p)) for p in sorted(glob.glob(os.path.join(HERE, "golden", "*.json")))]
+
+
+def _f(v):
+    return np.array([np.inf if x == "inf" else x for x in v], dtype=np.float64)
+
+
+@pytest.mark.parametrize("g", _golden(), ids=lambda g: g["name"])
+def test_golden(g):
+    op, comb = g["op"], g["combinator"]
+    assert g.get("cite"), "every fixture cites the rule it follows"
+    if comb == "reduce":
+        r = oracle.reduce_fwd(op, np.array(g["x"]))
+        np.testing.assert_array_equal(r["y"], g["y"])
+        if "k" in g:
+            assert r["k"] == g["k"]
+        if "n0" in g:
+            assert r["n0"] == g["n0"] and r["ypos"] == g["ypos"]
+        xb, _ = oracle.reduce_vjp(op, np.array(g["ybar"]), np.array(g["x"]))
+        np.testing.assert_allclose(xb[:, 0], g["xbar"], rtol=1e-15)
+    elif comb == "scan" and op == "linrec":
+        rs, _ = oracle.scan_fwd(op, np.array(g["a"]), np.array(g["b"]))
+        np.testing.assert_allclose(rs[:, 1], g["y"], rtol=1e-15)
+        np.testing.assert_allclose(rs[:, 0], g["A"], rtol=1e-15)
+        yb = np.stack([np.zeros(3), np.array(g["ybar"])], 1)
+        xb, _ = oracle.scan_vjp(op, yb, np.array(g["a"]), np.array(g["b"]))
+        np.testing.assert_allclose(xb[:, 0], g["abar"], rtol=1e-15)
+        np.testing.assert_allclose(xb[:, 1], g["bbar"], rtol=1e-15)
+    elif comb == "scan" and op == "mat2":
+        rs, _ = oracle.scan_fwd(op, np.array(g["M"]))
+        np.testing.assert_allclose(rs, g["P"], rtol=1e-15)
+        xb, _ = oracle.scan_vjp(op, np.array(g["Pbar"], dtype=float), np.array(g["M"]))
+        np.testing.assert_allclose(xb, g["Mbar"], rtol=1e-15, atol=0)
+    elif comb == "scan":
+        rs, _ = oracle.scan_fwd(op, np.array(g["x"]))
+        np.testing.assert_array_equal(rs[:, 0], g["y"])
+        xb, _ = oracle.scan_vjp(op, np.array(g["ybar"]), np.array(g["x"]))
+        np.testing.assert_allclose(xb[:, 0], g["xbar"], rtol=1e-15)
+    elif comb == "rbi":
+        idx = np.array(g["idx"], np.int32)
+        r = oracle.rbi_fwd(op, idx, g["m"], np.array(g["v"]))
+        np.testing.assert_array_equal(r["hist"][:, 0], _f(g["hist"]))
+        for key in ("count", "argk", "n0", "ypos"):
+            if key in g:
+                np.testing.assert_array_equal(r[key], g[key])
+        vb, _ = oracle.rbi_vjp(op, idx, g["m"], np.array(g["hbar"]), np.array(g["v"]))
+        np.testing.assert_allclose(vb[:, 0], g["vbar"], rtol=1e-15)
+    else:
+        raise AssertionError(comb)
+
+
+# ---------------------------------------------------------------------------
+# forward against library primitives
+# ---------------------------------------------------------------------------
+def test_scan_fwd_library():
+    rng = np.random.default_rng(1)
+    x = rng.uniform(0.5, 2.0, 500).astype(np.float32)
+    xd = x.astype(np.float64)
+    np.testing.assert_allclose(oracle.scan_fwd("add", x)[0][:, 0], np.cumsum(xd), rtol=1e-13)
+    np.testing.assert_allclose(oracle.scan_fwd("mul", x[:60])[0][:, 0], np.cumprod(xd[:60]), rtol=1e-13)
+    np.testing.assert_array_equal(oracle.scan_fwd("min", x)[0][:, 0], np.minimum.accumulate(xd))
+    np.testing.assert_array_equal(oracle.scan_fwd("max", x)[0][:, 0], np.maximum.accumulate(xd))
+    M = rng.standard_normal((40, 4)).astype(np.float32)
+    P = oracle.scan_fwd("mat2", M)[0]
+    acc = np.eye(2)
+    for i in range(40):
+        acc = acc @ M[i].astype(np.float64).reshape(2, 2)
+        np.testing.assert_allclose(P[i].reshape(2, 2), acc, rtol=1e-12, atol=1e-14)
+
+
+def test_reduce_fwd_library():
+    rng = np.random.default_rng(2)
+    x = rng.uniform(-2.0, 2.0, 333).astype(np.float32)
+    xd = x.astype(np.float64)
+    r = oracle.reduce_fwd("add", x)
+    np.testing.assert_allclose(r["y"][0], np.sum(xd), rtol=1e-13)
+    assert r["c"][0] == pytest.approx(np.sum(np.abs(xd)), rel=1e-13)
+    r = oracle.reduce_fwd("min", x)
+    assert r["y"][0] == xd.min() and r["k"] == int(np.argmin(xd))
+    r = oracle.reduce_fwd("max", x)
+    assert r["y"][0] == xd.max() and r["k"] == int(np.argmax(xd))
+    xm = x[:50].copy()
+    xm[[3, 17]] = 0
+    r = oracle.reduce_fwd("mul", xm)
+    nz = xm[xm != 0].astype(np.float64)
+    assert r["y"][0] == 0.0 and r["n0"] == 2
+    assert r["ypos"] == pytest.approx(np.prod(nz), rel=1e-13)
+    # empty input: neutral, sentinel index n = 0
+    r = oracle.reduce_fwd("min", np.zeros(0, np.float32))
+    assert r["y"][0] == np.inf and r["k"] == 0
+
+
+def test_rbi_fwd_library():
+    rng = np.random.default_rng(3)
+    n, m = 2000, 37
+    idx = rng.integers(-3, m + 3, n).astype(np.int32)
+    v = np.round(rng.standard_normal(n) * 8) / 8
+    v = v.astype(np.float32)
+    vd = v.astype(np.float64)
+    ok = (idx >= 0) & (idx < m)
+    r = oracle.rbi_fwd("add", idx, m, v)
+    np.testing.assert_allclose(r["hist"][:, 0], np.bincount(idx[ok], vd[ok], minlength=m), rtol=1e-12, atol=1e-12)
+    np.testing.assert_array_equal(r["count"], np.bincount(idx[ok], minlength=m))
+    for op, uf, init in (("min", np.minimum, np.inf), ("max", np.maximum, -np.inf)):
+        r = oracle.rbi_fwd(op, idx, m, v)
+        h = np.full(m, init)
+        uf.at(h, idx[ok], vd[ok])
+        np.testing.assert_array_equal(r["hist"][:, 0], h)
+        for k in range(m):
+            members = np.flatnonzero(ok & (idx == k))
+            if members.size == 0:
+                assert r["argk"][k] == n
+            else:
+                win = members[np.flatnonzero(vd[members] == h[k])[0]]
+                assert r["argk"][k] == win
+    vm = vd.copy()
+    vm[rng.choice(n, 100, replace=False)] = 0.0
+    r = oracle.rbi_fwd("mul", idx, m, vm)
+    n0 = np.bincount(idx[ok & (vm == 0)], minlength=m)
+    np.testing.assert_array_equal(r["n0"], n0)
+    yp = np.ones(m)
+    np.multiply.at(yp, idx[ok & (vm != 0)], vm[ok & (vm != 0)])
+    np.testing.assert_allclose(r["ypos"], yp, rtol=1e-12)
+    np.testing.assert_allclose(r["hist"][:, 0], np.where(n0 > 0, 0.0, yp), rtol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# closed forms of the adjoints
+# ---------------------------------------------------------------------------
+def test_closed_form_add():
+    rng = np.random.default_rng(4)
+    x = rng.standard_normal(300).astype(np.float32)
+    yb = rng.standard_normal(300)
+    xb, _ = oracle.scan_vjp("add", yb, x)
+    np.testing.assert_allclose(xb[:, 0], np.cumsum(yb[::-1])[::-1], rtol=1e-12, atol=1e-12)
+    xb, _ = oracle.reduce_vjp("add", np.array([0.7]), x)
+    np.testing.assert_array_equal(xb[:, 0], np.full(300, 0.7))
+
+
+@pytest.mark.parametrize("zeros", [0, 1, 2, 5])
+def test_closed_form_reduce_mul(zeros):
+    rng = np.random.default_rng(10 + zeros)
+    x = rng.uniform(0.5, 2.0, 40) * rng.choice([-1, 1], 40)
+    pos = rng.choice(40, zeros, replace=False)
+    x[pos] = 0.0
+    x = x.astype(np.float32).astype(np.float64)
+    yb = 1.3
+    xb, _ = oracle.reduce_vjp("mul", np.array([yb]), x)
+    nz = np.prod(x[x != 0])
+    if zeros == 0:
+        exp = np.prod(x) / x * yb
+    elif zeros == 1:
+        exp = np.zeros(40)
+        exp[pos[0]] = nz * yb
+    else:
+        exp = np.zeros(40)
+    np.testing.assert_allclose(xb[:, 0], exp, rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("op", ["min", "max"])
+def test_min_max_all_tie_patterns(op):
+    """Every pattern over {0,1,2} for n <= 7: reduce adjoint is the one-hot
+    at the lowest-index extremum; scan adjoint of position k sums y_bar over
+    the prefixes whose lowest-index extremum is k."""
+    sel = np.argmin if op == "min" else np.argmax
+    for n in range(1, 8):
+        for pat in itertools.product([0.0, 1.0, 2.0], repeat=n):
+            x = np.array(pat)
+            r = oracle.reduce_fwd(op, x)
+            k = int(sel(x))
+            assert r["k"] == k
+            xb, _ = oracle.reduce_vjp(op, np.array([3.0]), x)
+            exp = np.zeros(n)
+            exp[k] = 3.0
+            np.testing.assert_array_equal(xb[:, 0], exp)
+            if n <= 6:
+                yb = 2.0 ** np.arange(n)
+                xb, _ = oracle.scan_vjp(op, yb, x)
+                exp = np.zeros(n)
+                for j in range(n):
+                    exp[int(sel(x[: j + 1]))] += yb[j]
+                np.testing.assert_array_equal(xb[:, 0], exp)
+
+
+def test_closed_form_linrec():
+    """y_i = sum_j b_j prod_{k=j+1..i} a_k; lam_i = sum_{j>=i} ybar_j
+    prod_{k=i+1..j} a_k; b_bar = lam; a_bar_i = lam_i y_{i-1} (+ Abar part)."""
+    rng = np.random.default_rng(5)
+    n = 30
+    a = rng.uniform(0.5, 1.5, n)
+    b = rng.standard_normal(n)
+    yb = rng.standard_normal(n)
+    Ab = rng.standard_normal(n)
+    y = np.array([sum(b[j] * np.prod(a[j + 1:i + 1]) for j in range(i + 1)) for i in range(n)])
+    A = np.array([np.prod(a[: i + 1]) for i in range(n)])
+    rs, _ = oracle.scan_fwd("linrec", a, b)
+    np.testing.assert_allclose(rs[:, 1], y, rtol=1e-12, atol=1e-13)
+    np.testing.assert_allclose(rs[:, 0], A, rtol=1e-12)
+    lam = np.array([sum(yb[j] * np.prod(a[i + 1:j + 1]) for j in range(i, n)) for i in range(n)])
+    lamA = np.array([sum(Ab[j] * np.prod(a[i + 1:j + 1]) for j in range(i, n)) for i in range(n)])
+    yprev = np.concatenate([[0.0], y[:-1]])
+    Aprev = np.concatenate([[1.0], A[:-1]])
+    xb, _ = oracle.scan_vjp("linrec", np.stack([Ab, yb], 1), a, b)
+    np.testing.assert_allclose(xb[:, 1], lam, rtol=1e-11, atol=1e-12)
+    np.testing.assert_allclose(xb[:, 0], lam * yprev + lamA * Aprev, rtol=1e-11, atol=1e-12)
+    # a == 1: scan(+) of b;  a == 0: y = b
+    rs, _ = oracle.scan_fwd("linrec", np.ones(n), b)
+    np.testing.assert_allclose(rs[:, 1], np.cumsum(b), rtol=1e-12, atol=1e-13)
+    rs, _ = oracle.scan_fwd("linrec", np.zeros(n), b)
+    np.testing.assert_array_equal(rs[:, 1], b)
+    # reduce of linrec = last scan element; its adjoint = scan adjoint with
+    # y_bar only at the end
+    r = oracle.reduce_fwd("linrec", a, b)
+    np.testing.assert_allclose(r["y"], rs[-1] * 0 + oracle.scan_fwd("linrec", a, b)[0][-1], rtol=1e-13)
+
+
+def test_mat2_embeds_linrec_and_mul():
+    rng = np.random.default_rng(6)
+    n = 50
+    a = rng.uniform(0.5, 1.5, n)
+    b = rng.standard_normal(n)
+    # [[a,0],[b,1]] products: entry (0,0) = A, entry (1,0) = y
+    M = np.stack([a, np.zeros(n), b, np.ones(n)], 1)
+    P, _ = oracle.scan_fwd("mat2", M)
+    rs, _ = oracle.scan_fwd("linrec", a, b)
+    np.testing.assert_allclose(P[:, 0], rs[:, 0], rtol=1e-12)
+    np.testing.assert_allclose(P[:, 2], rs[:, 1], rtol=1e-12, atol=1e-13)
+    yb, Ab = rng.standard_normal(n), rng.standard_normal(n)
+    Pb = np.zeros((n, 4))
+    Pb[:, 0] = Ab
+    Pb[:, 2] = yb
+    Mb, _ = oracle.scan_vjp("mat2", Pb, M)
+    xb, _ = oracle.scan_vjp("linrec", np.stack([Ab, yb], 1), a, b)
+    np.testing.assert_allclose(Mb[:, 0], xb[:, 0], rtol=1e-11, atol=1e-12)
+    np.testing.assert_allclose(Mb[:, 2], xb[:, 1], rtol=1e-11, atol=1e-12)
+    # diagonal matrices are two independent scans with *
+    p, q = rng.uniform(0.5, 2, n), rng.uniform(0.5, 2, n)
+    M = np.stack([p, np.zeros(n), np.zeros(n), q], 1)
+    P, _ = oracle.scan_fwd("mat2", M)
+    np.testing.assert_allclose(P[:, 0], np.cumprod(p), rtol=1e-12)
+    np.testing.assert_allclose(P[:, 3], np.cumprod(q), rtol=1e-12)
+    Pb = rng.standard_normal((n, 4))
+    Mb, _ = oracle.scan_vjp("mat2", Pb, M)
+    np.testing.assert_allclose(Mb[:, 0], oracle.scan_vjp("mul", Pb[:, 0], p)[0][:, 0], rtol=1e-11)
+    np.testing.assert_allclose(Mb[:, 3], oracle.scan_vjp("mul", Pb[:, 3], q)[0][:, 0], rtol=1e-11)
+    # det P_i = prod det M_j
+    M = rng.standard_normal((n, 4)) * 0.8
+    P, _ = oracle.scan_fwd("mat2", M)
+    det = lambda X: X[:, 0] * X[:, 3] - X[:, 1] * X[:, 2]
+    scale = np.abs(P[:, 0] * P[:, 3]) + np.abs(P[:, 1] * P[:, 2])
+    assert np.all(np.abs(det(P) - np.cumprod(det(M))) <= 1e-12 * scale)
+
+
+def test_rbi_closed_forms():
+    rng = np.random.default_rng(7)
+    n, m = 3000, 41
+    idx = rng.integers(-2, m + 2, n).astype(np.int32)
+    ok = (idx >= 0) & (idx < m)
+    v = rng.standard_normal(n).astype(np.float32)
+    hb = rng.standard_normal(m)
+    vb, _ = oracle.rbi_vjp("add", idx, m, hb, v)
+    exp = np.where(ok, hb[np.clip(idx, 0, m - 1)], 0.0)
+    np.testing.assert_array_equal(vb[:, 0], exp)
+    cnt = np.bincount(idx[ok], minlength=m)
+    assert np.sum(vb) == pytest.approx(np.sum(cnt * hb), rel=1e-12)
+    for op in ("min", "max"):
+        r = oracle.rbi_fwd(op, idx, m, v)
+        vb, _ = oracle.rbi_vjp(op, idx, m, hb, v)
+        exp = np.zeros(n)
+        hit = r["argk"] < n
+        exp[r["argk"][hit]] = hb[hit]
+        np.testing.assert_array_equal(vb[:, 0], exp)
+    vm = v.astype(np.float64)
+    vm[rng.choice(n, 120, replace=False)] = 0.0
+    r = oracle.rbi_fwd("mul", idx, m, vm)
+    vb, _ = oracle.rbi_vjp("mul", idx, m, hb, vm)
+    for i in range(n):
+        if not ok[i]:
+            assert vb[i, 0] == 0.0
+            continue
+        k = idx[i]
+        if r["n0"][k] == 0:
+            e = r["ypos"][k] / vm[i] * hb[k]
+        elif r["n0"][k] == 1 and vm[i] == 0.0:
+            e = r["ypos"][k] * hb[k]
+        else:
+            e = 0.0
+        assert vb[i, 0] == pytest.approx(e, rel=1e-12, abs=0)
+
+
+# ---------------------------------------------------------------------------
+# brute-force Jacobians with dual numbers
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("op", OPS)
+@pytest.mark.parametrize("n", [1, 2, 3, 7, 16])
+def test_dual_jacobian_scan_reduce(op, n):
+    rng = np.random.default_rng(100 + n)
+    X = rand_elems(op, n, rng)
+    vals, J = dual_scan(op, X)
+    rs, crs = oracle.scan_fwd(op, *as_args(op, X))
+    np.testing.assert_allclose(rs, vals, rtol=1e-13, atol=1e-15)
+    assert np.all(crs >= np.abs(rs) * (1 - 1e-15))
+    yb = rng.standard_normal(X.shape)
+    xb, cxb = oracle.scan_vjp(op, yb, *as_args(op, X))
+    np.testing.assert_allclose(xb.reshape(-1), J.T @ yb.reshape(-1), rtol=1e-12, atol=1e-13)
+    assert np.all(cxb >= np.abs(xb) * (1 - 1e-12))
+    # reduce
+    y, Jr = dual_reduce(op, X)
+    r = oracle.reduce_fwd(op, *as_args(op, X))
+    np.testing.assert_allclose(r["y"], y, rtol=1e-13, atol=1e-15)
+    ybr = rng.standard_normal(D[op])
+    xb, _ = oracle.reduce_vjp(op, ybr, *as_args(op, X))
+    np.testing.assert_allclose(xb.reshape(-1), Jr.T @ ybr, rtol=1e-12, atol=1e-13)
+
+
+@pytest.mark.parametrize("op", OPS)
+def test_dual_jacobian_rbi(op):
+    rng = np.random.default_rng(200)
+    n, m = 16, 5
+    X = rand_elems(op, n, rng)
+    if op in ("min", "max"):
+        X = np.round(X * 2) / 2  # force ties
+    idx = rng.integers(-1, m + 1, n).astype(np.int32)
+    J = dual_rbi(op, idx, m, X)
+    hb = rng.standard_normal((m, D[op]))
+    vb, _ = oracle.rbi_vjp(op, idx, m, hb, *as_args(op, X))
+    np.testing.assert_allclose(vb.reshape(-1), J.T @ hb.reshape(-1), rtol=1e-12, atol=1e-13)
+
+
+# ---------------------------------------------------------------------------
+# finite differences of the oracle forward (smooth operators)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("op", ["add", "mul", "linrec", "mat2"])
+def test_finite_differences(op):
+    rng = np.random.default_rng(300)
+    n = 12
+    X = rand_elems(op, n, rng)
+    yb = rng.standard_normal(X.shape)
+    xb, _ = oracle.scan_vjp(op, yb, *as_args(op, X))
+    h = 1e-6
+    fd = np.zeros(X.size)
+    for j in range(X.size):
+        Xp, Xm = X.copy().reshape(-1), X.copy().reshape(-1)
+        Xp[j] += h
+        Xm[j] -= h
+        fp = oracle.scan_fwd(op, *as_args(op, Xp.reshape(X.shape)))[0]
+        fm = oracle.scan_fwd(op, *as_args(op, Xm.reshape(X.shape)))[0]
+        fd[j] = np.sum((fp - fm) * yb) / (2 * h)
+    np.testing.assert_allclose(xb.reshape(-1), fd, rtol=1e-6, atol=1e-7)
+
+
+# ---------------------------------------------------------------------------
+# the paper's alternative rules for the same adjoints
+# ---------------------------------------------------------------------------
+def local_vjp(f, x, ybar):
+    """VJP of f at x (a list of floats) by forward-mode duals."""
+    d = len(x)
+    xs = [Dual(float(x[t]), np.eye(d)[t]) for t in range(d)]
+    out = f(xs)
+    J = np.array([o.t if isinstance(o, Dual) else np.zeros(d) for o in out])
+    return J.T @ np.asarray(ybar, dtype=float)
+
+
+@pytest.mark.parametrize("op", OPS)
+def test_general_reduce_rule(op):
+    """Reduce rule figure: l = exclusive scan, r = reversed exclusive scan with
+    the flipped operator, then x_bar_i = vjp(x -> l_i (.) x (.) r_i)(x_i, y_bar)."""
+    rng = np.random.default_rng(400)
+    n = 25
+    X = rand_elems(op, n, rng)
+    yb = rng.standard_normal(D[op])
+    e = py_neutral(op)
+    ls, acc = [], list(e)
+    for i in range(n):
+        ls.append(acc)
+        acc = py_op(op, acc, list(X[i]))
+    rs, acc = [None] * n, list(e)
+    for i in range(n - 1, -1, -1):
+        rs[i] = acc
+        acc = py_op(op, list(X[i]), acc)  # flipped operator: y (.) x with x the new element on the left
+    exp = np.array([local_vjp(lambda x, i=i: py_op(op, py_op(op, ls[i], x), rs[i]), X[i], yb)
+                    for i in range(n)])
+    xb, _ = oracle.reduce_vjp(op, yb, *as_args(op, X))
+    np.testing.assert_allclose(xb, exp, rtol=1e-11, atol=1e-12)
+
+
+def _mat_vec_lin(c2, c1):
+    return c2 @ c1
+
+
+@pytest.mark.parametrize("op", OPS)
+def test_general_scan_rule(op):
+    """Scan rule figure: cs_i = d(rs_i (.) as_{i+1})/d rs_i (cs_{n-1} = I),
+    then a scan of reversed (y_bar, cs) pairs with linear-function
+    composition lin_o (b1,c1)(b2,c2) = (b2 + c2.b1, c2 x c1), then the map
+    a_bar_i = vjp(x -> rs_{i-1} (.) x)(as_i, rs_bar_i), a_bar_0 = rs_bar_0.
+    The Jacobians act transposed (the paper's notation caveat)."""
+    rng = np.random.default_rng(500)
+    n = 20
+    X = rand_elems(op, n, rng)
+    d = D[op]
+    yb = rng.standard_normal((n, d))
+    rs = [list(X[0])]
+    for i in range(1, n):
+        rs.append(py_op(op, rs[-1], list(X[i])))
+    cs = []
+    for i in range(n):
+        if i == n - 1:
+            cs.append(np.eye(d))
+        else:
+            xs = [Dual(float(rs[i][t]), np.eye(d)[t]) for t in range(d)]
+            out = py_op(op, xs, list(X[i + 1]))
+            cs.append(np.array([o.t if isinstance(o, Dual) else np.zeros(d) for o in out]))
+    # scan over the reversed sequence with lin_o, via recursive doubling
+    elems = [(yb[n - 1 - j].copy(), cs[n - 1 - j].T.copy()) for j in range(n)]
+
+    def lin_o(p, q):
+        b1, c1 = p
+        b2, c2 = q
+        return (b2 + c2 @ b1, _mat_vec_lin(c2, c1))
+
+    cur = list(elems)
+    step = 1
+    while step < n:
+        cur = [cur[j] if j < step else lin_o(cur[j - step], cur[j]) for j in range(n)]
+        step *= 2
+    rsbar = np.array([cur[n - 1 - i][0] for i in range(n)])
+    exp = np.zeros((n, d))
+    for i in range(n):
+        if i == 0:
+            exp[i] = rsbar[0]
+        else:
+            exp[i] = local_vjp(lambda x, i=i: py_op(op, rs[i - 1], x), X[i], rsbar[i])
+    xb, _ = oracle.scan_vjp(op, yb, *as_args(op, X))
+    np.testing.assert_allclose(xb, exp, rtol=1e-11, atol=1e-12)
+
+
+@pytest.mark.parametrize("op", OPS)
+def test_ppad_scan_rule(op):
+    """PPAD's rule (appendix figure): a right scan with op_lft over
+    (x, u_lft, x_bar) triples, then op_bar_2 against the shifted prefixes."""
+    rng = np.random.default_rng(600)
+    n = 18
+    X = rand_elems(op, n, rng)
+    d = D[op]
+    e = py_neutral(op)
+    xb_in = rng.standard_normal((n, d))
+    xs = [list(X[0])]
+    for i in range(1, n):
+        xs.append(py_op(op, xs[-1], list(X[i])))
+
+    def op_bar_1(x, y, rb):  # vjp of (a -> a (.) y) at x
+        return local_vjp(lambda a: py_op(op, a, y), x, rb)
+
+    def op_bar_2(x, y, rb):  # vjp of (b -> x (.) b) at y
+        return local_vjp(lambda b: py_op(op, x, b), y, rb)
+
+    def op_lft(p, q):
+        x1, a1, y1h = p
+        _, a2, y2h = q
+        return (x1, py_op(op, a1, a2), op_bar_1(x1, a1, y2h) + y1h)
+
+    u_lft = [list(X[i + 1]) if i < n - 1 else list(e) for i in range(n)]
+    m = [(xs[i], u_lft[i], xb_in[i]) for i in range(n)]
+    acc = (list(e), list(e), np.zeros(d))
+    xhat = [None] * n
+    for i in range(n - 1, -1, -1):
+        acc = op_lft(m[i], acc)
+        xhat[i] = acc[2]
+    x_rht = [list(e) if i == 0 else xs[i - 1] for i in range(n)]
+    exp = np.array([op_bar_2(x_rht[i], list(X[i]), xhat[i]) for i in range(n)])
+    xb, _ = oracle.scan_vjp(op, xb_in, *as_args(op, X))
+    np.testing.assert_allclose(xb, exp, rtol=1e-11, atol=1e-12)
+
+
+@pytest.mark.parametrize("op", OPS)
+def test_sort_based_rbi_rule(op):
+    """Reduce-by-index rule figure: stable sort of iota by key, forward and
+    reverse exclusive segmented scans, per-element vjp of l (.) x (.) r with
+    the bin's adjoint, scattered back; out-of-range keys get zero."""
+    rng = np.random.default_rng(700)
+    n, m = 60, 7
+    X = rand_elems(op, n, rng)
+    if op in ("min", "max"):
+        X = np.round(X * 2) / 2
+    d = D[op]
+    idx = rng.integers(-1, m + 1, n).astype(np.int32)
+    hb = rng.standard_normal((m, d))
+    e = py_neutral(op)
+    siota = np.argsort(idx, kind="stable")
+    sks = idx[siota]
+    svs = X[siota]
+    flag = np.array([i == 0 or sks[i - 1] != sks[i] for i in range(n)])
+    ls, acc = [], None
+    for i in range(n):
+        if flag[i]:
+            acc = list(e)
+        ls.append(acc)
+        acc = py_op(op, acc, list(svs[i]))
+    rsr = [None] * n
+    acc = None
+    for i in range(n - 1, -1, -1):
+        if i == n - 1 or flag[i + 1]:
+            acc = list(e)
+        rsr[i] = acc
+        acc = py_op(op, list(svs[i]), acc)
+    sbar = np.zeros((n, d))
+    for i in range(n):
+        k = sks[i]
+        if 0 <= k < m:
+            sbar[i] = local_vjp(lambda x, i=i: py_op(op, py_op(op, ls[i], x), rsr[i]), svs[i], hb[k])
+    exp = np.zeros((n, d))
+    exp[siota] = sbar
+    vb, _ = oracle.rbi_vjp(op, idx, m, hb, *as_args(op, X))
+    np.testing.assert_allclose(vb, exp, rtol=1e-11, atol=1e-12)
+
+
+def test_segmented_matches_per_instance():
+    from workloads import segmented
+    w = segmented(S=6, m=8, median=40, cap=200)
+    f = oracle.segmented_fwd(w["offsets"], w["a"], w["b"], w["idx"], 8)
+    off = w["offsets"]
+    for s in range(6):
+        lo, hi = off[s], off[s + 1]
+        rs, _ = oracle.scan_fwd("linrec", w["a"][lo:hi], w["b"][lo:hi])
+        np.testing.assert_array_equal(f["y"][lo:hi], rs[:, 1])
+        for k in range(8):
+            mem = np.flatnonzero(w["idx"][lo:hi] == k)
+            if mem.size == 0:
+                assert f["argk"][s, k] == hi - lo
+            else:
+                y32 = rs[mem, 1].astype(np.float32)
+                assert f["argk"][s, k] == mem[np.argmin(y32)]
+    ab, bb, cab, cbb = oracle.segmented_vjp(off, w["a"], w["b"], w["idx"], 8, w["ybar"], w["hbar"], f["argk"])
+    assert np.all(cab >= np.abs(ab)) and np.all(cbb >= np.abs(bb))
+    # the min-by-index adjoint plus y_bar, pushed through the linrec adjoint
+    s = 2
+    lo, hi = off[s], off[s + 1]
+    yt = w["ybar"][lo:hi].astype(np.float64).copy()
+    for k in range(8):
+        j = f["argk"][s, k]
+        if j < hi - lo:
+            yt[j] += w["hbar"][s * 8 + k]
+    xb, _ = oracle.scan_vjp("linrec", np.stack([np.zeros(hi - lo), yt], 1), w["a"][lo:hi], w["b"][lo:hi])
+    np.testing.assert_allclose(bb[lo:hi], xb[:, 1], rtol=1e-13)
