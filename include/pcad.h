@@ -1,0 +1,198 @@
+/*
+ * pcad.h -- forward pass and reverse-mode adjoint (vector-Jacobian product)
+ * of reduce, inclusive scan and reduce-by-index on one AMD Instinct MI355X
+ * (gfx950).
+ *
+ * The operations follow "Reverse-Mode AD of Reduce-by-Index and Scan in
+ * Futhark" (Bruun, Larsen, Hinnerskov, Oancea):
+ *   vjp f x y_bar returns x_bar = J^T y_bar           (Section 2.2)
+ *   reduce (.) e xs                                    (Section 3)
+ *   scan (.) e xs, inclusive                           (Section 5)
+ *   reduce_by_index hist (.) e ks vs                   (Section 4)
+ * Operators are +, *, min, max and two generic associative operators:
+ * linear-function composition and the 2x2 matrix product (Section 5.1,
+ * operator figure).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Every array pointer is a DEVICE pointer (hipMalloc'd or equivalent);
+ *   scalars and sizes are host values.  The caller owns all memory; the
+ *   library never allocates on these calls.  `stream` is a hipStream_t
+ *   (NULL = the null stream); every call is asynchronous on it.
+ * - Floats are IEEE binary32, indices int32.  All float arrays must be
+ *   16-byte aligned (else PCAD_E_MISALIGNED).
+ * - `batch` independent rows of `n` elements each, stored contiguously
+ *   row-major (row r starts at element r*n).  batch >= 1, 0 <= n <=
+ *   INT32_MAX, batch*n <= 2^40 (else PCAD_E_SIZE).
+ * - Element layouts per operator:
+ *     PCAD_ADD/MUL/MIN/MAX : x0 = x[batch*n];              x1 unused (NULL)
+ *     PCAD_LINREC          : x0 = a[batch*n] (multiplier), x1 = b[batch*n]
+ *                            (offset); the scan is y_i = a_i*y_{i-1} + b_i,
+ *                            y_{-1} = 0, with cumulative product
+ *                            A_i = a_0*...*a_i.
+ *     PCAD_MAT2            : x0 = M[batch*n][4], row-major 2x2
+ *                            [[m0,m1],[m2,m3]]; the scan is
+ *                            P_i = M_0 x ... x M_i.
+ * - Adjoints are OVERWRITTEN, unless `flags` has PCAD_ACCUMULATE, which gives
+ *   the paper's x_bar += ... (Eq. 1).
+ * - Arguments are validated before any launch and the status is returned
+ *   synchronously.  A failure of a HIP runtime call returns PCAD_E_HIP;
+ *   pcad_last_hip_error() gives its code.  Faults inside kernels surface at
+ *   the caller's next synchronisation of `stream`.
+ * - Workspace: `ws` / `ws_bytes` is caller-owned device scratch of at least
+ *   the size pcad_query() reports.  It MUST be zero-filled once before its
+ *   first use; the library leaves it reusable (its counters reset
+ *   themselves at the end of every launch).  Calls that share one workspace
+ *   must be ordered (same stream): concurrent calls on one workspace race.
+ * - Saved state: `saved` carries what a forward call keeps for the adjoint
+ *   call of the same arguments (layouts below); its size comes from
+ *   pcad_query().  The library never reads it before the forward wrote it.
+ * - Out-of-range keys of reduce-by-index (k < 0 or k >= m) are ignored by
+ *   the forward and receive a zero adjoint (Section 4, sequential
+ *   semantics).  min/max keep the LOWEST index among equal values
+ *   (Section 3.2 Min/Max; Section 4.2); -0.0 and +0.0 compare equal and the
+ *   winner's bit pattern is returned.
+ */
+#ifndef PCAD_H
+#define PCAD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PCAD_OK = 0,
+  PCAD_E_INVALID_ARG = 1, /* bad enum, negative size, unknown flag */
+  PCAD_E_UNSUPPORTED = 2, /* valid arguments, combination not implemented */
+  PCAD_E_NULLPTR = 3,     /* a required pointer is NULL */
+  PCAD_E_MISALIGNED = 4,  /* a float array is not 16-byte aligned */
+  PCAD_E_SIZE = 5,        /* n, m or batch out of the supported range */
+  PCAD_E_WORKSPACE = 6,   /* ws_bytes smaller than pcad_query() reports */
+  PCAD_E_HIP = 7          /* a HIP runtime call failed; see pcad_last_hip_error */
+} pcad_status;
+
+typedef enum { PCAD_REDUCE = 0, PCAD_SCAN = 1, PCAD_RBI = 2 } pcad_combinator;
+
+typedef enum {
+  PCAD_ADD = 0,
+  PCAD_MUL = 1,
+  PCAD_MIN = 2,
+  PCAD_MAX = 3,
+  PCAD_LINREC = 4, /* linear-function composition (a multiplier, b offset) */
+  PCAD_MAT2 = 5    /* 2x2 matrix product, row-major */
+} pcad_op;
+
+enum {
+  PCAD_ACCUMULATE = 1u << 0, /* adjoint calls: x_bar += contribution */
+};
+
+/* Human-readable name of a status code (static storage). */
+const char *pcad_status_string(int status);
+/* hipError_t of the last failed HIP runtime call in this thread (0 if none). */
+int pcad_last_hip_error(void);
+/* Library version string. */
+const char *pcad_version(void);
+
+/*
+ * pcad_query -- bytes of saved state and workspace for a call.
+ * Host-only; needs no GPU.  `m` is the bin count (RBI only, else ignored).
+ * Either output pointer may be NULL.
+ */
+int pcad_query(int combinator, int op, int64_t batch, int64_t n, int64_t m, unsigned flags,
+               size_t *saved_bytes, size_t *workspace_bytes);
+
+/*
+ * reduce (Section 3): y[r] = x[r,0] (.) x[r,1] (.) ... (.) x[r,n-1] per row r;
+ * the neutral element when n = 0.
+ *   y: batch elements (1, 1, 1, 1, 2 = (A, y), 4 floats per row by operator;
+ *      LINREC writes the pair (A, y) of the composed linear function).
+ *   saved layout per row:
+ *     ADD   : nothing;
+ *     MUL   : {uint32 n0; float y_pos} -- number of exact zeros and product
+ *             of the non-zero elements (Section 3.2 Multiplication);
+ *     MIN/MAX: {int32 k} -- lowest index attaining the extremum, n if empty
+ *             (Section 3.2 Min/Max);
+ *     LINREC/MAT2: the exclusive prefix of every tile of the row (opaque).
+ */
+int pcad_reduce_fwd(int op, int64_t batch, int64_t n, const float *x0, const float *x1,
+                    float *y, void *saved, unsigned flags, void *ws, size_t ws_bytes,
+                    void *stream);
+
+/*
+ * Adjoint of reduce: x_bar = J^T y_bar, with y_bar holding one element per
+ * row (same layout as y).  Rules: ADD broadcasts y_bar (Section 3.2
+ * Addition); MUL uses the three zero cases (Section 3.2 Multiplication);
+ * MIN/MAX write y_bar at index k only (Section 3.2 Min/Max); LINREC/MAT2 use
+ * the general rule x_bar_i = d(l_i (.) x_i (.) r_i)/dx_i^T y_bar (Eq. 2) with
+ * l_i, r_i the exclusive prefix and suffix (Section 3.1).
+ *   xbar0/xbar1: same layout as x0/x1 (LINREC: a_bar, b_bar).
+ */
+int pcad_reduce_vjp(int op, int64_t batch, int64_t n, const float *x0, const float *x1,
+                    const void *saved, const float *ybar, float *xbar0, float *xbar1,
+                    unsigned flags, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Inclusive scan (Section 5): rs_0 = x_0, rs_i = rs_{i-1} (.) x_i per row,
+ * by a single-pass decoupled look-back over tiles.
+ *   y0: the scan (scalar ops: x-layout; LINREC: y_i; MAT2: P_i, 4 floats).
+ *   y1: LINREC only, optional: the cumulative multiplier A_i (may be NULL).
+ *   saved: the exclusive prefix of every tile, which the adjoint call uses to
+ *          recompute the forward prefixes inside each tile instead of
+ *          storing them (the redundant-execution choice of the paper).
+ */
+int pcad_scan_fwd(int op, int64_t batch, int64_t n, const float *x0, const float *x1,
+                  float *y0, float *y1, void *saved, unsigned flags, void *ws,
+                  size_t ws_bytes, void *stream);
+
+/*
+ * Adjoint of the inclusive scan (Section 5.2): the backward linear recurrence
+ * lam_i = ybar_i + J_i^T lam_{i+1}, J_i = d(rs_i (.) x_{i+1})/d rs_i, solved
+ * by a right-to-left decoupled look-back scan of adjoint affine maps, fused
+ * with x_bar_i = d(rs_{i-1} (.) x_i)/d x_i^T lam_i (x_bar_0 = lam_0).
+ * Forward prefixes are recomputed inside each tile from `saved`.
+ *   ybar0: adjoint of y0 (x-layout; MAT2 4 floats per element).
+ *   ybar1: LINREC only, optional adjoint of A (NULL = zero).
+ *   xbar0/xbar1: LINREC: a_bar, b_bar; else xbar0 in x-layout.
+ */
+int pcad_scan_vjp(int op, int64_t batch, int64_t n, const float *x0, const float *x1,
+                  const void *saved, const float *ybar0, const float *ybar1, float *xbar0,
+                  float *xbar1, unsigned flags, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * reduce_by_index (Section 4): for every row r and bin k in [0,m),
+ *   hist[r,k] = (.) over v[r,i] with idx[r,i] == k, in ascending i,
+ * starting from the neutral element (the rewrite to a neutral initial
+ * histogram; the caller combines an initial histogram itself).
+ * Supported operators: ADD, MUL, MIN, MAX.  m >= 0, m <= 2^26.
+ *   hist: batch*m floats.
+ *   saved layout (per row, m entries each):
+ *     ADD    : nothing;
+ *     MUL    : {uint32 n0[m]; float y_pos[m]} (zero count and product of
+ *              non-zeros per bin, Section 4.2 Multiplication);
+ *     MIN/MAX: {int32 argk[m]} lowest index of the bin's extremum, n when
+ *              the bin is empty (Section 4.2 Min/Max rule figure).
+ */
+int pcad_rbi_fwd(int op, int64_t batch, int64_t n, int64_t m, const int32_t *idx,
+                 const float *v, float *hist, void *saved, unsigned flags, void *ws,
+                 size_t ws_bytes, void *stream);
+
+/*
+ * Adjoint of reduce_by_index with respect to the values:
+ *   ADD    : v_bar_i = hbar[idx_i] (gather)            (Section 4.2 Addition)
+ *   MUL    : v_bar_i = hbar[k]*(n0==0 ? y_pos/v_i : (n0==1 && v_i==0 ? y_pos : 0))
+ *                                                      (Section 4.2 Multiplication)
+ *   MIN/MAX: v_bar_i = hbar[k] if i == argk[k] else 0  (Section 4.2 Min/Max)
+ * with k = idx_i; out-of-range keys get 0.
+ */
+int pcad_rbi_vjp(int op, int64_t batch, int64_t n, int64_t m, const int32_t *idx,
+                 const float *v, const void *saved, const float *hbar, float *vbar,
+                 unsigned flags, void *ws, size_t ws_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PCAD_H */

@@ -104,6 +104,7 @@ static void combine_abs(int op, const double *cacc, const double *cx,
   switch (op) {
   case OP_MIN: out[0] = (acc[0] <= x[0]) ? cacc[0] : cx[0]; break;
   case OP_MAX: out[0] = (acc[0] >= x[0]) ? cacc[0] : cx[0]; break;
+  case OP_MAT2: out[0] = out[1] = out[2] = out[3] = cacc[0] * cx[0]; break;
   default: combine(op, cacc, cx, out); break;
   }
 }
@@ -161,6 +162,45 @@ static void partials_abs(int op, const double *acc, const double *x, const doubl
   else partials(op, cacc, ax, JA, JX);
 }
 
+/* Companions of the 2x2 matrix product are norm-wise: every entry of a
+ * product chain is bounded by the product of the factors' spectral norms,
+ * and the rounding error of any bracketing by a small multiple of u times
+ * that product.  (The entrywise |M_0||M_1|...|M_i| bound grows with the
+ * spectral radius of |M| >= 1 even when the product is orthogonal, which
+ * would make it useless for long chains.)  A MAT2 companion is stored as the
+ * same scalar in all four entries. */
+static double spec2(const double *m) {
+  double f = m[0] * m[0] + m[1] * m[1] + m[2] * m[2] + m[3] * m[3];
+  double det = m[0] * m[3] - m[1] * m[2];
+  double disc = f * f - 4.0 * det * det;
+  if (disc < 0.0) disc = 0.0;
+  return sqrt(0.5 * (f + sqrt(disc)));
+}
+
+static double frob(const double *m) {
+  return sqrt(m[0] * m[0] + m[1] * m[1] + m[2] * m[2] + m[3] * m[3]);
+}
+
+/* companion of one input element: |x|, or ||M||_2 broadcast for MAT2 */
+static void elem_abs(int op, const double *x, double *ax) {
+  if (op == OP_MAT2) {
+    double s = spec2(x);
+    ax[0] = ax[1] = ax[2] = ax[3] = s;
+  } else {
+    for (int t = 0; t < orc_dim(op); ++t) ax[t] = fabs(x[t]);
+  }
+}
+
+/* companion of an output adjoint: |ybar|, or ||Ybar||_F broadcast for MAT2 */
+static void adj_abs(int op, const double *y, double *ay) {
+  if (op == OP_MAT2) {
+    double s = frob(y);
+    ay[0] = ay[1] = ay[2] = ay[3] = s;
+  } else {
+    for (int t = 0; t < orc_dim(op); ++t) ay[t] = fabs(y[t]);
+  }
+}
+
 /* y += J^T v for a d x d matrix J */
 static void add_JTv(int d, const double *J, const double *v, double *y) {
   for (int c = 0; c < d; ++c) {
@@ -178,6 +218,26 @@ static void add_absJTv(int d, const double *J, const double *v, double *y) {
   }
 }
 
+/* companion of J^T v: entrywise |J|^T v, or for MAT2 the norm of the
+ * linear map (the other factor's 2-norm) times the scalar companion v */
+static void comp_JA(int op, const double *JA, const double *ax, const double *v, double *y) {
+  if (op == OP_MAT2) {
+    double t = ax[0] * v[0];
+    y[0] += t; y[1] += t; y[2] += t; y[3] += t;
+  } else {
+    add_absJTv(orc_dim(op), JA, v, y);
+  }
+}
+
+static void comp_JX(int op, const double *JX, const double *cacc, const double *v, double *y) {
+  if (op == OP_MAT2) {
+    double t = cacc[0] * v[0];
+    y[0] += t; y[1] += t; y[2] += t; y[3] += t;
+  } else {
+    add_absJTv(orc_dim(op), JX, v, y);
+  }
+}
+
 /* ------------------------------------------------------------------------ */
 /* scan                                                                      */
 /* ------------------------------------------------------------------------ */
@@ -190,11 +250,11 @@ int orc_scan_fwd(int op, int64_t n, const double *x, double *rs, double *c) {
   for (int64_t i = 0; i < n; ++i) {
     if (i == 0) {
       memcpy(rs, x, sizeof(double) * d);
-      if (c) for (int t = 0; t < d; ++t) c[t] = fabs(x[t]);
+      if (c) elem_abs(op, x, c);
       continue;
     }
     double ax[4];
-    for (int t = 0; t < d; ++t) ax[t] = fabs(x[i * d + t]);
+    elem_abs(op, x + i * d, ax);
     if (c) combine_abs(op, c + (i - 1) * d, ax, rs + (i - 1) * d, x + i * d, c + i * d);
     combine(op, rs + (i - 1) * d, x + i * d, rs + i * d);
   }
@@ -216,9 +276,10 @@ int orc_scan_vjp(int op, int64_t n, const double *x, const double *ybar, const d
   double *clam = (double *)malloc(sizeof(double) * n * d);
   if (!rs || !crs || !lam || !clam) { free(rs); free(crs); free(lam); free(clam); return 2; }
   orc_scan_fwd(op, n, x, rs, crs);
-  for (int64_t i = 0; i < n * d; ++i) {
-    lam[i] = ybar[i];
-    clam[i] = cybar ? cybar[i] : fabs(ybar[i]);
+  for (int64_t i = 0; i < n * d; ++i) lam[i] = ybar[i];
+  for (int64_t i = 0; i < n; ++i) {
+    if (cybar) memcpy(clam + i * d, cybar + i * d, sizeof(double) * d);
+    else adj_abs(op, ybar + i * d, clam + i * d);
   }
   double JA[16], JX[16], ax[4];
   for (int64_t i = n - 1; i >= 1; --i) {
@@ -226,13 +287,13 @@ int orc_scan_vjp(int op, int64_t n, const double *x, const double *ybar, const d
     for (int t = 0; t < d; ++t) xbar[i * d + t] = 0.0;
     add_JTv(d, JX, lam + i * d, xbar + i * d);
     add_JTv(d, JA, lam + i * d, lam + (i - 1) * d);
-    for (int t = 0; t < d; ++t) ax[t] = fabs(x[i * d + t]);
+    elem_abs(op, x + i * d, ax);
     partials_abs(op, rs + (i - 1) * d, x + i * d, crs + (i - 1) * d, ax, JA, JX);
     if (cxbar) {
       for (int t = 0; t < d; ++t) cxbar[i * d + t] = 0.0;
-      add_absJTv(d, JX, clam + i * d, cxbar + i * d);
+      comp_JX(op, JX, crs + (i - 1) * d, clam + i * d, cxbar + i * d);
     }
-    add_absJTv(d, JA, clam + i * d, clam + (i - 1) * d);
+    comp_JA(op, JA, ax, clam + i * d, clam + (i - 1) * d);
   }
   for (int t = 0; t < d; ++t) {
     xbar[t] = lam[t];
@@ -270,11 +331,11 @@ int orc_reduce_fwd(int op, int64_t n, const double *x, double *y, double *c, int
       /* the first element always replaces the neutral (a real element beats
        * the sentinel of the lifted min/max) */
       memcpy(acc, xi, sizeof(double) * d);
-      for (int t = 0; t < d; ++t) cacc[t] = fabs(xi[t]);
+      elem_abs(op, xi, cacc);
       win = 0;
       continue;
     }
-    for (int t = 0; t < d; ++t) ax[t] = fabs(xi[t]);
+    elem_abs(op, xi, ax);
     combine_abs(op, cacc, ax, acc, xi, cn);
     combine(op, acc, xi, nxt);
     if ((op == OP_MIN && xi[0] < acc[0]) || (op == OP_MAX && xi[0] > acc[0])) win = i;
@@ -301,19 +362,20 @@ int orc_reduce_vjp(int op, int64_t n, const double *x, const double *ybar, doubl
   if (!rs || !crs) { free(rs); free(crs); return 2; }
   orc_scan_fwd(op, n, x, rs, crs); /* the fold's intermediate accumulators */
   double lam[4], clam[4], nl[4], ncl[4], JA[16], JX[16], ax[4];
-  for (int t = 0; t < d; ++t) { lam[t] = ybar[t]; clam[t] = fabs(ybar[t]); }
+  for (int t = 0; t < d; ++t) lam[t] = ybar[t];
+  adj_abs(op, ybar, clam);
   for (int64_t i = n - 1; i >= 1; --i) {
     partials(op, rs + (i - 1) * d, x + i * d, JA, JX);
     for (int t = 0; t < d; ++t) { xbar[i * d + t] = 0.0; nl[t] = 0.0; ncl[t] = 0.0; }
     add_JTv(d, JX, lam, xbar + i * d);
     add_JTv(d, JA, lam, nl);
-    for (int t = 0; t < d; ++t) ax[t] = fabs(x[i * d + t]);
+    elem_abs(op, x + i * d, ax);
     partials_abs(op, rs + (i - 1) * d, x + i * d, crs + (i - 1) * d, ax, JA, JX);
     if (cxbar) {
       for (int t = 0; t < d; ++t) cxbar[i * d + t] = 0.0;
-      add_absJTv(d, JX, clam, cxbar + i * d);
+      comp_JX(op, JX, crs + (i - 1) * d, clam, cxbar + i * d);
     }
-    add_absJTv(d, JA, clam, ncl);
+    comp_JA(op, JA, ax, clam, ncl);
     memcpy(lam, nl, sizeof lam);
     memcpy(clam, ncl, sizeof clam);
   }
@@ -364,7 +426,7 @@ int orc_rbi_fwd(int op, int64_t n, int64_t m, const int32_t *idx, const double *
       if (n0 && vi[0] == 0.0) n0[k]++;
       if (ypos && vi[0] != 0.0) ypos[k] *= vi[0];
     }
-    for (int t = 0; t < d; ++t) av[t] = fabs(vi[t]);
+    elem_abs(op, vi, av);
     if (cnt[k] == 0) {
       memcpy(hist + k * d, vi, sizeof(double) * d);
       if (chist) memcpy(chist + k * d, av, sizeof(double) * d);
@@ -412,7 +474,7 @@ int orc_rbi_vjp(int op, int64_t n, int64_t m, const int32_t *idx, const double *
   for (int64_t i = 0; i < n; ++i) {
     int64_t k = idx[i];
     if (k < 0 || k >= m) continue;
-    for (int t = 0; t < d; ++t) av[t] = fabs(v[i * d + t]);
+    elem_abs(op, v + i * d, av);
     if (cnt[k] == 0) {
       first[i] = 1;
       memcpy(cur + k * d, v + i * d, sizeof(double) * d);
@@ -428,7 +490,8 @@ int orc_rbi_vjp(int op, int64_t n, int64_t m, const int32_t *idx, const double *
     }
     cnt[k]++;
   }
-  for (int64_t k = 0; k < m * d; ++k) { lam[k] = hbar[k]; clam[k] = fabs(hbar[k]); }
+  for (int64_t k = 0; k < m * d; ++k) lam[k] = hbar[k];
+  for (int64_t k = 0; k < m; ++k) adj_abs(op, hbar + k * d, clam + k * d);
   double JA[16], JX[16], nl[4], ncl[4];
   for (int64_t i = n - 1; i >= 0; --i) {
     int64_t k = idx[i];
@@ -449,10 +512,10 @@ int orc_rbi_vjp(int op, int64_t n, int64_t m, const int32_t *idx, const double *
     add_JTv(d, JX, lk, vbar + i * d);
     for (int t = 0; t < d; ++t) { nl[t] = 0.0; ncl[t] = 0.0; }
     add_JTv(d, JA, lk, nl);
-    for (int t = 0; t < d; ++t) av[t] = fabs(v[i * d + t]);
+    elem_abs(op, v + i * d, av);
     partials_abs(op, before + i * d, v + i * d, cbefore + i * d, av, JA, JX);
-    if (cvbar) add_absJTv(d, JX, clk, cvbar + i * d);
-    add_absJTv(d, JA, clk, ncl);
+    if (cvbar) comp_JX(op, JX, cbefore + i * d, clk, cvbar + i * d);
+    comp_JA(op, JA, av, clk, ncl);
     memcpy(lk, nl, sizeof(double) * d);
     memcpy(clk, ncl, sizeof(double) * d);
   }

@@ -1,0 +1,254 @@
+"""Python binding of libpcad: forward and reverse-mode adjoint of reduce,
+inclusive scan and reduce-by-index on AMD Instinct MI355X (gfx950).
+
+Every step runs in the HIP kernels of ``libpcad.so``; this module only
+marshals torch tensors (device memory and streams) into the C-ABI calls of
+``include/pcad.h``.  There is no CPU fallback: if the library is missing or
+no GPU is present, calls raise.
+
+Low level: ``pcad_*`` attributes are the C functions themselves (ctypes),
+with the same names and arguments as the header.
+
+High level (torch tensors on a ROCm device, float32 / int32, contiguous):
+  reduce_fwd / reduce_vjp, scan_fwd / scan_vjp, rbi_fwd / rbi_vjp
+and the autograd wrappers in ``paper_2310_03568_amd.autograd``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpcad.so")
+
+OPS = {"add": 0, "mul": 1, "min": 2, "max": 3, "linrec": 4, "mat2": 5}
+DIM = {"add": 1, "mul": 1, "min": 1, "max": 1, "linrec": 2, "mat2": 4}
+REDUCE, SCAN, RBI = 0, 1, 2
+ACCUMULATE = 1
+
+_lib = None
+
+
+class PcadError(RuntimeError):
+    pass
+
+
+def lib():
+    """The loaded libpcad (ctypes.CDLL).  Raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise PcadError(f"{LIB_PATH} is missing: build it with "
+                            "`python -m paper_2310_03568_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I, I64, U, SZ = (ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_uint,
+                            ctypes.c_size_t)
+        PSZ = ctypes.POINTER(ctypes.c_size_t)
+        sig = {
+            "pcad_status_string": ([I], ctypes.c_char_p),
+            "pcad_last_hip_error": ([], I),
+            "pcad_version": ([], ctypes.c_char_p),
+            "pcad_query": ([I, I, I64, I64, I64, U, PSZ, PSZ], I),
+            "pcad_reduce_fwd": ([I, I64, I64, P, P, P, P, U, P, SZ, P], I),
+            "pcad_reduce_vjp": ([I, I64, I64, P, P, P, P, P, P, U, P, SZ, P], I),
+            "pcad_scan_fwd": ([I, I64, I64, P, P, P, P, P, U, P, SZ, P], I),
+            "pcad_scan_vjp": ([I, I64, I64, P, P, P, P, P, P, P, U, P, SZ, P], I),
+            "pcad_rbi_fwd": ([I, I64, I64, I64, P, P, P, P, U, P, SZ, P], I),
+            "pcad_rbi_vjp": ([I, I64, I64, I64, P, P, P, P, P, U, P, SZ, P], I),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def __getattr__(name):
+    if name.startswith("pcad_"):
+        return getattr(lib(), name)
+    raise AttributeError(name)
+
+
+def check(status: int, what: str = ""):
+    if status != 0:
+        L = lib()
+        msg = L.pcad_status_string(status).decode()
+        hip = L.pcad_last_hip_error()
+        raise PcadError(f"{what}: {msg} (status {status}, hip error {hip})")
+
+
+# ---------------------------------------------------------------------------
+# workspace: one zero-initialised buffer per (device, stream), grown on demand
+# ---------------------------------------------------------------------------
+_ws = {}
+
+
+def workspace(nbytes: int, device: torch.device, stream=None) -> torch.Tensor:
+    stream = stream if stream is not None else torch.cuda.current_stream(device)
+    key = (device.index, stream.cuda_stream)
+    buf = _ws.get(key)
+    if buf is None or buf.numel() < nbytes:
+        size = max(int(nbytes), 4096)
+        size = 1 << (size - 1).bit_length()
+        buf = torch.zeros(size, dtype=torch.uint8, device=device)
+        _ws[key] = buf
+    return buf
+
+
+def query(comb: int, op: str, batch: int, n: int, m: int = 0):
+    s = ctypes.c_size_t(0)
+    w = ctypes.c_size_t(0)
+    check(lib().pcad_query(comb, OPS[op], batch, n, m, 0, ctypes.byref(s), ctypes.byref(w)),
+          "pcad_query")
+    return s.value, w.value
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else t.data_ptr()
+
+
+def _stream(device):
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _dev_check(*ts):
+    for t in ts:
+        if t is None:
+            continue
+        if not t.is_cuda:
+            raise PcadError("pcad needs device tensors (no CPU path)")
+        if not t.is_contiguous():
+            raise PcadError("pcad needs contiguous tensors")
+
+
+def _shape(op: str, x: torch.Tensor):
+    """(batch, n) of a value tensor: (..., n) for scalar ops and linrec,
+    (..., n, 4) for mat2."""
+    if op == "mat2":
+        if x.shape[-1] != 4:
+            raise PcadError("mat2 expects a trailing dimension of 4")
+        lead = x.shape[:-1]
+    else:
+        lead = x.shape
+    n = lead[-1] if len(lead) else 1
+    batch = 1
+    for d in lead[:-1]:
+        batch *= d
+    return batch, n, tuple(lead[:-1])
+
+
+# ---------------------------------------------------------------------------
+# reduce
+# ---------------------------------------------------------------------------
+def reduce_fwd(op: str, x0: torch.Tensor, x1: Optional[torch.Tensor] = None):
+    """Returns (y, saved).  y has shape lead + (d,) for linrec/mat2 (linrec:
+    (A, y) of the composed linear function), lead otherwise."""
+    _dev_check(x0, x1)
+    batch, n, lead = _shape(op, x0)
+    d = DIM[op]
+    s_b, w_b = query(REDUCE, op, batch, n)
+    dev = x0.device
+    y = torch.empty(lead + ((d,) if d > 1 else ()), dtype=torch.float32, device=dev)
+    saved = torch.empty(max(s_b, 16), dtype=torch.uint8, device=dev)
+    ws = workspace(w_b, dev)
+    check(lib().pcad_reduce_fwd(OPS[op], batch, n, _ptr(x0), _ptr(x1), _ptr(y), _ptr(saved), 0,
+                                _ptr(ws), ws.numel(), _stream(dev)), "pcad_reduce_fwd")
+    return y, saved
+
+
+def reduce_vjp(op: str, x0, x1, saved, ybar, out=None, accumulate: bool = False):
+    _dev_check(x0, x1, ybar)
+    batch, n, lead = _shape(op, x0)
+    s_b, w_b = query(REDUCE, op, batch, n)
+    dev = x0.device
+    if out is None:
+        out = (torch.empty_like(x0), torch.empty_like(x1)) if op == "linrec" else (torch.empty_like(x0),)
+    ws = workspace(w_b, dev)
+    check(lib().pcad_reduce_vjp(OPS[op], batch, n, _ptr(x0), _ptr(x1), _ptr(saved),
+                                _ptr(ybar.contiguous()), _ptr(out[0]),
+                                _ptr(out[1]) if len(out) > 1 else None,
+                                ACCUMULATE if accumulate else 0, _ptr(ws), ws.numel(),
+                                _stream(dev)), "pcad_reduce_vjp")
+    return out if op == "linrec" else out[0]
+
+
+# ---------------------------------------------------------------------------
+# scan
+# ---------------------------------------------------------------------------
+def scan_fwd(op: str, x0: torch.Tensor, x1: Optional[torch.Tensor] = None, want_A: bool = False):
+    """Returns (y, A, saved); A is the linrec cumulative multiplier when
+    ``want_A`` (else None)."""
+    _dev_check(x0, x1)
+    batch, n, lead = _shape(op, x0)
+    s_b, w_b = query(SCAN, op, batch, n)
+    dev = x0.device
+    y = torch.empty_like(x0)
+    A = torch.empty_like(x0) if (op == "linrec" and want_A) else None
+    saved = torch.empty(max(s_b, 16), dtype=torch.uint8, device=dev)
+    ws = workspace(w_b, dev)
+    check(lib().pcad_scan_fwd(OPS[op], batch, n, _ptr(x0), _ptr(x1), _ptr(y), _ptr(A),
+                              _ptr(saved), 0, _ptr(ws), ws.numel(), _stream(dev)),
+          "pcad_scan_fwd")
+    return y, A, saved
+
+
+def scan_vjp(op: str, x0, x1, saved, ybar, Abar=None, out=None, accumulate: bool = False):
+    """Adjoint of the scan.  Returns a_bar, b_bar for linrec, else x_bar."""
+    _dev_check(x0, x1, ybar, Abar)
+    batch, n, lead = _shape(op, x0)
+    s_b, w_b = query(SCAN, op, batch, n)
+    dev = x0.device
+    if out is None:
+        out = (torch.empty_like(x0), torch.empty_like(x1)) if op == "linrec" else (torch.empty_like(x0),)
+    ws = workspace(w_b, dev)
+    check(lib().pcad_scan_vjp(OPS[op], batch, n, _ptr(x0), _ptr(x1), _ptr(saved), _ptr(ybar),
+                              _ptr(Abar), _ptr(out[0]), _ptr(out[1]) if len(out) > 1 else None,
+                              ACCUMULATE if accumulate else 0, _ptr(ws), ws.numel(),
+                              _stream(dev)), "pcad_scan_vjp")
+    return out if op == "linrec" else out[0]
+
+
+# ---------------------------------------------------------------------------
+# reduce-by-index
+# ---------------------------------------------------------------------------
+def rbi_fwd(op: str, idx: torch.Tensor, v: torch.Tensor, m: int):
+    """Returns (hist, saved).  idx, v of shape (..., n); hist (..., m).
+    saved: mul -> uint32 n0[batch*m] then float y_pos[batch*m];
+    min/max -> int32 argk[batch*m]."""
+    _dev_check(idx, v)
+    batch, n, lead = _shape(op, v)
+    s_b, w_b = query(RBI, op, batch, n, m)
+    dev = v.device
+    hist = torch.empty(lead + (m,), dtype=torch.float32, device=dev)
+    saved = torch.empty(max(s_b, 16), dtype=torch.uint8, device=dev)
+    ws = workspace(w_b, dev)
+    check(lib().pcad_rbi_fwd(OPS[op], batch, n, m, _ptr(idx), _ptr(v), _ptr(hist), _ptr(saved), 0,
+                             _ptr(ws), ws.numel(), _stream(dev)), "pcad_rbi_fwd")
+    return hist, saved
+
+
+def rbi_vjp(op: str, idx, v, m: int, saved, hbar, out=None, accumulate: bool = False):
+    _dev_check(idx, v, hbar)
+    batch, n, lead = _shape(op, v)
+    s_b, w_b = query(RBI, op, batch, n, m)
+    dev = v.device
+    out = torch.empty_like(v) if out is None else out
+    ws = workspace(w_b, dev)
+    check(lib().pcad_rbi_vjp(OPS[op], batch, n, m, _ptr(idx), _ptr(v), _ptr(saved), _ptr(hbar),
+                             _ptr(out), ACCUMULATE if accumulate else 0, _ptr(ws), ws.numel(),
+                             _stream(dev)), "pcad_rbi_vjp")
+    return out
+
+
+def saved_argk(saved: torch.Tensor, batch: int, m: int) -> torch.Tensor:
+    return saved[: batch * m * 4].view(torch.int32).view(batch, m)
+
+
+def saved_mul(saved: torch.Tensor, batch: int, m: int):
+    n0 = saved[: batch * m * 4].view(torch.int32).view(batch, m)
+    yp = saved[batch * m * 4: batch * m * 8].view(torch.float32).view(batch, m)
+    return n0, yp

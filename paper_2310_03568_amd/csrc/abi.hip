@@ -1,0 +1,253 @@
+// C-ABI entry points: argument validation (host only, before any launch),
+// size queries, dispatch to the kernels.  See include/pcad.h.
+#include <stdint.h>
+#include <string.h>
+
+#include "../../include/pcad.h"
+#include "internal.hpp"
+
+using namespace pcad;
+
+namespace {
+
+thread_local int g_last_hip = 0;
+
+constexpr int64_t kMaxN = 2147483647LL;
+constexpr int64_t kMaxTotal = 1LL << 40;
+constexpr int64_t kMaxBins = 1LL << 26;
+constexpr unsigned kKnownFlags = PCAD_ACCUMULATE;
+
+int hip_status(hipError_t e) {
+  if (e == hipSuccess) return PCAD_OK;
+  g_last_hip = (int)e;
+  return PCAD_E_HIP;
+}
+
+bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
+int check_common(int op, int64_t batch, int64_t n, unsigned flags) {
+  if (op < PCAD_ADD || op > PCAD_MAT2) return PCAD_E_INVALID_ARG;
+  if (flags & ~kKnownFlags) return PCAD_E_INVALID_ARG;
+  if (batch < 0 || n < 0) return PCAD_E_INVALID_ARG;
+  if (n > kMaxN) return PCAD_E_SIZE;
+  if (batch > 0 && n > 0 && batch > kMaxTotal / n) return PCAD_E_SIZE;
+  return PCAD_OK;
+}
+
+// a required float array: non-null and 16-byte aligned
+int need(const void *p) {
+  if (!p) return PCAD_E_NULLPTR;
+  if (!aligned16(p)) return PCAD_E_MISALIGNED;
+  return PCAD_OK;
+}
+
+// an optional float array: null or 16-byte aligned
+int opt(const void *p) { return (p && !aligned16(p)) ? PCAD_E_MISALIGNED : PCAD_OK; }
+
+#define PCAD_TRY(expr)          \
+  do {                          \
+    const int _st = (expr);     \
+    if (_st != PCAD_OK) return _st; \
+  } while (0)
+
+int64_t scan_tiles(int op, int64_t batch, int64_t n) {
+  const int t = scan_tile_size(op);
+  return batch * ((n + t - 1) / t);
+}
+
+size_t scan_saved(int op, int64_t batch, int64_t n) {
+  return (size_t)scan_tiles(op, batch, n) * scan_elem_floats(op) * sizeof(float);
+}
+
+size_t scan_ws(int op, int64_t batch, int64_t n) {
+  const int fw = 2 * scan_elem_floats(op);
+  const int bw = scan_status_words(op, true);
+  const int w = fw > bw ? fw : bw;
+  return kCtlBytes + (size_t)scan_tiles(op, batch, n) * w * sizeof(uint64_t);
+}
+
+size_t reduce_saved(int op, int64_t batch, int64_t n) {
+  switch (op) {
+  case PCAD_ADD: return 0;
+  case PCAD_MUL: return (size_t)batch * 8;
+  case PCAD_MIN:
+  case PCAD_MAX: return (size_t)batch * 4;
+  default: return scan_saved(op, batch, n);
+  }
+}
+
+int query(int comb, int op, int64_t batch, int64_t n, int64_t m, size_t *saved, size_t *ws) {
+  size_t s = 0, w = 0;
+  switch (comb) {
+  case PCAD_REDUCE:
+    s = reduce_saved(op, batch, n);
+    w = reduce_ws_bytes(op, batch, n);
+    break;
+  case PCAD_SCAN:
+    s = scan_saved(op, batch, n);
+    w = scan_ws(op, batch, n);
+    break;
+  case PCAD_RBI:
+    if (op == PCAD_LINREC || op == PCAD_MAT2) return PCAD_E_UNSUPPORTED;
+    if (m < 0) return PCAD_E_INVALID_ARG;
+    if (m > kMaxBins) return PCAD_E_SIZE;
+    s = rbi_saved_bytes(op, batch, m);
+    w = rbi_ws_bytes(op, batch, n, m);
+    break;
+  default: return PCAD_E_INVALID_ARG;
+  }
+  if (saved) *saved = s;
+  if (ws) *ws = w;
+  return PCAD_OK;
+}
+
+int check_ws(int comb, int op, int64_t batch, int64_t n, int64_t m, const void *ws,
+             size_t ws_bytes) {
+  size_t need_ws = 0;
+  PCAD_TRY(query(comb, op, batch, n, m, nullptr, &need_ws));
+  if (ws_bytes < need_ws) return PCAD_E_WORKSPACE;
+  if (need_ws > 0 && !ws) return PCAD_E_NULLPTR;
+  if (ws && ((uintptr_t)ws & 255u)) return PCAD_E_MISALIGNED;
+  return PCAD_OK;
+}
+
+int check_saved(int comb, int op, int64_t batch, int64_t n, int64_t m, const void *saved) {
+  size_t s = 0;
+  PCAD_TRY(query(comb, op, batch, n, m, &s, nullptr));
+  if (s > 0 && !saved) return PCAD_E_NULLPTR;
+  if (saved && !aligned16(saved)) return PCAD_E_MISALIGNED;
+  return PCAD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *pcad_status_string(int status) {
+  switch (status) {
+  case PCAD_OK: return "ok";
+  case PCAD_E_INVALID_ARG: return "invalid argument";
+  case PCAD_E_UNSUPPORTED: return "unsupported combination";
+  case PCAD_E_NULLPTR: return "null pointer";
+  case PCAD_E_MISALIGNED: return "pointer not 16-byte aligned";
+  case PCAD_E_SIZE: return "size out of range";
+  case PCAD_E_WORKSPACE: return "workspace too small";
+  case PCAD_E_HIP: return "HIP runtime error";
+  }
+  return "unknown status";
+}
+
+int pcad_last_hip_error(void) { return g_last_hip; }
+
+const char *pcad_version(void) { return "pcad 0.1 gfx950"; }
+
+int pcad_query(int combinator, int op, int64_t batch, int64_t n, int64_t m, unsigned flags,
+               size_t *saved_bytes, size_t *workspace_bytes) {
+  PCAD_TRY(check_common(op, batch, n, flags));
+  return query(combinator, op, batch, n, m, saved_bytes, workspace_bytes);
+}
+
+int pcad_reduce_fwd(int op, int64_t batch, int64_t n, const float *x0, const float *x1, float *y,
+                    void *saved, unsigned flags, void *ws, size_t ws_bytes, void *stream) {
+  PCAD_TRY(check_common(op, batch, n, flags));
+  if (batch == 0) return PCAD_OK;
+  if (n > 0) {
+    PCAD_TRY(need(x0));
+    if (op == PCAD_LINREC) PCAD_TRY(need(x1));
+  }
+  PCAD_TRY(need(y));
+  PCAD_TRY(check_saved(PCAD_REDUCE, op, batch, n, 0, saved));
+  PCAD_TRY(check_ws(PCAD_REDUCE, op, batch, n, 0, ws, ws_bytes));
+  return hip_status(reduce_fwd_launch(op, batch, n, x0, x1, y, saved, ws, (hipStream_t)stream));
+}
+
+int pcad_reduce_vjp(int op, int64_t batch, int64_t n, const float *x0, const float *x1,
+                    const void *saved, const float *ybar, float *xbar0, float *xbar1,
+                    unsigned flags, void *ws, size_t ws_bytes, void *stream) {
+  PCAD_TRY(check_common(op, batch, n, flags));
+  if (batch == 0 || n == 0) return PCAD_OK;
+  if (op != PCAD_ADD) PCAD_TRY(need(x0));
+  if (op == PCAD_LINREC) PCAD_TRY(need(x1));
+  PCAD_TRY(need(ybar));
+  PCAD_TRY(need(xbar0));
+  if (op == PCAD_LINREC) PCAD_TRY(need(xbar1));
+  PCAD_TRY(check_saved(PCAD_REDUCE, op, batch, n, 0, saved));
+  PCAD_TRY(check_ws(PCAD_REDUCE, op, batch, n, 0, ws, ws_bytes));
+  return hip_status(reduce_vjp_launch(op, batch, n, x0, x1, saved, ybar, xbar0, xbar1,
+                                      (flags & PCAD_ACCUMULATE) != 0, ws, (hipStream_t)stream));
+}
+
+int pcad_scan_fwd(int op, int64_t batch, int64_t n, const float *x0, const float *x1, float *y0,
+                  float *y1, void *saved, unsigned flags, void *ws, size_t ws_bytes,
+                  void *stream) {
+  PCAD_TRY(check_common(op, batch, n, flags));
+  if (batch == 0 || n == 0) return PCAD_OK;
+  if (scan_tiles(op, batch, n) > 2147483647LL) return PCAD_E_SIZE;
+  PCAD_TRY(need(x0));
+  if (op == PCAD_LINREC) PCAD_TRY(need(x1));
+  PCAD_TRY(need(y0));
+  PCAD_TRY(opt(y1));
+  if (op != PCAD_LINREC && y1) return PCAD_E_INVALID_ARG;
+  PCAD_TRY(check_saved(PCAD_SCAN, op, batch, n, 0, saved));
+  PCAD_TRY(check_ws(PCAD_SCAN, op, batch, n, 0, ws, ws_bytes));
+  return hip_status(scan_fwd_launch(op, batch, n, x0, x1, y0, y1, static_cast<float *>(saved),
+                                    nullptr, false, ws, (hipStream_t)stream));
+}
+
+int pcad_scan_vjp(int op, int64_t batch, int64_t n, const float *x0, const float *x1,
+                  const void *saved, const float *ybar0, const float *ybar1, float *xbar0,
+                  float *xbar1, unsigned flags, void *ws, size_t ws_bytes, void *stream) {
+  PCAD_TRY(check_common(op, batch, n, flags));
+  if (batch == 0 || n == 0) return PCAD_OK;
+  if (scan_tiles(op, batch, n) > 2147483647LL) return PCAD_E_SIZE;
+  PCAD_TRY(need(x0));
+  if (op == PCAD_LINREC) PCAD_TRY(need(x1));
+  PCAD_TRY(need(ybar0));
+  PCAD_TRY(opt(ybar1));
+  if (op != PCAD_LINREC && ybar1) return PCAD_E_INVALID_ARG;
+  PCAD_TRY(need(xbar0));
+  if (op == PCAD_LINREC) PCAD_TRY(need(xbar1));
+  PCAD_TRY(check_saved(PCAD_SCAN, op, batch, n, 0, saved));
+  PCAD_TRY(check_ws(PCAD_SCAN, op, batch, n, 0, ws, ws_bytes));
+  return hip_status(scan_vjp_launch(op, batch, n, x0, x1, static_cast<const float *>(saved), ybar0,
+                                    ybar1, xbar0, xbar1, (flags & PCAD_ACCUMULATE) != 0, ws,
+                                    (hipStream_t)stream));
+}
+
+int pcad_rbi_fwd(int op, int64_t batch, int64_t n, int64_t m, const int32_t *idx, const float *v,
+                 float *hist, void *saved, unsigned flags, void *ws, size_t ws_bytes,
+                 void *stream) {
+  PCAD_TRY(check_common(op, batch, n, flags));
+  if (op == PCAD_LINREC || op == PCAD_MAT2) return PCAD_E_UNSUPPORTED;
+  if (m < 0) return PCAD_E_INVALID_ARG;
+  if (m > kMaxBins) return PCAD_E_SIZE;
+  if (batch == 0 || m == 0) return PCAD_OK;
+  if (n > 0) {
+    PCAD_TRY(need(idx));
+    PCAD_TRY(need(v));
+  }
+  PCAD_TRY(need(hist));
+  PCAD_TRY(check_saved(PCAD_RBI, op, batch, n, m, saved));
+  PCAD_TRY(check_ws(PCAD_RBI, op, batch, n, m, ws, ws_bytes));
+  return hip_status(rbi_fwd_launch(op, batch, n, m, idx, v, hist, saved, ws, (hipStream_t)stream));
+}
+
+int pcad_rbi_vjp(int op, int64_t batch, int64_t n, int64_t m, const int32_t *idx, const float *v,
+                 const void *saved, const float *hbar, float *vbar, unsigned flags, void *ws,
+                 size_t ws_bytes, void *stream) {
+  PCAD_TRY(check_common(op, batch, n, flags));
+  if (op == PCAD_LINREC || op == PCAD_MAT2) return PCAD_E_UNSUPPORTED;
+  if (m < 0) return PCAD_E_INVALID_ARG;
+  if (m > kMaxBins) return PCAD_E_SIZE;
+  if (batch == 0 || n == 0) return PCAD_OK;
+  PCAD_TRY(need(idx));
+  if (op == PCAD_MUL) PCAD_TRY(need(v));
+  if (m > 0) PCAD_TRY(need(hbar));
+  PCAD_TRY(need(vbar));
+  PCAD_TRY(check_saved(PCAD_RBI, op, batch, n, m, saved));
+  (void)ws; (void)ws_bytes;
+  return hip_status(rbi_vjp_launch(op, batch, n, m, idx, v, saved, hbar, vbar,
+                                   (flags & PCAD_ACCUMULATE) != 0, (hipStream_t)stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,421 @@
+// Device-side building blocks shared by the scan, reduce and reduce-by-index
+// kernels: element types, the forward operators, the adjoint affine maps of
+// the scan adjoint, wave64 scans, coalesced tile I/O, and the decoupled
+// look-back protocol with epoch-tagged status words.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pcad {
+
+constexpr int BLOCK = 256;
+constexpr int WAVE = 64;
+constexpr int WAVES = BLOCK / WAVE;
+
+// operator ids (same values as the public enum)
+enum { ADD = 0, MUL = 1, MIN = 2, MAX = 3, LINREC = 4, MAT2 = 5 };
+
+template <int N>
+struct Vec {
+  float f[N];
+};
+
+// ---------------------------------------------------------------------------
+// wave64 data movement (ds_bpermute through the LDS crossbar, no LDS storage)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+
+template <int N>
+__device__ __forceinline__ Vec<N> shfl_up(const Vec<N> &v, int d) {
+  Vec<N> r;
+#pragma unroll
+  for (int i = 0; i < N; ++i) r.f[i] = __shfl_up(v.f[i], d, WAVE);
+  return r;
+}
+
+template <int N>
+__device__ __forceinline__ Vec<N> shfl_down(const Vec<N> &v, int d) {
+  Vec<N> r;
+#pragma unroll
+  for (int i = 0; i < N; ++i) r.f[i] = __shfl_down(v.f[i], d, WAVE);
+  return r;
+}
+
+template <int N>
+__device__ __forceinline__ Vec<N> readlane(const Vec<N> &v, int l) {
+  Vec<N> r;
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+    r.f[i] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v.f[i]), l));
+  return r;
+}
+
+// strong-zero product: 0 * anything = 0, so an overflowed partial product
+// (inf) met by an exact zero does not turn into NaN.
+__device__ __forceinline__ float mulz(float a, float b) {
+  return (a == 0.0f || b == 0.0f) ? 0.0f : a * b;
+}
+
+// ---------------------------------------------------------------------------
+// forward operators.  comb(earlier, later) in index order.
+// ---------------------------------------------------------------------------
+template <int OP>
+struct Fwd;
+
+template <>
+struct Fwd<ADD> {
+  static constexpr int N = 1;
+  using T = Vec<1>;
+  __device__ static T id() { return {{0.0f}}; }
+  __device__ static T comb(const T &a, const T &b) { return {{a.f[0] + b.f[0]}}; }
+};
+
+template <>
+struct Fwd<MUL> {
+  static constexpr int N = 1;
+  using T = Vec<1>;
+  __device__ static T id() { return {{1.0f}}; }
+  __device__ static T comb(const T &a, const T &b) { return {{mulz(a.f[0], b.f[0])}}; }
+};
+
+template <>
+struct Fwd<MIN> {
+  static constexpr int N = 1;
+  using T = Vec<1>;
+  __device__ static T id() { return {{__builtin_inff()}}; }
+  // the earlier operand is kept on a tie (lowest index wins)
+  __device__ static T comb(const T &a, const T &b) { return {{b.f[0] < a.f[0] ? b.f[0] : a.f[0]}}; }
+};
+
+template <>
+struct Fwd<MAX> {
+  static constexpr int N = 1;
+  using T = Vec<1>;
+  __device__ static T id() { return {{-__builtin_inff()}}; }
+  __device__ static T comb(const T &a, const T &b) { return {{b.f[0] > a.f[0] ? b.f[0] : a.f[0]}}; }
+};
+
+// linear-function composition, element (A = multiplier, B = offset):
+// (A1,B1) then (A2,B2) = (A1*A2, A2*B1 + B2)
+template <>
+struct Fwd<LINREC> {
+  static constexpr int N = 2;
+  using T = Vec<2>;
+  __device__ static T id() { return {{1.0f, 0.0f}}; }
+  __device__ static T comb(const T &a, const T &b) {
+    return {{a.f[0] * b.f[0], __builtin_fmaf(b.f[0], a.f[1], b.f[1])}};
+  }
+};
+
+// 2x2 matrix product, row-major
+template <>
+struct Fwd<MAT2> {
+  static constexpr int N = 4;
+  using T = Vec<4>;
+  __device__ static T id() { return {{1.0f, 0.0f, 0.0f, 1.0f}}; }
+  __device__ static T comb(const T &p, const T &m) {
+    return {{__builtin_fmaf(p.f[0], m.f[0], p.f[1] * m.f[2]),
+             __builtin_fmaf(p.f[0], m.f[1], p.f[1] * m.f[3]),
+             __builtin_fmaf(p.f[2], m.f[0], p.f[3] * m.f[2]),
+             __builtin_fmaf(p.f[2], m.f[1], p.f[3] * m.f[3])}};
+  }
+};
+
+// ---------------------------------------------------------------------------
+// tile shapes.  A group is one 16-byte vector per input stream per lane:
+// EPL elements.  A tile is K groups of BLOCK lanes: element e of a tile
+// lives in group e / (BLOCK*EPL), lane (e % (BLOCK*EPL)) / EPL, slot e % EPL.
+// ---------------------------------------------------------------------------
+template <int OP>
+struct Shape {
+  static constexpr int EPL = (OP == MAT2) ? 1 : 4;
+  static constexpr int K = (OP == MAT2) ? 4 : 4;
+  static constexpr int TILE = BLOCK * EPL * K;
+};
+
+// 16-byte load of one group of one stream.  `S` floats per element.  When
+// the group is whole and the address 16-byte aligned, one dwordx4 load;
+// otherwise element-wise loads of the valid part with `fill` elsewhere.
+template <int S>
+__device__ __forceinline__ float4 load_group(const float *__restrict__ p, int64_t e, int valid,
+                                             bool vec_ok, float4 fill) {
+  if (valid >= 4 / S && (S == 4 || vec_ok)) {
+    return *reinterpret_cast<const float4 *>(p + e * S);
+  }
+  float r[4] = {fill.x, fill.y, fill.z, fill.w};
+  if (S == 4) {
+    if (valid > 0) {
+      float4 t = *reinterpret_cast<const float4 *>(p + e * 4);
+      r[0] = t.x; r[1] = t.y; r[2] = t.z; r[3] = t.w;
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (j < valid) r[j] = p[e + j];
+  }
+  return make_float4(r[0], r[1], r[2], r[3]);
+}
+
+template <int S>
+__device__ __forceinline__ void store_group(float *__restrict__ p, int64_t e, int valid,
+                                            bool vec_ok, float4 v) {
+  if (valid >= 4 / S && (S == 4 || vec_ok)) {
+    __builtin_nontemporal_store(v.x, p + e * S + 0);
+    __builtin_nontemporal_store(v.y, p + e * S + 1);
+    __builtin_nontemporal_store(v.z, p + e * S + 2);
+    __builtin_nontemporal_store(v.w, p + e * S + 3);
+    return;
+  }
+  float r[4] = {v.x, v.y, v.z, v.w};
+  if (S == 4) {
+    if (valid > 0) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) p[e * 4 + j] = r[j];
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (j < valid) p[e + j] = r[j];
+  }
+}
+
+__device__ __forceinline__ float f4get(const float4 &v, int j) {
+  return j == 0 ? v.x : (j == 1 ? v.y : (j == 2 ? v.z : v.w));
+}
+
+__device__ __forceinline__ void f4set(float4 &v, int j, float x) {
+  if (j == 0) v.x = x;
+  else if (j == 1) v.y = x;
+  else if (j == 2) v.z = x;
+  else v.w = x;
+}
+
+// ---------------------------------------------------------------------------
+// input / output streams per operator
+// ---------------------------------------------------------------------------
+template <int OP>
+struct IO;
+
+template <int OP>
+struct IOScalar {
+  static constexpr int NIN = 1, S = 1;
+  using FT = typename Fwd<OP>::T;
+  __device__ static float4 fill(int) {
+    const float e = Fwd<OP>::id().f[0];
+    return make_float4(e, e, e, e);
+  }
+  __device__ static FT elem(const float4 (&in)[NIN], int j) { return {{f4get(in[0], j)}}; }
+};
+template <>
+struct IO<ADD> : IOScalar<ADD> {};
+template <>
+struct IO<MUL> : IOScalar<MUL> {};
+template <>
+struct IO<MIN> : IOScalar<MIN> {};
+template <>
+struct IO<MAX> : IOScalar<MAX> {};
+
+template <>
+struct IO<LINREC> {
+  static constexpr int NIN = 2, S = 1;
+  using FT = Fwd<LINREC>::T;
+  __device__ static float4 fill(int s) {
+    return s == 0 ? make_float4(1, 1, 1, 1) : make_float4(0, 0, 0, 0);
+  }
+  __device__ static FT elem(const float4 (&in)[NIN], int j) {
+    return {{f4get(in[0], j), f4get(in[1], j)}};
+  }
+};
+
+template <>
+struct IO<MAT2> {
+  static constexpr int NIN = 1, S = 4;
+  using FT = Fwd<MAT2>::T;
+  __device__ static float4 fill(int) { return make_float4(1, 0, 0, 1); }
+  __device__ static FT elem(const float4 (&in)[NIN], int) {
+    return {{in[0].x, in[0].y, in[0].z, in[0].w}};
+  }
+};
+
+struct TileInfo {
+  int64_t tile;   // global tile index
+  int64_t row;
+  int lt;         // tile index within the row
+  int64_t base;   // global index of the tile's first element
+  int valid;      // elements of the tile inside the row
+  bool vec_ok;    // 16-byte aligned scalar streams
+};
+
+__device__ __forceinline__ TileInfo tile_info(int64_t tile, int64_t n, int tpr, int TILE) {
+  TileInfo t;
+  t.tile = tile;
+  t.row = tile / tpr;
+  t.lt = (int)(tile - t.row * tpr);
+  const int64_t ts = (int64_t)t.lt * TILE;
+  t.base = t.row * n + ts;
+  const int64_t rem = n - ts;
+  t.valid = (int)(rem < TILE ? rem : TILE);
+  t.vec_ok = (t.base & 3) == 0;
+  return t;
+}
+
+// ---------------------------------------------------------------------------
+// wave64 inclusive scans.  Tr::comb(earlier, later).
+//   forward: lower lanes are earlier;  reverse: higher lanes are earlier.
+// ---------------------------------------------------------------------------
+template <class Tr>
+__device__ __forceinline__ typename Tr::T wave_scan_fwd(typename Tr::T x) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int d = 1; d < WAVE; d <<= 1) {
+    typename Tr::T o = shfl_up(x, d);
+    if (lane >= d) x = Tr::comb(o, x);
+  }
+  return x;
+}
+
+template <class Tr>
+__device__ __forceinline__ typename Tr::T wave_scan_rev(typename Tr::T x) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int d = 1; d < WAVE; d <<= 1) {
+    typename Tr::T o = shfl_down(x, d);
+    if (lane + d < WAVE) x = Tr::comb(o, x);
+  }
+  return x;
+}
+
+// ordered reduction where lane L+1 is EARLIER than lane L; the full result
+// (lane 63 earliest ... lane 0 latest) lands in lane 0.
+template <class Tr>
+__device__ __forceinline__ typename Tr::T wave_reduce_desc(typename Tr::T x) {
+#pragma unroll
+  for (int d = 1; d < WAVE; d <<= 1) {
+    typename Tr::T o = shfl_down(x, d);
+    x = Tr::comb(o, x);
+  }
+  return x;
+}
+
+// ---------------------------------------------------------------------------
+// Look-back status words.  Every 32-bit component of a published value is
+// stored in its own 64-bit word {tag:32 | bits:32}; a word is valid for the
+// current launch iff its tag equals the launch tag, so no reset pass, fence
+// or flag/value ordering is needed: a reader spins until every word it needs
+// carries the tag.  Aggregates and inclusive prefixes use separate words.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void put_word(uint64_t *w, uint32_t tag, float v) {
+  uint64_t u = ((uint64_t)tag << 32) | (uint64_t)__float_as_uint(v);
+  __hip_atomic_store(w, u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int N>
+__device__ __forceinline__ void publish(uint64_t *w, uint32_t tag, const Vec<N> &v) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) put_word(w + i, tag, v.f[i]);
+}
+
+template <int N>
+__device__ __forceinline__ bool read_words(const uint64_t *w, uint32_t tag, Vec<N> &v) {
+  bool ok = true;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    uint64_t u = __hip_atomic_load(const_cast<uint64_t *>(w + i), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+    ok = ok && ((uint32_t)(u >> 32) == tag);
+    v.f[i] = __uint_as_float((uint32_t)u);
+  }
+  return ok;
+}
+
+// Per-launch control block at the start of every workspace:
+//   [0] next tile id, [1] finished blocks, [2] launch epoch.
+// Counters are reset by the last block of each launch, which also advances
+// the epoch, so the next launch on the same workspace starts clean.
+//   [3] error flag: 1 = tile id outside the grid (workspace not zeroed or
+//       shared by overlapping launches), 2 = a look-back wait timed out.
+struct Ctl {
+  unsigned next, done, epoch, err;
+};
+
+constexpr int kSpinLimit = 1 << 20;
+
+__device__ __forceinline__ void ctl_error(Ctl *ctl, unsigned code) {
+  __hip_atomic_store(&ctl->err, code, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ bool ctl_failed(Ctl *ctl) {
+  return __hip_atomic_load(&ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+}
+
+__device__ __forceinline__ unsigned ctl_load(unsigned *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void ctl_finish(Ctl *ctl, unsigned nblocks, uint32_t tag) {
+  unsigned d = __hip_atomic_fetch_add(&ctl->done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (d == nblocks - 1) {
+    __hip_atomic_store(&ctl->next, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&ctl->done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&ctl->epoch, tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// Decoupled look-back, run by one whole wave.  The tile's predecessors in
+// scan order sit at distances 1..dist_max; the predecessor at distance d has
+// status index `tile - dir*d`.  Status block of tile t: NA aggregate words
+// then NP prefix words at st + t*(NA+NP).  Returns (in every lane) the
+// combination of all predecessors, earliest first, built from the nearest
+// published inclusive prefix and the aggregates after it.
+// Every wait is bounded: after kSpinLimit polls, or as soon as any block has
+// flagged an error, the wave stops waiting (the result is then garbage and
+// the error flag tells the host).
+template <class Tr>
+__device__ typename Tr::T lookback(const uint64_t *st, int64_t tile, int dir, int dist_max,
+                                   uint32_t tag, Ctl *ctl) {
+  using T = typename Tr::T;
+  using P = typename Tr::P;
+  constexpr int NA = Tr::NA, NP = Tr::NP, NW = NA + NP;
+  const int lane = lane_id();
+  T acc = Tr::id();
+  bool have = false;
+  for (int base = 0; base < dist_max; base += WAVE) {
+    const int dist = base + lane + 1;
+    const bool inr = dist <= dist_max;
+    const uint64_t *w = st + (tile - (int64_t)dir * dist) * NW;
+    T agg = Tr::id();
+    P pre;
+    int state = inr ? 0 : 3;  // 3: out of range, 2: prefix, 1: aggregate, 0: not yet
+    int p;
+    for (int spin = 0;; ++spin) {
+      if (inr && state < 2) {
+        if (read_words<NP>(w + NA, tag, pre)) state = 2;
+        else if (read_words<NA>(w, tag, agg)) state = 1;
+        else state = 0;
+      }
+      const uint64_t pm = __ballot(state == 2);
+      p = pm ? (__ffsll((long long)pm) - 1) : WAVE;
+      const bool needed = lane <= p;
+      if (__ballot(needed && state == 0) == 0) break;
+      if ((spin & 255) == 255) {
+        if (spin >= kSpinLimit) {
+          ctl_error(ctl, 2u);
+          break;
+        }
+        if (ctl_failed(ctl)) break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    T v = Tr::id();
+    if (lane < p && state == 1) v = agg;
+    if (lane == p) v = Tr::from_pre(pre);
+    T win = readlane(wave_reduce_desc<Tr>(v), 0);
+    acc = have ? Tr::comb(win, acc) : win;
+    have = true;
+    if (p < WAVE) break;
+  }
+  return acc;
+}
+
+}  // namespace pcad

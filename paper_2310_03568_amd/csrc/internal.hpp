@@ -1,0 +1,42 @@
+// Declarations shared between the kernel translation units and the C-ABI
+// layer (host side only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pcad {
+
+// bytes reserved for the per-launch control block at the start of a workspace
+constexpr size_t kCtlBytes = 256;
+
+// scan
+int scan_tile_size(int op);
+int scan_elem_floats(int op);
+int scan_status_words(int op, bool abar);
+hipError_t scan_fwd_launch(int op, int64_t batch, int64_t n, const float *x0, const float *x1,
+                           float *y0, float *y1, float *saved, float *total, bool reduce,
+                           void *ws, hipStream_t s);
+hipError_t scan_vjp_launch(int op, int64_t batch, int64_t n, const float *x0, const float *x1,
+                           const float *saved, const float *yb0, const float *yb1, float *xb0,
+                           float *xb1, bool accumulate, void *ws, hipStream_t s);
+
+// reduce
+int reduce_blocks_per_row(int64_t batch, int64_t n);
+size_t reduce_ws_bytes(int op, int64_t batch, int64_t n);
+hipError_t reduce_fwd_launch(int op, int64_t batch, int64_t n, const float *x0, const float *x1,
+                             float *y, void *saved, void *ws, hipStream_t s);
+hipError_t reduce_vjp_launch(int op, int64_t batch, int64_t n, const float *x0, const float *x1,
+                             const void *saved, const float *ybar, float *xb0, float *xb1,
+                             bool accumulate, void *ws, hipStream_t s);
+
+// reduce-by-index
+size_t rbi_ws_bytes(int op, int64_t batch, int64_t n, int64_t m);
+size_t rbi_saved_bytes(int op, int64_t batch, int64_t m);
+hipError_t rbi_fwd_launch(int op, int64_t batch, int64_t n, int64_t m, const int32_t *idx,
+                          const float *v, float *hist, void *saved, void *ws, hipStream_t s);
+hipError_t rbi_vjp_launch(int op, int64_t batch, int64_t n, int64_t m, const int32_t *idx,
+                          const float *v, const void *saved, const float *hbar, float *vbar,
+                          bool accumulate, hipStream_t s);
+
+}  // namespace pcad

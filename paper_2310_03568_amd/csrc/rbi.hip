@@ -1,0 +1,384 @@
+// reduce_by_index (Section 4) for + * min max, and its adjoint (Section 4.2).
+//
+// Forward, three launches: neutral initialisation of the bins, the update
+// pass, and (min/max, *) a per-bin finalisation.
+//   update pass, small m: every block owns a contiguous chunk of one row and
+//     a private sub-histogram in LDS (the paper's multi-histogram idea,
+//     Section 4.2 Discussing Performance), merged into the global bins with
+//     one atomic per touched bin;
+//   update pass, large m: global atomics per element.
+// Lifted operators:
+//   min/max -- a packed 64-bit key {ord(v):32 | index:32} (index complemented
+//     for max) updated with 64-bit atomic min/max, so "smallest value, then
+//     smallest index" is a single native atomic instead of the mutex the
+//     paper's lifted (index, value) operator needs; the value is re-read from
+//     v at the winning index, so its bit pattern is kept;
+//   *       -- (zero count, product of non-zeros): an atomic add on the count
+//     and a compare-and-swap product.
+// Adjoint: one elementwise pass -- gather (+), three zero cases (*),
+// one-hot against the saved argk (min/max).
+#include "device.hpp"
+#include "internal.hpp"
+
+namespace pcad {
+
+// LDS sub-histogram limits (bins per block)
+constexpr int kLdsBinsF32 = 8192;   // + and *: 32 KB of values (+ 32 KB counts for *)
+constexpr int kLdsBinsU64 = 4096;   // min/max: 32 KB of keys
+
+// order-preserving map float -> uint32 (-0.0 folded onto +0.0)
+__device__ __forceinline__ uint32_t ord_f32(float v) {
+  uint32_t b = __float_as_uint(v == 0.0f ? 0.0f : v);
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+
+template <int OP>
+__device__ __forceinline__ uint64_t key_of(float v, uint32_t i) {
+  return OP == MIN ? (((uint64_t)ord_f32(v) << 32) | i)
+                   : (((uint64_t)ord_f32(v) << 32) | (uint32_t)(~i));
+}
+
+template <int OP>
+constexpr uint64_t key_init() {
+  return OP == MIN ? ~0ull : 0ull;
+}
+
+// CAS-loop product on global or LDS memory
+__device__ __forceinline__ void atomic_mul_f32(float *p, float v) {
+  unsigned *u = reinterpret_cast<unsigned *>(p);
+  unsigned old = __hip_atomic_load(u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (;;) {
+    const unsigned nw = __float_as_uint(__uint_as_float(old) * v);
+    if (__hip_atomic_compare_exchange_strong(u, &old, nw, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT))
+      return;
+  }
+}
+
+__device__ __forceinline__ void lds_mul_f32(float *p, float v) {
+  unsigned *u = reinterpret_cast<unsigned *>(p);
+  unsigned old = __hip_atomic_load(u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  for (;;) {
+    const unsigned nw = __float_as_uint(__uint_as_float(old) * v);
+    if (__hip_atomic_compare_exchange_strong(u, &old, nw, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_WORKGROUP))
+      return;
+  }
+}
+
+struct RbiArgs {
+  const int32_t *idx;
+  const float *v;
+  float *hist;        // ADD: bins; MUL: finalised values
+  uint32_t *n0;       // MUL: zero counts (saved)
+  float *ypos;        // MUL: product of non-zeros (saved)
+  uint64_t *keys;     // MIN/MAX: packed keys (workspace)
+  int32_t *argk;      // MIN/MAX: saved
+  int64_t n, m;
+  int64_t chunk;      // elements per block (multiple of 4)
+  int bpr;
+};
+
+// neutral initialisation of the bins
+template <int OP>
+__global__ __launch_bounds__(BLOCK) void k_rbi_init(RbiArgs a, int64_t total) {
+  for (int64_t k = (int64_t)blockIdx.x * BLOCK + threadIdx.x; k < total;
+       k += (int64_t)gridDim.x * BLOCK) {
+    if (OP == ADD) a.hist[k] = 0.0f;
+    if (OP == MUL) { a.n0[k] = 0u; a.ypos[k] = 1.0f; }
+    if (OP == MIN || OP == MAX) a.keys[k] = key_init<OP>();
+  }
+}
+
+// visit the (key, value, index) triples of this block's chunk
+template <class F>
+__device__ __forceinline__ void for_chunk(const RbiArgs &a, int64_t row, F &&f) {
+  const int64_t lo = (int64_t)blockIdx.x * a.chunk;
+  const int64_t hi = lo + a.chunk < a.n ? lo + a.chunk : a.n;
+  const int32_t *ir = a.idx + row * a.n;
+  const float *vr = a.v + row * a.n;
+  const bool vec_ok = ((row * a.n) & 3) == 0;
+  for (int64_t i = lo + (int64_t)threadIdx.x * 4; i < hi; i += (int64_t)BLOCK * 4) {
+    if (vec_ok && i + 4 <= hi) {
+      const int4 k4 = *reinterpret_cast<const int4 *>(ir + i);
+      const float4 v4 = *reinterpret_cast<const float4 *>(vr + i);
+      f(k4.x, v4.x, (uint32_t)i);
+      f(k4.y, v4.y, (uint32_t)(i + 1));
+      f(k4.z, v4.z, (uint32_t)(i + 2));
+      f(k4.w, v4.w, (uint32_t)(i + 3));
+    } else {
+      for (int j = 0; j < 4; ++j)
+        if (i + j < hi) f(ir[i + j], vr[i + j], (uint32_t)(i + j));
+    }
+  }
+}
+
+// update pass with an LDS sub-histogram per block
+template <int OP>
+__global__ __launch_bounds__(BLOCK) void k_rbi_lds(RbiArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int64_t row = blockIdx.y;
+  const int m = (int)a.m;
+  float *sf = reinterpret_cast<float *>(smem);
+  unsigned *sc = reinterpret_cast<unsigned *>(smem + (size_t)m * 4);
+  unsigned long long *sk = reinterpret_cast<unsigned long long *>(smem);
+  for (int k = threadIdx.x; k < m; k += BLOCK) {
+    if (OP == ADD) sf[k] = 0.0f;
+    if (OP == MUL) { sf[k] = 1.0f; sc[k] = 0u; }
+    if (OP == MIN || OP == MAX) sk[k] = key_init<OP>();
+  }
+  __syncthreads();
+  for_chunk(a, row, [&](int32_t k, float v, uint32_t i) {
+    if (k < 0 || k >= m) return;
+    if (OP == ADD) atomicAdd(&sf[k], v);
+    if (OP == MUL) {
+      if (v == 0.0f) atomicAdd(&sc[k], 1u);
+      else lds_mul_f32(&sf[k], v);
+    }
+    if (OP == MIN) atomicMin(&sk[k], (unsigned long long)key_of<MIN>(v, i));
+    if (OP == MAX) atomicMax(&sk[k], (unsigned long long)key_of<MAX>(v, i));
+  });
+  __syncthreads();
+  const int64_t gb = row * a.m;
+  for (int k = threadIdx.x; k < m; k += BLOCK) {
+    if (OP == ADD) {
+      const float s = sf[k];
+      if (s != 0.0f) unsafeAtomicAdd(&a.hist[gb + k], s);
+    }
+    if (OP == MUL) {
+      if (sc[k]) atomicAdd(&a.n0[gb + k], sc[k]);
+      if (sf[k] != 1.0f) atomic_mul_f32(&a.ypos[gb + k], sf[k]);
+    }
+    if (OP == MIN) {
+      const unsigned long long key = sk[k];
+      if (key != key_init<MIN>()) atomicMin(reinterpret_cast<unsigned long long *>(&a.keys[gb + k]), key);
+    }
+    if (OP == MAX) {
+      const unsigned long long key = sk[k];
+      if (key != key_init<MAX>()) atomicMax(reinterpret_cast<unsigned long long *>(&a.keys[gb + k]), key);
+    }
+  }
+}
+
+// update pass with global atomics
+template <int OP>
+__global__ __launch_bounds__(BLOCK) void k_rbi_global(RbiArgs a) {
+  const int64_t row = blockIdx.y;
+  const int64_t gb = row * a.m;
+  const int64_t m = a.m;
+  for_chunk(a, row, [&](int32_t k, float v, uint32_t i) {
+    if (k < 0 || k >= m) return;
+    if (OP == ADD) unsafeAtomicAdd(&a.hist[gb + k], v);
+    if (OP == MUL) {
+      if (v == 0.0f) atomicAdd(&a.n0[gb + k], 1u);
+      else atomic_mul_f32(&a.ypos[gb + k], v);
+    }
+    if (OP == MIN)
+      atomicMin(reinterpret_cast<unsigned long long *>(&a.keys[gb + k]),
+                (unsigned long long)key_of<MIN>(v, i));
+    if (OP == MAX)
+      atomicMax(reinterpret_cast<unsigned long long *>(&a.keys[gb + k]),
+                (unsigned long long)key_of<MAX>(v, i));
+  });
+}
+
+// per-bin finalisation: value and argk (min/max), value (mul)
+template <int OP>
+__global__ __launch_bounds__(BLOCK) void k_rbi_fin(RbiArgs a, int64_t total) {
+  for (int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * BLOCK) {
+    if (OP == MUL) {
+      a.hist[t] = a.n0[t] > 0 ? 0.0f : a.ypos[t];
+    } else {
+      const uint64_t key = a.keys[t];
+      const int64_t row = t / a.m;
+      if (key == key_init<OP>()) {
+        a.argk[t] = (int32_t)a.n;
+        a.hist[t] = OP == MIN ? __builtin_inff() : -__builtin_inff();
+      } else {
+        const uint32_t lo = (uint32_t)key;
+        const uint32_t i = OP == MIN ? lo : ~lo;
+        a.argk[t] = (int32_t)i;
+        a.hist[t] = a.v[row * a.n + i];
+      }
+    }
+  }
+}
+
+// adjoint: one elementwise pass per row
+struct RbiVjpArgs {
+  const int32_t *idx;
+  const float *v;
+  const float *hbar;
+  const uint32_t *n0;
+  const float *ypos;
+  const int32_t *argk;
+  float *vbar;
+  int64_t n, m;
+  int accumulate;
+};
+
+template <int OP>
+__global__ __launch_bounds__(BLOCK) void k_rbi_vjp(RbiVjpArgs a) {
+  const int64_t row = blockIdx.y;
+  const int32_t *ir = a.idx + row * a.n;
+  const float *vr = a.v + row * a.n;
+  float *ob = a.vbar + row * a.n;
+  const int64_t gb = row * a.m;
+  const bool vec_ok = ((row * a.n) & 3) == 0;
+  const int64_t stride = (int64_t)gridDim.x * BLOCK * 4;
+  for (int64_t i = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) * 4; i < a.n; i += stride) {
+    const bool full = vec_ok && i + 4 <= a.n;
+    int kk[4];
+    float vv[4] = {1.0f, 1.0f, 1.0f, 1.0f}, o[4];
+    if (full) {
+      const int4 k4 = *reinterpret_cast<const int4 *>(ir + i);
+      kk[0] = k4.x; kk[1] = k4.y; kk[2] = k4.z; kk[3] = k4.w;
+      if (OP == MUL) {
+        const float4 v4 = *reinterpret_cast<const float4 *>(vr + i);
+        vv[0] = v4.x; vv[1] = v4.y; vv[2] = v4.z; vv[3] = v4.w;
+      }
+    } else {
+      for (int j = 0; j < 4; ++j) {
+        kk[j] = (i + j < a.n) ? ir[i + j] : -1;
+        if (OP == MUL && i + j < a.n) vv[j] = vr[i + j];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int k = kk[j];
+      float r = 0.0f;
+      if (k >= 0 && k < a.m) {
+        const float h = a.hbar[gb + k];
+        if (OP == ADD) r = h;
+        if (OP == MUL) {
+          const uint32_t z = a.n0[gb + k];
+          const float p = a.ypos[gb + k];
+          r = z == 0 ? (p / vv[j]) * h : ((z == 1 && vv[j] == 0.0f) ? p * h : 0.0f);
+        }
+        if (OP == MIN || OP == MAX) r = (a.argk[gb + k] == (int32_t)(i + j)) ? h : 0.0f;
+      }
+      o[j] = r;
+    }
+    if (a.accumulate) {
+      for (int j = 0; j < 4; ++j)
+        if (i + j < a.n) o[j] += ob[i + j];
+    }
+    if (full) {
+      *reinterpret_cast<float4 *>(ob + i) = make_float4(o[0], o[1], o[2], o[3]);
+    } else {
+      for (int j = 0; j < 4; ++j)
+        if (i + j < a.n) ob[i + j] = o[j];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+static bool use_lds(int op, int64_t m) {
+  if (op == MIN || op == MAX) return m <= kLdsBinsU64;
+  return m <= kLdsBinsF32;
+}
+
+static size_t lds_bytes(int op, int64_t m) {
+  if (op == MIN || op == MAX) return (size_t)m * 8;
+  if (op == MUL) return (size_t)m * 8;
+  return (size_t)m * 4;
+}
+
+size_t rbi_saved_bytes(int op, int64_t batch, int64_t m) {
+  if (op == MUL) return (size_t)batch * m * 8;
+  if (op == MIN || op == MAX) return (size_t)batch * m * 4;
+  return 0;
+}
+
+size_t rbi_ws_bytes(int op, int64_t batch, int64_t n, int64_t m) {
+  (void)n;
+  if (op == MIN || op == MAX) return kCtlBytes + (size_t)batch * m * 8;
+  return kCtlBytes;
+}
+
+static int64_t grid1d(int64_t total) {
+  int64_t g = (total + BLOCK - 1) / BLOCK;
+  if (g > 16384) g = 16384;
+  if (g < 1) g = 1;
+  return g;
+}
+
+hipError_t rbi_fwd_launch(int op, int64_t batch, int64_t n, int64_t m, const int32_t *idx,
+                          const float *v, float *hist, void *saved, void *ws, hipStream_t s) {
+  if (batch == 0 || m == 0) return hipSuccess;
+  RbiArgs a;
+  a.idx = idx; a.v = v; a.hist = hist; a.n = n; a.m = m;
+  a.n0 = nullptr; a.ypos = nullptr; a.keys = nullptr; a.argk = nullptr;
+  const int64_t total = batch * m;
+  if (op == MUL) {
+    a.n0 = static_cast<uint32_t *>(saved);
+    a.ypos = reinterpret_cast<float *>(static_cast<uint32_t *>(saved) + total);
+  }
+  if (op == MIN || op == MAX) {
+    a.keys = reinterpret_cast<uint64_t *>(static_cast<char *>(ws) + kCtlBytes);
+    a.argk = static_cast<int32_t *>(saved);
+  }
+  const bool lds = use_lds(op, m);
+  // blocks per row: enough to fill the chip, few enough that the LDS
+  // sub-histogram of each block sees many elements
+  int64_t bpr = (n + 16383) / 16384;
+  int64_t cap = (lds ? 2048 : 65535) / (batch > 0 ? batch : 1);
+  if (cap < 1) cap = 1;
+  if (bpr > cap) bpr = cap;
+  if (bpr < 1) bpr = 1;
+  a.bpr = (int)bpr;
+  a.chunk = ((n + bpr - 1) / bpr + 3) / 4 * 4;
+  const dim3 gi((unsigned)grid1d(total));
+  const dim3 gu((unsigned)bpr, (unsigned)batch);
+  const size_t shm = lds_bytes(op, m);
+#define PCAD_RBI(OPV)                                                               \
+  case OPV:                                                                         \
+    hipLaunchKernelGGL(k_rbi_init<OPV>, gi, dim3(BLOCK), 0, s, a, total);           \
+    if (n > 0) {                                                                    \
+      if (lds) hipLaunchKernelGGL(k_rbi_lds<OPV>, gu, dim3(BLOCK), shm, s, a);      \
+      else hipLaunchKernelGGL(k_rbi_global<OPV>, gu, dim3(BLOCK), 0, s, a);         \
+    }                                                                               \
+    if (OPV != ADD) hipLaunchKernelGGL(k_rbi_fin<OPV>, gi, dim3(BLOCK), 0, s, a, total); \
+    break;
+  switch (op) {
+    PCAD_RBI(ADD)
+    PCAD_RBI(MUL)
+    PCAD_RBI(MIN)
+    PCAD_RBI(MAX)
+  default: return hipErrorInvalidValue;
+  }
+#undef PCAD_RBI
+  return hipGetLastError();
+}
+
+hipError_t rbi_vjp_launch(int op, int64_t batch, int64_t n, int64_t m, const int32_t *idx,
+                          const float *v, const void *saved, const float *hbar, float *vbar,
+                          bool accumulate, hipStream_t s) {
+  if (batch == 0 || n == 0) return hipSuccess;
+  RbiVjpArgs a;
+  a.idx = idx; a.v = v; a.hbar = hbar; a.vbar = vbar; a.n = n; a.m = m;
+  a.accumulate = accumulate ? 1 : 0;
+  a.n0 = nullptr; a.ypos = nullptr; a.argk = nullptr;
+  const int64_t total = batch * m;
+  if (op == MUL) {
+    a.n0 = static_cast<const uint32_t *>(saved);
+    a.ypos = reinterpret_cast<const float *>(static_cast<const uint32_t *>(saved) + total);
+  }
+  if (op == MIN || op == MAX) a.argk = static_cast<const int32_t *>(saved);
+  int64_t bx = (n + BLOCK * 4 * 4 - 1) / (BLOCK * 4 * 4);
+  if (bx > 65535) bx = 65535;
+  const dim3 grid((unsigned)bx, (unsigned)batch);
+  switch (op) {
+  case ADD: hipLaunchKernelGGL(k_rbi_vjp<ADD>, grid, dim3(BLOCK), 0, s, a); break;
+  case MUL: hipLaunchKernelGGL(k_rbi_vjp<MUL>, grid, dim3(BLOCK), 0, s, a); break;
+  case MIN: hipLaunchKernelGGL(k_rbi_vjp<MIN>, grid, dim3(BLOCK), 0, s, a); break;
+  case MAX: hipLaunchKernelGGL(k_rbi_vjp<MAX>, grid, dim3(BLOCK), 0, s, a); break;
+  default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace pcad

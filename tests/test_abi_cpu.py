@@ -1,0 +1,101 @@
+"""The C-ABI library on the CPU: it builds, loads, exports every symbol that
+include/pcad.h declares, and its host-side validation returns the documented
+status codes before touching the GPU (no compute call is made here)."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pcad.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    import paper_2310_03568_amd as pcad
+    if not os.path.exists(pcad.LIB_PATH):
+        from paper_2310_03568_amd import build
+        build.build()
+    return pcad.lib()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pcad_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(L):
+    names = declared_functions()
+    assert len(names) >= 10
+    for name in names:
+        assert hasattr(L, name), name
+
+
+def test_status_strings(L):
+    assert L.pcad_status_string(0) == b"ok"
+    assert L.pcad_status_string(6) == b"workspace too small"
+    assert L.pcad_status_string(99) == b"unknown status"
+    assert L.pcad_version().startswith(b"pcad")
+    assert L.pcad_last_hip_error() == 0
+
+
+def q(L, comb, op, batch, n, m=0, flags=0):
+    s = ctypes.c_size_t(0)
+    w = ctypes.c_size_t(0)
+    st = L.pcad_query(comb, op, batch, n, m, flags, ctypes.byref(s), ctypes.byref(w))
+    return st, s.value, w.value
+
+
+def test_query(L):
+    # scan of + over 10000 elements: 3 tiles of 4096, one float saved per tile
+    st, s, w = q(L, 1, 0, 1, 10000)
+    assert st == 0 and s == 3 * 4 and w >= 256 + 3 * 2 * 8
+    # linrec: 2 floats per tile; status words for the adjoint with A_bar (5)
+    st, s, w = q(L, 1, 4, 2, 4096)
+    assert st == 0 and s == 2 * 2 * 4 and w >= 256 + 2 * 5 * 8
+    # reduce *: (n0, y_pos) per row
+    assert q(L, 0, 1, 5, 100)[:2] == (0, 40)
+    # reduce min: k per row
+    assert q(L, 0, 2, 5, 100)[:2] == (0, 20)
+    # rbi min: argk per bin, 64-bit keys in the workspace
+    st, s, w = q(L, 2, 2, 2, 1000, 300)
+    assert st == 0 and s == 2 * 300 * 4 and w >= 2 * 300 * 8
+    # rbi mul: counts and products
+    assert q(L, 2, 1, 1, 10, 7)[1] == 7 * 8
+    # rbi with a generic operator is not provided
+    assert q(L, 2, 5, 1, 10, 7)[0] == 2
+
+
+def test_validation(L):
+    P = ctypes.c_void_p
+    good = P(1 << 20)        # aligned, never dereferenced: validation fails first
+    mis = P((1 << 20) + 4)
+    # bad operator / combinator / flags / sizes
+    assert q(L, 1, 9, 1, 10)[0] == 1
+    assert q(L, 7, 0, 1, 10)[0] == 1
+    assert q(L, 1, 0, 1, 10, flags=1 << 7)[0] == 1
+    assert q(L, 1, 0, -1, 10)[0] == 1
+    assert q(L, 1, 0, 1, 1 << 31)[0] == 5
+    assert q(L, 2, 0, 1, 10, -1)[0] == 1
+    assert q(L, 2, 0, 1, 10, (1 << 26) + 1)[0] == 5
+    # null / misaligned pointers, small workspace
+    assert L.pcad_scan_fwd(0, 1, 10, None, None, good, None, good, 0, good, 1 << 20, None) == 3
+    assert L.pcad_scan_fwd(0, 1, 10, mis, None, good, None, good, 0, good, 1 << 20, None) == 4
+    assert L.pcad_scan_fwd(0, 1, 10, good, None, good, None, good, 0, good, 8, None) == 6
+    assert L.pcad_scan_fwd(0, 1, 10, good, None, good, None, None, 0, good, 1 << 20, None) == 3
+    assert L.pcad_scan_fwd(4, 1, 10, good, None, good, None, good, 0, good, 1 << 20, None) == 3
+    assert L.pcad_scan_fwd(0, 1, 10, good, None, good, good, good, 0, good, 1 << 20, None) == 1
+    assert L.pcad_scan_vjp(0, 1, 10, good, None, good, None, None, good, None, 0, good, 1 << 20, None) == 3
+    assert L.pcad_reduce_fwd(1, 1, 10, good, None, good, None, 0, good, 1 << 20, None) == 3
+    assert L.pcad_rbi_fwd(5, 1, 10, 4, good, good, good, good, 0, good, 1 << 20, None) == 2
+    assert L.pcad_rbi_fwd(0, 1, 10, -4, good, good, good, good, 0, good, 1 << 20, None) == 1
+    assert L.pcad_rbi_vjp(2, 1, 10, 4, good, good, None, good, good, 0, None, 0, None) == 3
+    # degenerate sizes are valid no-ops that need no pointers
+    assert L.pcad_scan_fwd(0, 1, 0, None, None, None, None, None, 0, None, 0, None) == 0
+    assert L.pcad_scan_vjp(3, 0, 10, None, None, None, None, None, None, None, 0, None, 0, None) == 0
+    assert L.pcad_rbi_fwd(0, 1, 10, 0, None, None, None, None, 0, None, 0, None) == 0
+    assert L.pcad_reduce_vjp(2, 1, 0, None, None, None, None, None, None, 0, None, 0, None) == 0
