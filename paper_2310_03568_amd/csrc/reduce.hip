@@ -88,6 +88,20 @@ __device__ __forceinline__ bool get_lv(const uint64_t *w, uint32_t tag, LV &v) {
   return (uint32_t)(a >> 32) == tag && (uint32_t)(b >> 32) == tag;
 }
 
+// Arrival counter valid for one launch: a word whose tag is not this
+// launch's counts as zero, so the counters never need a reset pass and may
+// sit on memory that other calls used.  Returns the count before arrival.
+__device__ __forceinline__ unsigned tagged_arrive(uint64_t *w, uint32_t tag) {
+  uint64_t old = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (;;) {
+    const uint32_t cnt = ((uint32_t)(old >> 32) == tag) ? (uint32_t)old : 0u;
+    const uint64_t nw = ((uint64_t)tag << 32) | (uint64_t)(cnt + 1u);
+    if (__hip_atomic_compare_exchange_strong(w, &old, nw, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT))
+      return cnt;
+  }
+}
+
 // block-wide reduction of a commutative lifted value; result valid in thread 0
 template <int OP>
 __device__ LV block_reduce_lv(LV v, LV *s_w) {
@@ -111,7 +125,7 @@ struct RedArgs {
   int64_t n;
   int64_t chunk;      // elements per block (multiple of 4)
   int bpr;            // blocks per row
-  unsigned *rowcnt;   // [batch] arrival counters, self-resetting
+  uint64_t *rowcnt;   // [batch] arrival counters {tag:32 | count:32}
   uint64_t *parts;    // [batch][bpr][2] tagged words
   Ctl *ctl;
 };
@@ -146,10 +160,8 @@ __global__ __launch_bounds__(BLOCK) void k_reduce_fwd(RedArgs a) {
   acc = block_reduce_lv<OP>(acc, s_w);
   if (tid == 0) {
     put_lv(a.parts + (row * a.bpr + b) * 2, tag, acc);
-    const unsigned c = __hip_atomic_fetch_add(&a.rowcnt[row], 1u, __ATOMIC_RELAXED,
-                                              __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned c = tagged_arrive(&a.rowcnt[row], tag);
     s_last = (c == (unsigned)a.bpr - 1);
-    if (s_last) __hip_atomic_store(&a.rowcnt[row], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   __syncthreads();
   if (s_last) {
@@ -499,7 +511,7 @@ size_t reduce_ws_bytes(int op, int64_t batch, int64_t n) {
     return kCtlBytes + (size_t)tiles * 2 * scan_elem_floats(op) * sizeof(uint64_t);
   }
   const int bpr = reduce_blocks_per_row(batch, n);
-  const size_t cnt = ((size_t)batch * sizeof(unsigned) + 255) / 256 * 256;
+  const size_t cnt = ((size_t)batch * sizeof(uint64_t) + 255) / 256 * 256;
   return kCtlBytes + cnt + (size_t)batch * bpr * 2 * sizeof(uint64_t);
 }
 
@@ -520,8 +532,8 @@ hipError_t reduce_fwd_launch(int op, int64_t batch, int64_t n, const float *x0, 
   a.chunk = ((n + a.bpr - 1) / a.bpr + 3) / 4 * 4;
   a.ctl = reinterpret_cast<Ctl *>(ws);
   char *p = static_cast<char *>(ws) + kCtlBytes;
-  a.rowcnt = reinterpret_cast<unsigned *>(p);
-  a.parts = reinterpret_cast<uint64_t *>(p + ((size_t)batch * sizeof(unsigned) + 255) / 256 * 256);
+  a.rowcnt = reinterpret_cast<uint64_t *>(p);
+  a.parts = reinterpret_cast<uint64_t *>(p + ((size_t)batch * sizeof(uint64_t) + 255) / 256 * 256);
   const dim3 grid((unsigned)a.bpr, (unsigned)batch);
   switch (op) {
   case ADD: hipLaunchKernelGGL(k_reduce_fwd<ADD>, grid, dim3(BLOCK), 0, s, a); break;
