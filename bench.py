@@ -1,0 +1,215 @@
+"""Benchmark: forward + reverse-mode adjoint on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+
+A step is one pass of the hot path over one batch of synthetic input that is
+already resident in HBM: the forward and the adjoint.  Prints one JSON line.
+
+Workloads:
+  linrec  -- linear-recurrence scan y_i = a_i y_{i-1} + b_i, n = 2^26, fp32,
+             forward + adjoint w.r.t. a and b.
+  mat2    -- 2x2 matrix-product scan, n = 2^24, entries ~ N(0, 0.5).
+
+`value` is backward elements/s: n / (mean duration of the adjoint kernel,
+HIP events on the stream the kernel runs on).  `roofline` prices that kernel
+against the 8 TB/s HBM peak with the algorithmic bytes of the adjoint.
+`cpu_baseline` is the CPU FP64 oracle timed on the host (1 thread) on the
+same inputs; its outputs also gate the GPU results (`parity`).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "backward elems/s + % HBM peak, batched vs per-segment, at 1e-5 rel err"
+
+
+def _traffic(kernel: str, workload: str):
+    """HBM bytes per launch measured with rocprofv3 FETCH_SIZE/WRITE_SIZE,
+    scaled by a plain copy kernel; None when the kernel sources changed
+    since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.txt")
+    if not os.path.exists(path):
+        return None
+    import hashlib
+    src = os.path.join(ROOT, "paper_2310_03568_amd", "csrc")
+    h = hashlib.sha1()
+    for f in sorted(os.listdir(src)):
+        h.update(open(os.path.join(src, f), "rb").read())
+    digest = h.hexdigest()[:12]
+    for line in open(path):
+        parts = line.split()
+        if len(parts) >= 4 and parts[0] == kernel and parts[1] == workload and parts[2] == digest:
+            return float(parts[3])
+    return None
+
+
+def bench_linrec(args, pcad, torch, np):
+    from workloads import linrec
+    n = args.n or (1 << 26)
+    w = linrec(n=n)
+    dev = torch.device("cuda:0")
+    A = torch.from_numpy(w["a"]).to(dev)
+    B = torch.from_numpy(w["b"]).to(dev)
+    YB = torch.from_numpy(w["ybar"]).to(dev)
+    y = torch.empty_like(A)
+    ab = torch.empty_like(A)
+    bb = torch.empty_like(A)
+
+    def fwd():
+        return pcad.scan_fwd("linrec", A, B)
+
+    def bwd(saved):
+        pcad.scan_vjp("linrec", A, B, saved, YB, out=(ab, bb))
+
+    # algorithmic bytes: fwd reads a, b and writes y; adjoint reads a, b,
+    # ybar and writes a_bar, b_bar (the forward prefixes are recomputed)
+    return dict(n=n, fwd=fwd, bwd=bwd, bytes_fwd=12 * n, bytes_bwd=20 * n,
+                kernel="k_scan_vjp<LINREC>", inputs=w,
+                out=lambda: (ab, bb), cfg={"workload": "linrec scan, n=2^26, fp32 (a~U[0.9,1), b~N(0,1))",
+                                           "n": n, "op": "linrec", "combinator": "scan"})
+
+
+def bench_mat2(args, pcad, torch, np):
+    from workloads import mat2
+    n = args.n or (1 << 24)
+    w = mat2(n=n)
+    dev = torch.device("cuda:0")
+    M = torch.from_numpy(w["M"]).to(dev)
+    PB = torch.from_numpy(w["Pbar"]).to(dev)
+    mb = torch.empty_like(M)
+
+    def fwd():
+        return pcad.scan_fwd("mat2", M)
+
+    def bwd(saved):
+        pcad.scan_vjp("mat2", M, None, saved, PB, out=(mb,))
+
+    return dict(n=n, fwd=fwd, bwd=bwd, bytes_fwd=32 * n, bytes_bwd=48 * n,
+                kernel="k_scan_vjp<MAT2>", inputs=w, out=lambda: (mb,),
+                cfg={"workload": "2x2 matrix-product scan, n=2^24, fp32 (entries ~N(0,0.5))",
+                     "n": n, "op": "mat2", "combinator": "scan"})
+
+
+def cpu_baseline_and_parity(name, b, np):
+    """Times the oracle (fp64, one thread) on the same inputs and gates the
+    GPU outputs against it."""
+    import oracle
+    from oracle.gate import RTOL, gate
+    w = b["inputs"]
+    n = b["n"]
+    outs = [t.cpu().numpy() for t in b["out"]()]
+    if name == "linrec":
+        t0 = time.perf_counter()
+        yt = np.zeros((n, 2))
+        yt[:, 1] = w["ybar"]
+        xb, cx = oracle.scan_vjp("linrec", yt, w["a"], w["b"])
+        dt = time.perf_counter() - t0
+        r1 = gate(outs[0], xb[:, 0], cx[:, 0], RTOL["linrec"])
+        r2 = gate(outs[1], xb[:, 1], cx[:, 1], RTOL["linrec"])
+        par = dict(ok=r1["ok"] and r2["ok"] and r1["n_range_exceeded"] == 0 and r2["n_range_exceeded"] == 0,
+                   max_rel_a=r1["max_rel"], max_rel_b=r2["max_rel"],
+                   normwise_a=r1["normwise"], normwise_b=r2["normwise"],
+                   range_exceeded=r1["n_range_exceeded"] + r2["n_range_exceeded"])
+    else:
+        t0 = time.perf_counter()
+        xb, cx = oracle.scan_vjp("mat2", w["Pbar"], w["M"])
+        dt = time.perf_counter() - t0
+        r = gate(outs[0], xb, cx, RTOL["mat2"])
+        par = dict(ok=r["ok"], max_rel=r["max_rel"], normwise=r["normwise"],
+                   range_exceeded=r["n_range_exceeded"])
+    cpu = {"value": n / dt, "unit": "elem/s", "cores": 1, "kind": "oracle",
+           "sample": f"whole workload (n={n}): oracle adjoint incl. its forward re-execution, fp64, {dt:.2f} s"}
+    return cpu, par
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="linrec", choices=["linrec", "mat2"])
+    ap.add_argument("--n", type=int, default=0, help="override the element count")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
+              "this build has no multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2310_03568_amd as pcad
+
+    pcad.lib()
+    b = {"linrec": bench_linrec, "mat2": bench_mat2}[args.workload](args, pcad, torch, np)
+    torch.cuda.synchronize()
+
+    for _ in range(args.warmup):
+        _, _, saved = b["fwd"]()
+        b["bwd"](saved)
+    torch.cuda.synchronize()
+
+    stream = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
+           torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        e0, e1, e2 = ev[k]
+        e0.record(stream)
+        _, _, saved = b["fwd"]()
+        e1.record(stream)
+        b["bwd"](saved)
+        e2.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    t_fwd = np.array([e[0].elapsed_time(e[1]) for e in ev]) * 1e-3
+    t_bwd = np.array([e[1].elapsed_time(e[2]) for e in ev]) * 1e-3
+    n = b["n"]
+    tb = float(t_bwd.mean())
+    tf = float(t_fwd.mean())
+    achieved = b["bytes_bwd"] / tb / 1e9
+
+    cpu, par = (None, None)
+    if not args.no_cpu:
+        cpu, par = cpu_baseline_and_parity(args.workload, b, np)
+
+    out = {
+        "metric": METRIC,
+        "value": n / tb,
+        "unit": "elem/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": b["cfg"],
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": _traffic(b["kernel"], args.workload)},
+        "cpu_baseline": cpu,
+        "bwd_ms": tb * 1e3,
+        "fwd_ms": tf * 1e3,
+        "bwd_over_fwd": tb / tf,
+        "fwd_GBs": b["bytes_fwd"] / tf / 1e9,
+        "bwd_ci95_ms": 1.96 * float(t_bwd.std(ddof=1)) / np.sqrt(len(t_bwd)) * 1e3 if len(t_bwd) > 1 else 0.0,
+        "parity": par,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -330,16 +330,24 @@ __device__ __forceinline__ bool read_words(const uint64_t *w, uint32_t tag, Vec<
 }
 
 // Per-launch control block at the start of every workspace:
-//   [0] next tile id, [1] finished blocks, [2] launch epoch.
-// Counters are reset by the last block of each launch, which also advances
-// the epoch, so the next launch on the same workspace starts clean.
-//   [3] error flag: 1 = tile id outside the grid (workspace not zeroed or
-//       shared by overlapping launches), 2 = a look-back wait timed out.
+//   [0] rows finished in this launch, [1] launch epoch, [2] error flag
+//       (2 = a look-back wait timed out), [3] unused.
+// Tiles are taken in dispatch order (blockIdx), so no per-tile counter is
+// needed.  The tile that comes last in scan order in a row has, once its
+// look-back is done, seen every tile of its row publish (each publish
+// happens after that block read the epoch); it then arrives at [0], and the
+// last row to arrive resets [0] and advances the epoch for the next launch.
+// Only the control block needs zero-initialisation; everything else in a
+// workspace is validated by epoch tags.
 struct Ctl {
-  unsigned next, done, epoch, err;
+  unsigned rows_done, epoch, err, pad;
 };
 
 constexpr int kSpinLimit = 1 << 20;
+
+__device__ __forceinline__ unsigned ctl_load(unsigned *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 __device__ __forceinline__ void ctl_error(Ctl *ctl, unsigned code) {
   __hip_atomic_store(&ctl->err, code, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -349,55 +357,76 @@ __device__ __forceinline__ bool ctl_failed(Ctl *ctl) {
   return __hip_atomic_load(&ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
 }
 
-__device__ __forceinline__ unsigned ctl_load(unsigned *p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ void ctl_finish(Ctl *ctl, unsigned nblocks, uint32_t tag) {
-  unsigned d = __hip_atomic_fetch_add(&ctl->done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  if (d == nblocks - 1) {
-    __hip_atomic_store(&ctl->next, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(&ctl->done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// called once per row, by the row's last tile in scan order, after its
+// look-back (or immediately for a single-tile row)
+__device__ __forceinline__ void ctl_row_done(Ctl *ctl, unsigned nrows, uint32_t tag) {
+  const unsigned d =
+      __hip_atomic_fetch_add(&ctl->rows_done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (d == nrows - 1) {
+    __hip_atomic_store(&ctl->rows_done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __hip_atomic_store(&ctl->epoch, tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
+}
+
+// predecessors polled per lane and round trip, by status-word count
+template <int NW>
+constexpr int lookback_q() {
+  return NW <= 4 ? 4 : (NW <= 8 ? 2 : 1);
 }
 
 // Decoupled look-back, run by one whole wave.  The tile's predecessors in
 // scan order sit at distances 1..dist_max; the predecessor at distance d has
 // status index `tile - dir*d`.  Status block of tile t: NA aggregate words
-// then NP prefix words at st + t*(NA+NP).  Returns (in every lane) the
-// combination of all predecessors, earliest first, built from the nearest
-// published inclusive prefix and the aggregates after it.
-// Every wait is bounded: after kSpinLimit polls, or as soon as any block has
-// flagged an error, the wave stops waiting (the result is then garbage and
-// the error flag tells the host).
+// then NP prefix words at st + t*(NA+NP).  Lane L polls distances
+// base + L*Q + 1 .. base + L*Q + Q, so one round trip covers 64*Q tiles.
+// Returns (in every lane) the combination of all predecessors, earliest
+// first, built from the nearest published inclusive prefix and the
+// aggregates after it.  Every wait is bounded: after kSpinLimit polls, or as
+// soon as any block has flagged an error, the wave stops waiting (the result
+// is then garbage and the error flag tells the host).
 template <class Tr>
 __device__ typename Tr::T lookback(const uint64_t *st, int64_t tile, int dir, int dist_max,
                                    uint32_t tag, Ctl *ctl) {
   using T = typename Tr::T;
   using P = typename Tr::P;
   constexpr int NA = Tr::NA, NP = Tr::NP, NW = NA + NP;
+  constexpr int Q = lookback_q<NW>();
   const int lane = lane_id();
   T acc = Tr::id();
   bool have = false;
-  for (int base = 0; base < dist_max; base += WAVE) {
-    const int dist = base + lane + 1;
-    const bool inr = dist <= dist_max;
-    const uint64_t *w = st + (tile - (int64_t)dir * dist) * NW;
-    T agg = Tr::id();
-    P pre;
-    int state = inr ? 0 : 3;  // 3: out of range, 2: prefix, 1: aggregate, 0: not yet
-    int p;
+  for (int base = 0; base < dist_max; base += WAVE * Q) {
+    T agg[Q];
+    P pre[Q];
+    int state[Q];  // 3: out of range, 2: prefix, 1: aggregate, 0: not yet
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      agg[q] = Tr::id();
+      state[q] = (base + lane * Q + q + 1 <= dist_max) ? 0 : 3;
+    }
+    int plane = WAVE, pq = Q;
     for (int spin = 0;; ++spin) {
-      if (inr && state < 2) {
-        if (read_words<NP>(w + NA, tag, pre)) state = 2;
-        else if (read_words<NA>(w, tag, agg)) state = 1;
-        else state = 0;
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        if (state[q] < 2) {
+          const uint64_t *w = st + (tile - (int64_t)dir * (base + lane * Q + q + 1)) * NW;
+          if (read_words<NP>(w + NA, tag, pre[q])) state[q] = 2;
+          else if (read_words<NA>(w, tag, agg[q])) state[q] = 1;
+        }
       }
-      const uint64_t pm = __ballot(state == 2);
-      p = pm ? (__ffsll((long long)pm) - 1) : WAVE;
-      const bool needed = lane <= p;
-      if (__ballot(needed && state == 0) == 0) break;
+      int myq = Q;
+#pragma unroll
+      for (int q = Q - 1; q >= 0; --q)
+        if (state[q] == 2) myq = q;
+      const uint64_t pm = __ballot(myq < Q);
+      plane = pm ? (__ffsll((long long)pm) - 1) : WAVE;
+      pq = plane < WAVE ? __shfl(myq, plane, WAVE) : Q;
+      bool missing = false;
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const bool need = lane < plane || (lane == plane && q < pq);
+        missing = missing || (need && state[q] == 0);
+      }
+      if (__ballot(missing) == 0) break;
       if ((spin & 255) == 255) {
         if (spin >= kSpinLimit) {
           ctl_error(ctl, 2u);
@@ -407,13 +436,24 @@ __device__ typename Tr::T lookback(const uint64_t *st, int64_t tile, int dir, in
       }
       __builtin_amdgcn_s_sleep(1);
     }
+    // fold this lane's positions, farthest (earliest) first
     T v = Tr::id();
-    if (lane < p && state == 1) v = agg;
-    if (lane == p) v = Tr::from_pre(pre);
-    T win = readlane(wave_reduce_desc<Tr>(v), 0);
+    if (lane <= plane) {
+      const int top = (lane == plane) ? pq : Q - 1;
+      bool started = false;
+#pragma unroll
+      for (int q = Q - 1; q >= 0; --q) {
+        if (q > top) continue;
+        const T x = (lane == plane && q == pq) ? Tr::from_pre(pre[q])
+                                              : (state[q] == 1 ? agg[q] : Tr::id());
+        v = started ? Tr::comb(v, x) : x;
+        started = true;
+      }
+    }
+    const T win = readlane(wave_reduce_desc<Tr>(v), 0);
     acc = have ? Tr::comb(win, acc) : win;
     have = true;
-    if (p < WAVE) break;
+    if (plane < WAVE) break;
   }
   return acc;
 }

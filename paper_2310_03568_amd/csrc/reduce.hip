@@ -3,8 +3,8 @@
 // + * min max: a lifted grid reduction.  Each block folds a contiguous chunk
 // of a row into one lifted partial -- the sum; (zero count, product of the
 // non-zeros) for * (Section 3.2 Multiplication); (value, lowest index) for
-// min/max (Section 3.2 Min/Max) -- publishes it as epoch-tagged words, and
-// the last block of the row folds the row's partials in block order.  The
+// min/max (Section 3.2 Min/Max) -- and a second, stream-ordered launch
+// folds each row's partials.  The
 // adjoints are single elementwise passes (broadcast, the three zero cases,
 // the one-hot at k).
 //
@@ -71,37 +71,6 @@ __device__ __forceinline__ LV shfl_down_lv(const LV &v, int d) {
   return r;
 }
 
-__device__ __forceinline__ void put_lv(uint64_t *w, uint32_t tag, const LV &v) {
-  __hip_atomic_store(w, ((uint64_t)tag << 32) | __float_as_uint(v.f), __ATOMIC_RELAXED,
-                     __HIP_MEMORY_SCOPE_AGENT);
-  __hip_atomic_store(w + 1, ((uint64_t)tag << 32) | v.u, __ATOMIC_RELAXED,
-                     __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ bool get_lv(const uint64_t *w, uint32_t tag, LV &v) {
-  const uint64_t a = __hip_atomic_load(const_cast<uint64_t *>(w), __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-  const uint64_t b = __hip_atomic_load(const_cast<uint64_t *>(w + 1), __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-  v.f = __uint_as_float((uint32_t)a);
-  v.u = (uint32_t)b;
-  return (uint32_t)(a >> 32) == tag && (uint32_t)(b >> 32) == tag;
-}
-
-// Arrival counter valid for one launch: a word whose tag is not this
-// launch's counts as zero, so the counters never need a reset pass and may
-// sit on memory that other calls used.  Returns the count before arrival.
-__device__ __forceinline__ unsigned tagged_arrive(uint64_t *w, uint32_t tag) {
-  uint64_t old = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  for (;;) {
-    const uint32_t cnt = ((uint32_t)(old >> 32) == tag) ? (uint32_t)old : 0u;
-    const uint64_t nw = ((uint64_t)tag << 32) | (uint64_t)(cnt + 1u);
-    if (__hip_atomic_compare_exchange_strong(w, &old, nw, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                             __HIP_MEMORY_SCOPE_AGENT))
-      return cnt;
-  }
-}
-
 // block-wide reduction of a commutative lifted value; result valid in thread 0
 template <int OP>
 __device__ LV block_reduce_lv(LV v, LV *s_w) {
@@ -123,21 +92,18 @@ struct RedArgs {
   float *y;
   void *saved;
   int64_t n;
-  int64_t chunk;      // elements per block (multiple of 4)
-  int bpr;            // blocks per row
-  uint64_t *rowcnt;   // [batch] arrival counters {tag:32 | count:32}
-  uint64_t *parts;    // [batch][bpr][2] tagged words
-  Ctl *ctl;
+  int64_t chunk;  // elements per block (multiple of 4)
+  int bpr;        // blocks per row
+  LV *parts;      // [batch][bpr] lifted partials
 };
 
+// pass 1: every block folds its chunk of a row into one lifted partial
 template <int OP>
-__global__ __launch_bounds__(BLOCK) void k_reduce_fwd(RedArgs a) {
+__global__ __launch_bounds__(BLOCK) void k_reduce_part(RedArgs a) {
   __shared__ LV s_w[WAVES];
-  __shared__ unsigned s_epoch, s_last;
   const int tid = threadIdx.x;
   const int64_t row = blockIdx.y;
   const int b = blockIdx.x;
-  if (tid == 0) s_epoch = ctl_load(&a.ctl->epoch);
   const float *xr = a.x + row * a.n;
   const int64_t lo = (int64_t)b * a.chunk;
   const int64_t hi = lo + a.chunk < a.n ? lo + a.chunk : a.n;
@@ -151,50 +117,36 @@ __global__ __launch_bounds__(BLOCK) void k_reduce_fwd(RedArgs a) {
       acc = Lift<OP>::comb(acc, Lift<OP>::elem(v.z, (uint32_t)(i + 2)));
       acc = Lift<OP>::comb(acc, Lift<OP>::elem(v.w, (uint32_t)(i + 3)));
     } else {
+#pragma unroll
       for (int j = 0; j < 4; ++j)
         if (i + j < hi) acc = Lift<OP>::comb(acc, Lift<OP>::elem(xr[i + j], (uint32_t)(i + j)));
     }
   }
-  __syncthreads();
-  const uint32_t tag = s_epoch + 1;
   acc = block_reduce_lv<OP>(acc, s_w);
-  if (tid == 0) {
-    put_lv(a.parts + (row * a.bpr + b) * 2, tag, acc);
-    const unsigned c = tagged_arrive(&a.rowcnt[row], tag);
-    s_last = (c == (unsigned)a.bpr - 1);
-  }
-  __syncthreads();
-  if (s_last) {
-    // fold the row's partials; every partial word is tagged, so spin until
-    // the words of this launch are visible
-    LV r = Lift<OP>::id();
-    for (int p = tid; p < a.bpr; p += BLOCK) {
-      LV v;
-      for (int spin = 0; !get_lv(a.parts + (row * a.bpr + p) * 2, tag, v); ++spin) {
-        if (spin >= kSpinLimit) {
-          ctl_error(a.ctl, 2u);
-          break;
-        }
-        __builtin_amdgcn_s_sleep(1);
-      }
-      r = Lift<OP>::comb(r, v);
-    }
-    r = block_reduce_lv<OP>(r, s_w);
-    if (tid == 0) {
-      if (OP == ADD) {
-        a.y[row] = r.f;
-      } else if (OP == MUL) {
-        a.y[row] = r.u > 0 ? 0.0f : r.f;
-        uint32_t *sv = reinterpret_cast<uint32_t *>(a.saved) + row * 2;
-        sv[0] = r.u;
-        reinterpret_cast<float *>(sv)[1] = r.f;
-      } else {
-        a.y[row] = r.f;
-        reinterpret_cast<int32_t *>(a.saved)[row] = (int32_t)r.u;
-      }
+  if (tid == 0) a.parts[row * a.bpr + b] = acc;
+}
+
+// pass 2 (stream-ordered after pass 1): one block per row folds the partials
+template <int OP>
+__global__ __launch_bounds__(BLOCK) void k_reduce_fold(RedArgs a) {
+  __shared__ LV s_w[WAVES];
+  const int64_t row = blockIdx.x;
+  LV r = Lift<OP>::id();
+  for (int p = threadIdx.x; p < a.bpr; p += BLOCK) r = Lift<OP>::comb(r, a.parts[row * a.bpr + p]);
+  r = block_reduce_lv<OP>(r, s_w);
+  if (threadIdx.x == 0) {
+    if (OP == ADD) {
+      a.y[row] = r.f;
+    } else if (OP == MUL) {
+      a.y[row] = r.u > 0 ? 0.0f : r.f;
+      uint32_t *sv = reinterpret_cast<uint32_t *>(a.saved) + row * 2;
+      sv[0] = r.u;
+      reinterpret_cast<float *>(sv)[1] = r.f;
+    } else {
+      a.y[row] = r.f;
+      reinterpret_cast<int32_t *>(a.saved)[row] = (int32_t)r.u;
     }
   }
-  if (tid == 0) ctl_finish(a.ctl, gridDim.x * gridDim.y, tag);
 }
 
 // neutral results for rows of length 0
@@ -342,20 +294,14 @@ __global__ __launch_bounds__(BLOCK) void k_reduce_vjp_gen(RedGenArgs a) {
   __shared__ T s_wf[K][WAVES];
   __shared__ T s_wr[K][WAVES];
   __shared__ T s_carry;
-  __shared__ unsigned s_tile, s_epoch;
+  __shared__ unsigned s_epoch;
 
   const int tid = threadIdx.x, lane = lane_id(), wave = tid / WAVE;
-  if (tid == 0) {
-    const unsigned t = __hip_atomic_fetch_add(&a.ctl->next, 1u, __ATOMIC_RELAXED,
-                                              __HIP_MEMORY_SCOPE_AGENT);
-    s_tile = t < gridDim.x ? gridDim.x - 1 - t : 0xffffffffu;
-    s_epoch = ctl_load(&a.ctl->epoch);
-    if (t >= gridDim.x) ctl_error(a.ctl, 1u);
-  }
+  if (tid == 0) s_epoch = ctl_load(&a.ctl->epoch);
   __syncthreads();
-  if (s_tile == 0xffffffffu) return;
   const uint32_t tag = s_epoch + 1;
-  const TileInfo ti = tile_info(s_tile, a.n, a.tpr, TILE);
+  // descending tile order: dispatch order runs right to left
+  const TileInfo ti = tile_info(gridDim.x - 1 - blockIdx.x, a.n, a.tpr, TILE);
 
   float4 in[K][NIN];
   T xe[K][EPL];
@@ -445,6 +391,7 @@ __global__ __launch_bounds__(BLOCK) void k_reduce_vjp_gen(RedGenArgs a) {
     __syncthreads();
     carry = s_carry;
   }
+  if (tid == 0 && ti.lt == 0) ctl_row_done(a.ctl, gridDim.x / a.tpr, tag);
 
   float yb[4];
 #pragma unroll
@@ -489,7 +436,6 @@ __global__ __launch_bounds__(BLOCK) void k_reduce_vjp_gen(RedGenArgs a) {
     }
   }
 
-  if (tid == 0) ctl_finish(a.ctl, gridDim.x, tag);
 }
 
 // ---------------------------------------------------------------------------
@@ -511,8 +457,7 @@ size_t reduce_ws_bytes(int op, int64_t batch, int64_t n) {
     return kCtlBytes + (size_t)tiles * 2 * scan_elem_floats(op) * sizeof(uint64_t);
   }
   const int bpr = reduce_blocks_per_row(batch, n);
-  const size_t cnt = ((size_t)batch * sizeof(uint64_t) + 255) / 256 * 256;
-  return kCtlBytes + cnt + (size_t)batch * bpr * 2 * sizeof(uint64_t);
+  return kCtlBytes + (size_t)batch * bpr * sizeof(LV);
 }
 
 hipError_t reduce_fwd_launch(int op, int64_t batch, int64_t n, const float *x0, const float *x1,
@@ -530,18 +475,22 @@ hipError_t reduce_fwd_launch(int op, int64_t batch, int64_t n, const float *x0, 
   a.x = x0; a.y = y; a.saved = saved; a.n = n;
   a.bpr = reduce_blocks_per_row(batch, n);
   a.chunk = ((n + a.bpr - 1) / a.bpr + 3) / 4 * 4;
-  a.ctl = reinterpret_cast<Ctl *>(ws);
-  char *p = static_cast<char *>(ws) + kCtlBytes;
-  a.rowcnt = reinterpret_cast<uint64_t *>(p);
-  a.parts = reinterpret_cast<uint64_t *>(p + ((size_t)batch * sizeof(uint64_t) + 255) / 256 * 256);
+  a.parts = reinterpret_cast<LV *>(static_cast<char *>(ws) + kCtlBytes);
   const dim3 grid((unsigned)a.bpr, (unsigned)batch);
+  const dim3 fold((unsigned)batch);
+#define PCAD_RED(OPV)                                                          \
+  case OPV:                                                                    \
+    hipLaunchKernelGGL(k_reduce_part<OPV>, grid, dim3(BLOCK), 0, s, a);        \
+    hipLaunchKernelGGL(k_reduce_fold<OPV>, fold, dim3(BLOCK), 0, s, a);        \
+    break;
   switch (op) {
-  case ADD: hipLaunchKernelGGL(k_reduce_fwd<ADD>, grid, dim3(BLOCK), 0, s, a); break;
-  case MUL: hipLaunchKernelGGL(k_reduce_fwd<MUL>, grid, dim3(BLOCK), 0, s, a); break;
-  case MIN: hipLaunchKernelGGL(k_reduce_fwd<MIN>, grid, dim3(BLOCK), 0, s, a); break;
-  case MAX: hipLaunchKernelGGL(k_reduce_fwd<MAX>, grid, dim3(BLOCK), 0, s, a); break;
+    PCAD_RED(ADD)
+    PCAD_RED(MUL)
+    PCAD_RED(MIN)
+    PCAD_RED(MAX)
   default: return hipErrorInvalidValue;
   }
+#undef PCAD_RED
   return hipGetLastError();
 }
 

@@ -42,18 +42,13 @@ __global__ __launch_bounds__(BLOCK) void k_scan_fwd(ScanFwdArgs a) {
 
   __shared__ T s_wt[K][WAVES];
   __shared__ T s_carry;
-  __shared__ unsigned s_tile, s_epoch;
+  __shared__ unsigned s_epoch;
 
   const int tid = threadIdx.x, lane = lane_id(), wave = tid / WAVE;
-  if (tid == 0) {
-    s_tile = __hip_atomic_fetch_add(&a.ctl->next, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    s_epoch = ctl_load(&a.ctl->epoch);
-    if (s_tile >= gridDim.x) ctl_error(a.ctl, 1u);
-  }
+  if (tid == 0) s_epoch = ctl_load(&a.ctl->epoch);
   __syncthreads();
-  if (s_tile >= gridDim.x) return;
   const uint32_t tag = s_epoch + 1;
-  const TileInfo ti = tile_info(s_tile, a.n, a.tpr, TILE);
+  const TileInfo ti = tile_info(blockIdx.x, a.n, a.tpr, TILE);
 
   // load and thread-serial inclusive scan of each group
   T loc[K][EPL];
@@ -112,6 +107,7 @@ __global__ __launch_bounds__(BLOCK) void k_scan_fwd(ScanFwdArgs a) {
     __syncthreads();
     carry = s_carry;
   }
+  if (tid == 0 && ti.lt == a.tpr - 1) ctl_row_done(a.ctl, gridDim.x / a.tpr, tag);
   if (tid == 0 && a.saved) {
 #pragma unroll
     for (int i = 0; i < N; ++i) a.saved[ti.tile * N + i] = carry.f[i];
@@ -152,7 +148,6 @@ __global__ __launch_bounds__(BLOCK) void k_scan_fwd(ScanFwdArgs a) {
     }
   }
 
-  if (tid == 0) ctl_finish(a.ctl, gridDim.x, tag);
 }
 
 // ---------------------------------------------------------------------------
@@ -184,20 +179,14 @@ __global__ __launch_bounds__(BLOCK) void k_scan_vjp(ScanVjpArgs a) {
   __shared__ FT s_wf[K][WAVES];
   __shared__ MT s_wm[K][WAVES];
   __shared__ MT s_carry;
-  __shared__ unsigned s_tile, s_epoch;
+  __shared__ unsigned s_epoch;
 
   const int tid = threadIdx.x, lane = lane_id(), wave = tid / WAVE;
-  if (tid == 0) {
-    const unsigned t = __hip_atomic_fetch_add(&a.ctl->next, 1u, __ATOMIC_RELAXED,
-                                              __HIP_MEMORY_SCOPE_AGENT);
-    s_tile = t < gridDim.x ? gridDim.x - 1 - t : 0xffffffffu;
-    s_epoch = ctl_load(&a.ctl->epoch);
-    if (t >= gridDim.x) ctl_error(a.ctl, 1u);
-  }
+  if (tid == 0) s_epoch = ctl_load(&a.ctl->epoch);
   __syncthreads();
-  if (s_tile == 0xffffffffu) return;
   const uint32_t tag = s_epoch + 1;
-  const TileInfo ti = tile_info(s_tile, a.n, a.tpr, TILE);
+  // descending tile order: dispatch order runs right to left
+  const TileInfo ti = tile_info(gridDim.x - 1 - blockIdx.x, a.n, a.tpr, TILE);
 
   // loads: x (forward inputs) and ybar
   float4 in[K][NIN];
@@ -323,6 +312,7 @@ __global__ __launch_bounds__(BLOCK) void k_scan_vjp(ScanVjpArgs a) {
     __syncthreads();
     carry = s_carry;
   }
+  if (tid == 0 && ti.lt == 0) ctl_row_done(a.ctl, gridDim.x / a.tpr, tag);
 
   // thread-serial sweep, right to left
 #pragma unroll
@@ -368,7 +358,6 @@ __global__ __launch_bounds__(BLOCK) void k_scan_vjp(ScanVjpArgs a) {
     }
   }
 
-  if (tid == 0) ctl_finish(a.ctl, gridDim.x, tag);
 }
 
 // ---------------------------------------------------------------------------

@@ -40,7 +40,7 @@ def host(t):
 
 def ws_error():
     import paper_2310_03568_amd as p
-    errs = [int(b[:16].view(torch.int32)[3].item()) for b in p._ws.values()]
+    errs = [int(b[:16].view(torch.int32)[2].item()) for b in p._ws.values()]
     return max(errs) if errs else 0
 
 
