@@ -129,9 +129,11 @@ struct Fwd<MAT2> {
 // ---------------------------------------------------------------------------
 template <int OP>
 struct Shape {
+  static constexpr int THREADS = 1024;
+  static constexpr int W = THREADS / WAVE;
   static constexpr int EPL = (OP == MAT2) ? 1 : 4;
-  static constexpr int K = (OP == MAT2) ? 4 : 4;
-  static constexpr int TILE = BLOCK * EPL * K;
+  static constexpr int K = 2;
+  static constexpr int TILE = THREADS * EPL * K;
 };
 
 // 16-byte load of one group of one stream.  `S` floats per element.  When
@@ -284,6 +286,28 @@ __device__ __forceinline__ typename Tr::T wave_scan_rev(typename Tr::T x) {
     if (lane + d < WAVE) x = Tr::comb(o, x);
   }
   return x;
+}
+
+// Run by wave 0 only.  s_tot[g][w] holds the total of (group g, wave w) of a
+// tile; scan order is g-major, w-minor, or its reverse (REV).  Writes
+// s_pre[g][w] = init (.) (exclusive scan-order prefix) and returns the tile
+// total (in every lane of wave 0).  K*W <= 64.
+template <class Tr, int K, int W, bool REV>
+__device__ __forceinline__ typename Tr::T wave0_block_prefix(typename Tr::T (*s_tot)[W],
+                                                             typename Tr::T (*s_pre)[W],
+                                                             const typename Tr::T &init) {
+  using T = typename Tr::T;
+  constexpr int NI = K * W;
+  static_assert(NI <= WAVE, "too many wave totals for one wave");
+  const int lane = lane_id();
+  const int idx = REV ? (NI - 1 - lane) : lane;
+  T v = Tr::id();
+  if (lane < NI) v = s_tot[idx / W][idx % W];
+  const T inc = wave_scan_fwd<Tr>(v);
+  T ex = shfl_up(inc, 1);
+  if (lane == 0) ex = Tr::id();
+  if (lane < NI) s_pre[idx / W][idx % W] = Tr::comb(init, ex);
+  return readlane(inc, NI - 1);
 }
 
 // ordered reduction where lane L+1 is EARLIER than lane L; the full result

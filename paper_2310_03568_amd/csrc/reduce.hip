@@ -283,43 +283,44 @@ struct RedGenArgs {
 };
 
 template <int OP>
-__global__ __launch_bounds__(BLOCK) void k_reduce_vjp_gen(RedGenArgs a) {
+__global__ __launch_bounds__(Shape<OP>::THREADS) void k_reduce_vjp_gen(RedGenArgs a) {
   using F = FwdLB<OP>;
   using R = RevLB<OP>;
   using T = typename F::T;
   using Io = IO<OP>;
   constexpr int EPL = Shape<OP>::EPL, K = Shape<OP>::K, TILE = Shape<OP>::TILE;
+  constexpr int TH = Shape<OP>::THREADS, W = Shape<OP>::W;
   constexpr int NIN = Io::NIN, S = Io::S, N = Fwd<OP>::N;
 
-  __shared__ T s_wf[K][WAVES];
-  __shared__ T s_wr[K][WAVES];
+  __shared__ T s_ftot[K][W];
+  __shared__ T s_fpre[K][W];
+  __shared__ T s_rtot[K][W];
+  __shared__ T s_rpre[K][W];
   __shared__ T s_carry;
   __shared__ unsigned s_epoch;
 
   const int tid = threadIdx.x, lane = lane_id(), wave = tid / WAVE;
   if (tid == 0) s_epoch = ctl_load(&a.ctl->epoch);
-  __syncthreads();
-  const uint32_t tag = s_epoch + 1;
   // descending tile order: dispatch order runs right to left
   const TileInfo ti = tile_info(gridDim.x - 1 - blockIdx.x, a.n, a.tpr, TILE);
 
-  float4 in[K][NIN];
   T xe[K][EPL];
 #pragma unroll
   for (int g = 0; g < K; ++g) {
-    const int el = g * BLOCK * EPL + tid * EPL;
+    const int el = g * TH * EPL + tid * EPL;
     const int v = ti.valid - el;
     const float *src[2] = {a.x0, a.x1};
+    float4 in[NIN];
 #pragma unroll
     for (int s = 0; s < NIN; ++s)
-      in[g][s] = load_group<S>(src[s], ti.base + el, v, ti.vec_ok, Io::fill(s));
+      in[s] = load_group<S>(src[s], ti.base + el, v, ti.vec_ok, Io::fill(s));
 #pragma unroll
-    for (int j = 0; j < EPL; ++j) xe[g][j] = Io::elem(in[g], j);
+    for (int j = 0; j < EPL; ++j) xe[g][j] = Io::elem(in, j);
   }
 
-  // in-thread inclusive prefixes and exclusive suffixes
+  // in-thread inclusive prefixes and exclusive suffixes, then wave scans
   T locp[K][EPL], sufx[K][EPL];
-  T aggf[K], aggr[K];
+  T inf_[K], inr_[K];
 #pragma unroll
   for (int g = 0; g < K; ++g) {
     T acc = xe[g][0];
@@ -329,69 +330,46 @@ __global__ __launch_bounds__(BLOCK) void k_reduce_vjp_gen(RedGenArgs a) {
       acc = F::comb(acc, xe[g][j]);
       locp[g][j] = acc;
     }
-    aggf[g] = acc;
     T sacc = F::id();
 #pragma unroll
     for (int j = EPL - 1; j >= 0; --j) {
       sufx[g][j] = sacc;
       sacc = F::comb(xe[g][j], sacc);
     }
-    aggr[g] = sacc;
-  }
-  T inf_[K], inr_[K];
-#pragma unroll
-  for (int g = 0; g < K; ++g) {
-    inf_[g] = wave_scan_fwd<F>(aggf[g]);
-    inr_[g] = wave_scan_rev<R>(aggr[g]);
-    if (lane == WAVE - 1) s_wf[g][wave] = inf_[g];
-    if (lane == 0) s_wr[g][wave] = inr_[g];
+    inf_[g] = wave_scan_fwd<F>(acc);
+    inr_[g] = wave_scan_rev<R>(sacc);
+    if (lane == WAVE - 1) s_ftot[g][wave] = inf_[g];
+    if (lane == 0) s_rtot[g][wave] = inr_[g];
   }
   __syncthreads();
+  const uint32_t tag = s_epoch + 1;
 
-  // forward side: l_i = saved tile prefix (.) in-tile exclusive prefix
-  T lpre[K];
-  {
-    T run;
+  if (wave == 0) {
+    // forward side: l = saved tile prefix (.) in-tile exclusive prefix
+    T lcar;
 #pragma unroll
-    for (int i = 0; i < N; ++i) run.f[i] = a.saved[ti.tile * N + i];
-#pragma unroll
-    for (int g = 0; g < K; ++g)
-#pragma unroll
-      for (int w = 0; w < WAVES; ++w) {
-        if (w == wave) lpre[g] = run;
-        run = F::comb(run, s_wf[g][w]);
-      }
-  }
-  // reverse side: in-tile suffix after each (group, wave), and the tile total
-  T rpre[K];
-  T run = R::id();
-#pragma unroll
-  for (int g = K - 1; g >= 0; --g)
-#pragma unroll
-    for (int w = WAVES - 1; w >= 0; --w) {
-      if (w == wave) rpre[g] = run;
-      run = R::comb(run, s_wr[g][w]);
+    for (int i = 0; i < N; ++i) lcar.f[i] = a.saved[ti.tile * N + i];
+    wave0_block_prefix<F, K, W, false>(s_ftot, s_fpre, lcar);
+    // reverse side: in-tile suffixes, the tile total, and a right-to-left
+    // look-back over tile totals for the tile's exclusive suffix
+    const T tile_agg = wave0_block_prefix<R, K, W, true>(s_rtot, s_rpre, R::id());
+    uint64_t *st = a.status + ti.tile * (R::NA + R::NP);
+    const int dist_max = a.tpr - 1 - ti.lt;
+    T c = R::id();
+    if (dist_max == 0) {
+      if (lane == 0) publish<N>(st + R::NA, tag, tile_agg);
+    } else {
+      if (lane == 0) publish<N>(st, tag, tile_agg);
+      c = lookback<R>(a.status, ti.tile, -1, dist_max, tag, a.ctl);
+      if (lane == 0) publish<N>(st + R::NA, tag, R::comb(c, tile_agg));
     }
-  const T tile_agg = run;
-
-  uint64_t *st = a.status + ti.tile * (R::NA + R::NP);
-  const int dist_max = a.tpr - 1 - ti.lt;
-  T carry = R::id();
-  if (dist_max == 0) {
-    if (tid == 0) publish<N>(st + R::NA, tag, tile_agg);
-  } else {
-    if (tid == 0) publish<N>(st, tag, tile_agg);
-    if (wave == 0) {
-      const T c = lookback<R>(a.status, ti.tile, -1, dist_max, tag, a.ctl);
-      if (lane == 0) {
-        publish<N>(st + R::NA, tag, R::comb(c, tile_agg));
-        s_carry = c;
-      }
+    if (lane == 0) {
+      s_carry = c;
+      if (ti.lt == 0) ctl_row_done(a.ctl, gridDim.x / a.tpr, tag);
     }
-    __syncthreads();
-    carry = s_carry;
   }
-  if (tid == 0 && ti.lt == 0) ctl_row_done(a.ctl, gridDim.x / a.tpr, tag);
+  __syncthreads();
+  const T carry = s_carry;
 
   float yb[4];
 #pragma unroll
@@ -403,8 +381,8 @@ __global__ __launch_bounds__(BLOCK) void k_reduce_vjp_gen(RedGenArgs a) {
     if (lane == 0) exf = F::id();
     T exr = shfl_down(inr_[g], 1);
     if (lane == WAVE - 1) exr = R::id();
-    const T lth = F::comb(lpre[g], exf);                 // everything before this thread
-    const T rth = R::comb(R::comb(carry, rpre[g]), exr);  // everything after this thread
+    const T lth = F::comb(s_fpre[g][wave], exf);                 // everything before this thread
+    const T rth = R::comb(R::comb(carry, s_rpre[g][wave]), exr);  // everything after this thread
     float4 o[2];
     o[0] = make_float4(0, 0, 0, 0);
     o[1] = make_float4(0, 0, 0, 0);
@@ -421,7 +399,7 @@ __global__ __launch_bounds__(BLOCK) void k_reduce_vjp_gen(RedGenArgs a) {
         f4set(o[1], j, xb[1]);
       }
     }
-    const int el = g * BLOCK * EPL + tid * EPL;
+    const int el = g * TH * EPL + tid * EPL;
     const int v = ti.valid - el;
     float *dst[2] = {a.xb0, a.xb1};
     constexpr int NS = (OP == LINREC) ? 2 : 1;
@@ -435,7 +413,6 @@ __global__ __launch_bounds__(BLOCK) void k_reduce_vjp_gen(RedGenArgs a) {
       store_group<S>(dst[s], ti.base + el, v, ti.vec_ok, val);
     }
   }
-
 }
 
 // ---------------------------------------------------------------------------
@@ -507,8 +484,8 @@ hipError_t reduce_vjp_launch(int op, int64_t batch, int64_t n, const float *x0, 
     a.ctl = reinterpret_cast<Ctl *>(ws);
     a.status = reinterpret_cast<uint64_t *>(static_cast<char *>(ws) + kCtlBytes);
     const dim3 grid((unsigned)(batch * tpr));
-    if (op == LINREC) hipLaunchKernelGGL(k_reduce_vjp_gen<LINREC>, grid, dim3(BLOCK), 0, s, a);
-    else hipLaunchKernelGGL(k_reduce_vjp_gen<MAT2>, grid, dim3(BLOCK), 0, s, a);
+    if (op == LINREC) hipLaunchKernelGGL(k_reduce_vjp_gen<LINREC>, grid, dim3(Shape<LINREC>::THREADS), 0, s, a);
+    else hipLaunchKernelGGL(k_reduce_vjp_gen<MAT2>, grid, dim3(Shape<MAT2>::THREADS), 0, s, a);
     return hipGetLastError();
   }
   int64_t bx = (n + BLOCK * 4 * 4 - 1) / (BLOCK * 4 * 4);

@@ -33,29 +33,29 @@ struct ScanFwdArgs {
 };
 
 template <int OP, bool REDUCE>
-__global__ __launch_bounds__(BLOCK) void k_scan_fwd(ScanFwdArgs a) {
+__global__ __launch_bounds__(Shape<OP>::THREADS) void k_scan_fwd(ScanFwdArgs a) {
   using Op = FwdLB<OP>;
   using T = typename Op::T;
   using Io = IO<OP>;
   constexpr int EPL = Shape<OP>::EPL, K = Shape<OP>::K, TILE = Shape<OP>::TILE;
+  constexpr int TH = Shape<OP>::THREADS, W = Shape<OP>::W;
   constexpr int NIN = Io::NIN, S = Io::S, N = Fwd<OP>::N;
 
-  __shared__ T s_wt[K][WAVES];
+  __shared__ T s_tot[K][W];
+  __shared__ T s_pre[K][W];
   __shared__ T s_carry;
   __shared__ unsigned s_epoch;
 
   const int tid = threadIdx.x, lane = lane_id(), wave = tid / WAVE;
   if (tid == 0) s_epoch = ctl_load(&a.ctl->epoch);
-  __syncthreads();
-  const uint32_t tag = s_epoch + 1;
   const TileInfo ti = tile_info(blockIdx.x, a.n, a.tpr, TILE);
 
   // load and thread-serial inclusive scan of each group
   T loc[K][EPL];
-  T agg[K];
+  T incl[K];
 #pragma unroll
   for (int g = 0; g < K; ++g) {
-    const int el = g * BLOCK * EPL + tid * EPL;
+    const int el = g * TH * EPL + tid * EPL;
     const int v = ti.valid - el;
     float4 in[NIN];
     const float *src[2] = {a.x0, a.x1};
@@ -69,85 +69,68 @@ __global__ __launch_bounds__(BLOCK) void k_scan_fwd(ScanFwdArgs a) {
       acc = Op::comb(acc, Io::elem(in, j));
       loc[g][j] = acc;
     }
-    agg[g] = acc;
-  }
-
-  T incl[K];
-#pragma unroll
-  for (int g = 0; g < K; ++g) {
-    incl[g] = wave_scan_fwd<Op>(agg[g]);
-    if (lane == WAVE - 1) s_wt[g][wave] = incl[g];
+    incl[g] = wave_scan_fwd<Op>(acc);
+    if (lane == WAVE - 1) s_tot[g][wave] = incl[g];
   }
   __syncthreads();
+  const uint32_t tag = s_epoch + 1;
 
-  T pre[K];
-  T run = Op::id();
-#pragma unroll
-  for (int g = 0; g < K; ++g)
-#pragma unroll
-    for (int w = 0; w < WAVES; ++w) {
-      if (w == wave) pre[g] = run;
-      run = Op::comb(run, s_wt[g][w]);
+  // wave 0: block prefixes, publish, look back
+  if (wave == 0) {
+    const T tile_agg = wave0_block_prefix<Op, K, W, false>(s_tot, s_pre, Op::id());
+    uint64_t *st = a.status + ti.tile * (Op::NA + Op::NP);
+    T c = Op::id();
+    if (ti.lt == 0) {
+      if (lane == 0) publish<N>(st + Op::NA, tag, tile_agg);
+    } else {
+      if (lane == 0) publish<N>(st, tag, tile_agg);
+      c = lookback<Op>(a.status, ti.tile, +1, ti.lt, tag, a.ctl);
+      if (lane == 0) publish<N>(st + Op::NA, tag, Op::comb(c, tile_agg));
     }
-  const T tile_agg = run;
-
-  uint64_t *st = a.status + ti.tile * (Op::NA + Op::NP);
-  T carry = Op::id();
-  if (ti.lt == 0) {
-    if (tid == 0) publish<N>(st + Op::NA, tag, tile_agg);
-  } else {
-    if (tid == 0) publish<N>(st, tag, tile_agg);
-    if (wave == 0) {
-      const T c = lookback<Op>(a.status, ti.tile, +1, ti.lt, tag, a.ctl);
-      if (lane == 0) {
-        publish<N>(st + Op::NA, tag, Op::comb(c, tile_agg));
-        s_carry = c;
+    if (lane == 0) {
+      s_carry = c;
+      if (ti.lt == a.tpr - 1) ctl_row_done(a.ctl, gridDim.x / a.tpr, tag);
+      if (a.saved) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) a.saved[ti.tile * N + i] = c.f[i];
+      }
+      if (REDUCE && ti.lt == a.tpr - 1) {
+        const T tot = Op::comb(c, tile_agg);
+#pragma unroll
+        for (int i = 0; i < N; ++i) a.total[ti.row * N + i] = tot.f[i];
       }
     }
-    __syncthreads();
-    carry = s_carry;
   }
-  if (tid == 0 && ti.lt == a.tpr - 1) ctl_row_done(a.ctl, gridDim.x / a.tpr, tag);
-  if (tid == 0 && a.saved) {
-#pragma unroll
-    for (int i = 0; i < N; ++i) a.saved[ti.tile * N + i] = carry.f[i];
-  }
+  if (REDUCE) return;
+  __syncthreads();
+  const T carry = s_carry;
 
-  if (REDUCE) {
-    if (tid == 0 && ti.lt == a.tpr - 1) {
-      const T tot = Op::comb(carry, tile_agg);
 #pragma unroll
-      for (int i = 0; i < N; ++i) a.total[ti.row * N + i] = tot.f[i];
-    }
-  } else {
+  for (int g = 0; g < K; ++g) {
+    T ex = shfl_up(incl[g], 1);
+    if (lane == 0) ex = Op::id();
+    const T full = Op::comb(Op::comb(carry, s_pre[g][wave]), ex);
+    const int el = g * TH * EPL + tid * EPL;
+    const int v = ti.valid - el;
+    if (OP == MAT2) {
+      const T o = Op::comb(full, loc[g][0]);
+      store_group<4>(a.y0, ti.base + el, v, true, make_float4(o.f[0], o.f[1], o.f[2], o.f[3]));
+    } else {
+      float4 o0, o1;
 #pragma unroll
-    for (int g = 0; g < K; ++g) {
-      T ex = shfl_up(incl[g], 1);
-      if (lane == 0) ex = Op::id();
-      const T full = Op::comb(Op::comb(carry, pre[g]), ex);
-      const int el = g * BLOCK * EPL + tid * EPL;
-      const int v = ti.valid - el;
-      if (OP == MAT2) {
-        const T o = Op::comb(full, loc[g][0]);
-        store_group<4>(a.y0, ti.base + el, v, true, make_float4(o.f[0], o.f[1], o.f[2], o.f[3]));
-      } else {
-        float4 o0, o1;
-#pragma unroll
-        for (int j = 0; j < EPL; ++j) {
-          const T o = Op::comb(full, loc[g][j]);
-          if (OP == LINREC) {
-            f4set(o0, j, o.f[1]);
-            f4set(o1, j, o.f[0]);
-          } else {
-            f4set(o0, j, o.f[0]);
-          }
+      for (int j = 0; j < EPL; ++j) {
+        const T o = Op::comb(full, loc[g][j]);
+        if (OP == LINREC) {
+          f4set(o0, j, o.f[1]);
+          f4set(o1, j, o.f[0]);
+        } else {
+          f4set(o0, j, o.f[0]);
         }
-        store_group<1>(a.y0, ti.base + el, v, ti.vec_ok, o0);
-        if (OP == LINREC && a.y1) store_group<1>(a.y1, ti.base + el, v, ti.vec_ok, o1);
       }
+      store_group<1>(a.y0, ti.base + el, v, ti.vec_ok, o0);
+      if (OP == LINREC && a.y1) store_group<1>(a.y1, ti.base + el, v, ti.vec_ok, o1);
     }
   }
-
 }
 
 // ---------------------------------------------------------------------------
@@ -166,7 +149,7 @@ struct ScanVjpArgs {
 };
 
 template <int OP, bool ABAR>
-__global__ __launch_bounds__(BLOCK) void k_scan_vjp(ScanVjpArgs a) {
+__global__ __launch_bounds__(Shape<OP>::THREADS) void k_scan_vjp(ScanVjpArgs a) {
   using Op = FwdLB<OP>;
   using FT = typename Op::T;
   using A = Adj<OP, ABAR>;
@@ -174,17 +157,18 @@ __global__ __launch_bounds__(BLOCK) void k_scan_vjp(ScanVjpArgs a) {
   using MT = typename M::T;
   using Io = IO<OP>;
   constexpr int EPL = Shape<OP>::EPL, K = Shape<OP>::K, TILE = Shape<OP>::TILE;
+  constexpr int TH = Shape<OP>::THREADS, W = Shape<OP>::W;
   constexpr int NIN = Io::NIN, S = Io::S, N = Fwd<OP>::N;
 
-  __shared__ FT s_wf[K][WAVES];
-  __shared__ MT s_wm[K][WAVES];
+  __shared__ FT s_ftot[K][W];
+  __shared__ FT s_fpre[K][W];
+  __shared__ MT s_mtot[K][W];
+  __shared__ MT s_mpre[K][W];
   __shared__ MT s_carry;
   __shared__ unsigned s_epoch;
 
   const int tid = threadIdx.x, lane = lane_id(), wave = tid / WAVE;
   if (tid == 0) s_epoch = ctl_load(&a.ctl->epoch);
-  __syncthreads();
-  const uint32_t tag = s_epoch + 1;
   // descending tile order: dispatch order runs right to left
   const TileInfo ti = tile_info(gridDim.x - 1 - blockIdx.x, a.n, a.tpr, TILE);
 
@@ -193,7 +177,7 @@ __global__ __launch_bounds__(BLOCK) void k_scan_vjp(ScanVjpArgs a) {
   float4 yv[K][2];
 #pragma unroll
   for (int g = 0; g < K; ++g) {
-    const int el = g * BLOCK * EPL + tid * EPL;
+    const int el = g * TH * EPL + tid * EPL;
     const int v = ti.valid - el;
     const float *src[2] = {a.x0, a.x1};
 #pragma unroll
@@ -203,11 +187,10 @@ __global__ __launch_bounds__(BLOCK) void k_scan_vjp(ScanVjpArgs a) {
     if (ABAR) yv[g][1] = load_group<1>(a.yb1, ti.base + el, v, ti.vec_ok, make_float4(0, 0, 0, 0));
   }
 
-  // forward prefixes rs_{i-1} of every element, recomputed in the tile
-  FT pref[K][EPL];
+  // forward prefixes: thread-local inclusive scan and wave scan
+  FT loc[K][EPL];
+  FT fincl[K];
   if (A::NEEDS_PREFIX) {
-    FT loc[K][EPL];
-    FT agg[K];
 #pragma unroll
     for (int g = 0; g < K; ++g) {
       FT acc = Io::elem(in[g], 0);
@@ -217,38 +200,36 @@ __global__ __launch_bounds__(BLOCK) void k_scan_vjp(ScanVjpArgs a) {
         acc = Op::comb(acc, Io::elem(in[g], j));
         loc[g][j] = acc;
       }
-      agg[g] = acc;
+      fincl[g] = wave_scan_fwd<Op>(acc);
+      if (lane == WAVE - 1) s_ftot[g][wave] = fincl[g];
     }
-    FT incl[K];
+  }
+  // the forward prefix rs_{i-1} of slot j of group g, given the thread's
+  // exclusive prefix
+  auto prefix = [&](int g, int j, const FT &thr) -> FT {
+    return j == 0 ? thr : Op::comb(thr, loc[g][j - 1]);
+  };
+
+  __syncthreads();
+  FT thr_f[K];
+  if (A::NEEDS_PREFIX) {
+    if (wave == 0) {
+      FT carry;
 #pragma unroll
-    for (int g = 0; g < K; ++g) {
-      incl[g] = wave_scan_fwd<Op>(agg[g]);
-      if (lane == WAVE - 1) s_wf[g][wave] = incl[g];
+      for (int i = 0; i < N; ++i) carry.f[i] = a.saved[ti.tile * N + i];
+      wave0_block_prefix<Op, K, W, false>(s_ftot, s_fpre, carry);
     }
     __syncthreads();
-    FT carry;
-#pragma unroll
-    for (int i = 0; i < N; ++i) carry.f[i] = a.saved[ti.tile * N + i];
-    FT run = carry;
 #pragma unroll
     for (int g = 0; g < K; ++g) {
-      FT pre = run;
-#pragma unroll
-      for (int w = 0; w < WAVES; ++w) {
-        if (w == wave) pre = run;
-        run = Op::comb(run, s_wf[g][w]);
-      }
-      FT ex = shfl_up(incl[g], 1);
+      FT ex = shfl_up(fincl[g], 1);
       if (lane == 0) ex = Op::id();
-      const FT full = Op::comb(pre, ex);
-      pref[g][0] = full;
-#pragma unroll
-      for (int j = 1; j < EPL; ++j) pref[g][j] = Op::comb(full, loc[g][j - 1]);
+      thr_f[g] = Op::comb(s_fpre[g][wave], ex);
     }
   }
 
   // adjoint maps: thread aggregate per group = h_0 o h_1 o ... o h_{EPL-1}
-  MT tagg[K];
+  MT mincl[K];
 #pragma unroll
   for (int g = 0; g < K; ++g) {
     MT acc = M::id();
@@ -263,63 +244,45 @@ __global__ __launch_bounds__(BLOCK) void k_scan_vjp(ScanVjpArgs a) {
       }
       const bool first = ti.lt == 0 && g == 0 && tid == 0 && j == 0;
       const FT x = Io::elem(in[g], j);
-      const FT p = A::NEEDS_PREFIX ? pref[g][j] : Op::id();
+      const FT p = A::NEEDS_PREFIX ? prefix(g, j, thr_f[g]) : Op::id();
       const MT h = A::make(p, x, yb, first);
       acc = (j == EPL - 1) ? h : M::comb(acc, h);
     }
-    tagg[g] = acc;
-  }
-
-  MT incl[K];
-#pragma unroll
-  for (int g = 0; g < K; ++g) {
-    incl[g] = wave_scan_rev<M>(tagg[g]);
-    if (lane == 0) s_wm[g][wave] = incl[g];
+    mincl[g] = wave_scan_rev<M>(acc);
+    if (lane == 0) s_mtot[g][wave] = mincl[g];
   }
   __syncthreads();
-  MT pre[K];
-  MT run = M::id();
-#pragma unroll
-  for (int g = K - 1; g >= 0; --g)
-#pragma unroll
-    for (int w = WAVES - 1; w >= 0; --w) {
-      if (w == wave) pre[g] = run;
-      run = M::comb(run, s_wm[g][w]);
-    }
-  const MT tile_agg = run;
+  const uint32_t tag = s_epoch + 1;
 
-  // right-to-left look-back: successors sit at tile+1, tile+2, ...
-  uint64_t *st = a.status + ti.tile * (M::NA + M::NP);
-  const int dist_max = a.tpr - 1 - ti.lt;
-  MT carry;
-  {
+  if (wave == 0) {
+    const MT tile_agg = wave0_block_prefix<M, K, W, true>(s_mtot, s_mpre, M::id());
+    uint64_t *st = a.status + ti.tile * (M::NA + M::NP);
+    const int dist_max = a.tpr - 1 - ti.lt;
     typename M::P zero;
 #pragma unroll
     for (int i = 0; i < M::NP; ++i) zero.f[i] = 0.0f;
-    carry = M::from_pre(zero);
-  }
-  if (dist_max == 0) {
-    if (tid == 0) publish<M::NP>(st + M::NA, tag, M::apply0(M::comb(carry, tile_agg)));
-  } else {
-    if (tid == 0) publish<M::NA>(st, tag, tile_agg);
-    if (wave == 0) {
-      const MT c = lookback<M>(a.status, ti.tile, -1, dist_max, tag, a.ctl);
-      if (lane == 0) {
-        publish<M::NP>(st + M::NA, tag, M::apply0(M::comb(c, tile_agg)));
-        s_carry = c;
-      }
+    MT c = M::from_pre(zero);
+    if (dist_max == 0) {
+      if (lane == 0) publish<M::NP>(st + M::NA, tag, M::apply0(M::comb(c, tile_agg)));
+    } else {
+      if (lane == 0) publish<M::NA>(st, tag, tile_agg);
+      c = lookback<M>(a.status, ti.tile, -1, dist_max, tag, a.ctl);
+      if (lane == 0) publish<M::NP>(st + M::NA, tag, M::apply0(M::comb(c, tile_agg)));
     }
-    __syncthreads();
-    carry = s_carry;
+    if (lane == 0) {
+      s_carry = c;
+      if (ti.lt == 0) ctl_row_done(a.ctl, gridDim.x / a.tpr, tag);
+    }
   }
-  if (tid == 0 && ti.lt == 0) ctl_row_done(a.ctl, gridDim.x / a.tpr, tag);
+  __syncthreads();
+  const MT carry = s_carry;
 
   // thread-serial sweep, right to left
 #pragma unroll
   for (int g = 0; g < K; ++g) {
-    MT ex = shfl_down(incl[g], 1);
+    MT ex = shfl_down(mincl[g], 1);
     if (lane == WAVE - 1) ex = M::id();
-    typename M::P rho = M::apply0(M::comb(M::comb(carry, pre[g]), ex));
+    typename M::P rho = M::apply0(M::comb(M::comb(carry, s_mpre[g][wave]), ex));
     float4 o[2];
     o[0] = make_float4(0, 0, 0, 0);
     o[1] = make_float4(0, 0, 0, 0);
@@ -334,7 +297,7 @@ __global__ __launch_bounds__(BLOCK) void k_scan_vjp(ScanVjpArgs a) {
       }
       const bool first = ti.lt == 0 && g == 0 && tid == 0 && j == 0;
       const FT x = Io::elem(in[g], j);
-      const FT p = A::NEEDS_PREFIX ? pref[g][j] : Op::id();
+      const FT p = A::NEEDS_PREFIX ? prefix(g, j, thr_f[g]) : Op::id();
       float xb[4];
       A::step(p, x, yb, first, rho, xb);
       if (S == 4) {
@@ -344,7 +307,7 @@ __global__ __launch_bounds__(BLOCK) void k_scan_vjp(ScanVjpArgs a) {
         if (A::NXB == 2) f4set(o[1], j, xb[1]);
       }
     }
-    const int el = g * BLOCK * EPL + tid * EPL;
+    const int el = g * TH * EPL + tid * EPL;
     const int v = ti.valid - el;
     float *dst[2] = {a.xb0, a.xb1};
 #pragma unroll
@@ -357,7 +320,6 @@ __global__ __launch_bounds__(BLOCK) void k_scan_vjp(ScanVjpArgs a) {
       store_group<S>(dst[s], ti.base + el, v, ti.vec_ok, val);
     }
   }
-
 }
 
 // ---------------------------------------------------------------------------
@@ -396,13 +358,13 @@ int scan_status_words(int op, bool abar) {
 
 template <int OP, bool REDUCE>
 static hipError_t launch_fwd(const ScanFwdArgs &a, int64_t tiles, hipStream_t s) {
-  hipLaunchKernelGGL((k_scan_fwd<OP, REDUCE>), dim3((unsigned)tiles), dim3(BLOCK), 0, s, a);
+  hipLaunchKernelGGL((k_scan_fwd<OP, REDUCE>), dim3((unsigned)tiles), dim3(Shape<OP>::THREADS), 0, s, a);
   return hipGetLastError();
 }
 
 template <int OP, bool ABAR>
 static hipError_t launch_vjp(const ScanVjpArgs &a, int64_t tiles, hipStream_t s) {
-  hipLaunchKernelGGL((k_scan_vjp<OP, ABAR>), dim3((unsigned)tiles), dim3(BLOCK), 0, s, a);
+  hipLaunchKernelGGL((k_scan_vjp<OP, ABAR>), dim3((unsigned)tiles), dim3(Shape<OP>::THREADS), 0, s, a);
   return hipGetLastError();
 }
 

@@ -51,11 +51,11 @@ def q(L, comb, op, batch, n, m=0, flags=0):
 
 
 def test_query(L):
-    # scan of + over 10000 elements: 3 tiles of 4096, one float saved per tile
-    st, s, w = q(L, 1, 0, 1, 10000)
+    # scan of + over 20000 elements: 3 tiles of 8192, one float saved per tile
+    st, s, w = q(L, 1, 0, 1, 20000)
     assert st == 0 and s == 3 * 4 and w >= 256 + 3 * 2 * 8
     # linrec: 2 floats per tile; status words for the adjoint with A_bar (5)
-    st, s, w = q(L, 1, 4, 2, 4096)
+    st, s, w = q(L, 1, 4, 2, 8192)
     assert st == 0 and s == 2 * 2 * 4 and w >= 256 + 2 * 5 * 8
     # reduce *: (n0, y_pos) per row
     assert q(L, 0, 1, 5, 100)[:2] == (0, 40)
