@@ -340,6 +340,21 @@ __device__ __forceinline__ void publish(uint64_t *w, uint32_t tag, const Vec<N> 
   for (int i = 0; i < N; ++i) put_word(w + i, tag, v.f[i]);
 }
 
+__device__ __forceinline__ uint64_t load_word(const uint64_t *w) {
+  return __hip_atomic_load(const_cast<uint64_t *>(w), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int N>
+__device__ __forceinline__ bool decode_words(const uint64_t (&u)[N], uint32_t tag, Vec<N> &v) {
+  bool ok = true;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    ok = ok && ((uint32_t)(u[i] >> 32) == tag);
+    v.f[i] = __uint_as_float((uint32_t)u[i]);
+  }
+  return ok;
+}
+
 template <int N>
 __device__ __forceinline__ bool read_words(const uint64_t *w, uint32_t tag, Vec<N> &v) {
   bool ok = true;
@@ -429,12 +444,24 @@ __device__ typename Tr::T lookback(const uint64_t *st, int64_t tile, int dir, in
     }
     int plane = WAVE, pq = Q;
     for (int spin = 0;; ++spin) {
+      // one round trip per poll: every status word of every pending
+      // position is requested before any of them is examined
+      uint64_t wp[Q][NP], wa[Q][NA];
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
         if (state[q] < 2) {
           const uint64_t *w = st + (tile - (int64_t)dir * (base + lane * Q + q + 1)) * NW;
-          if (read_words<NP>(w + NA, tag, pre[q])) state[q] = 2;
-          else if (read_words<NA>(w, tag, agg[q])) state[q] = 1;
+#pragma unroll
+          for (int i = 0; i < NP; ++i) wp[q][i] = load_word(w + NA + i);
+#pragma unroll
+          for (int i = 0; i < NA; ++i) wa[q][i] = load_word(w + i);
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        if (state[q] < 2) {
+          if (decode_words<NP>(wp[q], tag, pre[q])) state[q] = 2;
+          else if (decode_words<NA>(wa[q], tag, agg[q])) state[q] = 1;
         }
       }
       int myq = Q;
