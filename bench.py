@@ -6,6 +6,9 @@ A step is one pass of the hot path over one batch of synthetic input that is
 already resident in HBM: the forward and the adjoint.  Prints one JSON line.
 
 Workloads:
+  segmented -- 4096 instances (lognormal lengths, median 4096, total about
+             2^26): linear-recurrence scan -> min-by-index into 512 bins,
+             forward + adjoint, each phase one hipGraph launch (default).
   linrec  -- linear-recurrence scan y_i = a_i y_{i-1} + b_i, n = 2^26, fp32,
              forward + adjoint w.r.t. a and b.
   mat2    -- 2x2 matrix-product scan, n = 2^24, entries ~ N(0, 0.5).
@@ -99,6 +102,95 @@ def bench_mat2(args, pcad, torch, np):
                      "n": n, "op": "mat2", "combinator": "scan"})
 
 
+def bench_segmented(args, pcad, torch, np):
+    """4096 instances of lognormal length (median 4096, total about 2^26):
+    linear-recurrence scan -> min-by-index into 512 bins, forward and
+    adjoint, each phase one hipGraph launch."""
+    from workloads import segmented
+    w = segmented(S=args.segments)
+    plan = pcad.BatchedPlan(w["offsets"], w["m"], per_segment=True)
+    plan.load(a=w["a"], b=w["b"], idx=w["idx"], ybar=w["ybar"], hbar=w["hbar"])
+    N, S, m = plan.n, plan.nseg, plan.m
+
+    def fwd():
+        plan.run(pcad.PHASE_FWD)
+        return None, None, None
+
+    def bwd(_saved):
+        plan.run(pcad.PHASE_BWD)
+
+    return dict(n=N, fwd=fwd, bwd=bwd, plan=plan, inputs=w,
+                # forward reads a, b, idx and writes y (+ h, argk per bin);
+                # adjoint reads a, b, y_bar, idx and writes a_bar, b_bar (+ argk,
+                # h_bar per bin); forward prefixes are recomputed, not stored
+                bytes_fwd=16 * N + 8 * S * m, bytes_bwd=24 * N + 8 * S * m,
+                kernel="k_seg_bwd", out=lambda: (plan.abar[:N], plan.bbar[:N]),
+                cfg={"workload": f"segmented: {S} instances, lognormal lengths (median 4096, cap 2^20), "
+                                 f"linrec scan -> min-by-index into {m} bins, fwd+adjoint, fp32",
+                     "instances": S, "elements": N, "bins": m, "work_items": plan.n_items,
+                     "combinator": "scan+reduce_by_index", "op": "linrec+min"})
+
+
+def segmented_extras(b, torch, np, reps=3):
+    """Single-launch (forward+adjoint) graph time and the per-instance
+    plain-call baseline on the same buffers."""
+    import paper_2310_03568_amd as pcad
+    plan = b["plan"]
+    out = {}
+    for name, fn in (("both_graph", lambda: plan.run(pcad.PHASE_BOTH)),
+                     ("per_segment_fwd", lambda: plan.run_per_segment(pcad.PHASE_FWD)),
+                     ("per_segment_bwd", lambda: plan.run_per_segment(pcad.PHASE_BWD))):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        out[name + "_ms"] = e0.elapsed_time(e1) / reps
+    return out
+
+
+def segmented_parity(b, torch, np):
+    """Oracle (fp64, one thread) on the whole workload: times the adjoint
+    (cpu_baseline) and gates the GPU forward and adjoint.  The adjoint is
+    re-run with the oracle's argmin decision in argk."""
+    import oracle
+    import paper_2310_03568_amd as pcad
+    from oracle.gate import gate
+    w, plan = b["inputs"], b["plan"]
+    N, S, m = plan.n, plan.nseg, plan.m
+    plan.run(pcad.PHASE_FWD)
+    torch.cuda.synchronize()
+    y = plan.y[:N].cpu().numpy()
+    argk = plan.argk.cpu().numpy().reshape(S, m)
+    t0 = time.perf_counter()
+    f = oracle.segmented_fwd(w["offsets"], w["a"], w["b"], w["idx"], m)
+    tf = time.perf_counter() - t0
+    ry = gate(y, f["y"], f["cy"], 1e-4)
+    mism = int((argk != f["argk"]).sum())
+    plan.argk.copy_(torch.from_numpy(f["argk"].reshape(-1).astype(np.int32)))
+    plan.run(pcad.PHASE_BWD)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ab, bb, cab, cbb = oracle.segmented_vjp(w["offsets"], w["a"], w["b"], w["idx"], m,
+                                            w["ybar"], w["hbar"], f["argk"])
+    tb = time.perf_counter() - t0
+    ra = gate(plan.abar[:N].cpu().numpy(), ab, cab, 1e-4)
+    rb = gate(plan.bbar[:N].cpu().numpy(), bb, cbb, 1e-4)
+    ok = ry["ok"] and ra["ok"] and rb["ok"] and (ry["n_range_exceeded"] + ra["n_range_exceeded"]
+                                                   + rb["n_range_exceeded"]) == 0
+    par = dict(ok=ok, y_max_rel=ry["max_rel"], a_max_rel=ra["max_rel"], b_max_rel=rb["max_rel"],
+               normwise_a=ra["normwise"], normwise_b=rb["normwise"],
+               argk_mismatch_bins=mism, range_exceeded=ry["n_range_exceeded"] + ra["n_range_exceeded"]
+               + rb["n_range_exceeded"])
+    cpu = {"value": N / tb, "unit": "elem/s", "cores": 1, "kind": "oracle",
+           "sample": f"whole workload ({S} instances, {N} elements): oracle adjoint incl. its "
+                     f"forward re-execution {tb:.2f} s (forward alone {tf:.2f} s), fp64"}
+    return cpu, par
+
+
 def cpu_baseline_and_parity(name, b, np):
     """Times the oracle (fp64, one thread) on the same inputs and gates the
     GPU outputs against it."""
@@ -136,9 +228,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="linrec", choices=["linrec", "mat2"])
+    ap.add_argument("--workload", default="segmented", choices=["segmented", "linrec", "mat2"])
+    ap.add_argument("--segments", type=int, default=4096, help="instances of the segmented workload")
     ap.add_argument("--n", type=int, default=0, help="override the element count")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="after the timed region, run a plain 256 MiB device copy 3 times "
+                         "(reference for scaling the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
@@ -150,7 +246,8 @@ def main():
     import paper_2310_03568_amd as pcad
 
     pcad.lib()
-    b = {"linrec": bench_linrec, "mat2": bench_mat2}[args.workload](args, pcad, torch, np)
+    b = {"linrec": bench_linrec, "mat2": bench_mat2,
+         "segmented": bench_segmented}[args.workload](args, pcad, torch, np)
     torch.cuda.synchronize()
 
     for _ in range(args.warmup):
@@ -179,9 +276,23 @@ def main():
     tf = float(t_fwd.mean())
     achieved = b["bytes_bwd"] / tb / 1e9
 
+    if args.calib_copy:
+        src = torch.empty(1 << 26, dtype=torch.float32, device="cuda:0").fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    extras = {}
+    if args.workload == "segmented":
+        extras = segmented_extras(b, torch, np)
     cpu, par = (None, None)
     if not args.no_cpu:
-        cpu, par = cpu_baseline_and_parity(args.workload, b, np)
+        if args.workload == "segmented":
+            cpu, par = segmented_parity(b, torch, np)
+        else:
+            cpu, par = cpu_baseline_and_parity(args.workload, b, np)
 
     out = {
         "metric": METRIC,
@@ -207,7 +318,11 @@ def main():
         "fwd_GBs": b["bytes_fwd"] / tf / 1e9,
         "bwd_ci95_ms": 1.96 * float(t_bwd.std(ddof=1)) / np.sqrt(len(t_bwd)) * 1e3 if len(t_bwd) > 1 else 0.0,
         "parity": par,
+        **extras,
     }
+    if "per_segment_bwd_ms" in extras:
+        out["per_segment_bwd_elem_s"] = n / (extras["per_segment_bwd_ms"] * 1e-3)
+        out["batched_over_per_segment_bwd"] = extras["per_segment_bwd_ms"] / (tb * 1e3)
     print(json.dumps(out), flush=True)
 
 

@@ -168,12 +168,12 @@ int pcad_scan_vjp(int op, int64_t batch, int64_t n, const float *x0, const float
  * histogram; the caller combines an initial histogram itself).
  * Supported operators: ADD, MUL, MIN, MAX.  m >= 0, m <= 2^26.
  *   hist: batch*m floats.
- *   saved layout (per row, m entries each):
+ *   saved layout (arrays of batch*m entries, bin k of row r at r*m + k):
  *     ADD    : nothing;
- *     MUL    : {uint32 n0[m]; float y_pos[m]} (zero count and product of
- *              non-zeros per bin, Section 4.2 Multiplication);
- *     MIN/MAX: {int32 argk[m]} lowest index of the bin's extremum, n when
- *              the bin is empty (Section 4.2 Min/Max rule figure).
+ *     MUL    : uint32 n0[batch*m], then float y_pos[batch*m] (zero count and
+ *              product of the non-zeros per bin, Section 4.2 Multiplication);
+ *     MIN/MAX: int32 argk[batch*m], the lowest index of the bin's extremum,
+ *              n when the bin is empty (Section 4.2 Min/Max rule figure).
  */
 int pcad_rbi_fwd(int op, int64_t batch, int64_t n, int64_t m, const int32_t *idx,
                  const float *v, float *hist, void *saved, unsigned flags, void *ws,
@@ -190,6 +190,56 @@ int pcad_rbi_fwd(int op, int64_t batch, int64_t n, int64_t m, const int32_t *idx
 int pcad_rbi_vjp(int op, int64_t batch, int64_t n, int64_t m, const int32_t *idx,
                  const float *v, const void *saved, const float *hbar, float *vbar,
                  unsigned flags, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Batched segmented plan: many independent instances of ragged length, each
+ *   y_s = linear-recurrence scan of (a_s, b_s)            (Section 5)
+ *   (h_s, argk_s) = reduce_by_index(min) of y_s into m bins with keys idx_s
+ *                                                          (Section 4)
+ * and their adjoint given y_bar (per element) and h_bar (per instance and
+ * bin): the min-by-index adjoint (Section 4.2 Min/Max) adds h_bar[s,k] at
+ * y position argk[s,k], and the sum feeds the scan adjoint (Section 5.2).
+ * The forward and the adjoint run as persistent look-back kernels over
+ * (instance, tile) work items, captured in hipGraphs at bind time; every
+ * run is one hipGraphLaunch.
+ *
+ *   offsets: HOST array of nseg+1 int64 element offsets (offsets[0] = 0,
+ *            non-decreasing); instance s is [offsets[s], offsets[s+1]).
+ *   m:       bins per instance, 1 <= m <= 4096.
+ *   flags:   PCAD_PLAN_PER_SEGMENT also sizes the workspace for
+ *            pcad_plan_run_per_segment (the same work as plain per-instance
+ *            calls, for comparison).
+ * Layouts (device): a, b, idx, y, y_bar, a_bar, b_bar: N = offsets[nseg]
+ * elements; h, argk, h_bar: nseg*m, row-major by instance.  argk is the
+ * instance-relative lowest index of the bin minimum, the instance length for
+ * an empty bin; h is +inf there.  The adjoint reads argk, so a caller may
+ * replace it between the two phases.  Keys outside [0,m) are ignored.
+ * The plan owns host state and graphs only; the caller owns `saved` and
+ * `ws` (sizes from pcad_plan_query; ws zero-filled before first use) and
+ * all buffers, which stay bound until the next pcad_plan_bind.
+ */
+enum { PCAD_PLAN_PER_SEGMENT = 1u << 0 };
+enum { PCAD_PHASE_FWD = 1, PCAD_PHASE_BWD = 2, PCAD_PHASE_BOTH = 3 };
+
+typedef struct pcad_plan pcad_plan;
+
+int pcad_plan_create(pcad_plan **plan, int64_t nseg, const int64_t *offsets, int64_t m,
+                     unsigned flags);
+int pcad_plan_query(const pcad_plan *plan, size_t *saved_bytes, size_t *workspace_bytes,
+                    int64_t *n_elements, int64_t *n_items);
+/* Uploads the plan's tables into ws, resets its merge keys, captures the
+ * graphs on `stream`; synchronises `stream` once. */
+int pcad_plan_bind(pcad_plan *plan, const float *a, const float *b, const int32_t *idx,
+                   float *y, float *h, int32_t *argk, const float *ybar, const float *hbar,
+                   float *abar, float *bbar, void *saved, void *ws, size_t ws_bytes,
+                   void *stream);
+/* phase: PCAD_PHASE_FWD, PCAD_PHASE_BWD or PCAD_PHASE_BOTH; one graph launch. */
+int pcad_plan_run(pcad_plan *plan, int phase, void *stream);
+/* The same results through plain per-instance calls of this library (scan,
+ * reduce_by_index and their adjoints, one instance after the other). */
+int pcad_plan_run_per_segment(pcad_plan *plan, int phase, void *stream);
+void pcad_plan_destroy(pcad_plan *plan);
+int pcad_plan_last_hip_error(void);
 
 #ifdef __cplusplus
 }

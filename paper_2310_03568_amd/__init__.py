@@ -58,6 +58,13 @@ def lib():
             "pcad_scan_vjp": ([I, I64, I64, P, P, P, P, P, P, P, U, P, SZ, P], I),
             "pcad_rbi_fwd": ([I, I64, I64, I64, P, P, P, P, U, P, SZ, P], I),
             "pcad_rbi_vjp": ([I, I64, I64, I64, P, P, P, P, P, U, P, SZ, P], I),
+            "pcad_plan_create": ([ctypes.POINTER(P), I64, P, I64, U], I),
+            "pcad_plan_query": ([P, PSZ, PSZ, ctypes.POINTER(I64), ctypes.POINTER(I64)], I),
+            "pcad_plan_bind": ([P, P, P, P, P, P, P, P, P, P, P, P, P, SZ, P], I),
+            "pcad_plan_run": ([P, I, P], I),
+            "pcad_plan_run_per_segment": ([P, I, P], I),
+            "pcad_plan_destroy": ([P], None),
+            "pcad_plan_last_hip_error": ([], I),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -252,3 +259,93 @@ def saved_mul(saved: torch.Tensor, batch: int, m: int):
     n0 = saved[: batch * m * 4].view(torch.int32).view(batch, m)
     yp = saved[batch * m * 4: batch * m * 8].view(torch.float32).view(batch, m)
     return n0, yp
+
+
+# ---------------------------------------------------------------------------
+# batched segmented plan
+# ---------------------------------------------------------------------------
+PHASE_FWD, PHASE_BWD, PHASE_BOTH = 1, 2, 3
+PLAN_PER_SEGMENT = 1
+
+
+class BatchedPlan:
+    """Many ragged instances of (linear-recurrence scan -> min-by-index into
+    m bins), forward and adjoint, each phase one hipGraph launch.
+
+    ``offsets``: host int64 array of nseg+1 element offsets.  Buffers are
+    allocated here (torch, on ``device``) and bound once; inputs are copied
+    into them with :meth:`load`.
+    """
+
+    def __init__(self, offsets, m: int, device=None, per_segment: bool = False):
+        import numpy as np
+        self.device = torch.device(device or "cuda:0")
+        off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+        self.offsets = off
+        self.nseg = off.shape[0] - 1
+        self.m = int(m)
+        h = ctypes.c_void_p()
+        check(lib().pcad_plan_create(ctypes.byref(h), self.nseg, off.ctypes.data, self.m,
+                                     PLAN_PER_SEGMENT if per_segment else 0), "pcad_plan_create")
+        self._h = h
+        s, w = ctypes.c_size_t(0), ctypes.c_size_t(0)
+        n, it = ctypes.c_int64(0), ctypes.c_int64(0)
+        check(lib().pcad_plan_query(h, ctypes.byref(s), ctypes.byref(w), ctypes.byref(n),
+                                    ctypes.byref(it)), "pcad_plan_query")
+        self.saved_bytes, self.ws_bytes, self.n, self.n_items = s.value, w.value, n.value, it.value
+        dev, N, S, m = self.device, self.n, self.nseg, self.m
+        f32 = dict(dtype=torch.float32, device=dev)
+        self.a = torch.empty(max(N, 4), **f32)
+        self.b = torch.empty(max(N, 4), **f32)
+        self.idx = torch.empty(max(N, 4), dtype=torch.int32, device=dev)
+        self.y = torch.empty(max(N, 4), **f32)
+        self.ybar = torch.empty(max(N, 4), **f32)
+        self.abar = torch.empty(max(N, 4), **f32)
+        self.bbar = torch.empty(max(N, 4), **f32)
+        self.h = torch.empty(S * m, **f32)
+        self.hbar = torch.empty(S * m, **f32)
+        self.argk = torch.empty(S * m, dtype=torch.int32, device=dev)
+        self.saved = torch.empty(max(self.saved_bytes, 256), dtype=torch.uint8, device=dev)
+        self.ws = torch.zeros(max(self.ws_bytes, 256), dtype=torch.uint8, device=dev)
+        st = torch.cuda.current_stream(dev).cuda_stream
+        check(lib().pcad_plan_bind(h, self.a.data_ptr(), self.b.data_ptr(), self.idx.data_ptr(),
+                                   self.y.data_ptr(), self.h.data_ptr(), self.argk.data_ptr(),
+                                   self.ybar.data_ptr(), self.hbar.data_ptr(),
+                                   self.abar.data_ptr(), self.bbar.data_ptr(),
+                                   self.saved.data_ptr(), self.ws.data_ptr(), self.ws.numel(), st),
+              "pcad_plan_bind")
+
+    def load(self, a=None, b=None, idx=None, ybar=None, hbar=None):
+        """Copy host or device arrays into the bound input buffers."""
+        for name, v in (("a", a), ("b", b), ("idx", idx), ("ybar", ybar), ("hbar", hbar)):
+            if v is None:
+                continue
+            t = torch.as_tensor(v)
+            dst = getattr(self, name)
+            dst[: t.numel()].copy_(t.reshape(-1).to(dst.dtype), non_blocking=False)
+
+    def run(self, phase: int = PHASE_BOTH):
+        st = torch.cuda.current_stream(self.device).cuda_stream
+        r = lib().pcad_plan_run(self._h, phase, st)
+        if r != 0:
+            raise PcadError(f"pcad_plan_run: status {r}, hip {lib().pcad_plan_last_hip_error()}")
+
+    def run_per_segment(self, phase: int = PHASE_BOTH):
+        st = torch.cuda.current_stream(self.device).cuda_stream
+        r = lib().pcad_plan_run_per_segment(self._h, phase, st)
+        if r != 0:
+            raise PcadError(f"pcad_plan_run_per_segment: status {r}, hip {lib().pcad_plan_last_hip_error()}")
+
+    def ws_error(self) -> int:
+        return int(self.ws[:16].view(torch.int32)[2].item())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().pcad_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -6,22 +6,28 @@
 #include "../../include/pcad.h"
 #include "internal.hpp"
 
+namespace pcad {
+
+thread_local int g_last_hip = 0;
+
+// records a failed HIP call for pcad_last_hip_error
+int hip_status(hipError_t e) {
+  if (e == hipSuccess) return PCAD_OK;
+  g_last_hip = (int)e;
+  return PCAD_E_HIP;
+}
+
+}  // namespace pcad
+
 using namespace pcad;
 
 namespace {
-
-thread_local int g_last_hip = 0;
 
 constexpr int64_t kMaxN = 2147483647LL;
 constexpr int64_t kMaxTotal = 1LL << 40;
 constexpr int64_t kMaxBins = 1LL << 26;
 constexpr unsigned kKnownFlags = PCAD_ACCUMULATE;
 
-int hip_status(hipError_t e) {
-  if (e == hipSuccess) return PCAD_OK;
-  g_last_hip = (int)e;
-  return PCAD_E_HIP;
-}
 
 bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 

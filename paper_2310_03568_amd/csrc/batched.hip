@@ -1,0 +1,685 @@
+// Batched segmented forward and adjoint of a chained workload: for every
+// instance s of a ragged batch,
+//   y_s = scan of (a_s, b_s) under linear-function composition
+//         (y_i = a_i*y_{i-1} + b_i),
+//   (h_s, argk_s) = reduce_by_index(min) of y_s into m bins with keys idx_s,
+// and the adjoint of both: y_bar_total = y_bar + onehot(h_bar at argk) fed to
+// the scan adjoint (Section 5.2), with the min-by-index adjoint
+// (Section 4.2 Min/Max) fused in.
+//
+// Work items are windows of SEG_T elements aligned to multiples of SEG_T in
+// the concatenated array and clipped to an instance, so 16-byte accesses stay
+// aligned whatever the instance offsets are.  Items run in dispatch order;
+// each instance carries its own look-back chain over its items.  A forward
+// item folds its outputs into an LDS sub-histogram of 64-bit (ord(y), index)
+// keys; an instance with one item finalises h/argk itself, longer instances
+// merge their keys with 64-bit atomic min and a small pass finalises them
+// (and resets the keys for the next launch).
+#include <algorithm>
+#include <vector>
+
+#include "../../include/pcad.h"
+#include "adjoint.hpp"
+#include "internal.hpp"
+
+namespace pcad {
+
+constexpr int SEG_TH = 1024;
+constexpr int SEG_K = 2;
+constexpr int SEG_EPL = 4;
+constexpr int SEG_W = SEG_TH / WAVE;
+constexpr int SEG_T = SEG_TH * SEG_EPL * SEG_K;
+constexpr int SEG_MAX_BINS = 4096;
+
+struct SegTables {
+  const int32_t *item_seg;   // [nitems] instance of each item
+  const int64_t *seg_off;    // [S+1] element offsets
+  const int32_t *seg_item0;  // [S+1] first item of each instance
+};
+
+struct SegItem {
+  int64_t s;
+  int li, nli;           // item index within the instance, items of the instance
+  int64_t wbase;         // first element of the aligned window
+  int64_t lo, hi;        // elements of the instance inside the window
+  int64_t start, len;    // the instance
+};
+
+__device__ __forceinline__ SegItem seg_item(const SegTables &t, int64_t item) {
+  SegItem r;
+  r.s = t.item_seg[item];
+  r.start = t.seg_off[r.s];
+  const int64_t en = t.seg_off[r.s + 1];
+  r.len = en - r.start;
+  const int i0 = t.seg_item0[r.s];
+  r.li = (int)(item - i0);
+  r.nli = t.seg_item0[r.s + 1] - i0;
+  r.wbase = (r.start / SEG_T + r.li) * (int64_t)SEG_T;
+  r.lo = r.start > r.wbase ? r.start : r.wbase;
+  r.hi = en < r.wbase + SEG_T ? en : r.wbase + SEG_T;
+  return r;
+}
+
+// elements [e, e+4) of which those in [lo, hi) are read; `fill` elsewhere
+__device__ __forceinline__ float4 ld_range(const float *__restrict__ p, int64_t e, int64_t lo,
+                                           int64_t hi, float fill) {
+  if (e >= lo && e + 4 <= hi) return *reinterpret_cast<const float4 *>(p + e);
+  float r[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) r[j] = (e + j >= lo && e + j < hi) ? p[e + j] : fill;
+  return make_float4(r[0], r[1], r[2], r[3]);
+}
+
+__device__ __forceinline__ int4 ld_range_i(const int32_t *__restrict__ p, int64_t e, int64_t lo,
+                                           int64_t hi) {
+  if (e >= lo && e + 4 <= hi) return *reinterpret_cast<const int4 *>(p + e);
+  int r[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) r[j] = (e + j >= lo && e + j < hi) ? p[e + j] : -1;
+  return make_int4(r[0], r[1], r[2], r[3]);
+}
+
+__device__ __forceinline__ void st_range(float *__restrict__ p, int64_t e, int64_t lo, int64_t hi,
+                                         float4 v) {
+  if (e >= lo && e + 4 <= hi) {
+    typedef float v4f __attribute__((ext_vector_type(4)));
+    v4f w = {v.x, v.y, v.z, v.w};
+    __builtin_nontemporal_store(w, reinterpret_cast<v4f *>(p + e));
+    return;
+  }
+  const float r[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+    if (e + j >= lo && e + j < hi) p[e + j] = r[j];
+}
+
+__device__ __forceinline__ int i4get(const int4 &v, int j) {
+  return j == 0 ? v.x : (j == 1 ? v.y : (j == 2 ? v.z : v.w));
+}
+
+// ---------------------------------------------------------------------------
+// forward
+// ---------------------------------------------------------------------------
+struct SegFwdArgs {
+  SegTables tab;
+  int S, m;
+  int nrows;           // instances with at least one element
+  const float *a, *b;
+  const int32_t *idx;
+  float *y, *h;
+  int32_t *argk;
+  float *carry;        // [nitems][2] exclusive prefix (A, y) of every item
+  uint64_t *keys;      // [S][m] merge keys of multi-item instances, ~0 between launches
+  Ctl *ctl;
+  uint64_t *status;
+};
+
+__global__ __launch_bounds__(SEG_TH) void k_seg_fwd(SegFwdArgs a) {
+  using Op = FwdLB<LINREC>;
+  using T = Op::T;
+  constexpr int K = SEG_K, EPL = SEG_EPL, W = SEG_W, TH = SEG_TH;
+
+  __shared__ T s_tot[K][W];
+  __shared__ T s_pre[K][W];
+  __shared__ T s_carry;
+  __shared__ unsigned s_epoch;
+  __shared__ unsigned long long s_keys[SEG_MAX_BINS];
+
+  const int tid = threadIdx.x, lane = lane_id(), wave = tid / WAVE;
+  if (tid == 0) s_epoch = ctl_load(&a.ctl->epoch);
+  const SegItem it = seg_item(a.tab, blockIdx.x);
+  for (int k = tid; k < a.m; k += TH) s_keys[k] = key_init<MIN>();
+
+  float4 av[K], bv[K];
+  int4 iv[K];
+#pragma unroll
+  for (int g = 0; g < K; ++g) {
+    const int64_t e = it.wbase + g * TH * EPL + tid * EPL;
+    av[g] = ld_range(a.a, e, it.lo, it.hi, 1.0f);
+    bv[g] = ld_range(a.b, e, it.lo, it.hi, 0.0f);
+    iv[g] = ld_range_i(a.idx, e, it.lo, it.hi);
+  }
+  T loc[K][EPL];
+  T incl[K];
+#pragma unroll
+  for (int g = 0; g < K; ++g) {
+    T acc = {{f4get(av[g], 0), f4get(bv[g], 0)}};
+    loc[g][0] = acc;
+#pragma unroll
+    for (int j = 1; j < EPL; ++j) {
+      acc = Op::comb(acc, T{{f4get(av[g], j), f4get(bv[g], j)}});
+      loc[g][j] = acc;
+    }
+    incl[g] = wave_scan_fwd<Op>(acc);
+    if (lane == WAVE - 1) s_tot[g][wave] = incl[g];
+  }
+  __syncthreads();
+  const uint32_t tag = s_epoch + 1;
+
+  if (wave == 0) {
+    const T tile_agg = wave0_block_prefix<Op, K, W, false>(s_tot, s_pre, Op::id());
+    uint64_t *st = a.status + (int64_t)blockIdx.x * (Op::NA + Op::NP);
+    T c = Op::id();
+    if (it.li == 0) {
+      if (lane == 0) publish<2>(st + Op::NA, tag, tile_agg);
+    } else {
+      if (lane == 0) publish<2>(st, tag, tile_agg);
+      c = lookback<Op>(a.status, blockIdx.x, +1, it.li, tag, a.ctl);
+      if (lane == 0) publish<2>(st + Op::NA, tag, Op::comb(c, tile_agg));
+    }
+    if (lane == 0) {
+      s_carry = c;
+      if (it.li == it.nli - 1) ctl_row_done(a.ctl, (unsigned)a.nrows, tag);
+      a.carry[(int64_t)blockIdx.x * 2 + 0] = c.f[0];
+      a.carry[(int64_t)blockIdx.x * 2 + 1] = c.f[1];
+    }
+  }
+  __syncthreads();
+  const T carry = s_carry;
+
+#pragma unroll
+  for (int g = 0; g < K; ++g) {
+    T ex = shfl_up(incl[g], 1);
+    if (lane == 0) ex = Op::id();
+    const T full = Op::comb(Op::comb(carry, s_pre[g][wave]), ex);
+    const int64_t e = it.wbase + g * TH * EPL + tid * EPL;
+    float4 o;
+#pragma unroll
+    for (int j = 0; j < EPL; ++j) {
+      const float yv = Op::comb(full, loc[g][j]).f[1];
+      f4set(o, j, yv);
+      const int k = i4get(iv[g], j);
+      if (k >= 0 && k < a.m)  // elements outside the instance carry key -1
+        atomicMin(&s_keys[k], (unsigned long long)key_of<MIN>(yv, (uint32_t)(e + j - it.start)));
+    }
+    st_range(a.y, e, it.lo, it.hi, o);
+  }
+  __syncthreads();
+
+  const int64_t hb = it.s * a.m;
+  if (it.nli == 1) {
+    // the item holds the whole instance: finalise directly
+    for (int k = tid; k < a.m; k += TH) {
+      const uint64_t key = s_keys[k];
+      if (key == key_init<MIN>()) {
+        a.h[hb + k] = __builtin_inff();
+        a.argk[hb + k] = (int32_t)it.len;
+      } else {
+        a.h[hb + k] = ord_inv((uint32_t)(key >> 32));
+        a.argk[hb + k] = (int32_t)(uint32_t)key;
+      }
+    }
+  } else {
+    for (int k = tid; k < a.m; k += TH) {
+      const unsigned long long key = s_keys[k];
+      if (key != key_init<MIN>())
+        __hip_atomic_fetch_min(reinterpret_cast<unsigned long long *>(&a.keys[hb + k]), key,
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
+// finalise the instances spanning several items; reset their keys
+__global__ __launch_bounds__(256) void k_seg_fin(SegFwdArgs a) {
+  const int64_t total = (int64_t)a.S * a.m;
+  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * 256) {
+    const int64_t s = t / a.m;
+    const int nli = a.tab.seg_item0[s + 1] - a.tab.seg_item0[s];
+    if (nli == 1) continue;  // finalised by its only item
+    if (nli == 0) {          // empty instance: neutral bin, sentinel 0
+      a.h[t] = __builtin_inff();
+      a.argk[t] = 0;
+      continue;
+    }
+    const uint64_t key = a.keys[t];
+    if (key == key_init<MIN>()) {
+      a.h[t] = __builtin_inff();
+      a.argk[t] = (int32_t)(a.tab.seg_off[s + 1] - a.tab.seg_off[s]);
+    } else {
+      a.h[t] = ord_inv((uint32_t)(key >> 32));
+      a.argk[t] = (int32_t)(uint32_t)key;
+      a.keys[t] = key_init<MIN>();
+    }
+  }
+}
+
+__global__ void k_fill_u64(uint64_t *p, int64_t n, uint64_t v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// adjoint
+// ---------------------------------------------------------------------------
+struct SegBwdArgs {
+  SegTables tab;
+  int64_t nitems;
+  int S, m;
+  int nrows;
+  const float *a, *b;
+  const int32_t *idx;
+  const float *carry;
+  const int32_t *argk;
+  const float *ybar, *hbar;
+  float *abar, *bbar;
+  Ctl *ctl;
+  uint64_t *status;
+};
+
+__global__ __launch_bounds__(SEG_TH) void k_seg_bwd(SegBwdArgs a) {
+  using Op = FwdLB<LINREC>;
+  using FT = Op::T;
+  using M = MapScal;
+  using MT = M::T;
+  constexpr int K = SEG_K, EPL = SEG_EPL, W = SEG_W, TH = SEG_TH;
+
+  __shared__ FT s_ftot[K][W];
+  __shared__ FT s_fpre[K][W];
+  __shared__ MT s_mtot[K][W];
+  __shared__ MT s_mpre[K][W];
+  __shared__ MT s_carry;
+  __shared__ unsigned s_epoch;
+  __shared__ int32_t s_ak[SEG_MAX_BINS];
+  __shared__ float s_hb[SEG_MAX_BINS];
+
+  const int tid = threadIdx.x, lane = lane_id(), wave = tid / WAVE;
+  if (tid == 0) s_epoch = ctl_load(&a.ctl->epoch);
+  const int64_t item = a.nitems - 1 - blockIdx.x;  // right to left
+  const SegItem it = seg_item(a.tab, item);
+  const int64_t hb = it.s * a.m;
+  for (int k = tid; k < a.m; k += TH) {
+    s_ak[k] = a.argk[hb + k];
+    s_hb[k] = a.hbar[hb + k];
+  }
+
+  float4 av[K], bv[K], yv[K];
+  int4 iv[K];
+#pragma unroll
+  for (int g = 0; g < K; ++g) {
+    const int64_t e = it.wbase + g * TH * EPL + tid * EPL;
+    av[g] = ld_range(a.a, e, it.lo, it.hi, 1.0f);
+    bv[g] = ld_range(a.b, e, it.lo, it.hi, 0.0f);
+    yv[g] = ld_range(a.ybar, e, it.lo, it.hi, 0.0f);
+    iv[g] = ld_range_i(a.idx, e, it.lo, it.hi);
+  }
+
+  // forward prefixes (A_{i-1}, y_{i-1}) recomputed from the saved item prefix
+  FT loc[K][EPL];
+  FT fincl[K];
+#pragma unroll
+  for (int g = 0; g < K; ++g) {
+    FT acc = {{f4get(av[g], 0), f4get(bv[g], 0)}};
+    loc[g][0] = acc;
+#pragma unroll
+    for (int j = 1; j < EPL; ++j) {
+      acc = Op::comb(acc, FT{{f4get(av[g], j), f4get(bv[g], j)}});
+      loc[g][j] = acc;
+    }
+    fincl[g] = wave_scan_fwd<Op>(acc);
+    if (lane == WAVE - 1) s_ftot[g][wave] = fincl[g];
+  }
+  __syncthreads();
+  if (wave == 0) {
+    const FT c = {{a.carry[item * 2 + 0], a.carry[item * 2 + 1]}};
+    wave0_block_prefix<Op, K, W, false>(s_ftot, s_fpre, c);
+  }
+  // y_bar_total = y_bar + h_bar at the bin's argmin (fused min-by-index adjoint)
+#pragma unroll
+  for (int g = 0; g < K; ++g) {
+    const int64_t e = it.wbase + g * TH * EPL + tid * EPL;
+#pragma unroll
+    for (int j = 0; j < EPL; ++j) {
+      const int k = i4get(iv[g], j);
+      if (k >= 0 && k < a.m && (int64_t)s_ak[k] == e + j - it.start)
+        f4set(yv[g], j, f4get(yv[g], j) + s_hb[k]);
+    }
+  }
+  __syncthreads();
+  FT thr_f[K];
+#pragma unroll
+  for (int g = 0; g < K; ++g) {
+    FT ex = shfl_up(fincl[g], 1);
+    if (lane == 0) ex = Op::id();
+    thr_f[g] = Op::comb(s_fpre[g][wave], ex);
+  }
+  auto prefix = [&](int g, int j) -> FT {
+    return j == 0 ? thr_f[g] : Op::comb(thr_f[g], loc[g][j - 1]);
+  };
+  using A = Adj<LINREC, false>;
+
+  MT mincl[K];
+#pragma unroll
+  for (int g = 0; g < K; ++g) {
+    MT acc = M::id();
+#pragma unroll
+    for (int j = EPL - 1; j >= 0; --j) {
+      const float yb[2] = {f4get(yv[g], j), 0.0f};
+      const MT hm = A::make(prefix(g, j), FT{{f4get(av[g], j), f4get(bv[g], j)}}, yb, false);
+      acc = (j == EPL - 1) ? hm : M::comb(acc, hm);
+    }
+    mincl[g] = wave_scan_rev<M>(acc);
+    if (lane == 0) s_mtot[g][wave] = mincl[g];
+  }
+  __syncthreads();
+  const uint32_t tag = s_epoch + 1;
+
+  if (wave == 0) {
+    const MT tile_agg = wave0_block_prefix<M, K, W, true>(s_mtot, s_mpre, M::id());
+    uint64_t *st = a.status + item * (M::NA + M::NP);
+    const int dist_max = it.nli - 1 - it.li;
+    MT c = M::from_pre(M::P{{0.0f}});
+    if (dist_max == 0) {
+      if (lane == 0) publish<M::NP>(st + M::NA, tag, M::apply0(M::comb(c, tile_agg)));
+    } else {
+      if (lane == 0) publish<M::NA>(st, tag, tile_agg);
+      c = lookback<M>(a.status, item, -1, dist_max, tag, a.ctl);
+      if (lane == 0) publish<M::NP>(st + M::NA, tag, M::apply0(M::comb(c, tile_agg)));
+    }
+    if (lane == 0) {
+      s_carry = c;
+      if (it.li == 0) ctl_row_done(a.ctl, (unsigned)a.nrows, tag);
+    }
+  }
+  __syncthreads();
+  const MT carry = s_carry;
+
+#pragma unroll
+  for (int g = 0; g < K; ++g) {
+    MT ex = shfl_down(mincl[g], 1);
+    if (lane == WAVE - 1) ex = M::id();
+    M::P rho = M::apply0(M::comb(M::comb(carry, s_mpre[g][wave]), ex));
+    float4 oa, ob;
+#pragma unroll
+    for (int j = EPL - 1; j >= 0; --j) {
+      const float yb[2] = {f4get(yv[g], j), 0.0f};
+      float xb[2];
+      A::step(prefix(g, j), FT{{f4get(av[g], j), f4get(bv[g], j)}}, yb, false, rho, xb);
+      f4set(oa, j, xb[0]);
+      f4set(ob, j, xb[1]);
+    }
+    const int64_t e = it.wbase + g * TH * EPL + tid * EPL;
+    st_range(a.abar, e, it.lo, it.hi, oa);
+    st_range(a.bbar, e, it.lo, it.hi, ob);
+  }
+}
+
+}  // namespace pcad
+
+// ---------------------------------------------------------------------------
+// plan (host)
+// ---------------------------------------------------------------------------
+using namespace pcad;
+
+struct pcad_plan {
+  int64_t S = 0, N = 0, m = 0, nitems = 0, nrows = 0;
+  unsigned flags = 0;
+  std::vector<int64_t> off;
+  std::vector<int32_t> item_seg, seg_item0;
+  // workspace layout
+  size_t ws_status = 0, ws_keys = 0, ws_tab = 0, ws_plain = 0, ws_bytes = 0;
+  size_t sv_carry = 0, sv_plain = 0, saved_bytes = 0;
+  size_t plain_ws_bytes = 0;
+  // bound buffers
+  bool bound = false;
+  const float *a = nullptr, *b = nullptr, *ybar = nullptr, *hbar = nullptr;
+  const int32_t *idx = nullptr;
+  float *y = nullptr, *h = nullptr, *abar = nullptr, *bbar = nullptr;
+  int32_t *argk = nullptr;
+  char *saved = nullptr, *ws = nullptr;
+  SegFwdArgs fa;
+  SegBwdArgs ba;
+  hipGraphExec_t g[4] = {nullptr, nullptr, nullptr, nullptr};
+  // graphs are captured on this private stream: the caller's stream may be
+  // the legacy null stream, which cannot be captured
+  hipStream_t cap = nullptr;
+};
+
+namespace {
+
+thread_local int g_plan_hip = 0;
+
+size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+int plan_hip(hipError_t e) {
+  if (e == hipSuccess) return PCAD_OK;
+  g_plan_hip = (int)e;
+  return hip_status(e);
+}
+
+hipError_t launch_fwd_nodes(pcad_plan *p, hipStream_t s) {
+  if (p->nitems > 0)
+    hipLaunchKernelGGL(k_seg_fwd, dim3((unsigned)p->nitems), dim3(SEG_TH), 0, s, p->fa);
+  hipLaunchKernelGGL(k_seg_fin, dim3(2048), dim3(256), 0, s, p->fa);
+  return hipGetLastError();
+}
+
+hipError_t launch_bwd_nodes(pcad_plan *p, hipStream_t s) {
+  if (p->nitems > 0)
+    hipLaunchKernelGGL(k_seg_bwd, dim3((unsigned)p->nitems), dim3(SEG_TH), 0, s, p->ba);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+extern "C" {
+
+int pcad_plan_create(pcad_plan **out, int64_t nseg, const int64_t *offsets, int64_t m,
+                     unsigned flags) {
+  if (!out || !offsets) return PCAD_E_NULLPTR;
+  *out = nullptr;
+  if (nseg < 1 || m < 1) return PCAD_E_INVALID_ARG;
+  if (m > SEG_MAX_BINS || nseg > (1 << 24)) return PCAD_E_SIZE;
+  if (flags & ~(unsigned)PCAD_PLAN_PER_SEGMENT) return PCAD_E_INVALID_ARG;
+  if (offsets[0] != 0) return PCAD_E_INVALID_ARG;
+  for (int64_t s = 0; s < nseg; ++s) {
+    if (offsets[s + 1] < offsets[s]) return PCAD_E_INVALID_ARG;
+    if (offsets[s + 1] - offsets[s] > 2147483647LL) return PCAD_E_SIZE;
+  }
+  if (offsets[nseg] > (1LL << 40)) return PCAD_E_SIZE;
+  pcad_plan *p = new pcad_plan();
+  p->S = nseg;
+  p->m = m;
+  p->flags = flags;
+  p->off.assign(offsets, offsets + nseg + 1);
+  p->N = offsets[nseg];
+  p->seg_item0.resize(nseg + 1);
+  int64_t items = 0;
+  for (int64_t s = 0; s < nseg; ++s) {
+    p->seg_item0[s] = (int32_t)items;
+    const int64_t st = offsets[s], en = offsets[s + 1];
+    if (en > st) {
+      items += (en - 1) / SEG_T - st / SEG_T + 1;
+      p->nrows++;
+    }
+    if (items > 2147483647LL) {
+      delete p;
+      return PCAD_E_SIZE;
+    }
+  }
+  p->seg_item0[nseg] = (int32_t)items;
+  p->nitems = items;
+  p->item_seg.resize(items > 0 ? items : 1);
+  for (int64_t s = 0; s < nseg; ++s)
+    for (int32_t i = p->seg_item0[s]; i < p->seg_item0[s + 1]; ++i) p->item_seg[i] = (int32_t)s;
+
+  // workspace: control block, status words, merge keys, tables, plain-path scratch
+  const int words = 4;  // linrec forward (2+2) and adjoint map (2+1) status words
+  size_t o = kCtlBytes;
+  p->ws_status = o;
+  o = align256(o + (size_t)(items > 0 ? items : 1) * words * sizeof(uint64_t));
+  p->ws_keys = o;
+  o = align256(o + (size_t)nseg * m * sizeof(uint64_t));
+  p->ws_tab = o;
+  o = align256(o + (size_t)p->item_seg.size() * 4 + (size_t)(nseg + 1) * 8 + (size_t)(nseg + 1) * 4 + 64);
+  p->ws_plain = o;
+  size_t sv = 0;
+  p->sv_carry = 0;
+  sv = align256((size_t)(items > 0 ? items : 1) * 2 * sizeof(float));
+  p->sv_plain = sv;
+  if (flags & PCAD_PLAN_PER_SEGMENT) {
+    // per-instance plain calls: one call's workspace (reused in order), the
+    // summed output adjoint, and the per-instance scan prefixes and argk
+    size_t wmax = 0, cmax = 0;
+    for (int64_t s = 0; s < nseg; ++s) {
+      const int64_t L = offsets[s + 1] - offsets[s];
+      size_t w1 = 0, w2 = 0, s1 = 0;
+      pcad_query(PCAD_SCAN, PCAD_LINREC, 1, L, 0, 0, &s1, &w1);
+      pcad_query(PCAD_RBI, PCAD_MIN, 1, L, m, 0, nullptr, &w2);
+      wmax = std::max(wmax, std::max(w1, w2));
+      cmax += align256(s1);
+    }
+    p->plain_ws_bytes = wmax;
+    o = align256(o + wmax);
+    o = align256(o + (size_t)p->N * sizeof(float));  // y_bar_total
+    sv = align256(sv + cmax);
+  }
+  p->ws_bytes = o;
+  p->saved_bytes = sv;
+  *out = p;
+  return PCAD_OK;
+}
+
+int pcad_plan_query(const pcad_plan *p, size_t *saved_bytes, size_t *workspace_bytes,
+                    int64_t *n_elements, int64_t *n_items) {
+  if (!p) return PCAD_E_NULLPTR;
+  if (saved_bytes) *saved_bytes = p->saved_bytes;
+  if (workspace_bytes) *workspace_bytes = p->ws_bytes;
+  if (n_elements) *n_elements = p->N;
+  if (n_items) *n_items = p->nitems;
+  return PCAD_OK;
+}
+
+int pcad_plan_bind(pcad_plan *p, const float *a, const float *b, const int32_t *idx, float *y,
+                   float *h, int32_t *argk, const float *ybar, const float *hbar, float *abar,
+                   float *bbar, void *saved, void *ws, size_t ws_bytes, void *stream) {
+  if (!p) return PCAD_E_NULLPTR;
+  if (!saved || !ws || !h || !argk || !hbar) return PCAD_E_NULLPTR;
+  if (p->N > 0 && (!a || !b || !idx || !y || !ybar || !abar || !bbar)) return PCAD_E_NULLPTR;
+  const void *al[] = {a, b, idx, y, h, argk, ybar, hbar, abar, bbar, saved};
+  for (const void *q : al)
+    if (q && ((uintptr_t)q & 15u)) return PCAD_E_MISALIGNED;
+  if ((uintptr_t)ws & 255u) return PCAD_E_MISALIGNED;
+  if (ws_bytes < p->ws_bytes) return PCAD_E_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  for (int i = 0; i < 4; ++i)
+    if (p->g[i]) {
+      (void)hipGraphExecDestroy(p->g[i]);
+      p->g[i] = nullptr;
+    }
+  p->bound = false;
+  p->a = a; p->b = b; p->idx = idx; p->y = y; p->h = h; p->argk = argk;
+  p->ybar = ybar; p->hbar = hbar; p->abar = abar; p->bbar = bbar;
+  p->saved = static_cast<char *>(saved);
+  p->ws = static_cast<char *>(ws);
+
+  // device tables
+  char *tab = p->ws + p->ws_tab;
+  int32_t *d_item_seg = reinterpret_cast<int32_t *>(tab);
+  int64_t *d_off = reinterpret_cast<int64_t *>(
+      tab + align256((size_t)p->item_seg.size() * 4));
+  int32_t *d_item0 = reinterpret_cast<int32_t *>(
+      reinterpret_cast<char *>(d_off) + align256((size_t)(p->S + 1) * 8));
+  int st = plan_hip(hipMemcpyAsync(d_item_seg, p->item_seg.data(), p->item_seg.size() * 4,
+                                   hipMemcpyHostToDevice, s));
+  if (st == PCAD_OK)
+    st = plan_hip(hipMemcpyAsync(d_off, p->off.data(), (p->S + 1) * 8, hipMemcpyHostToDevice, s));
+  if (st == PCAD_OK)
+    st = plan_hip(hipMemcpyAsync(d_item0, p->seg_item0.data(), (p->S + 1) * 4,
+                                 hipMemcpyHostToDevice, s));
+  if (st != PCAD_OK) return st;
+  // merge keys start (and stay, between launches) at the neutral key
+  uint64_t *keys = reinterpret_cast<uint64_t *>(p->ws + p->ws_keys);
+  hipLaunchKernelGGL(k_fill_u64, dim3(1024), dim3(256), 0, s, keys, p->S * p->m, key_init<MIN>());
+  if ((st = plan_hip(hipGetLastError())) != PCAD_OK) return st;
+  if ((st = plan_hip(hipStreamSynchronize(s))) != PCAD_OK) return st;
+
+  SegTables t{d_item_seg, d_off, d_item0};
+  Ctl *ctl = reinterpret_cast<Ctl *>(p->ws);
+  uint64_t *status = reinterpret_cast<uint64_t *>(p->ws + p->ws_status);
+  float *carry = reinterpret_cast<float *>(p->saved + p->sv_carry);
+  p->fa = SegFwdArgs{t, (int)p->S, (int)p->m, (int)p->nrows, a, b, idx, y, h, argk, carry,
+                     keys, ctl, status};
+  p->ba = SegBwdArgs{t, p->nitems, (int)p->S, (int)p->m, (int)p->nrows, a, b, idx, carry, argk,
+                     ybar, hbar, abar, bbar, ctl, status};
+
+  // one graph per phase: forward, adjoint, both
+  if (!p->cap && (st = plan_hip(hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking))) != PCAD_OK)
+    return st;
+  for (int ph = 1; ph <= 3; ++ph) {
+    hipGraph_t graph = nullptr;
+    if ((st = plan_hip(hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal))) != PCAD_OK)
+      return st;
+    hipError_t e = hipSuccess;
+    if (ph & 1) e = launch_fwd_nodes(p, p->cap);
+    if (e == hipSuccess && (ph & 2)) e = launch_bwd_nodes(p, p->cap);
+    const hipError_t e2 = hipStreamEndCapture(p->cap, &graph);
+    if (e != hipSuccess) return plan_hip(e);
+    if ((st = plan_hip(e2)) != PCAD_OK) return st;
+    st = plan_hip(hipGraphInstantiate(&p->g[ph], graph, nullptr, nullptr, 0));
+    (void)hipGraphDestroy(graph);
+    if (st != PCAD_OK) return st;
+  }
+  p->bound = true;
+  return PCAD_OK;
+}
+
+int pcad_plan_run(pcad_plan *p, int phase, void *stream) {
+  if (!p) return PCAD_E_NULLPTR;
+  if (!p->bound) return PCAD_E_INVALID_ARG;
+  if (phase < 1 || phase > 3) return PCAD_E_INVALID_ARG;
+  return plan_hip(hipGraphLaunch(p->g[phase], (hipStream_t)stream));
+}
+
+int pcad_plan_run_per_segment(pcad_plan *p, int phase, void *stream) {
+  if (!p) return PCAD_E_NULLPTR;
+  if (!p->bound || !(p->flags & PCAD_PLAN_PER_SEGMENT)) return PCAD_E_INVALID_ARG;
+  if (phase < 1 || phase > 3) return PCAD_E_INVALID_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  void *wsp = p->ws + p->ws_plain;
+  float *ytot = reinterpret_cast<float *>(p->ws + align256(p->ws_plain + p->plain_ws_bytes));
+  char *svp = p->saved + p->sv_plain;
+  size_t so = 0;
+  for (int64_t s_ = 0; s_ < p->S; ++s_) {
+    const int64_t o = p->off[s_], L = p->off[s_ + 1] - o;
+    size_t s1 = 0;
+    pcad_query(PCAD_SCAN, PCAD_LINREC, 1, L, 0, 0, &s1, nullptr);
+    float *carry = reinterpret_cast<float *>(svp + so);
+    so += align256(s1);
+    int32_t *ak = p->argk + s_ * p->m;
+    float *hh = p->h + s_ * p->m;
+    if (phase & 1) {
+      hipError_t e = scan_fwd_launch(PCAD_LINREC, 1, L, p->a + o, p->b + o, p->y + o, nullptr,
+                                     carry, nullptr, false, wsp, s);
+      if (e == hipSuccess)
+        e = rbi_fwd_launch(PCAD_MIN, 1, L, p->m, p->idx + o, p->y + o, hh, ak, wsp, s);
+      if (e != hipSuccess) return plan_hip(e);
+    }
+    if (phase & 2) {
+      hipError_t e = hipSuccess;
+      if (L > 0) e = hipMemcpyAsync(ytot + o, p->ybar + o, L * sizeof(float),
+                                    hipMemcpyDeviceToDevice, s);
+      if (e == hipSuccess)
+        e = rbi_vjp_launch(PCAD_MIN, 1, L, p->m, p->idx + o, p->y + o, ak, p->hbar + s_ * p->m,
+                           ytot + o, true, s);
+      if (e == hipSuccess)
+        e = scan_vjp_launch(PCAD_LINREC, 1, L, p->a + o, p->b + o, carry, ytot + o, nullptr,
+                            p->abar + o, p->bbar + o, false, wsp, s);
+      if (e != hipSuccess) return plan_hip(e);
+    }
+  }
+  return PCAD_OK;
+}
+
+void pcad_plan_destroy(pcad_plan *p) {
+  if (!p) return;
+  for (int i = 0; i < 4; ++i)
+    if (p->g[i]) (void)hipGraphExecDestroy(p->g[i]);
+  if (p->cap) (void)hipStreamDestroy(p->cap);
+  delete p;
+}
+
+int pcad_plan_last_hip_error(void) { return g_plan_hip; }
+
+}  // extern "C"

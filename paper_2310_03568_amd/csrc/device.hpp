@@ -58,6 +58,33 @@ __device__ __forceinline__ float mulz(float a, float b) {
 }
 
 // ---------------------------------------------------------------------------
+// Lifted min/max as one 64-bit word, so "smallest value, then smallest
+// index" is a single native 64-bit atomic min (or max with the index
+// complemented): key = {ord(v):32 | index:32}.  ord is the order-preserving
+// map float -> uint32 with -0.0 folded onto +0.0 (equal values tie).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t ord_f32(float v) {
+  uint32_t b = __float_as_uint(v == 0.0f ? 0.0f : v);
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+
+// inverse of ord_f32 (returns +0.0 for a folded zero)
+__device__ __forceinline__ float ord_inv(uint32_t o) {
+  return __uint_as_float((o & 0x80000000u) ? (o & 0x7fffffffu) : ~o);
+}
+
+template <int OP>
+__device__ __forceinline__ uint64_t key_of(float v, uint32_t i) {
+  return OP == MIN ? (((uint64_t)ord_f32(v) << 32) | i)
+                   : (((uint64_t)ord_f32(v) << 32) | (uint32_t)(~i));
+}
+
+template <int OP>
+constexpr uint64_t key_init() {
+  return OP == MIN ? ~0ull : 0ull;
+}
+
+// ---------------------------------------------------------------------------
 // forward operators.  comb(earlier, later) in index order.
 // ---------------------------------------------------------------------------
 template <int OP>
@@ -124,15 +151,25 @@ struct Fwd<MAT2> {
 
 // ---------------------------------------------------------------------------
 // tile shapes.  A group is one 16-byte vector per input stream per lane:
-// EPL elements.  A tile is K groups of BLOCK lanes: element e of a tile
-// lives in group e / (BLOCK*EPL), lane (e % (BLOCK*EPL)) / EPL, slot e % EPL.
+// EPL elements.  A tile is K groups of THREADS lanes: element e of a tile
+// lives in group e / (THREADS*EPL), lane (e % (THREADS*EPL)) / EPL, slot
+// e % EPL.
 // ---------------------------------------------------------------------------
+// Threads per block and groups per thread of the scan kernels (a tile is
+// THREADS * EPL * K elements); build-time knobs for tile-shape sweeps.
+#ifndef PCAD_SCAN_THREADS
+#define PCAD_SCAN_THREADS 1024
+#endif
+#ifndef PCAD_SCAN_K
+#define PCAD_SCAN_K 2
+#endif
+
 template <int OP>
 struct Shape {
-  static constexpr int THREADS = 1024;
+  static constexpr int THREADS = PCAD_SCAN_THREADS;
   static constexpr int W = THREADS / WAVE;
   static constexpr int EPL = (OP == MAT2) ? 1 : 4;
-  static constexpr int K = 2;
+  static constexpr int K = PCAD_SCAN_K;
   static constexpr int TILE = THREADS * EPL * K;
 };
 
@@ -163,10 +200,11 @@ template <int S>
 __device__ __forceinline__ void store_group(float *__restrict__ p, int64_t e, int valid,
                                             bool vec_ok, float4 v) {
   if (valid >= 4 / S && (S == 4 || vec_ok)) {
-    __builtin_nontemporal_store(v.x, p + e * S + 0);
-    __builtin_nontemporal_store(v.y, p + e * S + 1);
-    __builtin_nontemporal_store(v.z, p + e * S + 2);
-    __builtin_nontemporal_store(v.w, p + e * S + 3);
+    // one 16-byte streaming store per lane: whole 64-byte lines per quad of
+    // lanes, no partial-line writes
+    typedef float v4f __attribute__((ext_vector_type(4)));
+    v4f w = {v.x, v.y, v.z, v.w};
+    __builtin_nontemporal_store(w, reinterpret_cast<v4f *>(p + e * S));
     return;
   }
   float r[4] = {v.x, v.y, v.z, v.w};

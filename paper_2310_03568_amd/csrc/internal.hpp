@@ -10,6 +10,10 @@ namespace pcad {
 // bytes reserved for the per-launch control block at the start of a workspace
 constexpr size_t kCtlBytes = 256;
 
+// PCAD_OK for hipSuccess; otherwise records the error (pcad_last_hip_error)
+// and returns PCAD_E_HIP
+int hip_status(hipError_t e);
+
 // scan
 int scan_tile_size(int op);
 int scan_elem_floats(int op);

@@ -26,23 +26,6 @@ namespace pcad {
 constexpr int kLdsBinsF32 = 8192;   // + and *: 32 KB of values (+ 32 KB counts for *)
 constexpr int kLdsBinsU64 = 4096;   // min/max: 32 KB of keys
 
-// order-preserving map float -> uint32 (-0.0 folded onto +0.0)
-__device__ __forceinline__ uint32_t ord_f32(float v) {
-  uint32_t b = __float_as_uint(v == 0.0f ? 0.0f : v);
-  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
-}
-
-template <int OP>
-__device__ __forceinline__ uint64_t key_of(float v, uint32_t i) {
-  return OP == MIN ? (((uint64_t)ord_f32(v) << 32) | i)
-                   : (((uint64_t)ord_f32(v) << 32) | (uint32_t)(~i));
-}
-
-template <int OP>
-constexpr uint64_t key_init() {
-  return OP == MIN ? ~0ull : 0ull;
-}
-
 // CAS-loop product on global or LDS memory
 __device__ __forceinline__ void atomic_mul_f32(float *p, float v) {
   unsigned *u = reinterpret_cast<unsigned *>(p);
