@@ -139,9 +139,10 @@ int pcad_reduce_vjp(int op, int64_t batch, int64_t n, const float *x0, const flo
  * by a single-pass decoupled look-back over tiles.
  *   y0: the scan (scalar ops: x-layout; LINREC: y_i; MAT2: P_i, 4 floats).
  *   y1: LINREC only, optional: the cumulative multiplier A_i (may be NULL).
- *   saved: the exclusive prefix of every tile, which the adjoint call uses to
+ *   saved: the exclusive prefix of every tile, which pcad_scan_vjp uses to
  *          recompute the forward prefixes inside each tile instead of
- *          storing them (the redundant-execution choice of the paper).
+ *          storing them (the redundant-execution choice of the paper); may
+ *          be NULL when the adjoint will be the checkpoint form.
  */
 int pcad_scan_fwd(int op, int64_t batch, int64_t n, const float *x0, const float *x1,
                   float *y0, float *y1, void *saved, unsigned flags, void *ws,
@@ -160,6 +161,23 @@ int pcad_scan_fwd(int op, int64_t batch, int64_t n, const float *x0, const float
 int pcad_scan_vjp(int op, int64_t batch, int64_t n, const float *x0, const float *x1,
                   const void *saved, const float *ybar0, const float *ybar1, float *xbar0,
                   float *xbar1, unsigned flags, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Adjoint of the inclusive scan, checkpoint form: the forward prefixes
+ * rs_{i-1} are read from the stored forward outputs (the tape of
+ * intermediates, Section 2 on tapes versus redundant execution) instead of
+ * being recomputed inside each tile; no `saved` state is needed, so the
+ * forward call may pass saved = NULL.  Results equal pcad_scan_vjp's up to
+ * the rounding of the recomputed prefixes.
+ *   y0: the forward output y0 (required except for ADD, which reads none).
+ *   y1: LINREC only: the forward's A output; required iff ybar1 != NULL.
+ *   x1: LINREC only, may be NULL (the offsets b are not read).
+ *   Other arguments and the workspace as for pcad_scan_vjp.
+ */
+int pcad_scan_vjp_checkpoint(int op, int64_t batch, int64_t n, const float *x0, const float *x1,
+                             const float *y0, const float *y1, const float *ybar0,
+                             const float *ybar1, float *xbar0, float *xbar1, unsigned flags,
+                             void *ws, size_t ws_bytes, void *stream);
 
 /*
  * reduce_by_index (Section 4): for every row r and bin k in [0,m),

@@ -252,3 +252,34 @@ def segmented_vjp(offsets, a, b, idx, m: int, ybar, hbar, argk):
         cab[lo:hi] = c[:, 0]
         cbb[lo:hi] = c[:, 1]
     return ab, bb, cab, cbb
+
+
+# -------------------------------------------------------------------------
+# autograd workload: per sequence, loss = sum_i log|y_i| over the linear
+# recurrence y of (a, b), plus the sum over non-empty bins of the
+# max-by-index of v (an empty bin holds the neutral -inf and is left out).
+# The gradient composes the two adjoints by the chain rule of reverse mode
+# (Section 2): the scan adjoint seeded with d log|y|/dy = 1/y and the
+# max-by-index adjoint seeded with 1 on every non-empty bin.
+# -------------------------------------------------------------------------
+def autograd_loss(a, b, v, idx, m: int) -> float:
+    rs, _ = scan_fwd("linrec", a, b)
+    r = rbi_fwd("max", idx, m, v)
+    n = len(np.asarray(v).reshape(-1))
+    full = r["argk"] < n
+    return float(np.sum(np.log(np.abs(rs[:, 1]))) + np.sum(r["hist"][full, 0]))
+
+
+def autograd_grad(a, b, v, idx, m: int, ybar=None):
+    """Returns (a_bar, b_bar, v_bar, c_a, c_b, c_v) float64.  ``ybar``
+    replaces the seed 1/y of the scan adjoint when given (e.g. the float32
+    seed another implementation used)."""
+    a = np.asarray(a).reshape(-1)
+    n = a.shape[0]
+    rs, _ = scan_fwd("linrec", a, b)
+    yb = 1.0 / rs[:, 1] if ybar is None else _f64(ybar).reshape(-1)
+    xb, cx = scan_vjp("linrec", np.stack([np.zeros(n), yb], 1), a, b)
+    r = rbi_fwd("max", idx, m, v)
+    hb = (r["argk"] < n).astype(np.float64)
+    vb, cv = rbi_vjp("max", idx, m, hb, v)
+    return xb[:, 0], xb[:, 1], vb[:, 0], cx[:, 0], cx[:, 1], cv[:, 0]

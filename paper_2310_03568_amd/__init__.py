@@ -56,6 +56,7 @@ def lib():
             "pcad_reduce_vjp": ([I, I64, I64, P, P, P, P, P, P, U, P, SZ, P], I),
             "pcad_scan_fwd": ([I, I64, I64, P, P, P, P, P, U, P, SZ, P], I),
             "pcad_scan_vjp": ([I, I64, I64, P, P, P, P, P, P, P, U, P, SZ, P], I),
+            "pcad_scan_vjp_checkpoint": ([I, I64, I64, P, P, P, P, P, P, P, P, U, P, SZ, P], I),
             "pcad_rbi_fwd": ([I, I64, I64, I64, P, P, P, P, U, P, SZ, P], I),
             "pcad_rbi_vjp": ([I, I64, I64, I64, P, P, P, P, P, U, P, SZ, P], I),
             "pcad_plan_create": ([ctypes.POINTER(P), I64, P, I64, U], I),
@@ -186,16 +187,18 @@ def reduce_vjp(op: str, x0, x1, saved, ybar, out=None, accumulate: bool = False)
 # ---------------------------------------------------------------------------
 # scan
 # ---------------------------------------------------------------------------
-def scan_fwd(op: str, x0: torch.Tensor, x1: Optional[torch.Tensor] = None, want_A: bool = False):
+def scan_fwd(op: str, x0: torch.Tensor, x1: Optional[torch.Tensor] = None, want_A: bool = False,
+             keep_saved: bool = True):
     """Returns (y, A, saved); A is the linrec cumulative multiplier when
-    ``want_A`` (else None)."""
+    ``want_A`` (else None); saved (the tile prefixes) is None unless
+    ``keep_saved`` (the checkpoint adjoint does not read it)."""
     _dev_check(x0, x1)
     batch, n, lead = _shape(op, x0)
     s_b, w_b = query(SCAN, op, batch, n)
     dev = x0.device
     y = torch.empty_like(x0)
     A = torch.empty_like(x0) if (op == "linrec" and want_A) else None
-    saved = torch.empty(max(s_b, 16), dtype=torch.uint8, device=dev)
+    saved = torch.empty(max(s_b, 16), dtype=torch.uint8, device=dev) if keep_saved else None
     ws = workspace(w_b, dev)
     check(lib().pcad_scan_fwd(OPS[op], batch, n, _ptr(x0), _ptr(x1), _ptr(y), _ptr(A),
                               _ptr(saved), 0, _ptr(ws), ws.numel(), _stream(dev)),
@@ -216,6 +219,25 @@ def scan_vjp(op: str, x0, x1, saved, ybar, Abar=None, out=None, accumulate: bool
                               _ptr(Abar), _ptr(out[0]), _ptr(out[1]) if len(out) > 1 else None,
                               ACCUMULATE if accumulate else 0, _ptr(ws), ws.numel(),
                               _stream(dev)), "pcad_scan_vjp")
+    return out if op == "linrec" else out[0]
+
+
+def scan_vjp_checkpoint(op: str, x0, x1, y0, y1, ybar, Abar=None, out=None,
+                        accumulate: bool = False):
+    """Adjoint of the scan reading the forward outputs (y0; linrec: y and,
+    with Abar, A) instead of recomputing prefixes.  x1 (linrec b) may be None."""
+    _dev_check(x0, x1, y0, y1, ybar, Abar)
+    batch, n, lead = _shape(op, x0)
+    s_b, w_b = query(SCAN, op, batch, n)
+    dev = x0.device
+    if out is None:
+        out = (torch.empty_like(x0), torch.empty_like(x0)) if op == "linrec" else (torch.empty_like(x0),)
+    ws = workspace(w_b, dev)
+    check(lib().pcad_scan_vjp_checkpoint(OPS[op], batch, n, _ptr(x0), _ptr(x1), _ptr(y0),
+                                         _ptr(y1), _ptr(ybar), _ptr(Abar), _ptr(out[0]),
+                                         _ptr(out[1]) if len(out) > 1 else None,
+                                         ACCUMULATE if accumulate else 0, _ptr(ws), ws.numel(),
+                                         _stream(dev)), "pcad_scan_vjp_checkpoint")
     return out if op == "linrec" else out[0]
 
 

@@ -194,7 +194,7 @@ int pcad_scan_fwd(int op, int64_t batch, int64_t n, const float *x0, const float
   PCAD_TRY(need(y0));
   PCAD_TRY(opt(y1));
   if (op != PCAD_LINREC && y1) return PCAD_E_INVALID_ARG;
-  PCAD_TRY(check_saved(PCAD_SCAN, op, batch, n, 0, saved));
+  PCAD_TRY(opt(saved));  // NULL: no tile prefixes kept (checkpoint adjoint)
   PCAD_TRY(check_ws(PCAD_SCAN, op, batch, n, 0, ws, ws_bytes));
   return hip_status(scan_fwd_launch(op, batch, n, x0, x1, y0, y1, static_cast<float *>(saved),
                                     nullptr, false, ws, (hipStream_t)stream));
@@ -215,9 +215,36 @@ int pcad_scan_vjp(int op, int64_t batch, int64_t n, const float *x0, const float
   if (op == PCAD_LINREC) PCAD_TRY(need(xbar1));
   PCAD_TRY(check_saved(PCAD_SCAN, op, batch, n, 0, saved));
   PCAD_TRY(check_ws(PCAD_SCAN, op, batch, n, 0, ws, ws_bytes));
-  return hip_status(scan_vjp_launch(op, batch, n, x0, x1, static_cast<const float *>(saved), ybar0,
-                                    ybar1, xbar0, xbar1, (flags & PCAD_ACCUMULATE) != 0, ws,
-                                    (hipStream_t)stream));
+  return hip_status(scan_vjp_launch(op, batch, n, x0, x1, static_cast<const float *>(saved),
+                                    nullptr, nullptr, ybar0, ybar1, xbar0, xbar1,
+                                    (flags & PCAD_ACCUMULATE) != 0, ws, (hipStream_t)stream));
+}
+
+int pcad_scan_vjp_checkpoint(int op, int64_t batch, int64_t n, const float *x0, const float *x1,
+                             const float *y0, const float *y1, const float *ybar0,
+                             const float *ybar1, float *xbar0, float *xbar1, unsigned flags,
+                             void *ws, size_t ws_bytes, void *stream) {
+  PCAD_TRY(check_common(op, batch, n, flags));
+  if (batch == 0 || n == 0) return PCAD_OK;
+  if (scan_tiles(op, batch, n) > 2147483647LL) return PCAD_E_SIZE;
+  PCAD_TRY(need(x0));
+  PCAD_TRY(opt(x1));
+  if (op != PCAD_LINREC && x1) return PCAD_E_INVALID_ARG;
+  if (op != PCAD_ADD) PCAD_TRY(need(y0));
+  else PCAD_TRY(opt(y0));
+  PCAD_TRY(opt(y1));
+  PCAD_TRY(need(ybar0));
+  PCAD_TRY(opt(ybar1));
+  if (op != PCAD_LINREC && (ybar1 || y1)) return PCAD_E_INVALID_ARG;
+  if (ybar1 && !y1) return PCAD_E_NULLPTR;  // A_bar needs the A tape
+  PCAD_TRY(need(xbar0));
+  if (op == PCAD_LINREC) PCAD_TRY(need(xbar1));
+  PCAD_TRY(check_ws(PCAD_SCAN, op, batch, n, 0, ws, ws_bytes));
+  // ADD reads no prefix: its adjoint is the recompute form with nothing to recompute
+  const float *tp0 = op == PCAD_ADD ? nullptr : y0;
+  return hip_status(scan_vjp_launch(op, batch, n, x0, x1, nullptr, tp0, ybar1 ? y1 : nullptr,
+                                    ybar0, ybar1, xbar0, xbar1,
+                                    (flags & PCAD_ACCUMULATE) != 0, ws, (hipStream_t)stream));
 }
 
 int pcad_rbi_fwd(int op, int64_t batch, int64_t n, int64_t m, const int32_t *idx, const float *v,

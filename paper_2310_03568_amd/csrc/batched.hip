@@ -664,7 +664,8 @@ int pcad_plan_run_per_segment(pcad_plan *p, int phase, void *stream) {
         e = rbi_vjp_launch(PCAD_MIN, 1, L, p->m, p->idx + o, p->y + o, ak, p->hbar + s_ * p->m,
                            ytot + o, true, s);
       if (e == hipSuccess)
-        e = scan_vjp_launch(PCAD_LINREC, 1, L, p->a + o, p->b + o, carry, ytot + o, nullptr,
+        e = scan_vjp_launch(PCAD_LINREC, 1, L, p->a + o, p->b + o, carry, nullptr, nullptr,
+                            ytot + o, nullptr,
                             p->abar + o, p->bbar + o, false, wsp, s);
       if (e != hipSuccess) return plan_hip(e);
     }

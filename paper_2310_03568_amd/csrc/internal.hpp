@@ -21,9 +21,12 @@ int scan_status_words(int op, bool abar);
 hipError_t scan_fwd_launch(int op, int64_t batch, int64_t n, const float *x0, const float *x1,
                            float *y0, float *y1, float *saved, float *total, bool reduce,
                            void *ws, hipStream_t s);
+// tp0 (tp1): forward outputs y (LINREC: and A) for the checkpoint form,
+// NULL for the recompute form, which reads `saved`
 hipError_t scan_vjp_launch(int op, int64_t batch, int64_t n, const float *x0, const float *x1,
-                           const float *saved, const float *yb0, const float *yb1, float *xb0,
-                           float *xb1, bool accumulate, void *ws, hipStream_t s);
+                           const float *saved, const float *tp0, const float *tp1,
+                           const float *yb0, const float *yb1, float *xb0, float *xb1,
+                           bool accumulate, void *ws, hipStream_t s);
 
 // reduce
 int reduce_blocks_per_row(int64_t batch, int64_t n);

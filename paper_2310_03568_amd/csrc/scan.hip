@@ -174,7 +174,8 @@ __global__ __launch_bounds__(Shape<OP>::THREADS) void k_scan_fwd(ScanFwdArgs a) 
 // ---------------------------------------------------------------------------
 struct ScanVjpArgs {
   const float *x0, *x1;
-  const float *saved;
+  const float *saved;    // recompute: exclusive prefix of every tile
+  const float *tp0, *tp1;  // checkpoint: the forward outputs (y; LINREC also A)
   const float *yb0, *yb1;
   float *xb0, *xb1;
   int64_t n;
@@ -185,7 +186,10 @@ struct ScanVjpArgs {
   uint64_t *status;
 };
 
-template <int OP, bool ABAR>
+// CKPT: the forward prefix rs_{i-1} is read from the stored forward output
+// (the tape) instead of being recomputed inside the tile from the saved tile
+// prefix.  A linear recurrence with a tape never reads its offsets b.
+template <int OP, bool ABAR, bool CKPT>
 __global__ __launch_bounds__(Shape<OP>::THREADS) void k_scan_vjp(ScanVjpArgs a) {
   using Op = FwdLB<OP>;
   using FT = typename Op::T;
@@ -196,10 +200,17 @@ __global__ __launch_bounds__(Shape<OP>::THREADS) void k_scan_vjp(ScanVjpArgs a) 
   constexpr int EPL = Shape<OP>::EPL, K = Shape<OP>::K, TILE = Shape<OP>::TILE;
   constexpr int TH = Shape<OP>::THREADS, W = Shape<OP>::W;
   constexpr int NIN = Io::NIN, S = Io::S, N = Fwd<OP>::N;
-  constexpr int NB = NIN + (ABAR ? 2 : 1);  // streams per group: x..., y_bar[, A_bar]
+  constexpr bool RECOMP = A::NEEDS_PREFIX && !CKPT;
+  constexpr bool TAPE = A::NEEDS_PREFIX && CKPT;
+  // streams per group: x...; y_bar; [A_bar]; [tape y; [tape A]]
+  constexpr int NX = (TAPE && OP == LINREC) ? 1 : NIN;
+  constexpr int IYB = NX, IAB = NX + 1, IT = NX + 1 + (ABAR ? 1 : 0);
+  constexpr int NT = TAPE ? ((OP == LINREC && ABAR) ? 2 : 1) : 0;
+  constexpr int NB = IT + NT;
+  constexpr int NTP = NT > 0 ? NT : 1;
 
-  __shared__ FT s_ftot[K][W];
-  __shared__ FT s_fpre[K][W];
+  __shared__ FT s_ftot[RECOMP ? K : 1][W];
+  __shared__ FT s_fpre[RECOMP ? K : 1][W];
   __shared__ MT s_mtot[K][W];
   __shared__ MT s_mpre[K][W];
   __shared__ MT s_carry;
@@ -207,59 +218,109 @@ __global__ __launch_bounds__(Shape<OP>::THREADS) void k_scan_vjp(ScanVjpArgs a) 
 
   const int tid = threadIdx.x, lane = lane_id(), wave = tid / WAVE;
   const float *src[2] = {a.x0, a.x1};
-  auto tile_of = [&](int64_t k) { return a.ntiles - 1 - k; };  // right to left
-  auto load = [&](int64_t t, float4 (&buf)[K][NB]) {
+  const float *tp[2] = {a.tp0, a.tp1};
+  // tape value before a row's first element: the neutral prefix component
+  auto tape_id = [&](int s) -> float4 {
+    const FT e = Op::id();
+    if (OP == MAT2) return make_float4(e.f[0], e.f[1], e.f[2], e.f[3]);
+    const float v = (OP == LINREC) ? (s == 0 ? e.f[1] : e.f[0]) : e.f[0];
+    return make_float4(v, v, v, v);
+  };
+  // pv: for lane 0 only, the tape element just before the group (the other
+  // lanes take it from their left neighbour)
+  auto load = [&](int64_t t, float4 (&buf)[K][NB], float4 (&pv)[K][NTP]) {
     const TileInfo ti = tile_info(t, a.n, a.tpr, TILE);
 #pragma unroll
     for (int g = 0; g < K; ++g) {
       const int el = g * TH * EPL + tid * EPL;
       const int v = ti.valid - el;
 #pragma unroll
-      for (int s = 0; s < NIN; ++s)
+      for (int s = 0; s < NX; ++s)
         buf[g][s] = load_group<S>(src[s], ti.base + el, v, ti.vec_ok, Io::fill(s));
-      buf[g][NIN] = load_group<S>(a.yb0, ti.base + el, v, ti.vec_ok, make_float4(0, 0, 0, 0));
+      buf[g][IYB] = load_group<S>(a.yb0, ti.base + el, v, ti.vec_ok, make_float4(0, 0, 0, 0));
       if (ABAR)
-        buf[g][NB - 1] = load_group<1>(a.yb1, ti.base + el, v, ti.vec_ok, make_float4(0, 0, 0, 0));
+        buf[g][IAB] = load_group<1>(a.yb1, ti.base + el, v, ti.vec_ok, make_float4(0, 0, 0, 0));
+#pragma unroll
+      for (int s = 0; s < NT; ++s) {
+        buf[g][IT + s] = load_group<S>(tp[s], ti.base + el, v, ti.vec_ok, tape_id(s));
+        float4 q = tape_id(s);
+        if (lane == 0 && v > 0 && !(ti.lt == 0 && el == 0)) {
+          const int64_t e = ti.base + el - 1;
+          if (S == 4) q = *reinterpret_cast<const float4 *>(tp[s] + e * 4);
+          else q.x = tp[s][e];
+        }
+        pv[g][s] = q;
+      }
     }
   };
   auto ybar_of = [&](const float4 (&buf)[K][NB], int g, int j, float *yb) {
     if (S == 4) {
-      yb[0] = buf[g][NIN].x; yb[1] = buf[g][NIN].y; yb[2] = buf[g][NIN].z; yb[3] = buf[g][NIN].w;
+      yb[0] = buf[g][IYB].x; yb[1] = buf[g][IYB].y; yb[2] = buf[g][IYB].z; yb[3] = buf[g][IYB].w;
     } else {
-      yb[0] = f4get(buf[g][NIN], j);
-      yb[1] = ABAR ? f4get(buf[g][NB - 1], j) : 0.0f;
+      yb[0] = f4get(buf[g][IYB], j);
+      yb[1] = ABAR ? f4get(buf[g][IAB], j) : 0.0f;
     }
   };
   auto x_of = [&](const float4 (&buf)[K][NB], int g, int j) -> FT {
     float4 in[NIN];
 #pragma unroll
-    for (int s = 0; s < NIN; ++s) in[s] = buf[g][s];
+    for (int s = 0; s < NIN; ++s) in[s] = s < NX ? buf[g][s] : Io::fill(s);
     return Io::elem(in, j);
   };
 
   if (tid == 0) s_epoch = ctl_load(&a.ctl->epoch);
   int64_t k = blockIdx.x;
+  auto tile_of = [&](int64_t kk) { return a.ntiles - 1 - kk; };  // right to left
   float4 cur[K][NB];
-  load(tile_of(k), cur);
+  float4 cpv[K][NTP];
+  load(tile_of(k), cur, cpv);
   __syncthreads();
   const uint32_t tag = s_epoch + 1;
 
-  FT thr_f[K];   // forward prefix before each thread's group (incl. the tile carry)
+  FT thr_f[K];   // recompute: forward prefix before each thread's group
   MT mincl[K];   // wave-inclusive (from the right) adjoint-map aggregates
   MT agg = M::id();
   // the forward prefixes rs_{i-1} of the EPL slots of group g, ascending
   auto prefixes = [&](int g, FT (&p)[EPL]) {
-    FT acc = thr_f[g];
+    if (TAPE) {
+      if (S == 4) {
+        Vec<4> q = {{cur[g][IT].x, cur[g][IT].y, cur[g][IT].z, cur[g][IT].w}};
+        Vec<4> up = shfl_up(q, 1);
+        if (lane == 0) up = Vec<4>{{cpv[g][0].x, cpv[g][0].y, cpv[g][0].z, cpv[g][0].w}};
 #pragma unroll
-    for (int j = 0; j < EPL; ++j) {
-      p[j] = acc;
-      if (A::NEEDS_PREFIX && j + 1 < EPL) acc = Op::comb(acc, x_of(cur, g, j));
+        for (int i = 0; i < N; ++i) p[0].f[i] = up.f[i];
+      } else {
+        float prev[2][4];
+#pragma unroll
+        for (int s = 0; s < NT; ++s) {
+          const float4 q = cur[g][IT + s];
+          float w = __shfl_up(q.w, 1, WAVE);
+          if (lane == 0) w = cpv[g][s].x;
+          prev[s][0] = w; prev[s][1] = q.x; prev[s][2] = q.y; prev[s][3] = q.z;
+        }
+#pragma unroll
+        for (int j = 0; j < EPL; ++j) {
+          if (OP == LINREC) {
+            p[j].f[0] = NT == 2 ? prev[NT - 1][j] : 1.0f;  // A_{i-1}: read only with A_bar
+            p[j].f[1] = prev[0][j];
+          } else {
+            p[j].f[0] = prev[0][j];
+          }
+        }
+      }
+    } else {
+      FT acc = thr_f[g];
+#pragma unroll
+      for (int j = 0; j < EPL; ++j) {
+        p[j] = acc;
+        if (RECOMP && j + 1 < EPL) acc = Op::comb(acc, x_of(cur, g, j));
+      }
     }
   };
 
   auto phase1 = [&](int64_t kk) {
     const TileInfo ti = tile_info(tile_of(kk), a.n, a.tpr, TILE);
-    if (A::NEEDS_PREFIX) {
+    if (RECOMP) {
       FT fincl[K];
 #pragma unroll
       for (int g = 0; g < K; ++g) {
@@ -327,7 +388,8 @@ __global__ __launch_bounds__(Shape<OP>::THREADS) void k_scan_vjp(ScanVjpArgs a) 
     const int64_t kn = k + gridDim.x;
     const bool more = kn < a.ntiles;
     float4 nxt[K][NB];
-    if (more) load(tile_of(kn), nxt);
+    float4 npv[K][NTP];
+    if (more) load(tile_of(kn), nxt, npv);
 
     if (wave == 0) {
       typename M::P zero;
@@ -390,9 +452,12 @@ __global__ __launch_bounds__(Shape<OP>::THREADS) void k_scan_vjp(ScanVjpArgs a) 
     if (!more) break;
     k = kn;
 #pragma unroll
-    for (int g = 0; g < K; ++g)
+    for (int g = 0; g < K; ++g) {
 #pragma unroll
       for (int s = 0; s < NB; ++s) cur[g][s] = nxt[g][s];
+#pragma unroll
+      for (int s = 0; s < NTP; ++s) cpv[g][s] = npv[g][s];
+    }
     __syncthreads();  // LDS of the finished tile is rewritten below
     phase1(k);
   }
@@ -449,14 +514,14 @@ static hipError_t launch_fwd(const ScanFwdArgs &a, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int OP, bool ABAR>
+template <int OP, bool ABAR, bool CKPT>
 static hipError_t launch_vjp(const ScanVjpArgs &a, hipStream_t s) {
   static int64_t cap = 0;
-  if (cap == 0) cap = resident_blocks(k_scan_vjp<OP, ABAR>, Shape<OP>::THREADS);
+  if (cap == 0) cap = resident_blocks(k_scan_vjp<OP, ABAR, CKPT>, Shape<OP>::THREADS);
   if (cap == 0) return hipErrorInvalidDevice;
   const int64_t grid = a.ntiles < cap ? a.ntiles : cap;
-  hipLaunchKernelGGL((k_scan_vjp<OP, ABAR>), dim3((unsigned)grid), dim3(Shape<OP>::THREADS), 0,
-                     s, a);
+  hipLaunchKernelGGL((k_scan_vjp<OP, ABAR, CKPT>), dim3((unsigned)grid),
+                     dim3(Shape<OP>::THREADS), 0, s, a);
   return hipGetLastError();
 }
 
@@ -488,25 +553,30 @@ hipError_t scan_fwd_launch(int op, int64_t batch, int64_t n, const float *x0, co
 }
 
 hipError_t scan_vjp_launch(int op, int64_t batch, int64_t n, const float *x0, const float *x1,
-                           const float *saved, const float *yb0, const float *yb1, float *xb0,
-                           float *xb1, bool accumulate, void *ws, hipStream_t s) {
+                           const float *saved, const float *tp0, const float *tp1,
+                           const float *yb0, const float *yb1, float *xb0, float *xb1,
+                           bool accumulate, void *ws, hipStream_t s) {
   const int tile = scan_tile_size(op);
   const int tpr = (int)((n + tile - 1) / tile);
   const int64_t tiles = batch * (int64_t)tpr;
   if (tiles == 0) return hipSuccess;
   ScanVjpArgs a;
-  a.x0 = x0; a.x1 = x1; a.saved = saved; a.yb0 = yb0; a.yb1 = yb1; a.xb0 = xb0; a.xb1 = xb1;
+  a.x0 = x0; a.x1 = x1; a.saved = saved; a.tp0 = tp0; a.tp1 = tp1;
+  a.yb0 = yb0; a.yb1 = yb1; a.xb0 = xb0; a.xb1 = xb1;
   a.n = n; a.tpr = tpr; a.ntiles = tiles; a.accumulate = accumulate ? 1 : 0;
   a.ctl = reinterpret_cast<Ctl *>(ws);
   a.status = reinterpret_cast<uint64_t *>(static_cast<char *>(ws) + kCtlBytes);
+  const bool ck = tp0 != nullptr;
   switch (op) {
-  case ADD: return launch_vjp<ADD, false>(a, s);
-  case MUL: return launch_vjp<MUL, false>(a, s);
-  case MIN: return launch_vjp<MIN, false>(a, s);
-  case MAX: return launch_vjp<MAX, false>(a, s);
+  case ADD: return launch_vjp<ADD, false, false>(a, s);
+  case MUL: return ck ? launch_vjp<MUL, false, true>(a, s) : launch_vjp<MUL, false, false>(a, s);
+  case MIN: return ck ? launch_vjp<MIN, false, true>(a, s) : launch_vjp<MIN, false, false>(a, s);
+  case MAX: return ck ? launch_vjp<MAX, false, true>(a, s) : launch_vjp<MAX, false, false>(a, s);
   case LINREC:
-    return yb1 ? launch_vjp<LINREC, true>(a, s) : launch_vjp<LINREC, false>(a, s);
-  case MAT2: return launch_vjp<MAT2, false>(a, s);
+    if (yb1)
+      return ck ? launch_vjp<LINREC, true, true>(a, s) : launch_vjp<LINREC, true, false>(a, s);
+    return ck ? launch_vjp<LINREC, false, true>(a, s) : launch_vjp<LINREC, false, false>(a, s);
+  case MAT2: return ck ? launch_vjp<MAT2, false, true>(a, s) : launch_vjp<MAT2, false, false>(a, s);
   }
   return hipErrorInvalidValue;
 }

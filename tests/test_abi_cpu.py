@@ -86,10 +86,18 @@ def test_validation(L):
     assert L.pcad_scan_fwd(0, 1, 10, None, None, good, None, good, 0, good, 1 << 20, None) == 3
     assert L.pcad_scan_fwd(0, 1, 10, mis, None, good, None, good, 0, good, 1 << 20, None) == 4
     assert L.pcad_scan_fwd(0, 1, 10, good, None, good, None, good, 0, good, 8, None) == 6
-    assert L.pcad_scan_fwd(0, 1, 10, good, None, good, None, None, 0, good, 1 << 20, None) == 3
+    # saved may be NULL (checkpoint adjoint) but not misaligned
+    assert L.pcad_scan_fwd(0, 1, 10, good, None, good, None, mis, 0, good, 1 << 20, None) == 4
     assert L.pcad_scan_fwd(4, 1, 10, good, None, good, None, good, 0, good, 1 << 20, None) == 3
     assert L.pcad_scan_fwd(0, 1, 10, good, None, good, good, good, 0, good, 1 << 20, None) == 1
     assert L.pcad_scan_vjp(0, 1, 10, good, None, good, None, None, good, None, 0, good, 1 << 20, None) == 3
+    ck = L.pcad_scan_vjp_checkpoint
+    # tape required (except for +), A_bar needs the A tape, x1 only for linrec
+    assert ck(1, 1, 10, good, None, None, None, good, None, good, None, 0, good, 1 << 20, None) == 3
+    assert ck(4, 1, 10, good, None, good, None, good, good, good, good, 0, good, 1 << 20, None) == 3
+    assert ck(1, 1, 10, good, good, good, None, good, None, good, None, 0, good, 1 << 20, None) == 1
+    assert ck(2, 1, 10, good, None, good, good, good, None, good, None, 0, good, 1 << 20, None) == 1
+    assert ck(4, 1, 10, good, None, good, None, good, None, good, good, 0, good, 8, None) == 6
     assert L.pcad_reduce_fwd(1, 1, 10, good, None, good, None, 0, good, 1 << 20, None) == 3
     assert L.pcad_rbi_fwd(5, 1, 10, 4, good, good, good, good, 0, good, 1 << 20, None) == 2
     assert L.pcad_rbi_fwd(0, 1, 10, -4, good, good, good, good, 0, good, 1 << 20, None) == 1

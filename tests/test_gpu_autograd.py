@@ -1,0 +1,179 @@
+"""Autograd Functions over the HIP kernels against the oracle.
+
+The autograd workload (64 sequences of 2^16; loss = sum log|y| of the
+linear recurrence + sum over non-empty bins of max-by-index) runs in both
+saved-state forms; every Function is also checked on small random cases
+with a random cotangent.  The scan adjoint's seed is taken from autograd
+itself (a hook on y), so the oracle sees the float32 seed the kernels saw.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle.gate import RTOL, assert_gate
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ag():
+    import paper_2310_03568_amd as p
+    p.lib()
+    import paper_2310_03568_amd.autograd as a
+    return a
+
+
+def dev(x, grad=False):
+    t = torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    return t.requires_grad_(grad) if grad else t
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def run_loss(ag, w, mode):
+    a, b, v = dev(w["a"], True), dev(w["b"], True), dev(w["v"], True)
+    idx = dev(w["idx"])
+    seed = {}
+    y = ag.scan_linrec(a, b, mode=mode)
+    y.register_hook(lambda g: seed.setdefault("ybar", g.detach().clone()))
+    h = ag.reduce_by_index("max", idx, v, w["m"])
+    loss = torch.log(torch.abs(y)).sum() + torch.where(torch.isfinite(h), h, 0).sum()
+    loss.backward()
+    return host(a.grad), host(b.grad), host(v.grad), host(seed["ybar"]), float(loss)
+
+
+@pytest.mark.parametrize("mode", ["recompute", "checkpoint"])
+def test_autograd_workload(ag, mode):
+    from workloads import autograd
+    w = autograd()
+    B, T, m = w["a"].shape[0], w["a"].shape[1], w["m"]
+    print(f"autograd workload B={B} T={T} m={m} mode={mode}", flush=True)
+    torch.cuda.reset_peak_memory_stats()
+    ga, gb, gv, ybar, loss = run_loss(ag, w, mode)
+    print(f"peak bytes {torch.cuda.max_memory_allocated()} loss {loss}", flush=True)
+    ref_loss = 0.0
+    for s in range(B):
+        ref_loss += oracle.autograd_loss(w["a"][s], w["b"][s], w["v"][s], w["idx"][s], m)
+        ab, bb, vb, ca, cb, cv = oracle.autograd_grad(w["a"][s], w["b"][s], w["v"][s],
+                                                      w["idx"][s], m, ybar=ybar[s])
+        assert_gate(ga[s], ab, ca, RTOL["linrec"], what=f"a_bar seq {s}")
+        assert_gate(gb[s], bb, cb, RTOL["linrec"], what=f"b_bar seq {s}")
+        np.testing.assert_array_equal(gv[s], vb.astype(np.float32))
+    # the loss sums 4M float32 logs: compare in relative terms
+    assert abs(loss - ref_loss) <= 1e-4 * (abs(ref_loss) + B * T), (loss, ref_loss)
+
+
+def test_modes_agree(ag):
+    from workloads import autograd
+    w = autograd(B=4, T=1 << 14, m=1 << 14, seed=11)
+    r = run_loss(ag, w, "recompute")
+    c = run_loss(ag, w, "checkpoint")
+    np.testing.assert_array_equal(r[2], c[2])
+    for g, h, what in ((r[0], c[0], "a_bar"), (r[1], c[1], "b_bar")):
+        scale = np.abs(g).max()
+        assert np.max(np.abs(g - h)) <= 1e-4 * scale, what
+
+
+SCAN_OPS = ["add", "mul", "min", "max", "linrec", "mat2"]
+
+
+@pytest.mark.parametrize("op", SCAN_OPS)
+@pytest.mark.parametrize("mode", ["recompute", "checkpoint"])
+def test_scan_function(ag, op, mode):
+    rng = np.random.default_rng(hash((op, mode)) % 2**32)
+    n = 20_001
+    if op == "linrec":
+        x0 = rng.uniform(0.9, 1.0, (2, n)).astype(np.float32)
+        x1 = rng.standard_normal((2, n)).astype(np.float32)
+    elif op == "mat2":
+        x0 = (rng.standard_normal((2, n, 4)) * np.sqrt(0.5)).astype(np.float32)
+        x1 = None
+    else:
+        x0 = rng.uniform(0.5, 2.0, (2, n)).astype(np.float32)
+        x1 = None
+    X0 = dev(x0, True)
+    X1 = dev(x1, True) if x1 is not None else None
+    out = ag.scan(op, X0, X1, mode=mode, return_A=(op == "linrec"))
+    yb = rng.standard_normal(x0.shape).astype(np.float32)
+    if op == "linrec":
+        y, A = out
+        Ab = rng.standard_normal(x0.shape).astype(np.float32)
+        torch.autograd.backward([y, A], [dev(yb), dev(Ab)])
+    else:
+        out.backward(dev(yb))
+    g0 = host(X0.grad)
+    g1 = host(X1.grad) if X1 is not None else None
+    for r in range(2):
+        if op == "linrec":
+            xb, cx = oracle.scan_vjp(op, np.stack([Ab[r], yb[r]], 1), x0[r], x1[r])
+            assert_gate(g0[r], xb[:, 0], cx[:, 0], RTOL[op], what=f"{op} a_bar")
+            assert_gate(g1[r], xb[:, 1], cx[:, 1], RTOL[op], what=f"{op} b_bar")
+        elif op == "mat2":
+            xb, cx = oracle.scan_vjp(op, yb[r], x0[r])
+            assert_gate(g0[r], xb, cx, RTOL[op], max_range_exceeded=None, what="mat2")
+        else:
+            xb, cx = oracle.scan_vjp(op, yb[r], x0[r])
+            assert_gate(g0[r], xb[:, 0], cx[:, 0], RTOL[op], what=op)
+
+
+@pytest.mark.parametrize("op", SCAN_OPS)
+def test_reduce_function(ag, op):
+    rng = np.random.default_rng(len(op))
+    n = 30_001
+    x1 = None
+    if op == "linrec":
+        x0 = rng.uniform(0.9, 1.0, (3, n)).astype(np.float32)
+        x1 = rng.standard_normal((3, n)).astype(np.float32)
+    elif op == "mat2":
+        x0 = (rng.standard_normal((3, n, 4)) * np.sqrt(0.5)).astype(np.float32)
+    else:
+        x0 = rng.uniform(0.5, 2.0, (3, n)).astype(np.float32)
+        if op == "mul":
+            x0[1, 17] = 0.0
+    X0 = dev(x0, True)
+    X1 = dev(x1, True) if x1 is not None else None
+    y = ag.reduce(op, X0, X1)
+    yb = rng.standard_normal(tuple(y.shape)).astype(np.float32)
+    y.backward(dev(yb))
+    g0 = host(X0.grad)
+    for r in range(3):
+        xb, cx = oracle.reduce_vjp(op, yb[r], x0[r], None if x1 is None else x1[r])
+        if op == "linrec":
+            assert_gate(g0[r], xb[:, 0], cx[:, 0], RTOL[op], what="reduce linrec a_bar")
+            assert_gate(host(X1.grad)[r], xb[:, 1], cx[:, 1], RTOL[op], what="reduce linrec b_bar")
+        elif op == "mat2":
+            assert_gate(g0[r], xb, cx, RTOL[op], max_range_exceeded=None, what="reduce mat2")
+        else:
+            assert_gate(g0[r], xb[:, 0], cx[:, 0], RTOL[op], what=f"reduce {op}")
+
+
+@pytest.mark.parametrize("op", ["add", "mul", "min", "max"])
+def test_reduce_by_index_function(ag, op):
+    rng = np.random.default_rng(40 + len(op))
+    n, m = 50_000, 777
+    v = rng.uniform(0.5, 2.0, n).astype(np.float32)
+    if op in ("min", "max"):
+        v = np.floor(v * 8) / 8  # ties
+    if op == "mul":
+        v[rng.choice(n, 50, replace=False)] = 0.0
+    idx = rng.integers(-3, m + 3, n).astype(np.int32)  # some keys out of range
+    V = dev(v, True)
+    out = ag.reduce_by_index(op, dev(idx), V, m, return_argk=op in ("min", "max"))
+    h = out[0] if isinstance(out, tuple) else out
+    hb = rng.standard_normal(m).astype(np.float32)
+    h.backward(dev(hb))
+    vb, cv = oracle.rbi_vjp(op, idx, m, hb, v)
+    g = host(V.grad)
+    if op in ("add", "min", "max"):
+        np.testing.assert_array_equal(g, vb[:, 0].astype(np.float32))
+        if op != "add":
+            r = oracle.rbi_fwd(op, idx, m, v)
+            np.testing.assert_array_equal(host(out[1]).astype(np.int64), r["argk"])
+    else:
+        assert_gate(g, vb[:, 0], cv[:, 0], RTOL[op], what="rbi mul")

@@ -72,7 +72,7 @@ def rows(a, batch):
 SCAN_SIZES = [1, 2, 5, 63, 64, 65, 1023, 1024, 1025, 4095, 4096, 4097, 12293, 100_000]
 
 
-def check_scan(pcad, op, batch, n, seed, ties=False, abar=False):
+def check_scan(pcad, op, batch, n, seed, ties=False, abar=False, ckpt=False):
     rng = np.random.default_rng(seed)
     shape = (batch, n) if batch > 1 else (n,)
     x0, x1 = make_inputs(op, shape, rng, ties)
@@ -81,7 +81,13 @@ def check_scan(pcad, op, batch, n, seed, ties=False, abar=False):
     Ab = rng.standard_normal(shape).astype(np.float32) if abar else None
     X0, X1 = dev(x0), (dev(x1) if x1 is not None else None)
     y, A, saved = pcad.scan_fwd(op, X0, X1, want_A=(op == "linrec"))
-    g = pcad.scan_vjp(op, X0, X1, saved, dev(yb), dev(Ab) if abar else None)
+    if ckpt:
+        # the checkpoint form reads y (and A) instead of the tile prefixes;
+        # the linear recurrence's offsets are not passed at all
+        g = pcad.scan_vjp_checkpoint(op, X0, None, y, A if abar else None, dev(yb),
+                                     dev(Ab) if abar else None)
+    else:
+        g = pcad.scan_vjp(op, X0, X1, saved, dev(yb), dev(Ab) if abar else None)
     y = host(y)
     A = host(A) if A is not None else None
     g = [host(t) for t in g] if op == "linrec" else host(g)
@@ -133,6 +139,23 @@ def test_scan_batched_misaligned(pcad, op):
 def test_scan_ties(pcad, op):
     check_scan(pcad, op, 1, 50_000, seed=11, ties=True)
     check_scan(pcad, op, 2, 4099, seed=12, ties=True)
+
+
+@pytest.mark.parametrize("op", ALL)
+@pytest.mark.parametrize("n", [1, 5, 65, 4097, 12293, 100_000])
+def test_scan_checkpoint(pcad, op, n):
+    check_scan(pcad, op, 1, n, seed=100 + n, ckpt=True)
+
+
+@pytest.mark.parametrize("op", ALL)
+def test_scan_checkpoint_batched_misaligned(pcad, op):
+    check_scan(pcad, op, 3, 5001, seed=17, ckpt=True)
+
+
+def test_scan_checkpoint_ties_and_abar(pcad):
+    check_scan(pcad, "min", 2, 20_001, seed=18, ties=True, ckpt=True)
+    check_scan(pcad, "max", 1, 20_001, seed=19, ties=True, ckpt=True)
+    check_scan(pcad, "linrec", 2, 9001, seed=20, abar=True, ckpt=True)
 
 
 def test_scan_linrec_abar(pcad):
