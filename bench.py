@@ -131,6 +131,67 @@ def bench_segmented(args, pcad, torch, np):
                      "combinator": "scan+reduce_by_index", "op": "linrec+min"})
 
 
+def bench_autograd(args, pcad, torch, np):
+    """64 sequences of 2^16: loss = sum log|linrec scan| + sum over non-empty
+    bins of max-by-index (65536 bins); a step is the loss forward and its
+    backward through the autograd Functions."""
+    import paper_2310_03568_amd.autograd as ag
+    from workloads import autograd
+    w = autograd()
+    dev = torch.device("cuda:0")
+    a = torch.from_numpy(w["a"]).to(dev).requires_grad_(True)
+    bb = torch.from_numpy(w["b"]).to(dev).requires_grad_(True)
+    v = torch.from_numpy(w["v"]).to(dev).requires_grad_(True)
+    idx = torch.from_numpy(w["idx"]).to(dev)
+    B, T, m = a.shape[0], a.shape[1], w["m"]
+    state = {}
+
+    def fwd():
+        for t in (a, bb, v):
+            t.grad = None
+        y = ag.scan_linrec(a, bb, mode=args.mode)
+        h = ag.reduce_by_index("max", idx, v, m)
+        state["loss"] = torch.log(torch.abs(y)).sum() + torch.where(torch.isfinite(h), h, 0).sum()
+        return None, None, None
+
+    def bwd(_saved):
+        state.pop("loss").backward()
+
+    n = B * T
+    return dict(n=n, fwd=fwd, bwd=bwd, inputs=w, autograd=(a, bb, v, idx, m),
+                # forward: scan reads a, b, writes y; log|y| and its sum read y;
+                # histogram reads v, idx (+ 12 B per bin); backward: scan
+                # adjoint reads a, b, y_bar, writes a_bar, b_bar; v_bar one-hot
+                bytes_fwd=(12 + 8 + 8) * n, bytes_bwd=(20 + 8) * n,
+                kernel="k_scan_vjp<LINREC>", out=lambda: (a.grad, bb.grad, v.grad),
+                cfg={"workload": f"autograd: {B} sequences x {T}, loss = sum log|linrec scan| + "
+                                 f"sum of non-empty max-by-index ({m} bins), fwd+bwd, fp32, "
+                                 f"saved state: {args.mode}",
+                     "batch": B, "seq_len": T, "bins": m, "mode": args.mode})
+
+
+def autograd_extras(b, torch, np):
+    """Peak device memory of one loss forward + backward in each saved-state
+    form (allocations above what is resident before the step)."""
+    import paper_2310_03568_amd.autograd as ag
+    a, bb, v, idx, m = b["autograd"]
+    out = {}
+    for mode in ("recompute", "checkpoint"):
+        for t in (a, bb, v):
+            t.grad = None
+        torch.cuda.synchronize()
+        base = torch.cuda.memory_allocated()
+        torch.cuda.reset_peak_memory_stats()
+        y = ag.scan_linrec(a, bb, mode=mode)
+        h = ag.reduce_by_index("max", idx, v, m)
+        loss = torch.log(torch.abs(y)).sum() + torch.where(torch.isfinite(h), h, 0).sum()
+        del y, h
+        loss.backward()
+        torch.cuda.synchronize()
+        out[f"peak_extra_bytes_{mode}"] = int(torch.cuda.max_memory_allocated() - base)
+    return out
+
+
 def segmented_extras(b, torch, np, reps=3):
     """Single-launch (forward+adjoint) graph time and the per-instance
     plain-call baseline on the same buffers."""
@@ -223,15 +284,58 @@ def cpu_baseline_and_parity(name, b, np):
     return cpu, par
 
 
+def autograd_parity(b, torch, np):
+    """Oracle gradient of every sequence (seeded with the float32 1/y that the
+    last step fed the scan adjoint, recomputed here from the GPU's y) against
+    the autograd gradients; the oracle's time is the cpu_baseline."""
+    import oracle
+    import paper_2310_03568_amd.autograd as ag
+    from oracle.gate import gate
+    w = b["inputs"]
+    a, bb, v, idx, m = b["autograd"]
+    for t in (a, bb, v):
+        t.grad = None
+    y = ag.scan_linrec(a, bb, mode="recompute")
+    seed = {}
+    y.register_hook(lambda g: seed.setdefault("g", g.detach().clone()))
+    h = ag.reduce_by_index("max", idx, v, m)
+    (torch.log(torch.abs(y)).sum() + torch.where(torch.isfinite(h), h, 0).sum()).backward()
+    torch.cuda.synchronize()
+    ga, gb, gv = (t.grad.cpu().numpy() for t in (a, bb, v))
+    yb = seed["g"].cpu().numpy()
+    B = ga.shape[0]
+    ok, worst, rx = True, 0.0, 0
+    t0 = time.perf_counter()
+    for s in range(B):
+        ab, bbar, vb, ca, cb, cv = oracle.autograd_grad(w["a"][s], w["b"][s], w["v"][s], w["idx"][s],
+                                                        m, ybar=yb[s])
+        for g, r, c in ((ga[s], ab, ca), (gb[s], bbar, cb)):
+            res = gate(g, r, c, 1e-4)
+            ok = ok and res["ok"]
+            worst = max(worst, res["max_rel"])
+            rx += res["n_range_exceeded"]
+        ok = ok and bool(np.array_equal(gv[s], vb.astype(np.float32)))
+    dt = time.perf_counter() - t0
+    n = b["n"]
+    cpu = {"value": n / dt, "unit": "elem/s", "cores": 1, "kind": "oracle",
+           "sample": f"whole workload ({B} sequences): oracle forward + gradient, fp64, {dt:.2f} s"}
+    return cpu, dict(ok=ok and rx == 0, max_rel=worst, range_exceeded=rx)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="segmented", choices=["segmented", "linrec", "mat2"])
+    ap.add_argument("--workload", default="segmented",
+                    choices=["segmented", "linrec", "mat2", "autograd"])
+    ap.add_argument("--mode", default="recompute", choices=["recompute", "checkpoint"],
+                    help="saved-state form of the autograd workload's scan")
     ap.add_argument("--segments", type=int, default=4096, help="instances of the segmented workload")
     ap.add_argument("--n", type=int, default=0, help="override the element count")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the single-graph and per-instance comparison runs (profiling)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after the timed region, run a plain 256 MiB device copy 3 times "
                          "(reference for scaling the HBM byte counters)")
@@ -246,8 +350,8 @@ def main():
     import paper_2310_03568_amd as pcad
 
     pcad.lib()
-    b = {"linrec": bench_linrec, "mat2": bench_mat2,
-         "segmented": bench_segmented}[args.workload](args, pcad, torch, np)
+    b = {"linrec": bench_linrec, "mat2": bench_mat2, "segmented": bench_segmented,
+         "autograd": bench_autograd}[args.workload](args, pcad, torch, np)
     torch.cuda.synchronize()
 
     for _ in range(args.warmup):
@@ -285,12 +389,16 @@ def main():
         del src, dst
 
     extras = {}
-    if args.workload == "segmented":
+    if args.workload == "segmented" and not args.no_extras:
         extras = segmented_extras(b, torch, np)
+    if args.workload == "autograd" and not args.no_extras:
+        extras = autograd_extras(b, torch, np)
     cpu, par = (None, None)
     if not args.no_cpu:
         if args.workload == "segmented":
             cpu, par = segmented_parity(b, torch, np)
+        elif args.workload == "autograd":
+            cpu, par = autograd_parity(b, torch, np)
         else:
             cpu, par = cpu_baseline_and_parity(args.workload, b, np)
 

@@ -419,6 +419,7 @@ struct pcad_plan {
   std::vector<int32_t> item_seg, seg_item0;
   // workspace layout
   size_t ws_status = 0, ws_keys = 0, ws_tab = 0, ws_plain = 0, ws_bytes = 0;
+  size_t tab_off = 0, tab_item0 = 0;  // table offsets inside the table region
   size_t sv_carry = 0, sv_plain = 0, saved_bytes = 0;
   size_t plain_ws_bytes = 0;
   // bound buffers
@@ -512,7 +513,10 @@ int pcad_plan_create(pcad_plan **out, int64_t nseg, const int64_t *offsets, int6
   p->ws_keys = o;
   o = align256(o + (size_t)nseg * m * sizeof(uint64_t));
   p->ws_tab = o;
-  o = align256(o + (size_t)p->item_seg.size() * 4 + (size_t)(nseg + 1) * 8 + (size_t)(nseg + 1) * 4 + 64);
+  // the three tables, each starting on a 256-byte boundary (as bound)
+  p->tab_off = align256((size_t)p->item_seg.size() * 4);
+  p->tab_item0 = p->tab_off + align256((size_t)(nseg + 1) * 8);
+  o = align256(o + p->tab_item0 + (size_t)(nseg + 1) * 4);
   p->ws_plain = o;
   size_t sv = 0;
   p->sv_carry = 0;
@@ -577,10 +581,8 @@ int pcad_plan_bind(pcad_plan *p, const float *a, const float *b, const int32_t *
   // device tables
   char *tab = p->ws + p->ws_tab;
   int32_t *d_item_seg = reinterpret_cast<int32_t *>(tab);
-  int64_t *d_off = reinterpret_cast<int64_t *>(
-      tab + align256((size_t)p->item_seg.size() * 4));
-  int32_t *d_item0 = reinterpret_cast<int32_t *>(
-      reinterpret_cast<char *>(d_off) + align256((size_t)(p->S + 1) * 8));
+  int64_t *d_off = reinterpret_cast<int64_t *>(tab + p->tab_off);
+  int32_t *d_item0 = reinterpret_cast<int32_t *>(tab + p->tab_item0);
   int st = plan_hip(hipMemcpyAsync(d_item_seg, p->item_seg.data(), p->item_seg.size() * 4,
                                    hipMemcpyHostToDevice, s));
   if (st == PCAD_OK)

@@ -155,22 +155,29 @@ struct Fwd<MAT2> {
 // lives in group e / (THREADS*EPL), lane (e % (THREADS*EPL)) / EPL, slot
 // e % EPL.
 // ---------------------------------------------------------------------------
-// Threads per block and groups per thread of the scan kernels (a tile is
-// THREADS * EPL * K elements); build-time knobs for tile-shape sweeps.
-#ifndef PCAD_SCAN_THREADS
-#define PCAD_SCAN_THREADS 1024
+// Scan tile shapes.  A tile holds PCAD_SCAN_TILE elements (a quarter of
+// that for MAT2, whose elements are 16 bytes); the forward and the adjoint
+// kernels may use different block sizes (DIR 0 / 1) over the same tiles, so
+// the adjoint reads the forward's per-tile prefixes.  Build-time knobs for
+// shape sweeps.
+#ifndef PCAD_SCAN_TILE
+#define PCAD_SCAN_TILE 8192
 #endif
-#ifndef PCAD_SCAN_K
-#define PCAD_SCAN_K 2
+#ifndef PCAD_FWD_THREADS
+#define PCAD_FWD_THREADS 1024
+#endif
+#ifndef PCAD_VJP_THREADS
+#define PCAD_VJP_THREADS 512
 #endif
 
-template <int OP>
+template <int OP, int DIR = 0>
 struct Shape {
-  static constexpr int THREADS = PCAD_SCAN_THREADS;
-  static constexpr int W = THREADS / WAVE;
   static constexpr int EPL = (OP == MAT2) ? 1 : 4;
-  static constexpr int K = PCAD_SCAN_K;
-  static constexpr int TILE = THREADS * EPL * K;
+  static constexpr int TILE = (OP == MAT2) ? PCAD_SCAN_TILE / 4 : PCAD_SCAN_TILE;
+  static constexpr int THREADS = DIR == 0 ? PCAD_FWD_THREADS : PCAD_VJP_THREADS;
+  static constexpr int W = THREADS / WAVE;
+  static constexpr int K = TILE / (THREADS * EPL);
+  static_assert(K >= 1 && K * THREADS * EPL == TILE, "tile must be whole groups of the block");
 };
 
 // 16-byte load of one group of one stream.  `S` floats per element.  When
@@ -458,12 +465,15 @@ constexpr int lookback_q() {
 // base + L*Q + 1 .. base + L*Q + Q, so one round trip covers 64*Q tiles.
 // Returns (in every lane) the combination of all predecessors, earliest
 // first, built from the nearest published inclusive prefix and the
-// aggregates after it.  Every wait is bounded: after kSpinLimit polls, or as
-// soon as any block has flagged an error, the wave stops waiting (the result
-// is then garbage and the error flag tells the host).
+// aggregates after it.  When no inclusive prefix lies within dist_max, the
+// result is the combination of the dist_max aggregates and *hit (if given)
+// is set false; the caller then supplies the prefix before the window.
+// Every wait is bounded: after kSpinLimit polls, or as soon as any block has
+// flagged an error, the wave stops waiting (the result is then garbage and
+// the error flag tells the host).
 template <class Tr>
 __device__ typename Tr::T lookback(const uint64_t *st, int64_t tile, int dir, int dist_max,
-                                   uint32_t tag, Ctl *ctl) {
+                                   uint32_t tag, Ctl *ctl, bool *hit = nullptr) {
   using T = typename Tr::T;
   using P = typename Tr::P;
   constexpr int NA = Tr::NA, NP = Tr::NP, NW = NA + NP;
@@ -542,8 +552,12 @@ __device__ typename Tr::T lookback(const uint64_t *st, int64_t tile, int dir, in
     const T win = readlane(wave_reduce_desc<Tr>(v), 0);
     acc = have ? Tr::comb(win, acc) : win;
     have = true;
-    if (plane < WAVE) break;
+    if (plane < WAVE) {
+      if (hit) *hit = true;
+      return acc;
+    }
   }
+  if (hit) *hit = false;
   return acc;
 }
 

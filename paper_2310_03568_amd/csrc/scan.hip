@@ -70,53 +70,80 @@ __global__ __launch_bounds__(Shape<OP>::THREADS) void k_scan_fwd(ScanFwdArgs a) 
   };
 
   if (tid == 0) s_epoch = ctl_load(&a.ctl->epoch);
-  int64_t t = blockIdx.x;
+  const int64_t G = gridDim.x;
+  int64_t t = blockIdx.x;  // the tile whose outputs are pending
   float4 cur[K][NIN];
   load(t, cur);
   __syncthreads();
   const uint32_t tag = s_epoch + 1;
 
-  T loc[K][EPL];
-  T incl[K];
-  T agg = Op::id();  // tile aggregate, held by wave 0
-  // thread, wave and block scan of the tile in `cur`; publishes its aggregate
-  // (or, for a row's first tile, its inclusive prefix)
-  auto phase1 = [&](int64_t tt) {
+  // Scans the tile in `cur`: thread-serial inclusive values (lc), the
+  // exclusive prefix of each thread's group inside the tile (thr), and, in
+  // wave 0, the tile aggregate (ag), which is published (a row's first tile
+  // publishes it as its inclusive prefix).
+  auto phase1 = [&](int64_t tt, T (&thr)[K], T (&lc)[K][EPL], T &ag) {
     const TileInfo ti = tile_info(tt, a.n, a.tpr, TILE);
+    T incl[K];
 #pragma unroll
     for (int g = 0; g < K; ++g) {
       T acc = Io::elem(cur[g], 0);
-      loc[g][0] = acc;
+      lc[g][0] = acc;
 #pragma unroll
       for (int j = 1; j < EPL; ++j) {
         acc = Op::comb(acc, Io::elem(cur[g], j));
-        loc[g][j] = acc;
+        lc[g][j] = acc;
       }
       incl[g] = wave_scan_fwd<Op>(acc);
       if (lane == WAVE - 1) s_tot[g][wave] = incl[g];
     }
     __syncthreads();
     if (wave == 0) {
-      agg = wave0_block_prefix<Op, K, W, false>(s_tot, s_pre, Op::id());
+      ag = wave0_block_prefix<Op, K, W, false>(s_tot, s_pre, Op::id());
       uint64_t *st = a.status + ti.tile * (Op::NA + Op::NP);
-      if (lane == 0) publish<N>(ti.lt == 0 ? st + Op::NA : st, tag, agg);
+      if (lane == 0) publish<N>(ti.lt == 0 ? st + Op::NA : st, tag, ag);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int g = 0; g < K; ++g) {
+      T ex = shfl_up(incl[g], 1);
+      if (lane == 0) ex = Op::id();
+      thr[g] = Op::comb(s_pre[g][wave], ex);
     }
   };
 
-  phase1(t);
+  // The look-back of a tile runs one iteration after its aggregate was
+  // published: in between, the block scans and publishes its next tile, so
+  // the aggregates the look-back needs (the other blocks' tiles of the same
+  // round) have long been published when it polls.
+  T pthr[K], ploc[K][EPL];
+  T pagg = Op::id();       // wave 0: aggregate of the pending tile
+  T prev_incl = Op::id();  // wave 0: inclusive prefix of the block's previous tile
+  phase1(t, pthr, ploc, pagg);
+  int64_t tn = t + G;
+  if (tn < a.ntiles) load(tn, cur);
   for (;;) {
-    const TileInfo ti = tile_info(t, a.n, a.tpr, TILE);
-    const int64_t tn = t + gridDim.x;
     const bool more = tn < a.ntiles;
-    if (more) load(tn, cur);  // the current tile lives on in loc/incl
+    T nthr[K], nloc[K][EPL];
+    T nagg = Op::id();
+    if (more) {
+      phase1(tn, nthr, nloc, nagg);
+      if (tn + G < a.ntiles) load(tn + G, cur);
+    }
 
+    const TileInfo ti = tile_info(t, a.n, a.tpr, TILE);
     if (wave == 0) {
       T c = Op::id();
       if (ti.lt > 0) {
-        c = lookback<Op>(a.status, ti.tile, +1, ti.lt, tag, a.ctl);
+        // predecessors at distances 1..G-1 belong to other blocks; the one at
+        // distance G is this block's previous tile, whose prefix is known
+        const int win = ti.lt < G ? ti.lt : (int)(G - 1);
+        bool hit = false;
+        if (win > 0) c = lookback<Op>(a.status, ti.tile, +1, win, tag, a.ctl, &hit);
+        if (!hit) c = win > 0 ? Op::comb(prev_incl, c) : prev_incl;
         if (lane == 0)
-          publish<N>(a.status + ti.tile * (Op::NA + Op::NP) + Op::NA, tag, Op::comb(c, agg));
+          publish<N>(a.status + ti.tile * (Op::NA + Op::NP) + Op::NA, tag, Op::comb(c, pagg));
       }
+      prev_incl = Op::comb(c, pagg);
       if (lane == 0) {
         s_carry = c;
         if (ti.lt == a.tpr - 1) ctl_row_done(a.ctl, (unsigned)(a.ntiles / a.tpr), tag);
@@ -125,9 +152,8 @@ __global__ __launch_bounds__(Shape<OP>::THREADS) void k_scan_fwd(ScanFwdArgs a) 
           for (int i = 0; i < N; ++i) a.saved[ti.tile * N + i] = c.f[i];
         }
         if (REDUCE && ti.lt == a.tpr - 1) {
-          const T tot = Op::comb(c, agg);
 #pragma unroll
-          for (int i = 0; i < N; ++i) a.total[ti.row * N + i] = tot.f[i];
+          for (int i = 0; i < N; ++i) a.total[ti.row * N + i] = prev_incl.f[i];
         }
       }
     }
@@ -137,19 +163,17 @@ __global__ __launch_bounds__(Shape<OP>::THREADS) void k_scan_fwd(ScanFwdArgs a) 
       const T carry = s_carry;
 #pragma unroll
       for (int g = 0; g < K; ++g) {
-        T ex = shfl_up(incl[g], 1);
-        if (lane == 0) ex = Op::id();
-        const T full = Op::comb(Op::comb(carry, s_pre[g][wave]), ex);
+        const T full = Op::comb(carry, pthr[g]);
         const int el = g * TH * EPL + tid * EPL;
         const int v = ti.valid - el;
-        if (OP == MAT2) {
-          const T o = Op::comb(full, loc[g][0]);
+        if constexpr (OP == MAT2) {
+          const T o = Op::comb(full, ploc[g][0]);
           store_group<4>(a.y0, ti.base + el, v, true, make_float4(o.f[0], o.f[1], o.f[2], o.f[3]));
         } else {
           float4 o0, o1;
 #pragma unroll
           for (int j = 0; j < EPL; ++j) {
-            const T o = Op::comb(full, loc[g][j]);
+            const T o = Op::comb(full, ploc[g][j]);
             if (OP == LINREC) {
               f4set(o0, j, o.f[1]);
               f4set(o1, j, o.f[0]);
@@ -163,9 +187,17 @@ __global__ __launch_bounds__(Shape<OP>::THREADS) void k_scan_fwd(ScanFwdArgs a) 
       }
     }
     if (!more) break;
+    // s_carry is rewritten by wave 0 only after the barriers of the next
+    // phase1, which every thread reaches after reading it above
     t = tn;
-    __syncthreads();  // s_pre / s_carry of the finished tile are rewritten below
-    phase1(t);
+    tn = t + G;
+#pragma unroll
+    for (int g = 0; g < K; ++g) {
+      pthr[g] = nthr[g];
+#pragma unroll
+      for (int j = 0; j < EPL; ++j) ploc[g][j] = nloc[g][j];
+    }
+    pagg = nagg;
   }
 }
 
@@ -190,15 +222,15 @@ struct ScanVjpArgs {
 // (the tape) instead of being recomputed inside the tile from the saved tile
 // prefix.  A linear recurrence with a tape never reads its offsets b.
 template <int OP, bool ABAR, bool CKPT>
-__global__ __launch_bounds__(Shape<OP>::THREADS) void k_scan_vjp(ScanVjpArgs a) {
+__global__ __launch_bounds__((Shape<OP, 1>::THREADS)) void k_scan_vjp(ScanVjpArgs a) {
   using Op = FwdLB<OP>;
   using FT = typename Op::T;
   using A = Adj<OP, ABAR>;
   using M = typename A::M;
   using MT = typename M::T;
   using Io = IO<OP>;
-  constexpr int EPL = Shape<OP>::EPL, K = Shape<OP>::K, TILE = Shape<OP>::TILE;
-  constexpr int TH = Shape<OP>::THREADS, W = Shape<OP>::W;
+  constexpr int EPL = Shape<OP, 1>::EPL, K = Shape<OP, 1>::K, TILE = Shape<OP, 1>::TILE;
+  constexpr int TH = Shape<OP, 1>::THREADS, W = Shape<OP, 1>::W;
   constexpr int NIN = Io::NIN, S = Io::S, N = Fwd<OP>::N;
   constexpr bool RECOMP = A::NEEDS_PREFIX && !CKPT;
   constexpr bool TAPE = A::NEEDS_PREFIX && CKPT;
@@ -517,11 +549,11 @@ static hipError_t launch_fwd(const ScanFwdArgs &a, hipStream_t s) {
 template <int OP, bool ABAR, bool CKPT>
 static hipError_t launch_vjp(const ScanVjpArgs &a, hipStream_t s) {
   static int64_t cap = 0;
-  if (cap == 0) cap = resident_blocks(k_scan_vjp<OP, ABAR, CKPT>, Shape<OP>::THREADS);
+  if (cap == 0) cap = resident_blocks(k_scan_vjp<OP, ABAR, CKPT>, Shape<OP, 1>::THREADS);
   if (cap == 0) return hipErrorInvalidDevice;
   const int64_t grid = a.ntiles < cap ? a.ntiles : cap;
   hipLaunchKernelGGL((k_scan_vjp<OP, ABAR, CKPT>), dim3((unsigned)grid),
-                     dim3(Shape<OP>::THREADS), 0, s, a);
+                     dim3(Shape<OP, 1>::THREADS), 0, s, a);
   return hipGetLastError();
 }
 

@@ -150,3 +150,32 @@ def test_plan_argument_errors(pcad):
     assert L.pcad_plan_create(ctypes.byref(h), 2, off.ctypes.data, 8, 0) == 0
     assert L.pcad_plan_run(h, 1, None) == 1  # not bound
     L.pcad_plan_destroy(h)
+
+
+def test_plan_many_instances_both_paths_interleaved(pcad):
+    """4096 short instances (the instance count of the segmented workload):
+    graph and per-instance runs interleaved on one plan, each checked; the
+    per-instance calls share the plan's workspace with the graph kernels'
+    instance tables, which must stay intact."""
+    from workloads import segment_lengths
+    rng = np.random.default_rng(41)
+    L = list(segment_lengths(rng, 4096, median=96, cap=4000))
+    w = workload(L, 512, seed=42)
+    plan = pcad.BatchedPlan(w["offsets"], 512, per_segment=True)
+    plan.load(a=w["a"], b=w["b"], idx=w["idx"], ybar=w["ybar"], hbar=w["hbar"])
+    N = plan.n
+    f = None
+    for rnd in range(2):
+        for path in ("graph", "per-instance"):
+            run = plan.run if path == "graph" else plan.run_per_segment
+            run(pcad.PHASE_FWD)
+            torch.cuda.synchronize()
+            f = check_forward(pcad, w, plan.y[:N].cpu().numpy(), plan.h.cpu().numpy(),
+                              plan.argk.cpu().numpy(), f"{path} fwd round {rnd}")
+            plan.argk.copy_(torch.from_numpy(f["argk"].reshape(-1).astype(np.int32)))
+            run(pcad.PHASE_BWD)
+            torch.cuda.synchronize()
+            check_backward(w, f, plan.abar[:N].cpu().numpy(), plan.bbar[:N].cpu().numpy(),
+                           f"{path} bwd round {rnd}")
+    assert plan.ws_error() == 0
+    plan.close()
