@@ -223,7 +223,7 @@ int pcad_rbi_vjp(int op, int64_t batch, int64_t n, int64_t m, const int32_t *idx
  *
  *   offsets: HOST array of nseg+1 int64 element offsets (offsets[0] = 0,
  *            non-decreasing); instance s is [offsets[s], offsets[s+1]).
- *   m:       bins per instance, 1 <= m <= 4096.
+ *   m:       bins per instance, 1 <= m <= 1024 (PCAD_E_SIZE above).
  *   flags:   PCAD_PLAN_PER_SEGMENT also sizes the workspace for
  *            pcad_plan_run_per_segment (the same work as plain per-instance
  *            calls, for comparison).

@@ -24,15 +24,25 @@
 
 namespace pcad {
 
-constexpr int SEG_TH = 1024;
-constexpr int SEG_K = 2;
+constexpr int SEG_TH = 512;
+constexpr int SEG_K = 4;
 constexpr int SEG_EPL = 4;
 constexpr int SEG_W = SEG_TH / WAVE;
 constexpr int SEG_T = SEG_TH * SEG_EPL * SEG_K;
-constexpr int SEG_MAX_BINS = 4096;
+constexpr int SEG_MAX_BINS = 1024;
+
+// one record per work item, built on the host at bind time
+struct alignas(16) ItemRec {
+  int64_t wbase;   // first element of the aligned window
+  int64_t start;   // first element of the instance
+  int32_t lo, hi;  // the instance's part of the window, relative to wbase
+  int32_t s;       // instance
+  int32_t li, nli; // item index within the instance, items of the instance
+  int32_t len;     // elements of the instance
+};
 
 struct SegTables {
-  const int32_t *item_seg;   // [nitems] instance of each item
+  const ItemRec *items;      // [nitems]
   const int64_t *seg_off;    // [S+1] element offsets
   const int32_t *seg_item0;  // [S+1] first item of each instance
 };
@@ -46,18 +56,17 @@ struct SegItem {
 };
 
 __device__ __forceinline__ SegItem seg_item(const SegTables &t, int64_t item) {
-  SegItem r;
-  r.s = t.item_seg[item];
-  r.start = t.seg_off[r.s];
-  const int64_t en = t.seg_off[r.s + 1];
-  r.len = en - r.start;
-  const int i0 = t.seg_item0[r.s];
-  r.li = (int)(item - i0);
-  r.nli = t.seg_item0[r.s + 1] - i0;
-  r.wbase = (r.start / SEG_T + r.li) * (int64_t)SEG_T;
-  r.lo = r.start > r.wbase ? r.start : r.wbase;
-  r.hi = en < r.wbase + SEG_T ? en : r.wbase + SEG_T;
-  return r;
+  const ItemRec r = t.items[item];
+  SegItem q;
+  q.s = r.s;
+  q.li = r.li;
+  q.nli = r.nli;
+  q.wbase = r.wbase;
+  q.lo = r.wbase + r.lo;
+  q.hi = r.wbase + r.hi;
+  q.start = r.start;
+  q.len = r.len;
+  return q;
 }
 
 // elements [e, e+4) of which those in [lo, hi) are read; `fill` elsewhere
@@ -102,6 +111,7 @@ __device__ __forceinline__ int i4get(const int4 &v, int j) {
 // ---------------------------------------------------------------------------
 struct SegFwdArgs {
   SegTables tab;
+  int64_t nitems;
   int S, m;
   int nrows;           // instances with at least one element
   const float *a, *b;
@@ -114,6 +124,12 @@ struct SegFwdArgs {
   uint64_t *status;
 };
 
+// Persistent: the grid holds the resident blocks; block b takes items
+// b, b+G, ... in item order.  As in the plain scan, an item's look-back runs
+// one iteration after its aggregate was published (the block scans and
+// publishes its next item in between).  The pending item's item-local
+// prefixes and keys wait in LDS; its outputs and LDS sub-histogram follow
+// the look-back.
 __global__ __launch_bounds__(SEG_TH) void k_seg_fwd(SegFwdArgs a) {
   using Op = FwdLB<LINREC>;
   using T = Op::T;
@@ -124,98 +140,177 @@ __global__ __launch_bounds__(SEG_TH) void k_seg_fwd(SegFwdArgs a) {
   __shared__ T s_carry;
   __shared__ unsigned s_epoch;
   __shared__ unsigned long long s_keys[SEG_MAX_BINS];
+  __shared__ float4 s_pv[SEG_T / 2];  // pending item: (A, y) item-local prefix per element
+  __shared__ int4 s_pix[SEG_T / 4];   // pending item: bin keys
 
   const int tid = threadIdx.x, lane = lane_id(), wave = tid / WAVE;
+  const int64_t G = gridDim.x;
   if (tid == 0) s_epoch = ctl_load(&a.ctl->epoch);
-  const SegItem it = seg_item(a.tab, blockIdx.x);
-  for (int k = tid; k < a.m; k += TH) s_keys[k] = key_init<MIN>();
 
-  float4 av[K], bv[K];
-  int4 iv[K];
+  float4 ca[K], cb[K];  // the prefetched item
+  int4 ci[K];
+  auto load = [&](const SegItem &it) {
 #pragma unroll
-  for (int g = 0; g < K; ++g) {
-    const int64_t e = it.wbase + g * TH * EPL + tid * EPL;
-    av[g] = ld_range(a.a, e, it.lo, it.hi, 1.0f);
-    bv[g] = ld_range(a.b, e, it.lo, it.hi, 0.0f);
-    iv[g] = ld_range_i(a.idx, e, it.lo, it.hi);
-  }
-  T loc[K][EPL];
-  T incl[K];
-#pragma unroll
-  for (int g = 0; g < K; ++g) {
-    T acc = {{f4get(av[g], 0), f4get(bv[g], 0)}};
-    loc[g][0] = acc;
-#pragma unroll
-    for (int j = 1; j < EPL; ++j) {
-      acc = Op::comb(acc, T{{f4get(av[g], j), f4get(bv[g], j)}});
-      loc[g][j] = acc;
+    for (int g = 0; g < K; ++g) {
+      const int64_t e = it.wbase + g * TH * EPL + tid * EPL;
+      ca[g] = ld_range(a.a, e, it.lo, it.hi, 1.0f);
+      cb[g] = ld_range(a.b, e, it.lo, it.hi, 0.0f);
+      ci[g] = ld_range_i(a.idx, e, it.lo, it.hi);
     }
-    incl[g] = wave_scan_fwd<Op>(acc);
-    if (lane == WAVE - 1) s_tot[g][wave] = incl[g];
-  }
+  };
+  int64_t i = blockIdx.x;  // the item whose outputs are pending
+  SegItem it = seg_item(a.tab, i);
+  load(it);
   __syncthreads();
   const uint32_t tag = s_epoch + 1;
 
-  if (wave == 0) {
-    const T tile_agg = wave0_block_prefix<Op, K, W, false>(s_tot, s_pre, Op::id());
-    uint64_t *st = a.status + (int64_t)blockIdx.x * (Op::NA + Op::NP);
-    T c = Op::id();
-    if (it.li == 0) {
-      if (lane == 0) publish<2>(st + Op::NA, tag, tile_agg);
-    } else {
-      if (lane == 0) publish<2>(st, tag, tile_agg);
-      c = lookback<Op>(a.status, blockIdx.x, +1, it.li, tag, a.ctl);
-      if (lane == 0) publish<2>(st + Op::NA, tag, Op::comb(c, tile_agg));
-    }
-    if (lane == 0) {
-      s_carry = c;
-      if (it.li == it.nli - 1) ctl_row_done(a.ctl, (unsigned)a.nrows, tag);
-      a.carry[(int64_t)blockIdx.x * 2 + 0] = c.f[0];
-      a.carry[(int64_t)blockIdx.x * 2 + 1] = c.f[1];
-    }
-  }
-  __syncthreads();
-  const T carry = s_carry;
-
+  // scans the prefetched item into item-local inclusive prefixes (v) and, in
+  // wave 0, the item aggregate (ag), which is published (an instance's first
+  // item publishes it as its inclusive prefix)
+  auto phase1 = [&](const SegItem &jt, int64_t item, T (&v)[K][EPL], T &ag) {
+    T incl[K];
 #pragma unroll
-  for (int g = 0; g < K; ++g) {
-    T ex = shfl_up(incl[g], 1);
-    if (lane == 0) ex = Op::id();
-    const T full = Op::comb(Op::comb(carry, s_pre[g][wave]), ex);
-    const int64_t e = it.wbase + g * TH * EPL + tid * EPL;
-    float4 o;
+    for (int g = 0; g < K; ++g) {
+      T acc = {{f4get(ca[g], 0), f4get(cb[g], 0)}};
+      v[g][0] = acc;
 #pragma unroll
-    for (int j = 0; j < EPL; ++j) {
-      const float yv = Op::comb(full, loc[g][j]).f[1];
-      f4set(o, j, yv);
-      const int k = i4get(iv[g], j);
-      if (k >= 0 && k < a.m)  // elements outside the instance carry key -1
-        atomicMin(&s_keys[k], (unsigned long long)key_of<MIN>(yv, (uint32_t)(e + j - it.start)));
+      for (int j = 1; j < EPL; ++j) {
+        acc = Op::comb(acc, T{{f4get(ca[g], j), f4get(cb[g], j)}});
+        v[g][j] = acc;
+      }
+      incl[g] = wave_scan_fwd<Op>(acc);
+      if (lane == WAVE - 1) s_tot[g][wave] = incl[g];
     }
-    st_range(a.y, e, it.lo, it.hi, o);
-  }
-  __syncthreads();
+    __syncthreads();
+    if (wave == 0) {
+      ag = wave0_block_prefix<Op, K, W, false>(s_tot, s_pre, Op::id());
+      uint64_t *st = a.status + item * (Op::NA + Op::NP);
+      if (lane == 0) publish<2>(jt.li == 0 ? st + Op::NA : st, tag, ag);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int g = 0; g < K; ++g) {
+      T ex = shift_up1(incl[g]);
+      if (lane == 0) ex = Op::id();
+      const T thr = Op::comb(s_pre[g][wave], ex);
+#pragma unroll
+      for (int j = 0; j < EPL; ++j) v[g][j] = Op::comb(thr, v[g][j]);
+    }
+  };
+  // element el of an item: group el / (TH*EPL), thread (el % (TH*EPL)) / EPL
+  auto put_pending = [&](const T (&v)[K][EPL], const int4 (&ix)[K]) {
+#pragma unroll
+    for (int g = 0; g < K; ++g) {
+      const int q = g * TH + tid;  // 4-element group index
+      s_pv[q * 2 + 0] = make_float4(v[g][0].f[0], v[g][0].f[1], v[g][1].f[0], v[g][1].f[1]);
+      s_pv[q * 2 + 1] = make_float4(v[g][2].f[0], v[g][2].f[1], v[g][3].f[0], v[g][3].f[1]);
+      s_pix[q] = ix[g];
+    }
+  };
 
-  const int64_t hb = it.s * a.m;
-  if (it.nli == 1) {
-    // the item holds the whole instance: finalise directly
-    for (int k = tid; k < a.m; k += TH) {
-      const uint64_t key = s_keys[k];
-      if (key == key_init<MIN>()) {
-        a.h[hb + k] = __builtin_inff();
-        a.argk[hb + k] = (int32_t)it.len;
-      } else {
-        a.h[hb + k] = ord_inv((uint32_t)(key >> 32));
-        a.argk[hb + k] = (int32_t)(uint32_t)key;
+  T pagg = Op::id();       // wave 0: aggregate of the pending item
+  T prev_incl = Op::id();  // wave 0: inclusive prefix of the block's previous item
+  {
+    T v[K][EPL];
+    phase1(it, i, v, pagg);
+    put_pending(v, ci);
+  }
+  int64_t in = i + G;
+  SegItem nt = it;
+  if (in < a.nitems) {
+    nt = seg_item(a.tab, in);
+    load(nt);
+  }
+  for (;;) {
+    const bool more = in < a.nitems;
+    T nv[K][EPL];
+    int4 niv[K];
+    T nagg = Op::id();
+    SegItem nnt = nt;
+    if (more) {
+      phase1(nt, in, nv, nagg);
+#pragma unroll
+      for (int g = 0; g < K; ++g) niv[g] = ci[g];
+      if (in + G < a.nitems) {
+        nnt = seg_item(a.tab, in + G);
+        load(nnt);
       }
     }
-  } else {
-    for (int k = tid; k < a.m; k += TH) {
-      const unsigned long long key = s_keys[k];
-      if (key != key_init<MIN>())
-        __hip_atomic_fetch_min(reinterpret_cast<unsigned long long *>(&a.keys[hb + k]), key,
-                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+
+    if (wave == 0) {
+      T c = Op::id();
+      if (it.li > 0) {
+        // predecessors at distances 1..G-1 belong to other blocks; the one at
+        // distance G is this block's previous item, in the same instance
+        const int win = it.li < G ? it.li : (int)(G - 1);
+        bool hit = false;
+        if (win > 0) c = lookback<Op>(a.status, i, +1, win, tag, a.ctl, &hit);
+        if (!hit) c = win > 0 ? Op::comb(prev_incl, c) : prev_incl;
+        if (lane == 0) publish<2>(a.status + i * (Op::NA + Op::NP) + Op::NA, tag, Op::comb(c, pagg));
+      }
+      prev_incl = Op::comb(c, pagg);
+      if (lane == 0) {
+        s_carry = c;
+        if (it.li == it.nli - 1) ctl_row_done(a.ctl, (unsigned)a.nrows, tag);
+        a.carry[i * 2 + 0] = c.f[0];
+        a.carry[i * 2 + 1] = c.f[1];
+      }
     }
+    for (int k = tid; k < a.m; k += TH) s_keys[k] = key_init<MIN>();
+    __syncthreads();
+    const T carry = s_carry;
+
+#pragma unroll
+    for (int g = 0; g < K; ++g) {
+      const int q = g * TH + tid;
+      const float4 p0 = s_pv[q * 2 + 0], p1 = s_pv[q * 2 + 1];
+      const int4 ix = s_pix[q];
+      const float pa[4] = {p0.x, p0.z, p1.x, p1.z}, py[4] = {p0.y, p0.w, p1.y, p1.w};
+      const int64_t e = it.wbase + g * TH * EPL + tid * EPL;
+      float4 o;
+#pragma unroll
+      for (int j = 0; j < EPL; ++j) {
+        const float yv = Op::comb(carry, T{{pa[j], py[j]}}).f[1];
+        f4set(o, j, yv);
+        const int k = i4get(ix, j);
+        if (k >= 0 && k < a.m)  // elements outside the instance carry key -1
+          atomicMin(&s_keys[k], (unsigned long long)key_of<MIN>(yv, (uint32_t)(e + j - it.start)));
+      }
+      st_range(a.y, e, it.lo, it.hi, o);
+    }
+    __syncthreads();
+    // the pending slot is free: the next item waits there
+    if (more) put_pending(nv, niv);
+
+    const int64_t hb = it.s * a.m;
+    if (it.nli == 1) {
+      // the item holds the whole instance: finalise directly
+      for (int k = tid; k < a.m; k += TH) {
+        const uint64_t key = s_keys[k];
+        if (key == key_init<MIN>()) {
+          a.h[hb + k] = __builtin_inff();
+          a.argk[hb + k] = (int32_t)it.len;
+        } else {
+          a.h[hb + k] = ord_inv((uint32_t)(key >> 32));
+          a.argk[hb + k] = (int32_t)(uint32_t)key;
+        }
+      }
+    } else {
+      for (int k = tid; k < a.m; k += TH) {
+        const unsigned long long key = s_keys[k];
+        if (key != key_init<MIN>())
+          __hip_atomic_fetch_min(reinterpret_cast<unsigned long long *>(&a.keys[hb + k]), key,
+                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+    if (!more) break;
+    // s_keys, s_pv, s_carry and s_pre are rewritten only after barriers that
+    // every thread reaches after its reads above
+    i = in;
+    it = nt;
+    in = i + G;
+    nt = nnt;
+    pagg = nagg;
   }
 }
 
@@ -268,12 +363,20 @@ struct SegBwdArgs {
   uint64_t *status;
 };
 
+// Persistent: block b takes items nitems-1-b, nitems-1-b-G, ... (right to
+// left).  One iteration prefetches the next item (inputs and the bins'
+// argk / h_bar entries), resolves the current item's look-back, sweeps and
+// stores it, then scans the next item: y_bar_total = y_bar + h_bar at the
+// bin's argmin, forward prefixes recomputed from the saved item prefix, the
+// adjoint maps scanned right to left and the item aggregate published.
 __global__ __launch_bounds__(SEG_TH) void k_seg_bwd(SegBwdArgs a) {
   using Op = FwdLB<LINREC>;
   using FT = Op::T;
   using M = MapScal;
   using MT = M::T;
+  using A = Adj<LINREC, false>;
   constexpr int K = SEG_K, EPL = SEG_EPL, W = SEG_W, TH = SEG_TH;
+  constexpr int TPT = SEG_MAX_BINS / TH;  // bin entries per thread
 
   __shared__ FT s_ftot[K][W];
   __shared__ FT s_fpre[K][W];
@@ -285,123 +388,185 @@ __global__ __launch_bounds__(SEG_TH) void k_seg_bwd(SegBwdArgs a) {
   __shared__ float s_hb[SEG_MAX_BINS];
 
   const int tid = threadIdx.x, lane = lane_id(), wave = tid / WAVE;
+  const int64_t G = gridDim.x;
   if (tid == 0) s_epoch = ctl_load(&a.ctl->epoch);
-  const int64_t item = a.nitems - 1 - blockIdx.x;  // right to left
-  const SegItem it = seg_item(a.tab, item);
-  const int64_t hb = it.s * a.m;
-  for (int k = tid; k < a.m; k += TH) {
-    s_ak[k] = a.argk[hb + k];
-    s_hb[k] = a.hbar[hb + k];
-  }
 
-  float4 av[K], bv[K], yv[K];
-  int4 iv[K];
-#pragma unroll
-  for (int g = 0; g < K; ++g) {
-    const int64_t e = it.wbase + g * TH * EPL + tid * EPL;
-    av[g] = ld_range(a.a, e, it.lo, it.hi, 1.0f);
-    bv[g] = ld_range(a.b, e, it.lo, it.hi, 0.0f);
-    yv[g] = ld_range(a.ybar, e, it.lo, it.hi, 0.0f);
-    iv[g] = ld_range_i(a.idx, e, it.lo, it.hi);
-  }
-
-  // forward prefixes (A_{i-1}, y_{i-1}) recomputed from the saved item prefix
-  FT loc[K][EPL];
-  FT fincl[K];
-#pragma unroll
-  for (int g = 0; g < K; ++g) {
-    FT acc = {{f4get(av[g], 0), f4get(bv[g], 0)}};
-    loc[g][0] = acc;
-#pragma unroll
-    for (int j = 1; j < EPL; ++j) {
-      acc = Op::comb(acc, FT{{f4get(av[g], j), f4get(bv[g], j)}});
-      loc[g][j] = acc;
-    }
-    fincl[g] = wave_scan_fwd<Op>(acc);
-    if (lane == WAVE - 1) s_ftot[g][wave] = fincl[g];
-  }
-  __syncthreads();
-  if (wave == 0) {
-    const FT c = {{a.carry[item * 2 + 0], a.carry[item * 2 + 1]}};
-    wave0_block_prefix<Op, K, W, false>(s_ftot, s_fpre, c);
-  }
-  // y_bar_total = y_bar + h_bar at the bin's argmin (fused min-by-index adjoint)
-#pragma unroll
-  for (int g = 0; g < K; ++g) {
-    const int64_t e = it.wbase + g * TH * EPL + tid * EPL;
-#pragma unroll
-    for (int j = 0; j < EPL; ++j) {
-      const int k = i4get(iv[g], j);
-      if (k >= 0 && k < a.m && (int64_t)s_ak[k] == e + j - it.start)
-        f4set(yv[g], j, f4get(yv[g], j) + s_hb[k]);
-    }
-  }
-  __syncthreads();
-  FT thr_f[K];
-#pragma unroll
-  for (int g = 0; g < K; ++g) {
-    FT ex = shfl_up(fincl[g], 1);
-    if (lane == 0) ex = Op::id();
-    thr_f[g] = Op::comb(s_fpre[g][wave], ex);
-  }
-  auto prefix = [&](int g, int j) -> FT {
-    return j == 0 ? thr_f[g] : Op::comb(thr_f[g], loc[g][j - 1]);
+  struct Buf {
+    float4 a[K], b[K], yb[K];
+    int4 ix[K];
+    int32_t ak[TPT];
+    float hb[TPT];
   };
-  using A = Adj<LINREC, false>;
-
-  MT mincl[K];
+  auto load = [&](const SegItem &it, Buf &B) {
 #pragma unroll
-  for (int g = 0; g < K; ++g) {
-    MT acc = M::id();
-#pragma unroll
-    for (int j = EPL - 1; j >= 0; --j) {
-      const float yb[2] = {f4get(yv[g], j), 0.0f};
-      const MT hm = A::make(prefix(g, j), FT{{f4get(av[g], j), f4get(bv[g], j)}}, yb, false);
-      acc = (j == EPL - 1) ? hm : M::comb(acc, hm);
+    for (int g = 0; g < K; ++g) {
+      const int64_t e = it.wbase + g * TH * EPL + tid * EPL;
+      B.a[g] = ld_range(a.a, e, it.lo, it.hi, 1.0f);
+      B.b[g] = ld_range(a.b, e, it.lo, it.hi, 0.0f);
+      B.yb[g] = ld_range(a.ybar, e, it.lo, it.hi, 0.0f);
+      B.ix[g] = ld_range_i(a.idx, e, it.lo, it.hi);
     }
-    mincl[g] = wave_scan_rev<M>(acc);
-    if (lane == 0) s_mtot[g][wave] = mincl[g];
-  }
+    const int64_t hb = it.s * a.m;
+#pragma unroll
+    for (int r = 0; r < TPT; ++r) {
+      const int k = tid + r * TH;
+      B.ak[r] = k < a.m ? a.argk[hb + k] : 0;
+      B.hb[r] = k < a.m ? a.hbar[hb + k] : 0.0f;
+    }
+  };
+  auto item_of = [&](int64_t kk) { return a.nitems - 1 - kk; };
+
+  int64_t k = blockIdx.x;
+  SegItem it = seg_item(a.tab, item_of(k));
+  Buf cur;
+  load(it, cur);
   __syncthreads();
   const uint32_t tag = s_epoch + 1;
 
-  if (wave == 0) {
-    const MT tile_agg = wave0_block_prefix<M, K, W, true>(s_mtot, s_mpre, M::id());
-    uint64_t *st = a.status + item * (M::NA + M::NP);
-    const int dist_max = it.nli - 1 - it.li;
-    MT c = M::from_pre(M::P{{0.0f}});
-    if (dist_max == 0) {
-      if (lane == 0) publish<M::NP>(st + M::NA, tag, M::apply0(M::comb(c, tile_agg)));
-    } else {
-      if (lane == 0) publish<M::NA>(st, tag, tile_agg);
-      c = lookback<M>(a.status, item, -1, dist_max, tag, a.ctl);
-      if (lane == 0) publish<M::NP>(st + M::NA, tag, M::apply0(M::comb(c, tile_agg)));
+  FT thr_f[K], loc[K][EPL];
+  MT mincl[K];
+  MT agg = M::id();        // wave 0: map aggregate of the current item
+  MT prev_incl = M::id();  // wave 0: carry into the block's previous item, combined with it
+  auto prefix = [&](int g, int j) -> FT {
+    return j == 0 ? thr_f[g] : Op::comb(thr_f[g], loc[g][j - 1]);
+  };
+
+  // scans the item in `cur` (its bin entries already in LDS)
+  auto phase1 = [&](const SegItem &jt, int64_t item) {
+    // y_bar_total = y_bar + h_bar at the bin's argmin (fused min-by-index adjoint)
+#pragma unroll
+    for (int g = 0; g < K; ++g) {
+      const int64_t e = jt.wbase + g * TH * EPL + tid * EPL;
+#pragma unroll
+      for (int j = 0; j < EPL; ++j) {
+        const int kb = i4get(cur.ix[g], j);
+        if (kb >= 0 && kb < a.m && (int64_t)s_ak[kb] == e + j - jt.start)
+          f4set(cur.yb[g], j, f4get(cur.yb[g], j) + s_hb[kb]);
+      }
     }
-    if (lane == 0) {
-      s_carry = c;
-      if (it.li == 0) ctl_row_done(a.ctl, (unsigned)a.nrows, tag);
+    // forward prefixes (A_{i-1}, y_{i-1}) recomputed from the saved item prefix
+    FT fincl[K];
+#pragma unroll
+    for (int g = 0; g < K; ++g) {
+      FT acc = {{f4get(cur.a[g], 0), f4get(cur.b[g], 0)}};
+      loc[g][0] = acc;
+#pragma unroll
+      for (int j = 1; j < EPL; ++j) {
+        acc = Op::comb(acc, FT{{f4get(cur.a[g], j), f4get(cur.b[g], j)}});
+        loc[g][j] = acc;
+      }
+      fincl[g] = wave_scan_fwd<Op>(acc);
+      if (lane == WAVE - 1) s_ftot[g][wave] = fincl[g];
     }
-  }
+    __syncthreads();
+    if (wave == 0) {
+      const FT c = {{a.carry[item * 2 + 0], a.carry[item * 2 + 1]}};
+      wave0_block_prefix<Op, K, W, false>(s_ftot, s_fpre, c);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int g = 0; g < K; ++g) {
+      FT ex = shift_up1(fincl[g]);
+      if (lane == 0) ex = Op::id();
+      thr_f[g] = Op::comb(s_fpre[g][wave], ex);
+    }
+#pragma unroll
+    for (int g = 0; g < K; ++g) {
+      MT acc = M::id();
+#pragma unroll
+      for (int j = EPL - 1; j >= 0; --j) {
+        const float yb[2] = {f4get(cur.yb[g], j), 0.0f};
+        const MT hm = A::make(prefix(g, j), FT{{f4get(cur.a[g], j), f4get(cur.b[g], j)}}, yb, false);
+        acc = (j == EPL - 1) ? hm : M::comb(acc, hm);
+      }
+      mincl[g] = wave_scan_rev<M>(acc);
+      if (lane == 0) s_mtot[g][wave] = mincl[g];
+    }
+    __syncthreads();
+    if (wave == 0) {
+      agg = wave0_block_prefix<M, K, W, true>(s_mtot, s_mpre, M::id());
+      uint64_t *st = a.status + item * (M::NA + M::NP);
+      if (lane == 0) {
+        if (jt.li == jt.nli - 1)
+          publish<M::NP>(st + M::NA, tag, M::apply0(M::comb(M::from_pre(M::P{{0.0f}}), agg)));
+        else
+          publish<M::NA>(st, tag, agg);
+      }
+    }
+  };
+  auto put_bins = [&](const Buf &B) {
+#pragma unroll
+    for (int r = 0; r < TPT; ++r) {
+      const int kb = tid + r * TH;
+      if (kb < a.m) {
+        s_ak[kb] = B.ak[r];
+        s_hb[kb] = B.hb[r];
+      }
+    }
+  };
+
+  put_bins(cur);
   __syncthreads();
-  const MT carry = s_carry;
+  phase1(it, item_of(k));
+  for (;;) {
+    const int64_t item = item_of(k);
+    const int64_t kn = k + G;
+    const bool more = kn < a.nitems;
+    SegItem nt = it;
+    Buf nxt;
+    if (more) {
+      nt = seg_item(a.tab, item_of(kn));
+      load(nt, nxt);
+    }
+
+    if (wave == 0) {
+      MT c = M::from_pre(M::P{{0.0f}});
+      const int dist_max = it.nli - 1 - it.li;
+      if (dist_max > 0) {
+        // successors at distances 1..G-1 belong to other blocks; the one at
+        // distance G is this block's previous item, in the same instance
+        const int win = dist_max < G ? dist_max : (int)(G - 1);
+        bool hit = false;
+        if (win > 0) c = lookback<M>(a.status, item, -1, win, tag, a.ctl, &hit);
+        if (!hit) c = win > 0 ? M::comb(prev_incl, c) : prev_incl;
+        if (lane == 0)
+          publish<M::NP>(a.status + item * (M::NA + M::NP) + M::NA, tag, M::apply0(M::comb(c, agg)));
+      }
+      prev_incl = M::from_pre(M::apply0(M::comb(c, agg)));
+      if (lane == 0) {
+        s_carry = c;
+        if (it.li == 0) ctl_row_done(a.ctl, (unsigned)a.nrows, tag);
+      }
+    }
+    __syncthreads();
+    const MT carry = s_carry;
 
 #pragma unroll
-  for (int g = 0; g < K; ++g) {
-    MT ex = shfl_down(mincl[g], 1);
-    if (lane == WAVE - 1) ex = M::id();
-    M::P rho = M::apply0(M::comb(M::comb(carry, s_mpre[g][wave]), ex));
-    float4 oa, ob;
+    for (int g = 0; g < K; ++g) {
+      MT ex = shift_down1(mincl[g]);
+      if (lane == WAVE - 1) ex = M::id();
+      M::P rho = M::apply0(M::comb(M::comb(carry, s_mpre[g][wave]), ex));
+      float4 oa, ob;
 #pragma unroll
-    for (int j = EPL - 1; j >= 0; --j) {
-      const float yb[2] = {f4get(yv[g], j), 0.0f};
-      float xb[2];
-      A::step(prefix(g, j), FT{{f4get(av[g], j), f4get(bv[g], j)}}, yb, false, rho, xb);
-      f4set(oa, j, xb[0]);
-      f4set(ob, j, xb[1]);
+      for (int j = EPL - 1; j >= 0; --j) {
+        const float yb[2] = {f4get(cur.yb[g], j), 0.0f};
+        float xb[2];
+        A::step(prefix(g, j), FT{{f4get(cur.a[g], j), f4get(cur.b[g], j)}}, yb, false, rho, xb);
+        f4set(oa, j, xb[0]);
+        f4set(ob, j, xb[1]);
+      }
+      const int64_t e = it.wbase + g * TH * EPL + tid * EPL;
+      st_range(a.abar, e, it.lo, it.hi, oa);
+      st_range(a.bbar, e, it.lo, it.hi, ob);
     }
-    const int64_t e = it.wbase + g * TH * EPL + tid * EPL;
-    st_range(a.abar, e, it.lo, it.hi, oa);
-    st_range(a.bbar, e, it.lo, it.hi, ob);
+    if (!more) break;
+    k = kn;
+    it = nt;
+    cur = nxt;
+    __syncthreads();  // LDS of the finished item is rewritten below
+    put_bins(cur);
+    __syncthreads();
+    phase1(it, item_of(k));
   }
 }
 
@@ -416,7 +581,8 @@ struct pcad_plan {
   int64_t S = 0, N = 0, m = 0, nitems = 0, nrows = 0;
   unsigned flags = 0;
   std::vector<int64_t> off;
-  std::vector<int32_t> item_seg, seg_item0;
+  std::vector<ItemRec> item_rec;
+  std::vector<int32_t> seg_item0;
   // workspace layout
   size_t ws_status = 0, ws_keys = 0, ws_tab = 0, ws_plain = 0, ws_bytes = 0;
   size_t tab_off = 0, tab_item0 = 0;  // table offsets inside the table region
@@ -449,16 +615,34 @@ int plan_hip(hipError_t e) {
   return hip_status(e);
 }
 
+// persistent grids: as many blocks as can be resident at once (a block waits
+// only on items of lower order in its direction, owned by resident blocks)
+template <class F>
+int64_t seg_grid(F kernel, int64_t nitems) {
+  int dev = 0, cus = 0, occ = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, SEG_TH, 0) != hipSuccess) return 0;
+  const int64_t cap = (int64_t)cus * (occ > 0 ? occ : 1);
+  return nitems < cap ? nitems : cap;
+}
+
 hipError_t launch_fwd_nodes(pcad_plan *p, hipStream_t s) {
-  if (p->nitems > 0)
-    hipLaunchKernelGGL(k_seg_fwd, dim3((unsigned)p->nitems), dim3(SEG_TH), 0, s, p->fa);
+  if (p->nitems > 0) {
+    const int64_t grid = seg_grid(k_seg_fwd, p->nitems);
+    if (grid == 0) return hipErrorInvalidDevice;
+    hipLaunchKernelGGL(k_seg_fwd, dim3((unsigned)grid), dim3(SEG_TH), 0, s, p->fa);
+  }
   hipLaunchKernelGGL(k_seg_fin, dim3(2048), dim3(256), 0, s, p->fa);
   return hipGetLastError();
 }
 
 hipError_t launch_bwd_nodes(pcad_plan *p, hipStream_t s) {
-  if (p->nitems > 0)
-    hipLaunchKernelGGL(k_seg_bwd, dim3((unsigned)p->nitems), dim3(SEG_TH), 0, s, p->ba);
+  if (p->nitems > 0) {
+    const int64_t grid = seg_grid(k_seg_bwd, p->nitems);
+    if (grid == 0) return hipErrorInvalidDevice;
+    hipLaunchKernelGGL(k_seg_bwd, dim3((unsigned)grid), dim3(SEG_TH), 0, s, p->ba);
+  }
   return hipGetLastError();
 }
 
@@ -501,9 +685,22 @@ int pcad_plan_create(pcad_plan **out, int64_t nseg, const int64_t *offsets, int6
   }
   p->seg_item0[nseg] = (int32_t)items;
   p->nitems = items;
-  p->item_seg.resize(items > 0 ? items : 1);
-  for (int64_t s = 0; s < nseg; ++s)
-    for (int32_t i = p->seg_item0[s]; i < p->seg_item0[s + 1]; ++i) p->item_seg[i] = (int32_t)s;
+  p->item_rec.resize(items > 0 ? items : 1);
+  for (int64_t s = 0; s < nseg; ++s) {
+    const int64_t st = offsets[s], en = offsets[s + 1];
+    const int32_t i0 = p->seg_item0[s], nli = p->seg_item0[s + 1] - i0;
+    for (int32_t li = 0; li < nli; ++li) {
+      ItemRec &r = p->item_rec[i0 + li];
+      r.wbase = (st / SEG_T + li) * (int64_t)SEG_T;
+      r.start = st;
+      r.lo = (int32_t)(std::max(st, r.wbase) - r.wbase);
+      r.hi = (int32_t)(std::min(en, r.wbase + SEG_T) - r.wbase);
+      r.s = (int32_t)s;
+      r.li = li;
+      r.nli = nli;
+      r.len = (int32_t)(en - st);
+    }
+  }
 
   // workspace: control block, status words, merge keys, tables, plain-path scratch
   const int words = 4;  // linrec forward (2+2) and adjoint map (2+1) status words
@@ -514,7 +711,7 @@ int pcad_plan_create(pcad_plan **out, int64_t nseg, const int64_t *offsets, int6
   o = align256(o + (size_t)nseg * m * sizeof(uint64_t));
   p->ws_tab = o;
   // the three tables, each starting on a 256-byte boundary (as bound)
-  p->tab_off = align256((size_t)p->item_seg.size() * 4);
+  p->tab_off = align256(p->item_rec.size() * sizeof(ItemRec));
   p->tab_item0 = p->tab_off + align256((size_t)(nseg + 1) * 8);
   o = align256(o + p->tab_item0 + (size_t)(nseg + 1) * 4);
   p->ws_plain = o;
@@ -580,10 +777,10 @@ int pcad_plan_bind(pcad_plan *p, const float *a, const float *b, const int32_t *
 
   // device tables
   char *tab = p->ws + p->ws_tab;
-  int32_t *d_item_seg = reinterpret_cast<int32_t *>(tab);
+  ItemRec *d_items = reinterpret_cast<ItemRec *>(tab);
   int64_t *d_off = reinterpret_cast<int64_t *>(tab + p->tab_off);
   int32_t *d_item0 = reinterpret_cast<int32_t *>(tab + p->tab_item0);
-  int st = plan_hip(hipMemcpyAsync(d_item_seg, p->item_seg.data(), p->item_seg.size() * 4,
+  int st = plan_hip(hipMemcpyAsync(d_items, p->item_rec.data(), p->item_rec.size() * sizeof(ItemRec),
                                    hipMemcpyHostToDevice, s));
   if (st == PCAD_OK)
     st = plan_hip(hipMemcpyAsync(d_off, p->off.data(), (p->S + 1) * 8, hipMemcpyHostToDevice, s));
@@ -597,11 +794,11 @@ int pcad_plan_bind(pcad_plan *p, const float *a, const float *b, const int32_t *
   if ((st = plan_hip(hipGetLastError())) != PCAD_OK) return st;
   if ((st = plan_hip(hipStreamSynchronize(s))) != PCAD_OK) return st;
 
-  SegTables t{d_item_seg, d_off, d_item0};
+  SegTables t{d_items, d_off, d_item0};
   Ctl *ctl = reinterpret_cast<Ctl *>(p->ws);
   uint64_t *status = reinterpret_cast<uint64_t *>(p->ws + p->ws_status);
   float *carry = reinterpret_cast<float *>(p->saved + p->sv_carry);
-  p->fa = SegFwdArgs{t, (int)p->S, (int)p->m, (int)p->nrows, a, b, idx, y, h, argk, carry,
+  p->fa = SegFwdArgs{t, p->nitems, (int)p->S, (int)p->m, (int)p->nrows, a, b, idx, y, h, argk, carry,
                      keys, ctl, status};
   p->ba = SegBwdArgs{t, p->nitems, (int)p->S, (int)p->m, (int)p->nrows, a, b, idx, carry, argk,
                      ybar, hbar, abar, bbar, ctl, status};

@@ -166,6 +166,9 @@ struct Fwd<MAT2> {
 #ifndef PCAD_FWD_THREADS
 #define PCAD_FWD_THREADS 1024
 #endif
+#ifndef PCAD_FWD_THREADS_WIDE  // LINREC and MAT2 (more state per element)
+#define PCAD_FWD_THREADS_WIDE 512
+#endif
 #ifndef PCAD_VJP_THREADS
 #define PCAD_VJP_THREADS 512
 #endif
@@ -174,7 +177,9 @@ template <int OP, int DIR = 0>
 struct Shape {
   static constexpr int EPL = (OP == MAT2) ? 1 : 4;
   static constexpr int TILE = (OP == MAT2) ? PCAD_SCAN_TILE / 4 : PCAD_SCAN_TILE;
-  static constexpr int THREADS = DIR == 0 ? PCAD_FWD_THREADS : PCAD_VJP_THREADS;
+  static constexpr int THREADS =
+      DIR == 1 ? PCAD_VJP_THREADS
+               : ((OP == LINREC || OP == MAT2) ? PCAD_FWD_THREADS_WIDE : PCAD_FWD_THREADS);
   static constexpr int W = THREADS / WAVE;
   static constexpr int K = TILE / (THREADS * EPL);
   static_assert(K >= 1 && K * THREADS * EPL == TILE, "tile must be whole groups of the block");
@@ -311,25 +316,82 @@ __device__ __forceinline__ TileInfo tile_info(int64_t tile, int64_t n, int tpr, 
 // wave64 inclusive scans.  Tr::comb(earlier, later).
 //   forward: lower lanes are earlier;  reverse: higher lanes are earlier.
 // ---------------------------------------------------------------------------
-template <class Tr>
-__device__ __forceinline__ typename Tr::T wave_scan_fwd(typename Tr::T x) {
-  const int lane = lane_id();
+// ---------------------------------------------------------------------------
+// Cross-lane steps through DPP (data-parallel primitives: the VALU reads a
+// neighbour lane's register in the same instruction, no LDS round trip).
+// Control codes of the GFX9 DPP encoding.
+// ---------------------------------------------------------------------------
+constexpr int kDppRowShl = 0x100;   // + n: lane i reads lane i+n of its row of 16
+constexpr int kDppRowShr = 0x110;   // + n: lane i reads lane i-n of its row
+constexpr int kDppWaveShl1 = 0x130; // lane i reads lane i+1 of the wave
+constexpr int kDppWaveShr1 = 0x138; // lane i reads lane i-1 of the wave
+constexpr int kDppBcast15 = 0x142;  // lane 15 of a row to the next row
+constexpr int kDppBcast31 = 0x143;  // lane 31 to rows 2 and 3
+
+template <int CTRL, int ROWS = 0xf>
+__device__ __forceinline__ float dpp_f(float v) {
+  // lanes without a source (or outside ROWS) keep their own value
+  return __int_as_float(
+      __builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), CTRL, ROWS, 0xf, false));
+}
+
+template <int CTRL, int ROWS = 0xf, int N>
+__device__ __forceinline__ Vec<N> dpp_v(const Vec<N> &v) {
+  Vec<N> r;
 #pragma unroll
-  for (int d = 1; d < WAVE; d <<= 1) {
-    typename Tr::T o = shfl_up(x, d);
-    if (lane >= d) x = Tr::comb(o, x);
-  }
-  return x;
+  for (int i = 0; i < N; ++i) r.f[i] = dpp_f<CTRL, ROWS>(v.f[i]);
+  return r;
+}
+
+// x = comb(neighbour, x) where `valid`, x unchanged elsewhere
+template <class Tr, int CTRL, int ROWS = 0xf>
+__device__ __forceinline__ typename Tr::T dpp_step(const typename Tr::T &x, bool valid) {
+  const typename Tr::T o = dpp_v<CTRL, ROWS>(x);
+  return valid ? Tr::comb(o, x) : x;
+}
+
+// lane i gets lane i-1's value (lane 0 keeps its own)
+template <int N>
+__device__ __forceinline__ Vec<N> shift_up1(const Vec<N> &v) {
+  return dpp_v<kDppWaveShr1>(v);
+}
+
+// lane i gets lane i+1's value (lane 63 keeps its own)
+template <int N>
+__device__ __forceinline__ Vec<N> shift_down1(const Vec<N> &v) {
+  return dpp_v<kDppWaveShl1>(v);
 }
 
 template <class Tr>
-__device__ __forceinline__ typename Tr::T wave_scan_rev(typename Tr::T x) {
+__device__ __forceinline__ typename Tr::T wave_scan_fwd(typename Tr::T x) {
+  // rows of 16 lanes: shifts by 1, 2, 4, 8 inside a row, then the row
+  // totals through the row broadcasts of lanes 15 and 31
   const int lane = lane_id();
-#pragma unroll
-  for (int d = 1; d < WAVE; d <<= 1) {
-    typename Tr::T o = shfl_down(x, d);
-    if (lane + d < WAVE) x = Tr::comb(o, x);
-  }
+  x = dpp_step<Tr, kDppRowShr + 1>(x, (lane & 15) >= 1);
+  x = dpp_step<Tr, kDppRowShr + 2>(x, (lane & 15) >= 2);
+  x = dpp_step<Tr, kDppRowShr + 4>(x, (lane & 15) >= 4);
+  x = dpp_step<Tr, kDppRowShr + 8>(x, (lane & 15) >= 8);
+  x = dpp_step<Tr, kDppBcast15, 0xa>(x, (lane & 16) != 0);
+  x = dpp_step<Tr, kDppBcast31, 0xc>(x, lane >= 32);
+  return x;
+}
+
+// Inclusive scan from the right: lane i gets x_63 (.) ... (.) x_i, the
+// higher lanes being the earlier operands.
+template <class Tr>
+__device__ __forceinline__ typename Tr::T wave_scan_rev(typename Tr::T x) {
+  using T = typename Tr::T;
+  const int lane = lane_id();
+  x = dpp_step<Tr, kDppRowShl + 1>(x, (lane & 15) + 1 < 16);
+  x = dpp_step<Tr, kDppRowShl + 2>(x, (lane & 15) + 2 < 16);
+  x = dpp_step<Tr, kDppRowShl + 4>(x, (lane & 15) + 4 < 16);
+  x = dpp_step<Tr, kDppRowShl + 8>(x, (lane & 15) + 8 < 16);
+  // lane 16r now holds the total of row r; rows take the later rows' totals
+  const T t1 = readlane(x, 16), t2 = readlane(x, 32), t3 = readlane(x, 48);
+  const T s2 = Tr::comb(t3, t2);
+  const T s1 = Tr::comb(s2, t1);
+  const int row = lane >> 4;
+  if (row < 3) x = Tr::comb(row == 2 ? t3 : (row == 1 ? s2 : s1), x);
   return x;
 }
 
@@ -349,7 +411,7 @@ __device__ __forceinline__ typename Tr::T wave0_block_prefix(typename Tr::T (*s_
   T v = Tr::id();
   if (lane < NI) v = s_tot[idx / W][idx % W];
   const T inc = wave_scan_fwd<Tr>(v);
-  T ex = shfl_up(inc, 1);
+  T ex = shift_up1(inc);
   if (lane == 0) ex = Tr::id();
   if (lane < NI) s_pre[idx / W][idx % W] = Tr::comb(init, ex);
   return readlane(inc, NI - 1);

@@ -377,9 +377,9 @@ __global__ __launch_bounds__(Shape<OP>::THREADS) void k_reduce_vjp_gen(RedGenArg
 
 #pragma unroll
   for (int g = 0; g < K; ++g) {
-    T exf = shfl_up(inf_[g], 1);
+    T exf = shift_up1(inf_[g]);
     if (lane == 0) exf = F::id();
-    T exr = shfl_down(inr_[g], 1);
+    T exr = shift_down1(inr_[g]);
     if (lane == WAVE - 1) exr = R::id();
     const T lth = F::comb(s_fpre[g][wave], exf);                 // everything before this thread
     const T rth = R::comb(R::comb(carry, s_rpre[g][wave]), exr);  // everything after this thread

@@ -105,7 +105,7 @@ __global__ __launch_bounds__(Shape<OP>::THREADS) void k_scan_fwd(ScanFwdArgs a) 
     __syncthreads();
 #pragma unroll
     for (int g = 0; g < K; ++g) {
-      T ex = shfl_up(incl[g], 1);
+      T ex = shift_up1(incl[g]);
       if (lane == 0) ex = Op::id();
       thr[g] = Op::comb(s_pre[g][wave], ex);
     }
@@ -317,7 +317,7 @@ __global__ __launch_bounds__((Shape<OP, 1>::THREADS)) void k_scan_vjp(ScanVjpArg
     if (TAPE) {
       if (S == 4) {
         Vec<4> q = {{cur[g][IT].x, cur[g][IT].y, cur[g][IT].z, cur[g][IT].w}};
-        Vec<4> up = shfl_up(q, 1);
+        Vec<4> up = shift_up1(q);
         if (lane == 0) up = Vec<4>{{cpv[g][0].x, cpv[g][0].y, cpv[g][0].z, cpv[g][0].w}};
 #pragma unroll
         for (int i = 0; i < N; ++i) p[0].f[i] = up.f[i];
@@ -326,7 +326,7 @@ __global__ __launch_bounds__((Shape<OP, 1>::THREADS)) void k_scan_vjp(ScanVjpArg
 #pragma unroll
         for (int s = 0; s < NT; ++s) {
           const float4 q = cur[g][IT + s];
-          float w = __shfl_up(q.w, 1, WAVE);
+          float w = dpp_f<kDppWaveShr1>(q.w);
           if (lane == 0) w = cpv[g][s].x;
           prev[s][0] = w; prev[s][1] = q.x; prev[s][2] = q.y; prev[s][3] = q.z;
         }
@@ -372,7 +372,7 @@ __global__ __launch_bounds__((Shape<OP, 1>::THREADS)) void k_scan_vjp(ScanVjpArg
       __syncthreads();
 #pragma unroll
       for (int g = 0; g < K; ++g) {
-        FT ex = shfl_up(fincl[g], 1);
+        FT ex = shift_up1(fincl[g]);
         if (lane == 0) ex = Op::id();
         thr_f[g] = Op::comb(s_fpre[g][wave], ex);
       }
@@ -446,7 +446,7 @@ __global__ __launch_bounds__((Shape<OP, 1>::THREADS)) void k_scan_vjp(ScanVjpArg
     // thread-serial sweep, right to left
 #pragma unroll
     for (int g = 0; g < K; ++g) {
-      MT ex = shfl_down(mincl[g], 1);
+      MT ex = shift_down1(mincl[g]);
       if (lane == WAVE - 1) ex = M::id();
       typename M::P rho = M::apply0(M::comb(M::comb(carry, s_mpre[g][wave]), ex));
       FT p[EPL];
