@@ -51,17 +51,23 @@ struct MapAdd {
 // scalar affine map (o, W): * min max and the linear recurrence without an
 // adjoint of the cumulative product.  Strong zeros keep an exact 0 in W from
 // meeting an overflowed partial (inf) as NaN.
-struct MapScal {
+// STRONG: products with an exact zero factor are exact zeros (the `*` and
+// min/max selectors, whose adjoints may meet an overflowed partial product);
+// the linear recurrence uses plain fused multiply-adds
+template <bool STRONG>
+struct MapScalT {
   using T = Vec<2>;  // o, W
   using P = Vec<1>;
   static constexpr int NA = 2, NP = 1;
   __device__ static T id() { return {{0.0f, 1.0f}}; }
   __device__ static T comb(const T &e, const T &l) {
-    return {{l.f[0] + mulz(l.f[1], e.f[0]), mulz(l.f[1], e.f[1])}};
+    if (STRONG) return {{l.f[0] + mulz(l.f[1], e.f[0]), mulz(l.f[1], e.f[1])}};
+    return {{__builtin_fmaf(l.f[1], e.f[0], l.f[0]), l.f[1] * e.f[1]}};
   }
   __device__ static T from_pre(const P &p) { return {{p.f[0], 0.0f}}; }
   __device__ static P apply0(const T &t) { return {{t.f[0]}}; }
 };
+using MapScal = MapScalT<true>;
 
 // linear recurrence with an adjoint of the cumulative product: rho is the
 // pair (rho_y, rho_A) and J_{i-1} = diag(a_i, a_i) (RBDS, q = 1, k = 2)
@@ -185,7 +191,7 @@ struct Adj<MAX, ABAR> : AdjMinMax<MAX, ABAR> {};
 //   b_bar = lam_y,  a_bar = lam_y*y_{i-1} + lam_A*A_{i-1},  rho = a*lam
 template <>
 struct Adj<LINREC, false> {
-  using M = MapScal;
+  using M = MapScalT<false>;
   using FT = Fwd<LINREC>::T;
   static constexpr bool NEEDS_PREFIX = true;
   static constexpr int NY = 1, NXB = 2;

@@ -53,6 +53,8 @@ struct SegItem {
   int64_t wbase;         // first element of the aligned window
   int64_t lo, hi;        // elements of the instance inside the window
   int64_t start, len;    // the instance
+  int lo_r, hi_r;        // lo, hi relative to wbase
+  int wofs;              // wbase - start: instance index of the window's first element
 };
 
 __device__ __forceinline__ SegItem seg_item(const SegTables &t, int64_t item) {
@@ -66,40 +68,45 @@ __device__ __forceinline__ SegItem seg_item(const SegTables &t, int64_t item) {
   q.hi = r.wbase + r.hi;
   q.start = r.start;
   q.len = r.len;
+  q.lo_r = r.lo;
+  q.hi_r = r.hi;
+  q.wofs = (int)(r.wbase - r.start);
   return q;
 }
 
-// elements [e, e+4) of which those in [lo, hi) are read; `fill` elsewhere
-__device__ __forceinline__ float4 ld_range(const float *__restrict__ p, int64_t e, int64_t lo,
-                                           int64_t hi, float fill) {
-  if (e >= lo && e + 4 <= hi) return *reinterpret_cast<const float4 *>(p + e);
+// elements [e, e+4) of the window at `w` (block-uniform pointer) of which
+// those in [lo, hi) are read; `fill` elsewhere
+__device__ __forceinline__ float4 ld_range(const float *__restrict__ w, int e, int lo, int hi,
+                                           float fill) {
+  const unsigned o = (unsigned)e;
+  if (e >= lo && e + 4 <= hi) return *reinterpret_cast<const float4 *>(w + o);
   float r[4];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) r[j] = (e + j >= lo && e + j < hi) ? p[e + j] : fill;
+  for (int j = 0; j < 4; ++j) r[j] = (e + j >= lo && e + j < hi) ? w[o + j] : fill;
   return make_float4(r[0], r[1], r[2], r[3]);
 }
 
-__device__ __forceinline__ int4 ld_range_i(const int32_t *__restrict__ p, int64_t e, int64_t lo,
-                                           int64_t hi) {
-  if (e >= lo && e + 4 <= hi) return *reinterpret_cast<const int4 *>(p + e);
+__device__ __forceinline__ int4 ld_range_i(const int32_t *__restrict__ w, int e, int lo, int hi) {
+  const unsigned o = (unsigned)e;
+  if (e >= lo && e + 4 <= hi) return *reinterpret_cast<const int4 *>(w + o);
   int r[4];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) r[j] = (e + j >= lo && e + j < hi) ? p[e + j] : -1;
+  for (int j = 0; j < 4; ++j) r[j] = (e + j >= lo && e + j < hi) ? w[o + j] : -1;
   return make_int4(r[0], r[1], r[2], r[3]);
 }
 
-__device__ __forceinline__ void st_range(float *__restrict__ p, int64_t e, int64_t lo, int64_t hi,
-                                         float4 v) {
+__device__ __forceinline__ void st_range(float *__restrict__ w, int e, int lo, int hi, float4 v) {
+  const unsigned o = (unsigned)e;
   if (e >= lo && e + 4 <= hi) {
     typedef float v4f __attribute__((ext_vector_type(4)));
-    v4f w = {v.x, v.y, v.z, v.w};
-    __builtin_nontemporal_store(w, reinterpret_cast<v4f *>(p + e));
+    v4f x = {v.x, v.y, v.z, v.w};
+    __builtin_nontemporal_store(x, reinterpret_cast<v4f *>(w + o));
     return;
   }
   const float r[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
   for (int j = 0; j < 4; ++j)
-    if (e + j >= lo && e + j < hi) p[e + j] = r[j];
+    if (e + j >= lo && e + j < hi) w[o + j] = r[j];
 }
 
 __device__ __forceinline__ int i4get(const int4 &v, int j) {
@@ -152,10 +159,10 @@ __global__ __launch_bounds__(SEG_TH) void k_seg_fwd(SegFwdArgs a) {
   auto load = [&](const SegItem &it) {
 #pragma unroll
     for (int g = 0; g < K; ++g) {
-      const int64_t e = it.wbase + g * TH * EPL + tid * EPL;
-      ca[g] = ld_range(a.a, e, it.lo, it.hi, 1.0f);
-      cb[g] = ld_range(a.b, e, it.lo, it.hi, 0.0f);
-      ci[g] = ld_range_i(a.idx, e, it.lo, it.hi);
+      const int e = g * TH * EPL + tid * EPL;
+      ca[g] = ld_range(a.a + it.wbase, e, it.lo_r, it.hi_r, 1.0f);
+      cb[g] = ld_range(a.b + it.wbase, e, it.lo_r, it.hi_r, 0.0f);
+      ci[g] = ld_range_i(a.idx + it.wbase, e, it.lo_r, it.hi_r);
     }
   };
   int64_t i = blockIdx.x;  // the item whose outputs are pending
@@ -266,7 +273,7 @@ __global__ __launch_bounds__(SEG_TH) void k_seg_fwd(SegFwdArgs a) {
       const float4 p0 = s_pv[q * 2 + 0], p1 = s_pv[q * 2 + 1];
       const int4 ix = s_pix[q];
       const float pa[4] = {p0.x, p0.z, p1.x, p1.z}, py[4] = {p0.y, p0.w, p1.y, p1.w};
-      const int64_t e = it.wbase + g * TH * EPL + tid * EPL;
+      const int e = g * TH * EPL + tid * EPL;
       float4 o;
 #pragma unroll
       for (int j = 0; j < EPL; ++j) {
@@ -274,9 +281,9 @@ __global__ __launch_bounds__(SEG_TH) void k_seg_fwd(SegFwdArgs a) {
         f4set(o, j, yv);
         const int k = i4get(ix, j);
         if (k >= 0 && k < a.m)  // elements outside the instance carry key -1
-          atomicMin(&s_keys[k], (unsigned long long)key_of<MIN>(yv, (uint32_t)(e + j - it.start)));
+          atomicMin(&s_keys[k], (unsigned long long)key_of<MIN>(yv, (uint32_t)(it.wofs + e + j)));
       }
-      st_range(a.y, e, it.lo, it.hi, o);
+      st_range(a.y + it.wbase, e, it.lo_r, it.hi_r, o);
     }
     __syncthreads();
     // the pending slot is free: the next item waits there
@@ -355,7 +362,7 @@ struct SegBwdArgs {
   int nrows;
   const float *a, *b;
   const int32_t *idx;
-  const float *carry;
+  const float *y;        // forward output (read for the prefixes y_{i-1})
   const int32_t *argk;
   const float *ybar, *hbar;
   float *abar, *bbar;
@@ -364,22 +371,22 @@ struct SegBwdArgs {
 };
 
 // Persistent: block b takes items nitems-1-b, nitems-1-b-G, ... (right to
-// left).  One iteration prefetches the next item (inputs and the bins'
-// argk / h_bar entries), resolves the current item's look-back, sweeps and
-// stores it, then scans the next item: y_bar_total = y_bar + h_bar at the
-// bin's argmin, forward prefixes recomputed from the saved item prefix, the
-// adjoint maps scanned right to left and the item aggregate published.
+// left).  One iteration prefetches the next item (a, the forward output y,
+// y_bar, keys, and the bins' argk / h_bar entries), resolves the current
+// item's look-back, sweeps and stores it, then scans the next item:
+// y_bar_total = y_bar + h_bar at the bin's argmin, the adjoint maps of the
+// recurrence scanned right to left and the item aggregate published.  The
+// forward prefix y_{i-1} that a_bar needs is read from the forward output
+// (the forward of this workload stores y anyway), so the adjoint never
+// re-runs the forward recurrence and never reads b.
 __global__ __launch_bounds__(SEG_TH) void k_seg_bwd(SegBwdArgs a) {
-  using Op = FwdLB<LINREC>;
-  using FT = Op::T;
-  using M = MapScal;
+  using FT = Fwd<LINREC>::T;
+  using M = MapScalT<false>;
   using MT = M::T;
   using A = Adj<LINREC, false>;
   constexpr int K = SEG_K, EPL = SEG_EPL, W = SEG_W, TH = SEG_TH;
   constexpr int TPT = SEG_MAX_BINS / TH;  // bin entries per thread
 
-  __shared__ FT s_ftot[K][W];
-  __shared__ FT s_fpre[K][W];
   __shared__ MT s_mtot[K][W];
   __shared__ MT s_mpre[K][W];
   __shared__ MT s_carry;
@@ -392,19 +399,24 @@ __global__ __launch_bounds__(SEG_TH) void k_seg_bwd(SegBwdArgs a) {
   if (tid == 0) s_epoch = ctl_load(&a.ctl->epoch);
 
   struct Buf {
-    float4 a[K], b[K], yb[K];
+    float4 a[K], y[K], yb[K];
     int4 ix[K];
+    float yp0[K];  // lane 0: y of the element before the lane's group (0 at an instance start)
     int32_t ak[TPT];
     float hb[TPT];
   };
   auto load = [&](const SegItem &it, Buf &B) {
 #pragma unroll
     for (int g = 0; g < K; ++g) {
-      const int64_t e = it.wbase + g * TH * EPL + tid * EPL;
-      B.a[g] = ld_range(a.a, e, it.lo, it.hi, 1.0f);
-      B.b[g] = ld_range(a.b, e, it.lo, it.hi, 0.0f);
-      B.yb[g] = ld_range(a.ybar, e, it.lo, it.hi, 0.0f);
-      B.ix[g] = ld_range_i(a.idx, e, it.lo, it.hi);
+      const int e = g * TH * EPL + tid * EPL;
+      B.a[g] = ld_range(a.a + it.wbase, e, it.lo_r, it.hi_r, 1.0f);
+      B.y[g] = ld_range(a.y + it.wbase, e, it.lo_r, it.hi_r, 0.0f);
+      B.yb[g] = ld_range(a.ybar + it.wbase, e, it.lo_r, it.hi_r, 0.0f);
+      B.ix[g] = ld_range_i(a.idx + it.wbase, e, it.lo_r, it.hi_r);
+      // element e-1 lies in the instance iff its instance index is >= 0 and
+      // it is before the instance's end in this window
+      B.yp0[g] = 0.0f;
+      if (lane == 0 && it.wofs + e - 1 >= 0 && e - 1 < it.hi_r) B.yp0[g] = a.y[it.wbase + e - 1];
     }
     const int64_t hb = it.s * a.m;
 #pragma unroll
@@ -423,60 +435,24 @@ __global__ __launch_bounds__(SEG_TH) void k_seg_bwd(SegBwdArgs a) {
   __syncthreads();
   const uint32_t tag = s_epoch + 1;
 
-  FT thr_f[K], loc[K][EPL];
   MT mincl[K];
   MT agg = M::id();        // wave 0: map aggregate of the current item
   MT prev_incl = M::id();  // wave 0: carry into the block's previous item, combined with it
-  auto prefix = [&](int g, int j) -> FT {
-    return j == 0 ? thr_f[g] : Op::comb(thr_f[g], loc[g][j - 1]);
-  };
 
   // scans the item in `cur` (its bin entries already in LDS)
   auto phase1 = [&](const SegItem &jt, int64_t item) {
-    // y_bar_total = y_bar + h_bar at the bin's argmin (fused min-by-index adjoint)
 #pragma unroll
     for (int g = 0; g < K; ++g) {
-      const int64_t e = jt.wbase + g * TH * EPL + tid * EPL;
-#pragma unroll
-      for (int j = 0; j < EPL; ++j) {
-        const int kb = i4get(cur.ix[g], j);
-        if (kb >= 0 && kb < a.m && (int64_t)s_ak[kb] == e + j - jt.start)
-          f4set(cur.yb[g], j, f4get(cur.yb[g], j) + s_hb[kb]);
-      }
-    }
-    // forward prefixes (A_{i-1}, y_{i-1}) recomputed from the saved item prefix
-    FT fincl[K];
-#pragma unroll
-    for (int g = 0; g < K; ++g) {
-      FT acc = {{f4get(cur.a[g], 0), f4get(cur.b[g], 0)}};
-      loc[g][0] = acc;
-#pragma unroll
-      for (int j = 1; j < EPL; ++j) {
-        acc = Op::comb(acc, FT{{f4get(cur.a[g], j), f4get(cur.b[g], j)}});
-        loc[g][j] = acc;
-      }
-      fincl[g] = wave_scan_fwd<Op>(acc);
-      if (lane == WAVE - 1) s_ftot[g][wave] = fincl[g];
-    }
-    __syncthreads();
-    if (wave == 0) {
-      const FT c = {{a.carry[item * 2 + 0], a.carry[item * 2 + 1]}};
-      wave0_block_prefix<Op, K, W, false>(s_ftot, s_fpre, c);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int g = 0; g < K; ++g) {
-      FT ex = shift_up1(fincl[g]);
-      if (lane == 0) ex = Op::id();
-      thr_f[g] = Op::comb(s_fpre[g][wave], ex);
-    }
-#pragma unroll
-    for (int g = 0; g < K; ++g) {
+      const int e = g * TH * EPL + tid * EPL;
       MT acc = M::id();
 #pragma unroll
       for (int j = EPL - 1; j >= 0; --j) {
+        // y_bar_total = y_bar + h_bar at the bin's argmin (fused min-by-index adjoint)
+        const int kb = i4get(cur.ix[g], j);
+        if (kb >= 0 && kb < a.m && s_ak[kb] == jt.wofs + e + j)
+          f4set(cur.yb[g], j, f4get(cur.yb[g], j) + s_hb[kb]);
         const float yb[2] = {f4get(cur.yb[g], j), 0.0f};
-        const MT hm = A::make(prefix(g, j), FT{{f4get(cur.a[g], j), f4get(cur.b[g], j)}}, yb, false);
+        const MT hm = A::make(FT{{1.0f, 0.0f}}, FT{{f4get(cur.a[g], j), 0.0f}}, yb, false);
         acc = (j == EPL - 1) ? hm : M::comb(acc, hm);
       }
       mincl[g] = wave_scan_rev<M>(acc);
@@ -546,18 +522,22 @@ __global__ __launch_bounds__(SEG_TH) void k_seg_bwd(SegBwdArgs a) {
       MT ex = shift_down1(mincl[g]);
       if (lane == WAVE - 1) ex = M::id();
       M::P rho = M::apply0(M::comb(M::comb(carry, s_mpre[g][wave]), ex));
+      // y_{i-1} of the four slots: the left neighbour's last y for the first
+      float yprev0 = dpp_f<kDppWaveShr1>(cur.y[g].w);
+      if (lane == 0) yprev0 = cur.yp0[g];
+      const float yprev[4] = {yprev0, cur.y[g].x, cur.y[g].y, cur.y[g].z};
       float4 oa, ob;
 #pragma unroll
       for (int j = EPL - 1; j >= 0; --j) {
         const float yb[2] = {f4get(cur.yb[g], j), 0.0f};
         float xb[2];
-        A::step(prefix(g, j), FT{{f4get(cur.a[g], j), f4get(cur.b[g], j)}}, yb, false, rho, xb);
+        A::step(FT{{1.0f, yprev[j]}}, FT{{f4get(cur.a[g], j), 0.0f}}, yb, false, rho, xb);
         f4set(oa, j, xb[0]);
         f4set(ob, j, xb[1]);
       }
-      const int64_t e = it.wbase + g * TH * EPL + tid * EPL;
-      st_range(a.abar, e, it.lo, it.hi, oa);
-      st_range(a.bbar, e, it.lo, it.hi, ob);
+      const int e = g * TH * EPL + tid * EPL;
+      st_range(a.abar + it.wbase, e, it.lo_r, it.hi_r, oa);
+      st_range(a.bbar + it.wbase, e, it.lo_r, it.hi_r, ob);
     }
     if (!more) break;
     k = kn;
@@ -800,7 +780,7 @@ int pcad_plan_bind(pcad_plan *p, const float *a, const float *b, const int32_t *
   float *carry = reinterpret_cast<float *>(p->saved + p->sv_carry);
   p->fa = SegFwdArgs{t, p->nitems, (int)p->S, (int)p->m, (int)p->nrows, a, b, idx, y, h, argk, carry,
                      keys, ctl, status};
-  p->ba = SegBwdArgs{t, p->nitems, (int)p->S, (int)p->m, (int)p->nrows, a, b, idx, carry, argk,
+  p->ba = SegBwdArgs{t, p->nitems, (int)p->S, (int)p->m, (int)p->nrows, a, b, idx, y, argk,
                      ybar, hbar, abar, bbar, ctl, status};
 
   // one graph per phase: forward, adjoint, both

@@ -185,50 +185,57 @@ struct Shape {
   static_assert(K >= 1 && K * THREADS * EPL == TILE, "tile must be whole groups of the block");
 };
 
-// 16-byte load of one group of one stream.  `S` floats per element.  When
-// the group is whole and the address 16-byte aligned, one dwordx4 load;
+// 16-byte load of one group of one stream: element `el` (a lane's first)
+// of the tile starting at element `base`.  `S` floats per element.  When the
+// group is whole and the address 16-byte aligned, one dwordx4 load;
 // otherwise element-wise loads of the valid part with `fill` elsewhere.
+// The tile's base pointer is block-uniform and the lane offset 32-bit, so
+// the address is a scalar base plus a vector offset.
 template <int S>
-__device__ __forceinline__ float4 load_group(const float *__restrict__ p, int64_t e, int valid,
-                                             bool vec_ok, float4 fill) {
+__device__ __forceinline__ float4 load_group(const float *__restrict__ p, int64_t base, int el,
+                                             int valid, bool vec_ok, float4 fill) {
+  const float *__restrict__ q = p + base * S;
+  const unsigned o = (unsigned)el * S;
   if (valid >= 4 / S && (S == 4 || vec_ok)) {
-    return *reinterpret_cast<const float4 *>(p + e * S);
+    return *reinterpret_cast<const float4 *>(q + o);
   }
   float r[4] = {fill.x, fill.y, fill.z, fill.w};
   if (S == 4) {
     if (valid > 0) {
-      float4 t = *reinterpret_cast<const float4 *>(p + e * 4);
+      float4 t = *reinterpret_cast<const float4 *>(q + o);
       r[0] = t.x; r[1] = t.y; r[2] = t.z; r[3] = t.w;
     }
   } else {
 #pragma unroll
     for (int j = 0; j < 4; ++j)
-      if (j < valid) r[j] = p[e + j];
+      if (j < valid) r[j] = q[o + j];
   }
   return make_float4(r[0], r[1], r[2], r[3]);
 }
 
 template <int S>
-__device__ __forceinline__ void store_group(float *__restrict__ p, int64_t e, int valid,
+__device__ __forceinline__ void store_group(float *__restrict__ p, int64_t base, int el, int valid,
                                             bool vec_ok, float4 v) {
+  float *__restrict__ q = p + base * S;
+  const unsigned o = (unsigned)el * S;
   if (valid >= 4 / S && (S == 4 || vec_ok)) {
     // one 16-byte streaming store per lane: whole 64-byte lines per quad of
     // lanes, no partial-line writes
     typedef float v4f __attribute__((ext_vector_type(4)));
     v4f w = {v.x, v.y, v.z, v.w};
-    __builtin_nontemporal_store(w, reinterpret_cast<v4f *>(p + e * S));
+    __builtin_nontemporal_store(w, reinterpret_cast<v4f *>(q + o));
     return;
   }
   float r[4] = {v.x, v.y, v.z, v.w};
   if (S == 4) {
     if (valid > 0) {
 #pragma unroll
-      for (int j = 0; j < 4; ++j) p[e * 4 + j] = r[j];
+      for (int j = 0; j < 4; ++j) q[o + j] = r[j];
     }
   } else {
 #pragma unroll
     for (int j = 0; j < 4; ++j)
-      if (j < valid) p[e + j] = r[j];
+      if (j < valid) q[o + j] = r[j];
   }
 }
 

@@ -313,7 +313,7 @@ __global__ __launch_bounds__(Shape<OP>::THREADS) void k_reduce_vjp_gen(RedGenArg
     float4 in[NIN];
 #pragma unroll
     for (int s = 0; s < NIN; ++s)
-      in[s] = load_group<S>(src[s], ti.base + el, v, ti.vec_ok, Io::fill(s));
+      in[s] = load_group<S>(src[s], ti.base, el, v, ti.vec_ok, Io::fill(s));
 #pragma unroll
     for (int j = 0; j < EPL; ++j) xe[g][j] = Io::elem(in, j);
   }
@@ -407,10 +407,10 @@ __global__ __launch_bounds__(Shape<OP>::THREADS) void k_reduce_vjp_gen(RedGenArg
     for (int s = 0; s < NS; ++s) {
       float4 val = o[s];
       if (a.accumulate) {
-        const float4 old = load_group<S>(dst[s], ti.base + el, v, ti.vec_ok, make_float4(0, 0, 0, 0));
+        const float4 old = load_group<S>(dst[s], ti.base, el, v, ti.vec_ok, make_float4(0, 0, 0, 0));
         val.x += old.x; val.y += old.y; val.z += old.z; val.w += old.w;
       }
-      store_group<S>(dst[s], ti.base + el, v, ti.vec_ok, val);
+      store_group<S>(dst[s], ti.base, el, v, ti.vec_ok, val);
     }
   }
 }

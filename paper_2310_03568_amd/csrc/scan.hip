@@ -65,7 +65,7 @@ __global__ __launch_bounds__(Shape<OP>::THREADS) void k_scan_fwd(ScanFwdArgs a) 
       const int el = g * TH * EPL + tid * EPL;
 #pragma unroll
       for (int s = 0; s < NIN; ++s)
-        buf[g][s] = load_group<S>(src[s], ti.base + el, ti.valid - el, ti.vec_ok, Io::fill(s));
+        buf[g][s] = load_group<S>(src[s], ti.base, el, ti.valid - el, ti.vec_ok, Io::fill(s));
     }
   };
 
@@ -168,7 +168,7 @@ __global__ __launch_bounds__(Shape<OP>::THREADS) void k_scan_fwd(ScanFwdArgs a) 
         const int v = ti.valid - el;
         if constexpr (OP == MAT2) {
           const T o = Op::comb(full, ploc[g][0]);
-          store_group<4>(a.y0, ti.base + el, v, true, make_float4(o.f[0], o.f[1], o.f[2], o.f[3]));
+          store_group<4>(a.y0, ti.base, el, v, true, make_float4(o.f[0], o.f[1], o.f[2], o.f[3]));
         } else {
           float4 o0, o1;
 #pragma unroll
@@ -181,8 +181,8 @@ __global__ __launch_bounds__(Shape<OP>::THREADS) void k_scan_fwd(ScanFwdArgs a) 
               f4set(o0, j, o.f[0]);
             }
           }
-          store_group<1>(a.y0, ti.base + el, v, ti.vec_ok, o0);
-          if (OP == LINREC && a.y1) store_group<1>(a.y1, ti.base + el, v, ti.vec_ok, o1);
+          store_group<1>(a.y0, ti.base, el, v, ti.vec_ok, o0);
+          if (OP == LINREC && a.y1) store_group<1>(a.y1, ti.base, el, v, ti.vec_ok, o1);
         }
       }
     }
@@ -268,13 +268,13 @@ __global__ __launch_bounds__((Shape<OP, 1>::THREADS)) void k_scan_vjp(ScanVjpArg
       const int v = ti.valid - el;
 #pragma unroll
       for (int s = 0; s < NX; ++s)
-        buf[g][s] = load_group<S>(src[s], ti.base + el, v, ti.vec_ok, Io::fill(s));
-      buf[g][IYB] = load_group<S>(a.yb0, ti.base + el, v, ti.vec_ok, make_float4(0, 0, 0, 0));
+        buf[g][s] = load_group<S>(src[s], ti.base, el, v, ti.vec_ok, Io::fill(s));
+      buf[g][IYB] = load_group<S>(a.yb0, ti.base, el, v, ti.vec_ok, make_float4(0, 0, 0, 0));
       if (ABAR)
-        buf[g][IAB] = load_group<1>(a.yb1, ti.base + el, v, ti.vec_ok, make_float4(0, 0, 0, 0));
+        buf[g][IAB] = load_group<1>(a.yb1, ti.base, el, v, ti.vec_ok, make_float4(0, 0, 0, 0));
 #pragma unroll
       for (int s = 0; s < NT; ++s) {
-        buf[g][IT + s] = load_group<S>(tp[s], ti.base + el, v, ti.vec_ok, tape_id(s));
+        buf[g][IT + s] = load_group<S>(tp[s], ti.base, el, v, ti.vec_ok, tape_id(s));
         float4 q = tape_id(s);
         if (lane == 0 && v > 0 && !(ti.lt == 0 && el == 0)) {
           const int64_t e = ti.base + el - 1;
@@ -475,10 +475,10 @@ __global__ __launch_bounds__((Shape<OP, 1>::THREADS)) void k_scan_vjp(ScanVjpArg
       for (int s = 0; s < A::NXB / (S == 4 ? 4 : 1); ++s) {
         float4 val = o[s];
         if (a.accumulate) {
-          const float4 old = load_group<S>(dst[s], ti.base + el, v, ti.vec_ok, make_float4(0, 0, 0, 0));
+          const float4 old = load_group<S>(dst[s], ti.base, el, v, ti.vec_ok, make_float4(0, 0, 0, 0));
           val.x += old.x; val.y += old.y; val.z += old.z; val.w += old.w;
         }
-        store_group<S>(dst[s], ti.base + el, v, ti.vec_ok, val);
+        store_group<S>(dst[s], ti.base, el, v, ti.vec_ok, val);
       }
     }
     if (!more) break;
