@@ -24,11 +24,23 @@
 
 namespace pcad {
 
-constexpr int SEG_TH = 512;
-constexpr int SEG_K = 4;
+// items of SEG_T elements; block sizes of the forward and adjoint kernels
+// (build-time knobs for shape sweeps)
+#ifndef PCAD_SEG_FWD_THREADS
+#define PCAD_SEG_FWD_THREADS 512
+#endif
+#ifndef PCAD_SEG_VJP_THREADS
+#define PCAD_SEG_VJP_THREADS 512
+#endif
+#ifndef PCAD_SEG_TILE
+#define PCAD_SEG_TILE 8192
+#endif
+constexpr int SEG_T = PCAD_SEG_TILE;
 constexpr int SEG_EPL = 4;
-constexpr int SEG_W = SEG_TH / WAVE;
-constexpr int SEG_T = SEG_TH * SEG_EPL * SEG_K;
+constexpr int SEG_THF = PCAD_SEG_FWD_THREADS, SEG_KF = SEG_T / (SEG_THF * SEG_EPL);
+constexpr int SEG_THB = PCAD_SEG_VJP_THREADS, SEG_KB = SEG_T / (SEG_THB * SEG_EPL);
+static_assert(SEG_KF * SEG_THF * SEG_EPL == SEG_T && SEG_KB * SEG_THB * SEG_EPL == SEG_T,
+              "items must be whole groups of the block");
 constexpr int SEG_MAX_BINS = 1024;
 
 // one record per work item, built on the host at bind time
@@ -137,10 +149,10 @@ struct SegFwdArgs {
 // publishes its next item in between).  The pending item's item-local
 // prefixes and keys wait in LDS; its outputs and LDS sub-histogram follow
 // the look-back.
-__global__ __launch_bounds__(SEG_TH) void k_seg_fwd(SegFwdArgs a) {
+__global__ __launch_bounds__(SEG_THF) void k_seg_fwd(SegFwdArgs a) {
   using Op = FwdLB<LINREC>;
   using T = Op::T;
-  constexpr int K = SEG_K, EPL = SEG_EPL, W = SEG_W, TH = SEG_TH;
+  constexpr int K = SEG_KF, EPL = SEG_EPL, TH = SEG_THF, W = TH / WAVE;
 
   __shared__ T s_tot[K][W];
   __shared__ T s_pre[K][W];
@@ -280,8 +292,10 @@ __global__ __launch_bounds__(SEG_TH) void k_seg_fwd(SegFwdArgs a) {
         const float yv = Op::comb(carry, T{{pa[j], py[j]}}).f[1];
         f4set(o, j, yv);
         const int k = i4get(ix, j);
-        if (k >= 0 && k < a.m)  // elements outside the instance carry key -1
-          atomicMin(&s_keys[k], (unsigned long long)key_of<MIN>(yv, (uint32_t)(it.wofs + e + j)));
+        if (k >= 0 && k < a.m) {  // elements outside the instance carry key -1
+          const unsigned long long key = key_of<MIN>(yv, (uint32_t)(it.wofs + e + j));
+          atomicMin(&s_keys[k], key);
+        }
       }
       st_range(a.y + it.wbase, e, it.lo_r, it.hi_r, o);
     }
@@ -379,13 +393,13 @@ struct SegBwdArgs {
 // forward prefix y_{i-1} that a_bar needs is read from the forward output
 // (the forward of this workload stores y anyway), so the adjoint never
 // re-runs the forward recurrence and never reads b.
-__global__ __launch_bounds__(SEG_TH) void k_seg_bwd(SegBwdArgs a) {
+__global__ __launch_bounds__(SEG_THB) void k_seg_bwd(SegBwdArgs a) {
   using FT = Fwd<LINREC>::T;
   using M = MapScalT<false>;
   using MT = M::T;
   using A = Adj<LINREC, false>;
-  constexpr int K = SEG_K, EPL = SEG_EPL, W = SEG_W, TH = SEG_TH;
-  constexpr int TPT = SEG_MAX_BINS / TH;  // bin entries per thread
+  constexpr int K = SEG_KB, EPL = SEG_EPL, TH = SEG_THB, W = TH / WAVE;
+  constexpr int TPT = (SEG_MAX_BINS + TH - 1) / TH;  // bin entries per thread
 
   __shared__ MT s_mtot[K][W];
   __shared__ MT s_mpre[K][W];
@@ -598,20 +612,20 @@ int plan_hip(hipError_t e) {
 // persistent grids: as many blocks as can be resident at once (a block waits
 // only on items of lower order in its direction, owned by resident blocks)
 template <class F>
-int64_t seg_grid(F kernel, int64_t nitems) {
+int64_t seg_grid(F kernel, int threads, int64_t nitems) {
   int dev = 0, cus = 0, occ = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, SEG_TH, 0) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, threads, 0) != hipSuccess) return 0;
   const int64_t cap = (int64_t)cus * (occ > 0 ? occ : 1);
   return nitems < cap ? nitems : cap;
 }
 
 hipError_t launch_fwd_nodes(pcad_plan *p, hipStream_t s) {
   if (p->nitems > 0) {
-    const int64_t grid = seg_grid(k_seg_fwd, p->nitems);
+    const int64_t grid = seg_grid(k_seg_fwd, SEG_THF, p->nitems);
     if (grid == 0) return hipErrorInvalidDevice;
-    hipLaunchKernelGGL(k_seg_fwd, dim3((unsigned)grid), dim3(SEG_TH), 0, s, p->fa);
+    hipLaunchKernelGGL(k_seg_fwd, dim3((unsigned)grid), dim3(SEG_THF), 0, s, p->fa);
   }
   hipLaunchKernelGGL(k_seg_fin, dim3(2048), dim3(256), 0, s, p->fa);
   return hipGetLastError();
@@ -619,9 +633,9 @@ hipError_t launch_fwd_nodes(pcad_plan *p, hipStream_t s) {
 
 hipError_t launch_bwd_nodes(pcad_plan *p, hipStream_t s) {
   if (p->nitems > 0) {
-    const int64_t grid = seg_grid(k_seg_bwd, p->nitems);
+    const int64_t grid = seg_grid(k_seg_bwd, SEG_THB, p->nitems);
     if (grid == 0) return hipErrorInvalidDevice;
-    hipLaunchKernelGGL(k_seg_bwd, dim3((unsigned)grid), dim3(SEG_TH), 0, s, p->ba);
+    hipLaunchKernelGGL(k_seg_bwd, dim3((unsigned)grid), dim3(SEG_THB), 0, s, p->ba);
   }
   return hipGetLastError();
 }
