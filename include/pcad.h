@@ -259,6 +259,24 @@ int pcad_plan_run_per_segment(pcad_plan *plan, int phase, void *stream);
 void pcad_plan_destroy(pcad_plan *plan);
 int pcad_plan_last_hip_error(void);
 
+/*
+ * Tuning knobs: launch parameters an autotuner may set (the block size of the
+ * scan kernels per operator and direction, the bin count up to which
+ * reduce-by-index keeps private LDS histograms, and elements per histogram
+ * block).  Knobs never change results' or saved states' layouts, only speed;
+ * they are process-wide and read at launch time, so setting one while
+ * another host thread launches is a race on that launch's choice only.
+ *   pcad_knob_set: PCAD_E_INVALID_ARG for an unknown name or a value outside
+ *                  the knob's range (block sizes: 256, 512 or 1024).
+ *   pcad_knob_name: NULL for an index outside [0, pcad_knob_count()).
+ *   pcad_knob_reset: every knob back to its built-in default.
+ */
+int pcad_knob_count(void);
+const char *pcad_knob_name(int i);
+int pcad_knob_get(const char *name, int64_t *value);
+int pcad_knob_set(const char *name, int64_t value);
+void pcad_knob_reset(void);
+
 #ifdef __cplusplus
 }
 #endif

@@ -66,6 +66,11 @@ def lib():
             "pcad_plan_run_per_segment": ([P, I, P], I),
             "pcad_plan_destroy": ([P], None),
             "pcad_plan_last_hip_error": ([], I),
+            "pcad_knob_count": ([], I),
+            "pcad_knob_name": ([I], ctypes.c_char_p),
+            "pcad_knob_get": ([ctypes.c_char_p, ctypes.POINTER(I64)], I),
+            "pcad_knob_set": ([ctypes.c_char_p, I64], I),
+            "pcad_knob_reset": ([], None),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -87,6 +92,29 @@ def check(status: int, what: str = ""):
         msg = L.pcad_status_string(status).decode()
         hip = L.pcad_last_hip_error()
         raise PcadError(f"{what}: {msg} (status {status}, hip error {hip})")
+
+
+# ---------------------------------------------------------------------------
+# tuning knobs (launch parameters; results do not depend on them)
+# ---------------------------------------------------------------------------
+def knobs() -> dict:
+    """Current value of every tuning knob, by name."""
+    L = lib()
+    out = {}
+    for i in range(L.pcad_knob_count()):
+        name = L.pcad_knob_name(i)
+        v = ctypes.c_int64(0)
+        check(L.pcad_knob_get(name, ctypes.byref(v)), "pcad_knob_get")
+        out[name.decode()] = v.value
+    return out
+
+
+def set_knob(name: str, value: int):
+    check(lib().pcad_knob_set(name.encode(), int(value)), f"pcad_knob_set({name}={value})")
+
+
+def reset_knobs():
+    lib().pcad_knob_reset()
 
 
 # ---------------------------------------------------------------------------

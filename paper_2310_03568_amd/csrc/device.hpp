@@ -173,6 +173,17 @@ struct Fwd<MAT2> {
 #define PCAD_VJP_THREADS 512
 #endif
 
+// a tile of the scan kernels split over TH_ threads
+template <int OP, int TH_>
+struct ShapeT {
+  static constexpr int EPL = (OP == MAT2) ? 1 : 4;
+  static constexpr int TILE = (OP == MAT2) ? PCAD_SCAN_TILE / 4 : PCAD_SCAN_TILE;
+  static constexpr int THREADS = TH_;
+  static constexpr int W = THREADS / WAVE;
+  static constexpr int K = TILE / (THREADS * EPL);
+  static_assert(K >= 1 && K * THREADS * EPL == TILE, "tile must be whole groups of the block");
+};
+
 template <int OP, int DIR = 0>
 struct Shape {
   static constexpr int EPL = (OP == MAT2) ? 1 : 4;

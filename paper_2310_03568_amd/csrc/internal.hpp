@@ -14,6 +14,11 @@ constexpr size_t kCtlBytes = 256;
 // and returns PCAD_E_HIP
 int hip_status(hipError_t e);
 
+// tuning knobs (knobs.hip)
+int knob_scan_threads(int op, int dir);  // dir 0 forward, 1 adjoint
+int64_t knob_rbi_lds_max_bins(bool u64);
+int64_t knob_rbi_elems_per_block();
+
 // scan
 int scan_tile_size(int op);
 int scan_elem_floats(int op);

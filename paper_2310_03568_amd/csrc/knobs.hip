@@ -1,0 +1,90 @@
+// Tuning knobs: the launch parameters an autotuner may choose (block sizes of
+// the scan kernels, the reduce-by-index strategy threshold and chunking).
+// No knob changes a result's layout or a saved state's layout; only speed
+// depends on them.  Values are process-wide and read at launch time.
+#include <string.h>
+
+#include "../../include/pcad.h"
+#include "internal.hpp"
+
+namespace pcad {
+namespace {
+
+struct Knob {
+  const char *name;
+  int64_t def, lo, hi;
+  bool pow2;  // value must be a power of two
+  int64_t value;
+};
+
+// order: scan forward threads by operator, scan adjoint threads by operator,
+// then the reduce-by-index knobs (indices used below)
+Knob g_knobs[] = {
+    {"scan.fwd.threads.add", 1024, 256, 1024, true, 1024},
+    {"scan.fwd.threads.mul", 1024, 256, 1024, true, 1024},
+    {"scan.fwd.threads.min", 1024, 256, 1024, true, 1024},
+    {"scan.fwd.threads.max", 1024, 256, 1024, true, 1024},
+    {"scan.fwd.threads.linrec", 512, 256, 1024, true, 512},
+    {"scan.fwd.threads.mat2", 512, 256, 1024, true, 512},
+    {"scan.vjp.threads.add", 512, 256, 1024, true, 512},
+    {"scan.vjp.threads.mul", 512, 256, 1024, true, 512},
+    {"scan.vjp.threads.min", 512, 256, 1024, true, 512},
+    {"scan.vjp.threads.max", 512, 256, 1024, true, 512},
+    {"scan.vjp.threads.linrec", 512, 256, 1024, true, 512},
+    {"scan.vjp.threads.mat2", 512, 256, 1024, true, 512},
+    // bins up to which a block keeps a private LDS histogram (+ and *: float
+    // values; min/max: 64-bit keys); above it, global atomics
+    {"rbi.lds_max_bins_f32", 8192, 0, 8192, false, 8192},
+    {"rbi.lds_max_bins_u64", 4096, 0, 4096, false, 4096},
+    // elements per block of the histogram kernels
+    {"rbi.elems_per_block", 16384, 1024, 1 << 20, true, 16384},
+};
+constexpr int kNumKnobs = (int)(sizeof(g_knobs) / sizeof(g_knobs[0]));
+constexpr int kRbiF32 = 12, kRbiU64 = 13, kRbiEpb = 14;
+
+Knob *find(const char *name) {
+  if (!name) return nullptr;
+  for (Knob &k : g_knobs)
+    if (strcmp(k.name, name) == 0) return &k;
+  return nullptr;
+}
+
+}  // namespace
+
+int knob_scan_threads(int op, int dir) { return (int)g_knobs[(dir ? 6 : 0) + op].value; }
+int64_t knob_rbi_lds_max_bins(bool u64) { return g_knobs[u64 ? kRbiU64 : kRbiF32].value; }
+int64_t knob_rbi_elems_per_block() { return g_knobs[kRbiEpb].value; }
+
+}  // namespace pcad
+
+using namespace pcad;
+
+extern "C" {
+
+int pcad_knob_count(void) { return kNumKnobs; }
+
+const char *pcad_knob_name(int i) { return (i >= 0 && i < kNumKnobs) ? g_knobs[i].name : nullptr; }
+
+int pcad_knob_get(const char *name, int64_t *value) {
+  if (!name || !value) return PCAD_E_NULLPTR;
+  const Knob *k = find(name);
+  if (!k) return PCAD_E_INVALID_ARG;
+  *value = k->value;
+  return PCAD_OK;
+}
+
+int pcad_knob_set(const char *name, int64_t value) {
+  if (!name) return PCAD_E_NULLPTR;
+  Knob *k = find(name);
+  if (!k) return PCAD_E_INVALID_ARG;
+  if (value < k->lo || value > k->hi) return PCAD_E_INVALID_ARG;
+  if (k->pow2 && (value & (value - 1)) != 0) return PCAD_E_INVALID_ARG;
+  k->value = value;
+  return PCAD_OK;
+}
+
+void pcad_knob_reset(void) {
+  for (Knob &k : g_knobs) k.value = k.def;
+}
+
+}  // extern "C"

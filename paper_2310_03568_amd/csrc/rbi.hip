@@ -143,26 +143,86 @@ __global__ __launch_bounds__(BLOCK) void k_rbi_lds(RbiArgs a) {
   }
 }
 
-// update pass with global atomics
+// Update pass for bin counts beyond a full LDS histogram: each block keeps
+// an LDS hash table of the bins it meets (open addressing, linear probing),
+// so repeated bins -- skewed keys -- combine in LDS and reach global memory
+// once per block; a key that finds no slot within kProbes probes goes
+// straight to a global atomic (distinct bins contend little).
+constexpr int kHashSlots = 4096;
+constexpr int kProbes = 8;
+
 template <int OP>
-__global__ __launch_bounds__(BLOCK) void k_rbi_global(RbiArgs a) {
+__device__ __forceinline__ void rbi_global_update(const RbiArgs &a, int64_t g, float v,
+                                                  uint32_t i) {
+  if (OP == ADD) unsafeAtomicAdd(&a.hist[g], v);
+  if (OP == MUL) {
+    if (v == 0.0f) atomicAdd(&a.n0[g], 1u);
+    else atomic_mul_f32(&a.ypos[g], v);
+  }
+  if (OP == MIN)
+    atomicMin(reinterpret_cast<unsigned long long *>(&a.keys[g]),
+              (unsigned long long)key_of<MIN>(v, i));
+  if (OP == MAX)
+    atomicMax(reinterpret_cast<unsigned long long *>(&a.keys[g]),
+              (unsigned long long)key_of<MAX>(v, i));
+}
+
+template <int OP>
+__global__ __launch_bounds__(BLOCK) void k_rbi_hash(RbiArgs a) {
+  constexpr bool KEYS = OP == MIN || OP == MAX;
+  __shared__ int32_t s_bin[kHashSlots];
+  __shared__ float s_f[KEYS ? 1 : kHashSlots];
+  __shared__ unsigned s_c[OP == MUL ? kHashSlots : 1];
+  __shared__ unsigned long long s_k[KEYS ? kHashSlots : 1];
   const int64_t row = blockIdx.y;
   const int64_t gb = row * a.m;
   const int64_t m = a.m;
+  for (int t = threadIdx.x; t < kHashSlots; t += BLOCK) {
+    s_bin[t] = -1;
+    if (OP == ADD) s_f[t] = 0.0f;
+    if (OP == MUL) { s_f[t] = 1.0f; s_c[t] = 0u; }
+    if (KEYS) s_k[t] = key_init<OP>();
+  }
+  __syncthreads();
   for_chunk(a, row, [&](int32_t k, float v, uint32_t i) {
     if (k < 0 || k >= m) return;
-    if (OP == ADD) unsafeAtomicAdd(&a.hist[gb + k], v);
-    if (OP == MUL) {
-      if (v == 0.0f) atomicAdd(&a.n0[gb + k], 1u);
-      else atomic_mul_f32(&a.ypos[gb + k], v);
+    uint32_t h = ((uint32_t)k * 2654435761u) >> (32 - 12);  // kHashSlots = 2^12
+#pragma unroll 1
+    for (int p = 0; p < kProbes; ++p) {
+      int32_t cur = __hip_atomic_load(&s_bin[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      if (cur == -1) {
+        int32_t expect = -1;
+        __hip_atomic_compare_exchange_strong(&s_bin[h], &expect, k, __ATOMIC_RELAXED,
+                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        cur = expect == -1 ? k : expect;  // the slot is ours, or holds the winner's bin
+      }
+      if (cur == k) {
+        if (OP == ADD) atomicAdd(&s_f[h], v);
+        if (OP == MUL) {
+          if (v == 0.0f) atomicAdd(&s_c[h], 1u);
+          else lds_mul_f32(&s_f[h], v);
+        }
+        if (OP == MIN) atomicMin(&s_k[h], (unsigned long long)key_of<MIN>(v, i));
+        if (OP == MAX) atomicMax(&s_k[h], (unsigned long long)key_of<MAX>(v, i));
+        return;
+      }
+      h = (h + 1) & (kHashSlots - 1);
     }
-    if (OP == MIN)
-      atomicMin(reinterpret_cast<unsigned long long *>(&a.keys[gb + k]),
-                (unsigned long long)key_of<MIN>(v, i));
-    if (OP == MAX)
-      atomicMax(reinterpret_cast<unsigned long long *>(&a.keys[gb + k]),
-                (unsigned long long)key_of<MAX>(v, i));
+    rbi_global_update<OP>(a, gb + k, v, i);
   });
+  __syncthreads();
+  for (int t = threadIdx.x; t < kHashSlots; t += BLOCK) {
+    const int32_t k = s_bin[t];
+    if (k < 0) continue;
+    const int64_t g = gb + k;
+    if (OP == ADD) unsafeAtomicAdd(&a.hist[g], s_f[t]);
+    if (OP == MUL) {
+      if (s_c[t]) atomicAdd(&a.n0[g], s_c[t]);
+      if (s_f[t] != 1.0f) atomic_mul_f32(&a.ypos[g], s_f[t]);
+    }
+    if (OP == MIN) atomicMin(reinterpret_cast<unsigned long long *>(&a.keys[g]), s_k[t]);
+    if (OP == MAX) atomicMax(reinterpret_cast<unsigned long long *>(&a.keys[g]), s_k[t]);
+  }
 }
 
 // per-bin finalisation: value and argk (min/max), value (mul)
@@ -260,8 +320,8 @@ __global__ __launch_bounds__(BLOCK) void k_rbi_vjp(RbiVjpArgs a) {
 // host side
 // ---------------------------------------------------------------------------
 static bool use_lds(int op, int64_t m) {
-  if (op == MIN || op == MAX) return m <= kLdsBinsU64;
-  return m <= kLdsBinsF32;
+  if (op == MIN || op == MAX) return m <= kLdsBinsU64 && m <= knob_rbi_lds_max_bins(true);
+  return m <= kLdsBinsF32 && m <= knob_rbi_lds_max_bins(false);
 }
 
 static size_t lds_bytes(int op, int64_t m) {
@@ -307,7 +367,8 @@ hipError_t rbi_fwd_launch(int op, int64_t batch, int64_t n, int64_t m, const int
   const bool lds = use_lds(op, m);
   // blocks per row: enough to fill the chip, few enough that the LDS
   // sub-histogram of each block sees many elements
-  int64_t bpr = (n + 16383) / 16384;
+  const int64_t epb = knob_rbi_elems_per_block();
+  int64_t bpr = (n + epb - 1) / epb;
   int64_t cap = (lds ? 2048 : 65535) / (batch > 0 ? batch : 1);
   if (cap < 1) cap = 1;
   if (bpr > cap) bpr = cap;
@@ -322,7 +383,7 @@ hipError_t rbi_fwd_launch(int op, int64_t batch, int64_t n, int64_t m, const int
     hipLaunchKernelGGL(k_rbi_init<OPV>, gi, dim3(BLOCK), 0, s, a, total);           \
     if (n > 0) {                                                                    \
       if (lds) hipLaunchKernelGGL(k_rbi_lds<OPV>, gu, dim3(BLOCK), shm, s, a);      \
-      else hipLaunchKernelGGL(k_rbi_global<OPV>, gu, dim3(BLOCK), 0, s, a);         \
+      else hipLaunchKernelGGL(k_rbi_hash<OPV>, gu, dim3(BLOCK), 0, s, a);           \
     }                                                                               \
     if (OPV != ADD) hipLaunchKernelGGL(k_rbi_fin<OPV>, gi, dim3(BLOCK), 0, s, a, total); \
     break;

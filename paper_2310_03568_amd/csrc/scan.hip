@@ -42,13 +42,14 @@ struct ScanFwdArgs {
   uint64_t *status;
 };
 
-template <int OP, bool REDUCE>
-__global__ __launch_bounds__(Shape<OP>::THREADS) void k_scan_fwd(ScanFwdArgs a) {
+template <int OP, bool REDUCE, int TH_>
+__global__ __launch_bounds__(TH_) void k_scan_fwd(ScanFwdArgs a) {
   using Op = FwdLB<OP>;
   using T = typename Op::T;
   using Io = IO<OP>;
-  constexpr int EPL = Shape<OP>::EPL, K = Shape<OP>::K, TILE = Shape<OP>::TILE;
-  constexpr int TH = Shape<OP>::THREADS, W = Shape<OP>::W;
+  using Sh = ShapeT<OP, TH_>;
+  constexpr int EPL = Sh::EPL, K = Sh::K, TILE = Sh::TILE;
+  constexpr int TH = Sh::THREADS, W = Sh::W;
   constexpr int NIN = Io::NIN, S = Io::S, N = Fwd<OP>::N;
 
   __shared__ T s_tot[K][W];
@@ -221,16 +222,17 @@ struct ScanVjpArgs {
 // CKPT: the forward prefix rs_{i-1} is read from the stored forward output
 // (the tape) instead of being recomputed inside the tile from the saved tile
 // prefix.  A linear recurrence with a tape never reads its offsets b.
-template <int OP, bool ABAR, bool CKPT>
-__global__ __launch_bounds__((Shape<OP, 1>::THREADS)) void k_scan_vjp(ScanVjpArgs a) {
+template <int OP, bool ABAR, bool CKPT, int TH_>
+__global__ __launch_bounds__(TH_) void k_scan_vjp(ScanVjpArgs a) {
   using Op = FwdLB<OP>;
   using FT = typename Op::T;
   using A = Adj<OP, ABAR>;
   using M = typename A::M;
   using MT = typename M::T;
   using Io = IO<OP>;
-  constexpr int EPL = Shape<OP, 1>::EPL, K = Shape<OP, 1>::K, TILE = Shape<OP, 1>::TILE;
-  constexpr int TH = Shape<OP, 1>::THREADS, W = Shape<OP, 1>::W;
+  using Sh = ShapeT<OP, TH_>;
+  constexpr int EPL = Sh::EPL, K = Sh::K, TILE = Sh::TILE;
+  constexpr int TH = Sh::THREADS, W = Sh::W;
   constexpr int NIN = Io::NIN, S = Io::S, N = Fwd<OP>::N;
   constexpr bool RECOMP = A::NEEDS_PREFIX && !CKPT;
   constexpr bool TAPE = A::NEEDS_PREFIX && CKPT;
@@ -535,26 +537,44 @@ int64_t resident_blocks(F kernel, int threads) {
   return (int64_t)cus * (occ > 0 ? occ : 1);
 }
 
-template <int OP, bool REDUCE>
-static hipError_t launch_fwd(const ScanFwdArgs &a, hipStream_t s) {
+template <int OP, bool REDUCE, int TH>
+static hipError_t launch_fwd_t(const ScanFwdArgs &a, hipStream_t s) {
   static int64_t cap = 0;
-  if (cap == 0) cap = resident_blocks(k_scan_fwd<OP, REDUCE>, Shape<OP>::THREADS);
+  if (cap == 0) cap = resident_blocks(k_scan_fwd<OP, REDUCE, TH>, TH);
   if (cap == 0) return hipErrorInvalidDevice;
   const int64_t grid = a.ntiles < cap ? a.ntiles : cap;
-  hipLaunchKernelGGL((k_scan_fwd<OP, REDUCE>), dim3((unsigned)grid), dim3(Shape<OP>::THREADS), 0,
-                     s, a);
+  hipLaunchKernelGGL((k_scan_fwd<OP, REDUCE, TH>), dim3((unsigned)grid), dim3(TH), 0, s, a);
+  return hipGetLastError();
+}
+
+// block size from the tuning knobs (the tile, and so every saved layout, is
+// the same for every block size)
+template <int OP, bool REDUCE>
+static hipError_t launch_fwd(const ScanFwdArgs &a, hipStream_t s) {
+  switch (knob_scan_threads(OP, 0)) {
+  case 256: return launch_fwd_t<OP, REDUCE, 256>(a, s);
+  case 512: return launch_fwd_t<OP, REDUCE, 512>(a, s);
+  default: return launch_fwd_t<OP, REDUCE, 1024>(a, s);
+  }
+}
+
+template <int OP, bool ABAR, bool CKPT, int TH>
+static hipError_t launch_vjp_t(const ScanVjpArgs &a, hipStream_t s) {
+  static int64_t cap = 0;
+  if (cap == 0) cap = resident_blocks(k_scan_vjp<OP, ABAR, CKPT, TH>, TH);
+  if (cap == 0) return hipErrorInvalidDevice;
+  const int64_t grid = a.ntiles < cap ? a.ntiles : cap;
+  hipLaunchKernelGGL((k_scan_vjp<OP, ABAR, CKPT, TH>), dim3((unsigned)grid), dim3(TH), 0, s, a);
   return hipGetLastError();
 }
 
 template <int OP, bool ABAR, bool CKPT>
 static hipError_t launch_vjp(const ScanVjpArgs &a, hipStream_t s) {
-  static int64_t cap = 0;
-  if (cap == 0) cap = resident_blocks(k_scan_vjp<OP, ABAR, CKPT>, Shape<OP, 1>::THREADS);
-  if (cap == 0) return hipErrorInvalidDevice;
-  const int64_t grid = a.ntiles < cap ? a.ntiles : cap;
-  hipLaunchKernelGGL((k_scan_vjp<OP, ABAR, CKPT>), dim3((unsigned)grid),
-                     dim3(Shape<OP, 1>::THREADS), 0, s, a);
-  return hipGetLastError();
+  switch (knob_scan_threads(OP, 1)) {
+  case 256: return launch_vjp_t<OP, ABAR, CKPT, 256>(a, s);
+  case 1024: return launch_vjp_t<OP, ABAR, CKPT, 1024>(a, s);
+  default: return launch_vjp_t<OP, ABAR, CKPT, 512>(a, s);
+  }
 }
 
 hipError_t scan_fwd_launch(int op, int64_t batch, int64_t n, const float *x0, const float *x1,

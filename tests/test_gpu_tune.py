@@ -1,0 +1,73 @@
+"""Every value of every tuning knob gives oracle-exact results (each scan
+block size is its own kernel instantiation), and the quick tuner run
+produces a cache of valid knob values."""
+from __future__ import annotations
+
+import json
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle.gate import RTOL, assert_gate
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture()
+def pcad():
+    import paper_2310_03568_amd as p
+    p.lib()
+    p.reset_knobs()
+    yield p
+    p.reset_knobs()
+
+
+@pytest.mark.parametrize("threads", [256, 512, 1024])
+@pytest.mark.parametrize("op", ["add", "mul", "min", "max", "linrec", "mat2"])
+def test_scan_block_sizes(pcad, op, threads):
+    from test_gpu_parity import check_scan
+    pcad.set_knob(f"scan.fwd.threads.{op}", threads)
+    pcad.set_knob(f"scan.vjp.threads.{op}", threads)
+    print(f"scan {op} threads {threads}", flush=True)
+    check_scan(pcad, op, 1, 30_011, seed=threads + len(op))
+    check_scan(pcad, op, 2, 9_000, seed=threads + 7, ckpt=op != "add")
+
+
+@pytest.mark.parametrize("strategy", ["lds", "global"])
+@pytest.mark.parametrize("op", ["add", "mul", "min", "max"])
+def test_rbi_strategies(pcad, op, strategy):
+    if strategy == "global":
+        pcad.set_knob("rbi.lds_max_bins_f32", 0)
+        pcad.set_knob("rbi.lds_max_bins_u64", 0)
+    pcad.set_knob("rbi.elems_per_block", 4096)
+    rng = np.random.default_rng(5)
+    n, m = 70_001, 300
+    v = rng.uniform(0.5, 2.0, n).astype(np.float32)
+    if op in ("min", "max"):
+        v = np.floor(v * 8) / 8
+    if op == "mul":
+        v[rng.choice(n, 70, replace=False)] = 0.0
+    idx = rng.integers(-2, m + 2, n).astype(np.int32)
+    h, saved = pcad.rbi_fwd(op, torch.from_numpy(idx).cuda(), torch.from_numpy(v).cuda(), m)
+    torch.cuda.synchronize()
+    r = oracle.rbi_fwd(op, idx, m, v)
+    if op in ("min", "max"):
+        np.testing.assert_array_equal(h.cpu().numpy(), r["hist"][:, 0].astype(np.float32))
+        np.testing.assert_array_equal(pcad.saved_argk(saved, 1, m).cpu().numpy()[0], r["argk"])
+    else:
+        assert_gate(h.cpu().numpy(), r["hist"][:, 0], r["c"][:, 0], RTOL[op],
+                    max_range_exceeded=m if op == "mul" else 0, what=f"rbi {op} {strategy}")
+
+
+def test_quick_tune_writes_valid_cache(pcad, tmp_path):
+    from paper_2310_03568_amd import tune
+    out = tmp_path / "tune.json"
+    cache = tune.tune(str(out), quick=True)
+    assert json.loads(out.read_text())["knobs"] == cache["knobs"]
+    assert tune.load(str(out))
+    k = pcad.knobs()
+    for name, v in cache["knobs"].items():
+        assert k[name] == v
+    print(json.dumps(cache["knobs"]), flush=True)
