@@ -41,9 +41,12 @@
  *   the caller's next synchronisation of `stream`.
  * - Workspace: `ws` / `ws_bytes` is caller-owned device scratch of at least
  *   the size pcad_query() reports.  It MUST be zero-filled once before its
- *   first use; the library leaves it reusable (its counters reset
- *   themselves at the end of every launch).  Calls that share one workspace
- *   must be ordered (same stream): concurrent calls on one workspace race.
+ *   first use.  Every call leaves it holding only its control block (the
+ *   first 256 bytes), look-back status words tagged with the launch that
+ *   wrote them, and zeros -- scratch data is cleared before a call returns --
+ *   so one workspace serves any sequence of calls of this library.  Do not
+ *   write other data into it.  Calls that share one workspace must be
+ *   ordered (same stream): concurrent calls on one workspace race.
  * - Saved state: `saved` carries what a forward call keeps for the adjoint
  *   call of the same arguments (layouts below); its size comes from
  *   pcad_query().  The library never reads it before the forward wrote it.
@@ -184,14 +187,27 @@ int pcad_scan_vjp_checkpoint(int op, int64_t batch, int64_t n, const float *x0, 
  *   hist[r,k] = (.) over v[r,i] with idx[r,i] == k, in ascending i,
  * starting from the neutral element (the rewrite to a neutral initial
  * histogram; the caller combines an initial histogram itself).
- * Supported operators: ADD, MUL, MIN, MAX.  m >= 0, m <= 2^26.
+ * Operators: ADD, MUL, MIN, MAX, and the ordered LINREC and MAT2, whose
+ * per-bin fold takes the bin's elements in ascending index (the sequential
+ * semantics of Section 4).  m >= 0, m <= 2^26; n at most 2^28.
+ * Strategies: a private LDS histogram per block (ADD/MUL up to 8192 bins,
+ * MIN/MAX up to 4096), an LDS hash table of the bins a block meets, or a
+ * stable sort by bin followed by a segmented scan of each run (the rule
+ * figure's sort; always for LINREC/MAT2 and for larger bin counts).
+ *   v: n floats per row; LINREC: n pairs (a, b) interleaved; MAT2: n
+ *      row-major 2x2 matrices (4 floats).  hist: m entries of the same
+ *      width per row.
  *   hist: batch*m floats.
  *   saved layout (arrays of batch*m entries, bin k of row r at r*m + k):
  *     ADD    : nothing;
  *     MUL    : uint32 n0[batch*m], then float y_pos[batch*m] (zero count and
  *              product of the non-zeros per bin, Section 4.2 Multiplication);
  *     MIN/MAX: int32 argk[batch*m], the lowest index of the bin's extremum,
- *              n when the bin is empty (Section 4.2 Min/Max rule figure).
+ *              n when the bin is empty (Section 4.2 Min/Max rule figure);
+ *     then, wherever the sort-based path may run (LINREC, MAT2, and bin
+ *     counts beyond the LDS histogram), 256-byte aligned, per row the sorted
+ *     keys, the permutation and the sort's scratch (opaque), which the
+ *     ordered adjoint reuses instead of sorting again.
  */
 int pcad_rbi_fwd(int op, int64_t batch, int64_t n, int64_t m, const int32_t *idx,
                  const float *v, float *hist, void *saved, unsigned flags, void *ws,
@@ -203,7 +219,11 @@ int pcad_rbi_fwd(int op, int64_t batch, int64_t n, int64_t m, const int32_t *idx
  *   MUL    : v_bar_i = hbar[k]*(n0==0 ? y_pos/v_i : (n0==1 && v_i==0 ? y_pos : 0))
  *                                                      (Section 4.2 Multiplication)
  *   MIN/MAX: v_bar_i = hbar[k] if i == argk[k] else 0  (Section 4.2 Min/Max)
- * with k = idx_i; out-of-range keys get 0.
+ *   LINREC/MAT2: v_bar_i = d(L_i (.) v_i (.) R_i)/dv_i^T hbar[k], with L_i and
+ *            R_i the ordered folds of the bin's elements before and after i
+ *            (the sort-based rule of Section 4, from the sort in `saved`)
+ * with k = idx_i; out-of-range keys get 0.  v is required for MUL, LINREC
+ * and MAT2; the ordered operators also need the workspace.
  */
 int pcad_rbi_vjp(int op, int64_t batch, int64_t n, int64_t m, const int32_t *idx,
                  const float *v, const void *saved, const float *hbar, float *vbar,
@@ -262,10 +282,15 @@ int pcad_plan_last_hip_error(void);
 /*
  * Tuning knobs: launch parameters an autotuner may set (the block size of the
  * scan kernels per operator and direction, the bin count up to which
- * reduce-by-index keeps private LDS histograms, and elements per histogram
- * block).  Knobs never change results' or saved states' layouts, only speed;
- * they are process-wide and read at launch time, so setting one while
- * another host thread launches is a race on that launch's choice only.
+ * reduce-by-index keeps private LDS histograms, elements per histogram
+ * block, and the bin count from which the commutative operators sort by bin
+ * rather than use the LDS hash table).  Knobs never change the sizes or
+ * layouts of saved states and workspaces; they change speed and, for + and
+ * *, the order in which floating-point values are combined (results stay
+ * within the same error bound; min/max values, arg-extrema and zero counts
+ * do not change).  They are process-wide and read at launch time, so setting
+ * one while another host thread launches is a race on that launch's choice
+ * only.
  *   pcad_knob_set: PCAD_E_INVALID_ARG for an unknown name or a value outside
  *                  the knob's range (block sizes: 256, 512 or 1024).
  *   pcad_knob_name: NULL for an index outside [0, pcad_knob_count()).

@@ -272,15 +272,34 @@ def scan_vjp_checkpoint(op: str, x0, x1, y0, y1, ybar, Abar=None, out=None,
 # ---------------------------------------------------------------------------
 # reduce-by-index
 # ---------------------------------------------------------------------------
+def _rbi_shape(op: str, v: torch.Tensor):
+    """(batch, n, lead, d): v is (..., n) for + * min max and (..., n, d) for
+    linrec (d = 2, pairs (a, b)) and mat2 (d = 4)."""
+    d = DIM[op]
+    if d == 1:
+        batch, n, lead = _shape(op, v)
+        return batch, n, lead, 1
+    if v.shape[-1] != d or v.dim() < 2:
+        raise PcadError(f"{op} reduce_by_index expects values of shape (..., n, {d})")
+    lead = tuple(v.shape[:-2])
+    batch = 1
+    for x in lead:
+        batch *= x
+    return batch, v.shape[-2], lead, d
+
+
 def rbi_fwd(op: str, idx: torch.Tensor, v: torch.Tensor, m: int):
-    """Returns (hist, saved).  idx, v of shape (..., n); hist (..., m).
+    """Returns (hist, saved).  idx (..., n); v (..., n) or (..., n, d) for
+    linrec (pairs (a, b)) and mat2; hist (..., m) or (..., m, d).
     saved: mul -> uint32 n0[batch*m] then float y_pos[batch*m];
-    min/max -> int32 argk[batch*m]."""
+    min/max -> int32 argk[batch*m]; then, where the sort-based path may run
+    (the ordered operators always, the others beyond the LDS capacity),
+    each row's sort (sorted keys and permutation) for the adjoint."""
     _dev_check(idx, v)
-    batch, n, lead = _shape(op, v)
+    batch, n, lead, d = _rbi_shape(op, v)
     s_b, w_b = query(RBI, op, batch, n, m)
     dev = v.device
-    hist = torch.empty(lead + (m,), dtype=torch.float32, device=dev)
+    hist = torch.empty(lead + (m,) + ((d,) if d > 1 else ()), dtype=torch.float32, device=dev)
     saved = torch.empty(max(s_b, 16), dtype=torch.uint8, device=dev)
     ws = workspace(w_b, dev)
     check(lib().pcad_rbi_fwd(OPS[op], batch, n, m, _ptr(idx), _ptr(v), _ptr(hist), _ptr(saved), 0,
@@ -290,7 +309,7 @@ def rbi_fwd(op: str, idx: torch.Tensor, v: torch.Tensor, m: int):
 
 def rbi_vjp(op: str, idx, v, m: int, saved, hbar, out=None, accumulate: bool = False):
     _dev_check(idx, v, hbar)
-    batch, n, lead = _shape(op, v)
+    batch, n, lead, d = _rbi_shape(op, v)
     s_b, w_b = query(RBI, op, batch, n, m)
     dev = v.device
     out = torch.empty_like(v) if out is None else out

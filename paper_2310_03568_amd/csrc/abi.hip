@@ -94,10 +94,10 @@ int query(int comb, int op, int64_t batch, int64_t n, int64_t m, size_t *saved, 
     w = scan_ws(op, batch, n);
     break;
   case PCAD_RBI:
-    if (op == PCAD_LINREC || op == PCAD_MAT2) return PCAD_E_UNSUPPORTED;
     if (m < 0) return PCAD_E_INVALID_ARG;
     if (m > kMaxBins) return PCAD_E_SIZE;
-    s = rbi_saved_bytes(op, batch, m);
+    if (!sort_supported(n)) return PCAD_E_SIZE;
+    s = rbi_saved_bytes(op, batch, n, m);
     w = rbi_ws_bytes(op, batch, n, m);
     break;
   default: return PCAD_E_INVALID_ARG;
@@ -251,7 +251,6 @@ int pcad_rbi_fwd(int op, int64_t batch, int64_t n, int64_t m, const int32_t *idx
                  float *hist, void *saved, unsigned flags, void *ws, size_t ws_bytes,
                  void *stream) {
   PCAD_TRY(check_common(op, batch, n, flags));
-  if (op == PCAD_LINREC || op == PCAD_MAT2) return PCAD_E_UNSUPPORTED;
   if (m < 0) return PCAD_E_INVALID_ARG;
   if (m > kMaxBins) return PCAD_E_SIZE;
   if (batch == 0 || m == 0) return PCAD_OK;
@@ -269,18 +268,18 @@ int pcad_rbi_vjp(int op, int64_t batch, int64_t n, int64_t m, const int32_t *idx
                  const void *saved, const float *hbar, float *vbar, unsigned flags, void *ws,
                  size_t ws_bytes, void *stream) {
   PCAD_TRY(check_common(op, batch, n, flags));
-  if (op == PCAD_LINREC || op == PCAD_MAT2) return PCAD_E_UNSUPPORTED;
   if (m < 0) return PCAD_E_INVALID_ARG;
   if (m > kMaxBins) return PCAD_E_SIZE;
   if (batch == 0 || n == 0) return PCAD_OK;
   PCAD_TRY(need(idx));
-  if (op == PCAD_MUL) PCAD_TRY(need(v));
+  const bool ordered = op == PCAD_LINREC || op == PCAD_MAT2;
+  if (op == PCAD_MUL || ordered) PCAD_TRY(need(v));
   if (m > 0) PCAD_TRY(need(hbar));
   PCAD_TRY(need(vbar));
   PCAD_TRY(check_saved(PCAD_RBI, op, batch, n, m, saved));
-  (void)ws; (void)ws_bytes;
+  if (ordered) PCAD_TRY(check_ws(PCAD_RBI, op, batch, n, m, ws, ws_bytes));
   return hip_status(rbi_vjp_launch(op, batch, n, m, idx, v, saved, hbar, vbar,
-                                   (flags & PCAD_ACCUMULATE) != 0, (hipStream_t)stream));
+                                   (flags & PCAD_ACCUMULATE) != 0, ws, (hipStream_t)stream));
 }
 
 }  // extern "C"

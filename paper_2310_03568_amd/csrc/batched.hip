@@ -855,7 +855,7 @@ int pcad_plan_run_per_segment(pcad_plan *p, int phase, void *stream) {
                                     hipMemcpyDeviceToDevice, s);
       if (e == hipSuccess)
         e = rbi_vjp_launch(PCAD_MIN, 1, L, p->m, p->idx + o, p->y + o, ak, p->hbar + s_ * p->m,
-                           ytot + o, true, s);
+                           ytot + o, true, wsp, s);
       if (e == hipSuccess)
         e = scan_vjp_launch(PCAD_LINREC, 1, L, p->a + o, p->b + o, carry, nullptr, nullptr,
                             ytot + o, nullptr,

@@ -18,6 +18,29 @@ int hip_status(hipError_t e);
 int knob_scan_threads(int op, int dir);  // dir 0 forward, 1 adjoint
 int64_t knob_rbi_lds_max_bins(bool u64);
 int64_t knob_rbi_elems_per_block();
+int64_t knob_rbi_sort_min_bins();
+
+// stable sort of element indices by bin (sort.hip): keys outside [0, m)
+// sort last as m
+int sort_passes(int64_t m);
+bool sort_supported(int64_t n);
+size_t sort_ws_bytes(int64_t n, int64_t m);
+hipError_t sort_by_key(const int32_t *keys, int64_t n, int64_t m, int32_t *keys_out,
+                       int32_t *perm_out, void *ws, hipStream_t s);
+
+// sort-based reduce-by-index of one row (rbi_sorted.hip): `ctl` is the
+// control block at the start of the call's workspace, `region` the row's
+// workspace part (look-back status words; an accumulating ordered adjoint's
+// L), `area` the row's part of the saved state (sorted keys, permutation and
+// the sort's scratch)
+size_t rbi_sort_area_bytes(int64_t n, int64_t m);
+size_t rbi_sorted_ws_bytes(int op, int64_t n, int64_t m);
+hipError_t rbi_sorted_fwd_row(int op, int64_t n, int64_t m, const int32_t *idx, const float *v,
+                              float *hist, uint32_t *n0, float *ypos, uint64_t *keys, void *ctl,
+                              void *region, void *area, hipStream_t s);
+hipError_t rbi_sorted_vjp_row(int op, int64_t n, int64_t m, const float *v, const float *hbar,
+                              float *vbar, bool accumulate, void *ctl, void *region,
+                              const void *area, hipStream_t s);
 
 // scan
 int scan_tile_size(int op);
@@ -44,11 +67,11 @@ hipError_t reduce_vjp_launch(int op, int64_t batch, int64_t n, const float *x0, 
 
 // reduce-by-index
 size_t rbi_ws_bytes(int op, int64_t batch, int64_t n, int64_t m);
-size_t rbi_saved_bytes(int op, int64_t batch, int64_t m);
+size_t rbi_saved_bytes(int op, int64_t batch, int64_t n, int64_t m);
 hipError_t rbi_fwd_launch(int op, int64_t batch, int64_t n, int64_t m, const int32_t *idx,
                           const float *v, float *hist, void *saved, void *ws, hipStream_t s);
 hipError_t rbi_vjp_launch(int op, int64_t batch, int64_t n, int64_t m, const int32_t *idx,
                           const float *v, const void *saved, const float *hbar, float *vbar,
-                          bool accumulate, hipStream_t s);
+                          bool accumulate, void *ws, hipStream_t s);
 
 }  // namespace pcad

@@ -38,9 +38,14 @@ Knob g_knobs[] = {
     {"rbi.lds_max_bins_u64", 4096, 0, 4096, false, 4096},
     // elements per block of the histogram kernels
     {"rbi.elems_per_block", 16384, 1024, 1 << 20, true, 16384},
+    // beyond the LDS histogram, bin counts from which the commutative
+    // operators sort by bin instead of combining in an LDS hash table (the
+    // hash table measured faster at every bin count up to 2^22, uniform and
+    // Zipf keys, so by default only the ordered operators sort)
+    {"rbi.sort_min_bins", 1 << 26, 0, 1 << 26, false, 1 << 26},
 };
 constexpr int kNumKnobs = (int)(sizeof(g_knobs) / sizeof(g_knobs[0]));
-constexpr int kRbiF32 = 12, kRbiU64 = 13, kRbiEpb = 14;
+constexpr int kRbiF32 = 12, kRbiU64 = 13, kRbiEpb = 14, kRbiSort = 15;
 
 Knob *find(const char *name) {
   if (!name) return nullptr;
@@ -54,6 +59,7 @@ Knob *find(const char *name) {
 int knob_scan_threads(int op, int dir) { return (int)g_knobs[(dir ? 6 : 0) + op].value; }
 int64_t knob_rbi_lds_max_bins(bool u64) { return g_knobs[u64 ? kRbiU64 : kRbiF32].value; }
 int64_t knob_rbi_elems_per_block() { return g_knobs[kRbiEpb].value; }
+int64_t knob_rbi_sort_min_bins() { return g_knobs[kRbiSort].value; }
 
 }  // namespace pcad
 

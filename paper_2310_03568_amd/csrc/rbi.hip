@@ -70,6 +70,11 @@ __global__ __launch_bounds__(BLOCK) void k_rbi_init(RbiArgs a, int64_t total) {
     if (OP == ADD) a.hist[k] = 0.0f;
     if (OP == MUL) { a.n0[k] = 0u; a.ypos[k] = 1.0f; }
     if (OP == MIN || OP == MAX) a.keys[k] = key_init<OP>();
+    if (OP == LINREC) { a.hist[2 * k] = 1.0f; a.hist[2 * k + 1] = 0.0f; }
+    if (OP == MAT2) {
+      a.hist[4 * k] = 1.0f; a.hist[4 * k + 1] = 0.0f;
+      a.hist[4 * k + 2] = 0.0f; a.hist[4 * k + 3] = 1.0f;
+    }
   }
 }
 
@@ -234,6 +239,7 @@ __global__ __launch_bounds__(BLOCK) void k_rbi_fin(RbiArgs a, int64_t total) {
       a.hist[t] = a.n0[t] > 0 ? 0.0f : a.ypos[t];
     } else {
       const uint64_t key = a.keys[t];
+      a.keys[t] = 0;  // leave the workspace holding no data between calls
       const int64_t row = t / a.m;
       if (key == key_init<OP>()) {
         a.argk[t] = (int32_t)a.n;
@@ -330,16 +336,46 @@ static size_t lds_bytes(int op, int64_t m) {
   return (size_t)m * 4;
 }
 
-size_t rbi_saved_bytes(int op, int64_t batch, int64_t m) {
+static size_t op_saved_bytes(int op, int64_t batch, int64_t m) {
   if (op == MUL) return (size_t)batch * m * 8;
   if (op == MIN || op == MAX) return (size_t)batch * m * 4;
   return 0;
 }
 
+// the sort-based path: always for the ordered operators; for the others
+// beyond the LDS capacity (a fixed bound, so the workspace size does not
+// depend on the knobs), from the knob's bin count on
+static bool sorted_may(int op, int64_t m) {
+  if (op == LINREC || op == MAT2) return true;
+  return m > ((op == MIN || op == MAX) ? kLdsBinsU64 : kLdsBinsF32);
+}
+
+static bool use_sorted(int op, int64_t m) {
+  if (op == LINREC || op == MAT2) return true;
+  return sorted_may(op, m) && m >= knob_rbi_sort_min_bins();
+}
+
+static size_t base_ws_bytes(int op, int64_t batch, int64_t m) {
+  const size_t b = (op == MIN || op == MAX) ? kCtlBytes + (size_t)batch * m * 8 : kCtlBytes;
+  return (b + 255) / 256 * 256;
+}
+
 size_t rbi_ws_bytes(int op, int64_t batch, int64_t n, int64_t m) {
-  (void)n;
-  if (op == MIN || op == MAX) return kCtlBytes + (size_t)batch * m * 8;
-  return kCtlBytes;
+  size_t b = base_ws_bytes(op, batch, m);
+  if (sorted_may(op, m)) b += rbi_sorted_ws_bytes(op, n, m);
+  return b;
+}
+
+// saved state: the operator's own (zero counts and products; arg-extrema)
+// then, where the sort-based path may run, each row's sort
+static size_t op_saved_aligned(int op, int64_t batch, int64_t m) {
+  return (op_saved_bytes(op, batch, m) + 255) / 256 * 256;
+}
+
+size_t rbi_saved_bytes(int op, int64_t batch, int64_t n, int64_t m) {
+  size_t b = op_saved_bytes(op, batch, m);
+  if (sorted_may(op, m)) b = op_saved_aligned(op, batch, m) + (size_t)batch * rbi_sort_area_bytes(n, m);
+  return b;
 }
 
 static int64_t grid1d(int64_t total) {
@@ -363,6 +399,39 @@ hipError_t rbi_fwd_launch(int op, int64_t batch, int64_t n, int64_t m, const int
   if (op == MIN || op == MAX) {
     a.keys = reinterpret_cast<uint64_t *>(static_cast<char *>(ws) + kCtlBytes);
     a.argk = static_cast<int32_t *>(saved);
+  }
+  if (use_sorted(op, m)) {
+    const int d = op == LINREC ? 2 : (op == MAT2 ? 4 : 1);
+    void *sws = static_cast<char *>(ws) + base_ws_bytes(op, batch, m);
+    const dim3 gi((unsigned)grid1d(total));
+#define PCAD_RBI_INIT(OPV) \
+  case OPV: hipLaunchKernelGGL(k_rbi_init<OPV>, gi, dim3(BLOCK), 0, s, a, total); break;
+    switch (op) {
+      PCAD_RBI_INIT(ADD)
+      PCAD_RBI_INIT(MUL)
+      PCAD_RBI_INIT(MIN)
+      PCAD_RBI_INIT(MAX)
+      PCAD_RBI_INIT(LINREC)
+      PCAD_RBI_INIT(MAT2)
+    default: return hipErrorInvalidValue;
+    }
+#undef PCAD_RBI_INIT
+    char *area = static_cast<char *>(saved) + op_saved_aligned(op, batch, m);
+    const size_t ab = rbi_sort_area_bytes(n, m);
+    for (int64_t r = 0; r < batch; ++r) {
+      hipError_t e = rbi_sorted_fwd_row(
+          op, n, m, idx + r * n, v + r * n * d, hist ? hist + r * m * d : nullptr,
+          a.n0 ? a.n0 + r * m : nullptr, a.ypos ? a.ypos + r * m : nullptr,
+          a.keys ? a.keys + r * m : nullptr, ws, sws, area + r * ab, s);
+      if (e != hipSuccess) return e;
+    }
+    switch (op) {
+    case MUL: hipLaunchKernelGGL(k_rbi_fin<MUL>, gi, dim3(BLOCK), 0, s, a, total); break;
+    case MIN: hipLaunchKernelGGL(k_rbi_fin<MIN>, gi, dim3(BLOCK), 0, s, a, total); break;
+    case MAX: hipLaunchKernelGGL(k_rbi_fin<MAX>, gi, dim3(BLOCK), 0, s, a, total); break;
+    default: break;
+    }
+    return hipGetLastError();
   }
   const bool lds = use_lds(op, m);
   // blocks per row: enough to fill the chip, few enough that the LDS
@@ -400,8 +469,20 @@ hipError_t rbi_fwd_launch(int op, int64_t batch, int64_t n, int64_t m, const int
 
 hipError_t rbi_vjp_launch(int op, int64_t batch, int64_t n, int64_t m, const int32_t *idx,
                           const float *v, const void *saved, const float *hbar, float *vbar,
-                          bool accumulate, hipStream_t s) {
+                          bool accumulate, void *ws, hipStream_t s) {
   if (batch == 0 || n == 0) return hipSuccess;
+  if (op == LINREC || op == MAT2) {
+    const int d = op == LINREC ? 2 : 4;
+    void *sws = static_cast<char *>(ws) + base_ws_bytes(op, batch, m);
+    const char *area = static_cast<const char *>(saved) + op_saved_aligned(op, batch, m);
+    const size_t ab = rbi_sort_area_bytes(n, m);
+    for (int64_t r = 0; r < batch; ++r) {
+      hipError_t e = rbi_sorted_vjp_row(op, n, m, v + r * n * d, hbar + r * m * d,
+                                        vbar + r * n * d, accumulate, ws, sws, area + r * ab, s);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
   RbiVjpArgs a;
   a.idx = idx; a.v = v; a.hbar = hbar; a.vbar = vbar; a.n = n; a.m = m;
   a.accumulate = accumulate ? 1 : 0;

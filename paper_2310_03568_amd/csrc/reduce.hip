@@ -132,7 +132,10 @@ __global__ __launch_bounds__(BLOCK) void k_reduce_fold(RedArgs a) {
   __shared__ LV s_w[WAVES];
   const int64_t row = blockIdx.x;
   LV r = Lift<OP>::id();
-  for (int p = threadIdx.x; p < a.bpr; p += BLOCK) r = Lift<OP>::comb(r, a.parts[row * a.bpr + p]);
+  for (int p = threadIdx.x; p < a.bpr; p += BLOCK) {
+    r = Lift<OP>::comb(r, a.parts[row * a.bpr + p]);
+    a.parts[row * a.bpr + p] = LV{};  // leave the workspace holding no data between calls
+  }
   r = block_reduce_lv<OP>(r, s_w);
   if (threadIdx.x == 0) {
     if (OP == ADD) {

@@ -14,7 +14,11 @@ speed.  Each group is searched on the shapes of the workloads it serves:
   which reduce-by-index keeps a private LDS histogram per block rather than
   using global atomics -- the largest tested m at which the LDS strategy wins
   under both uniform and Zipf(1.1) keys (the skew buckets);
-* ``rbi.elems_per_block``: elements per histogram block, timed at m = 256.
+* ``rbi.elems_per_block``: elements per histogram block, timed at m = 256;
+* ``rbi.sort_min_bins``: the smallest tested bin count beyond the LDS
+  capacity from which sorting by bin (then a segmented scan) beats the LDS
+  hash table under both key distributions; 2^26 (never, below that) if it
+  wins at none.
 
 The cache records the device it was measured on; ``load`` applies it only on
 the same device name and architecture, otherwise the built-in defaults stay.
@@ -139,6 +143,23 @@ def tune_rbi(pcad, timings: dict, quick: bool) -> dict:
     pcad.reset_knobs()
     best["rbi.elems_per_block"] = min(res, key=res.get)
     timings["rbi.elems_per_block"] = {str(k): t for k, t in res.items()}
+    never = 1 << 26
+    threshold = never
+    for m in ((1 << 16, 1 << 20) if quick else (1 << 14, 1 << 16, 1 << 18, 1 << 20, 1 << 22)):
+        sort_wins = True
+        for zipf in (False, True):
+            idx, v = _rbi_inputs(n, m, zipf)
+            t = {}
+            for strat, val in (("hash", never), ("sorted", 0)):
+                pcad.set_knob("rbi.sort_min_bins", val)
+                t[strat] = _time(lambda: pcad.rbi_fwd("add", idx, v, m), 5)
+            timings[f"rbi.sort_min_bins@m={m},{'zipf' if zipf else 'uniform'}"] = t
+            sort_wins = sort_wins and t["sorted"] <= t["hash"]
+        pcad.reset_knobs()
+        if sort_wins:
+            threshold = m
+            break
+    best["rbi.sort_min_bins"] = threshold
     return best
 
 

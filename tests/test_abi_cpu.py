@@ -66,8 +66,14 @@ def test_query(L):
     assert st == 0 and s == 2 * 300 * 4 and w >= 2 * 300 * 8
     # rbi mul: counts and products
     assert q(L, 2, 1, 1, 10, 7)[1] == 7 * 8
-    # rbi with a generic operator is not provided
-    assert q(L, 2, 5, 1, 10, 7)[0] == 2
+    # rbi of an ordered operator: the row's sort is saved (sorted keys and
+    # the permutation, two int arrays of n, plus the sort's scratch) for the
+    # adjoint to reuse; the workspace holds the look-back status words and
+    # room for the exclusive run prefixes L (2 floats per element for LINREC)
+    st, s, w = q(L, 2, 5, 1, 10_000, 7)
+    assert st == 0 and s >= 2 * 10_000 * 4 and w >= 2 * 10_000 * 4
+    st2, s2, _ = q(L, 2, 5, 3, 10_000, 7)
+    assert st2 == 0 and s2 == 3 * s
 
 
 def test_validation(L):
@@ -99,7 +105,8 @@ def test_validation(L):
     assert ck(2, 1, 10, good, None, good, good, good, None, good, None, 0, good, 1 << 20, None) == 1
     assert ck(4, 1, 10, good, None, good, None, good, None, good, good, 0, good, 8, None) == 6
     assert L.pcad_reduce_fwd(1, 1, 10, good, None, good, None, 0, good, 1 << 20, None) == 3
-    assert L.pcad_rbi_fwd(5, 1, 10, 4, good, good, good, good, 0, good, 1 << 20, None) == 2
+    assert L.pcad_rbi_fwd(5, 1, 10, 4, good, good, good, good, 0, good, 256, None) == 6
+    assert L.pcad_rbi_vjp(4, 1, 10, 4, good, None, None, good, good, 0, good, 1 << 20, None) == 3
     assert L.pcad_rbi_fwd(0, 1, 10, -4, good, good, good, good, 0, good, 1 << 20, None) == 1
     assert L.pcad_rbi_vjp(2, 1, 10, 4, good, good, None, good, good, 0, None, 0, None) == 3
     # degenerate sizes are valid no-ops that need no pointers

@@ -400,3 +400,56 @@ def test_rbi_zero_bins(pcad):
         assert h.numel() == 0
         vb = host(pcad.rbi_vjp(op, I, V, 0, s, torch.zeros(0, device="cuda")))
         np.testing.assert_array_equal(vb, [0, 0, 0])
+
+
+# ---------------------------------------------------------------------------
+# reduce-by-index of the ordered (non-commutative) operators: per-bin folds in
+# ascending element order, through the sort-based path
+# ---------------------------------------------------------------------------
+def check_rbi_ordered(pcad, op, batch, n, m, seed, dist="uniform"):
+    rng = np.random.default_rng(seed)
+    d = oracle.DIM[op]
+    if op == "linrec":
+        a = rng.uniform(0.9, 1.0, (batch, n))
+        b = rng.standard_normal((batch, n))
+        v = np.stack([a, b], -1).astype(np.float32)
+    else:
+        v = (rng.standard_normal((batch, n, 4)) * np.sqrt(0.5)).astype(np.float32)
+    if dist == "zipf":
+        from workloads import zipf_keys
+        idx = zipf_keys(rng, batch * n, m).reshape(batch, n)
+    else:
+        idx = rng.integers(0, max(m, 1), (batch, n)).astype(np.int32)
+    if n > 0:
+        fl = idx.reshape(-1)
+        k = rng.choice(fl.size, max(fl.size // 97, 1), replace=False)
+        fl[k] = rng.choice([-1, m, m + 5], k.size)
+    hb = rng.standard_normal((batch, m, d)).astype(np.float32)
+    I, V = dev(idx.astype(np.int32)), dev(v)
+    h, saved = pcad.rbi_fwd(op, I, V, m)
+    vb = pcad.rbi_vjp(op, I, V, m, saved, dev(hb))
+    h, vb = host(h).reshape(batch, m, d), host(vb).reshape(batch, n, d)
+    rt = RTOL[op]
+    for r in range(batch):
+        args = (v[r, :, 0], v[r, :, 1]) if op == "linrec" else (v[r],)
+        o = oracle.rbi_fwd(op, idx[r], m, *args)
+        # MAT2 products over long runs of N(0, 0.5) factors leave the float32
+        # range: those bins are checked norm-wise
+        mx = None if op == "mat2" else 0
+        assert_gate(h[r], o["hist"], o["c"], rt, max_range_exceeded=mx, what=f"rbi {op} hist row {r}")
+        xb, cx = oracle.rbi_vjp(op, idx[r], m, hb[r], *args)
+        assert_gate(vb[r], xb, cx, rt, max_range_exceeded=mx, what=f"rbi_vjp {op} row {r}")
+    assert ws_error() == 0
+
+
+@pytest.mark.parametrize("op", ["linrec", "mat2"])
+@pytest.mark.parametrize("n,m", [(0, 3), (1, 1), (2049, 1), (2049, 7), (50_001, 300),
+                                 (50_001, 70_000), (200_000, 1 << 20)])
+def test_rbi_ordered(pcad, op, n, m):
+    check_rbi_ordered(pcad, op, 1, n, m, seed=n + 3 * m)
+
+
+@pytest.mark.parametrize("op", ["linrec", "mat2"])
+def test_rbi_ordered_batched_and_skewed(pcad, op):
+    check_rbi_ordered(pcad, op, 3, 7001, 129, seed=44)
+    check_rbi_ordered(pcad, op, 1, 100_000, 1000, seed=45, dist="zipf")

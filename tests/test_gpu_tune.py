@@ -35,15 +35,24 @@ def test_scan_block_sizes(pcad, op, threads):
     check_scan(pcad, op, 2, 9_000, seed=threads + 7, ckpt=op != "add")
 
 
-@pytest.mark.parametrize("strategy", ["lds", "global"])
+@pytest.mark.parametrize("strategy", ["lds", "global", "hash_large", "sorted"])
 @pytest.mark.parametrize("op", ["add", "mul", "min", "max"])
 def test_rbi_strategies(pcad, op, strategy):
+    """lds: private LDS histograms; global: the hash path forced at a small
+    bin count; hash_large / sorted: beyond the LDS capacity, the hash table
+    (default) or the sort by bin with a segmented scan"""
+    m = 300
     if strategy == "global":
         pcad.set_knob("rbi.lds_max_bins_f32", 0)
         pcad.set_knob("rbi.lds_max_bins_u64", 0)
+    if strategy in ("hash_large", "sorted"):
+        m = 20_011
+    if strategy == "sorted":
+        pcad.set_knob("rbi.sort_min_bins", 0)
     pcad.set_knob("rbi.elems_per_block", 4096)
+    print(f"rbi {op} {strategy} m={m}", flush=True)
     rng = np.random.default_rng(5)
-    n, m = 70_001, 300
+    n = 70_001
     v = rng.uniform(0.5, 2.0, n).astype(np.float32)
     if op in ("min", "max"):
         v = np.floor(v * 8) / 8
