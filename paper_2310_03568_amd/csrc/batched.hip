@@ -181,7 +181,7 @@ __global__ __launch_bounds__(SEG_THF) void k_seg_fwd(SegFwdArgs a) {
   SegItem it = seg_item(a.tab, i);
   load(it);
   __syncthreads();
-  const uint32_t tag = s_epoch + 1;
+  const uint32_t tag = next_tag(s_epoch);
 
   // scans the prefetched item into item-local inclusive prefixes (v) and, in
   // wave 0, the item aggregate (ag), which is published (an instance's first
@@ -447,7 +447,7 @@ __global__ __launch_bounds__(SEG_THB) void k_seg_bwd(SegBwdArgs a) {
   Buf cur;
   load(it, cur);
   __syncthreads();
-  const uint32_t tag = s_epoch + 1;
+  const uint32_t tag = next_tag(s_epoch);
 
   MT mincl[K];
   MT agg = M::id();        // wave 0: map aggregate of the current item

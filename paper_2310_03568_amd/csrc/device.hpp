@@ -58,6 +58,22 @@ __device__ __forceinline__ float mulz(float a, float b) {
 }
 
 // ---------------------------------------------------------------------------
+// float += in LDS.  ds_add_f32 runs at a fixed low rate whatever the
+// addresses, while a compare-and-swap runs at the full LDS rate when lanes
+// hit different words; so one compare-and-swap is tried first and only the
+// lanes that lost it (several lanes on one bin: skewed keys) fall back to
+// ds_add_f32.  Either way v is added exactly once.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void lds_add_f32(float *p, float v) {
+  unsigned *u = reinterpret_cast<unsigned *>(p);
+  unsigned old = __hip_atomic_load(u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  if (!__hip_atomic_compare_exchange_strong(u, &old, __float_as_uint(__uint_as_float(old) + v),
+                                            __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_WORKGROUP))
+    atomicAdd(p, v);
+}
+
+// ---------------------------------------------------------------------------
 // Lifted min/max as one 64-bit word, so "smallest value, then smallest
 // index" is a single native 64-bit atomic min (or max with the index
 // complemented): key = {ord(v):32 | index:32}.  ord is the order-preserving
@@ -508,6 +524,12 @@ struct Ctl {
 };
 
 constexpr int kSpinLimit = 1 << 20;
+
+// The tag of the launch after the one with epoch e.  Tags stay in
+// [1, 2^31): a zeroed word never matches, and neither does workspace data
+// whose 8-byte words have an upper half >= 2^31 (the records and tables of
+// the partitioned reduce-by-index).
+__device__ __forceinline__ uint32_t next_tag(uint32_t e) { return e >= 0x7fffffffu ? 1u : e + 1u; }
 
 __device__ __forceinline__ unsigned ctl_load(unsigned *p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

@@ -19,6 +19,7 @@ int knob_scan_threads(int op, int dir);  // dir 0 forward, 1 adjoint
 int64_t knob_rbi_lds_max_bins(bool u64);
 int64_t knob_rbi_elems_per_block();
 int64_t knob_rbi_sort_min_bins();
+bool knob_rbi_partition();
 
 // stable sort of element indices by bin (sort.hip): keys outside [0, m)
 // sort last as m
@@ -27,6 +28,21 @@ bool sort_supported(int64_t n);
 size_t sort_ws_bytes(int64_t n, int64_t m);
 hipError_t sort_by_key(const int32_t *keys, int64_t n, int64_t m, int32_t *keys_out,
                        int32_t *perm_out, void *ws, hipStream_t s);
+
+// exclusive scan of ne uint32 entries in place (sort.hip); tot: scratch of
+// iscan_totals(ne) entries, left zero; needs iscan_fits(ne)
+int64_t iscan_totals(int64_t ne);
+bool iscan_fits(int64_t ne);
+hipError_t iscan_u32(uint32_t *v, int64_t ne, uint32_t *tot, hipStream_t s);
+
+// partitioned reduce-by-index of one row for + * min max beyond the LDS
+// histogram capacity (rbi_part.hip): `region` is the row's workspace part;
+// writes every bin and the saved state (n0/ypos, argk) directly
+bool rbi_part_may(int op, int64_t m);
+size_t rbi_part_ws_bytes(int op, int64_t n, int64_t m);
+hipError_t rbi_part_fwd_row(int op, int64_t n, int64_t m, const int32_t *idx, const float *v,
+                            float *hist, uint32_t *n0, float *ypos, int32_t *argk, void *region,
+                            hipStream_t s);
 
 // sort-based reduce-by-index of one row (rbi_sorted.hip): `ctl` is the
 // control block at the start of the call's workspace, `region` the row's

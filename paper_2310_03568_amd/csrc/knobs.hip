@@ -43,9 +43,12 @@ Knob g_knobs[] = {
     // hash table measured faster at every bin count up to 2^22, uniform and
     // Zipf keys, so by default only the ordered operators sort)
     {"rbi.sort_min_bins", 1 << 26, 0, 1 << 26, false, 1 << 26},
+    // beyond the LDS histogram: 1 partitions the elements by bin range and
+    // builds LDS histograms per range, 0 uses the LDS hash table
+    {"rbi.partition", 1, 0, 1, false, 1},
 };
 constexpr int kNumKnobs = (int)(sizeof(g_knobs) / sizeof(g_knobs[0]));
-constexpr int kRbiF32 = 12, kRbiU64 = 13, kRbiEpb = 14, kRbiSort = 15;
+constexpr int kRbiF32 = 12, kRbiU64 = 13, kRbiEpb = 14, kRbiSort = 15, kRbiPart = 16;
 
 Knob *find(const char *name) {
   if (!name) return nullptr;
@@ -60,6 +63,7 @@ int knob_scan_threads(int op, int dir) { return (int)g_knobs[(dir ? 6 : 0) + op]
 int64_t knob_rbi_lds_max_bins(bool u64) { return g_knobs[u64 ? kRbiU64 : kRbiF32].value; }
 int64_t knob_rbi_elems_per_block() { return g_knobs[kRbiEpb].value; }
 int64_t knob_rbi_sort_min_bins() { return g_knobs[kRbiSort].value; }
+bool knob_rbi_partition() { return g_knobs[kRbiPart].value != 0; }
 
 }  // namespace pcad
 

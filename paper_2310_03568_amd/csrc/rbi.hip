@@ -118,7 +118,7 @@ __global__ __launch_bounds__(BLOCK) void k_rbi_lds(RbiArgs a) {
   __syncthreads();
   for_chunk(a, row, [&](int32_t k, float v, uint32_t i) {
     if (k < 0 || k >= m) return;
-    if (OP == ADD) atomicAdd(&sf[k], v);
+    if (OP == ADD) lds_add_f32(&sf[k], v);
     if (OP == MUL) {
       if (v == 0.0f) atomicAdd(&sc[k], 1u);
       else lds_mul_f32(&sf[k], v);
@@ -202,7 +202,7 @@ __global__ __launch_bounds__(BLOCK) void k_rbi_hash(RbiArgs a) {
         cur = expect == -1 ? k : expect;  // the slot is ours, or holds the winner's bin
       }
       if (cur == k) {
-        if (OP == ADD) atomicAdd(&s_f[h], v);
+        if (OP == ADD) lds_add_f32(&s_f[h], v);
         if (OP == MUL) {
           if (v == 0.0f) atomicAdd(&s_c[h], 1u);
           else lds_mul_f32(&s_f[h], v);
@@ -355,15 +355,28 @@ static bool use_sorted(int op, int64_t m) {
   return sorted_may(op, m) && m >= knob_rbi_sort_min_bins();
 }
 
+// the partitioned path: the commutative operators beyond the LDS capacity
+// (a fixed bound, like sorted_may), unless the knob picks the hash table
+static bool part_may(int op, int64_t m) {
+  if (op == LINREC || op == MAT2) return false;
+  return m > ((op == MIN || op == MAX) ? kLdsBinsU64 : kLdsBinsF32) && rbi_part_may(op, m);
+}
+
+static bool use_part(int op, int64_t n, int64_t m) {
+  return n > 0 && part_may(op, m) && knob_rbi_partition() && !use_sorted(op, m);
+}
+
 static size_t base_ws_bytes(int op, int64_t batch, int64_t m) {
   const size_t b = (op == MIN || op == MAX) ? kCtlBytes + (size_t)batch * m * 8 : kCtlBytes;
   return (b + 255) / 256 * 256;
 }
 
 size_t rbi_ws_bytes(int op, int64_t batch, int64_t n, int64_t m) {
-  size_t b = base_ws_bytes(op, batch, m);
-  if (sorted_may(op, m)) b += rbi_sorted_ws_bytes(op, n, m);
-  return b;
+  // one row at a time: the sort's or the partition's scratch (whichever
+  // may run) after the operator's own workspace
+  const size_t so = sorted_may(op, m) ? rbi_sorted_ws_bytes(op, n, m) : 0;
+  const size_t pa = part_may(op, m) ? rbi_part_ws_bytes(op, n, m) : 0;
+  return base_ws_bytes(op, batch, m) + (so > pa ? so : pa);
 }
 
 // saved state: the operator's own (zero counts and products; arg-extrema)
@@ -430,6 +443,17 @@ hipError_t rbi_fwd_launch(int op, int64_t batch, int64_t n, int64_t m, const int
     case MIN: hipLaunchKernelGGL(k_rbi_fin<MIN>, gi, dim3(BLOCK), 0, s, a, total); break;
     case MAX: hipLaunchKernelGGL(k_rbi_fin<MAX>, gi, dim3(BLOCK), 0, s, a, total); break;
     default: break;
+    }
+    return hipGetLastError();
+  }
+  if (use_part(op, n, m)) {
+    void *region = static_cast<char *>(ws) + base_ws_bytes(op, batch, m);
+    for (int64_t r = 0; r < batch; ++r) {
+      hipError_t e = rbi_part_fwd_row(op, n, m, idx + r * n, v + r * n, hist + r * m,
+                                      a.n0 ? a.n0 + r * m : nullptr,
+                                      a.ypos ? a.ypos + r * m : nullptr,
+                                      a.argk ? a.argk + r * m : nullptr, region, s);
+      if (e != hipSuccess) return e;
     }
     return hipGetLastError();
   }

@@ -198,7 +198,7 @@ __global__ __launch_bounds__(RS_TH) void k_rbi_sorted(RsArgs a) {
   const T incl = wave_scan_fwd<Tr>(acc);
   if (lane == WAVE - 1) s_tot[0][wave] = incl;
   __syncthreads();
-  const uint32_t tag = s_epoch + 1;
+  const uint32_t tag = next_tag(s_epoch);
   if (wave == 0) {
     const T agg = wave0_block_prefix<Tr, 1, RS_W, false>(s_tot, s_pre, Tr::id());
     uint64_t *st = a.status + tile * (Tr::NA + Tr::NP);
@@ -312,7 +312,7 @@ __global__ __launch_bounds__(RS_TH) void k_rbi_sorted_vjp(RsArgs a) {
   const T incl = wave_scan_rev<Tr>(acc);
   if (lane == 0) s_tot[0][wave] = incl;
   __syncthreads();
-  const uint32_t tag = s_epoch + 1;
+  const uint32_t tag = next_tag(s_epoch);
   if (wave == 0) {
     const T agg = wave0_block_prefix<Tr, 1, RS_W, true>(s_tot, s_pre, Tr::id());
     uint64_t *st = a.status + tile * (Tr::NA + Tr::NP);

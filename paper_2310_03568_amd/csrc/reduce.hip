@@ -345,7 +345,7 @@ __global__ __launch_bounds__(Shape<OP>::THREADS) void k_reduce_vjp_gen(RedGenArg
     if (lane == 0) s_rtot[g][wave] = inr_[g];
   }
   __syncthreads();
-  const uint32_t tag = s_epoch + 1;
+  const uint32_t tag = next_tag(s_epoch);
 
   if (wave == 0) {
     // forward side: l = saved tile prefix (.) in-tile exclusive prefix

@@ -76,7 +76,7 @@ __global__ __launch_bounds__(TH_) void k_scan_fwd(ScanFwdArgs a) {
   float4 cur[K][NIN];
   load(t, cur);
   __syncthreads();
-  const uint32_t tag = s_epoch + 1;
+  const uint32_t tag = next_tag(s_epoch);
 
   // Scans the tile in `cur`: thread-serial inclusive values (lc), the
   // exclusive prefix of each thread's group inside the tile (thr), and, in
@@ -309,7 +309,7 @@ __global__ __launch_bounds__(TH_) void k_scan_vjp(ScanVjpArgs a) {
   float4 cpv[K][NTP];
   load(tile_of(k), cur, cpv);
   __syncthreads();
-  const uint32_t tag = s_epoch + 1;
+  const uint32_t tag = next_tag(s_epoch);
 
   FT thr_f[K];   // recompute: forward prefix before each thread's group
   MT mincl[K];   // wave-inclusive (from the right) adjoint-map aggregates

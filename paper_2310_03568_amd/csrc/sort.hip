@@ -120,11 +120,28 @@ __global__ __launch_bounds__(SCAN_TH) void k_iscan_totals(uint32_t *tot, int64_t
   }
 }
 
-__global__ __launch_bounds__(SCAN_TH) void k_iscan_add(uint32_t *v, int64_t n, const uint32_t *tot) {
+// the block totals are cleared once read (workspace data is not left
+// behind)
+__global__ __launch_bounds__(SCAN_TH) void k_iscan_add(uint32_t *v, int64_t n, uint32_t *tot) {
   const uint32_t add = tot[blockIdx.x];
   const int64_t base = (int64_t)blockIdx.x * SCAN_TH * SCAN_PER;
   for (int j = threadIdx.x; j < SCAN_TH * SCAN_PER; j += SCAN_TH)
     if (base + j < n) v[base + j] += add;
+  __syncthreads();
+  if (threadIdx.x == 0) tot[blockIdx.x] = 0u;
+}
+
+int64_t iscan_totals(int64_t ne) { return (ne + SCAN_TH * SCAN_PER - 1) / (SCAN_TH * SCAN_PER); }
+
+bool iscan_fits(int64_t ne) { return iscan_totals(ne) <= SCAN_TH * SCAN_PER; }
+
+hipError_t iscan_u32(uint32_t *v, int64_t ne, uint32_t *tot, hipStream_t s) {
+  if (ne <= 0) return hipSuccess;
+  const int64_t nt = iscan_totals(ne);
+  hipLaunchKernelGGL(k_iscan_local, dim3((unsigned)nt), dim3(SCAN_TH), 0, s, v, ne, tot);
+  hipLaunchKernelGGL(k_iscan_totals, dim3(1), dim3(SCAN_TH), 0, s, tot, nt);
+  hipLaunchKernelGGL(k_iscan_add, dim3((unsigned)nt), dim3(SCAN_TH), 0, s, v, ne, tot);
+  return hipGetLastError();
 }
 
 // stable scatter of (key, perm) by digit; perm_in == nullptr means the
@@ -213,7 +230,6 @@ hipError_t sort_by_key(const int32_t *keys, int64_t n, int64_t m, int32_t *keys_
   if (n == 0) return hipSuccess;
   const int nb = (int)((n + SORT_CH - 1) / SORT_CH);
   const int64_t ne = (int64_t)nb * SORT_D;
-  const int64_t nt = (ne + SCAN_TH * SCAN_PER - 1) / (SCAN_TH * SCAN_PER);
   auto al = [](size_t x) { return (x + 255) / 256 * 256; };
   char *w = static_cast<char *>(ws);
   int32_t *tk = reinterpret_cast<int32_t *>(w);
@@ -231,9 +247,8 @@ hipError_t sort_by_key(const int32_t *keys, int64_t n, int64_t m, int32_t *keys_
     int32_t *op = last ? perm_out : (odd_from_end ? tp : perm_out);
     const int shift = 8 * p;
     hipLaunchKernelGGL(k_sort_hist, dim3(nb), dim3(SORT_TH), 0, s, ik, n, m, p == 0, shift, nb, counts);
-    hipLaunchKernelGGL(k_iscan_local, dim3((unsigned)nt), dim3(SCAN_TH), 0, s, counts, ne, tot);
-    hipLaunchKernelGGL(k_iscan_totals, dim3(1), dim3(SCAN_TH), 0, s, tot, nt);
-    hipLaunchKernelGGL(k_iscan_add, dim3((unsigned)nt), dim3(SCAN_TH), 0, s, counts, ne, tot);
+    hipError_t e = iscan_u32(counts, ne, tot, s);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_sort_scatter, dim3(nb), dim3(SORT_TH), 0, s, ik, ip, n, m, p == 0, shift,
                        nb, counts, ok, op);
     ik = ok;

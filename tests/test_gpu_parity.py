@@ -392,6 +392,15 @@ def test_rbi_zipf(pcad, op, m):
     check_rbi(pcad, op, 1, 200_000, m, seed=43, dist="zipf")
 
 
+@pytest.mark.parametrize("op", SCALAR)
+@pytest.mark.parametrize("dist", ["uniform", "zipf"])
+def test_rbi_many_bins(pcad, op, dist):
+    """Bin counts far beyond the LDS capacity: hundreds of bin ranges (the
+    partitioned path), skewed keys splitting the hot range over many blocks"""
+    check_rbi(pcad, op, 1, 1 << 21, 1 << 22, seed=46, dist=dist)
+    check_rbi(pcad, op, 1, 999_999, 3 * 8192 + 5, seed=47, dist=dist)
+
+
 def test_rbi_zero_bins(pcad):
     for op in SCALAR:
         I = dev(np.array([0, 3, -1], np.int32))
