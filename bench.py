@@ -12,6 +12,10 @@ Workloads:
   linrec  -- linear-recurrence scan y_i = a_i y_{i-1} + b_i, n = 2^26, fp32,
              forward + adjoint w.r.t. a and b.
   mat2    -- 2x2 matrix-product scan, n = 2^24, entries ~ N(0, 0.5).
+  rbi     -- reduce-by-index, n = 2^26 values into --bins bins (uniform or
+             Zipf(1.1) keys), operator --op; extras: a sweep over
+             m in {256, 65536, 2^22} x both key distributions x + * min max.
+  autograd -- 64 x 2^16 loss forward + backward through torch.autograd.
 
 `value` is backward elements/s: n / (mean duration of the adjoint kernel,
 HIP events on the stream the kernel runs on).  `roofline` prices that kernel
@@ -129,6 +133,107 @@ def bench_segmented(args, pcad, torch, np):
                                  f"linrec scan -> min-by-index into {m} bins, fwd+adjoint, fp32",
                      "instances": S, "elements": N, "bins": m, "work_items": plan.n_items,
                      "combinator": "scan+reduce_by_index", "op": "linrec+min"})
+
+
+def bench_rbi(args, pcad, torch, np):
+    """Reduce-by-index of n = 2^26 values into m bins (uniform or Zipf(1.1)
+    keys, values ~ N(0,1)): the histogram forward and its adjoint."""
+    from workloads import rbi
+    n = args.n or (1 << 26)
+    m, op = args.bins, args.op
+    w = rbi(op, n=n, m=m, dist=args.dist)
+    dev = torch.device("cuda:0")
+    I = torch.from_numpy(w["idx"]).to(dev)
+    V = torch.from_numpy(w["v"]).to(dev)
+    HB = torch.from_numpy(w["hbar"]).to(dev)
+    vb = torch.empty_like(V)
+    state = {}
+
+    def fwd():
+        h, saved = pcad.rbi_fwd(op, I, V, m)
+        state["h"] = h
+        return None, None, saved
+
+    def bwd(saved):
+        pcad.rbi_vjp(op, I, V, m, saved, HB, out=vb)
+
+    # compulsory bytes.  Forward: reads idx, v; writes the bins (+ saved per
+    # bin: n0 and y_pos for *, argk for min/max).  Adjoint: reads idx (+ v
+    # for *), writes v_bar, and reads each bin's hbar (+ saved) once
+    per_bin = {"add": 4, "mul": 12, "min": 8, "max": 8}[op]
+    per_elem_bwd = {"add": 8, "mul": 12, "min": 8, "max": 8}[op]
+    return dict(n=n, fwd=fwd, bwd=bwd, inputs=w, bytes_fwd=8 * n + per_bin * m,
+                bytes_bwd=per_elem_bwd * n + per_bin * m, kernel=f"k_rbi_vjp<{op.upper()}>",
+                out=lambda: (state["h"], vb),
+                cfg={"workload": f"reduce_by_index {op}, n=2^{n.bit_length() - 1}, m={m}, "
+                                 f"{args.dist} keys, values ~N(0,1), fwd+adjoint, fp32",
+                     "n": n, "bins": m, "keys": args.dist, "op": op, "combinator": "reduce_by_index"})
+
+
+def rbi_sweep(torch, reps=3):
+    """Forward and adjoint times of reduce-by-index at n = 2^26 over the bin
+    counts {256, 65536, 2^22}, uniform and Zipf(1.1) keys, + * min max.
+    Inputs are drawn on the device (torch generator, seeded): timing only."""
+    import paper_2310_03568_amd as pcad
+    n = 1 << 26
+    g = torch.Generator(device="cuda:0").manual_seed(231003568)
+    v = torch.randn(n, device="cuda:0", generator=g)
+    out = {}
+    for m in (256, 65536, 1 << 22):
+        cdf = torch.cumsum(torch.arange(1, m + 1, device="cuda:0", dtype=torch.float64) ** -1.1, 0)
+        cdf /= cdf[-1].clone()
+        for dist in ("uniform", "zipf"):
+            if dist == "uniform":
+                idx = torch.randint(0, m, (n,), device="cuda:0", generator=g, dtype=torch.int32)
+            else:
+                u = torch.rand(n, device="cuda:0", generator=g, dtype=torch.float64)
+                idx = torch.searchsorted(cdf, u, right=True).clamp_(max=m - 1).to(torch.int32)
+            hb = torch.randn(m, device="cuda:0", generator=g)
+            for op in ("add", "mul", "min", "max"):
+                h, saved = pcad.rbi_fwd(op, idx, v, m)
+                vb = pcad.rbi_vjp(op, idx, v, m, saved, hb)
+                times = []
+                for fn in (lambda: pcad.rbi_fwd(op, idx, v, m),
+                           lambda: pcad.rbi_vjp(op, idx, v, m, saved, hb, out=vb)):
+                    fn()
+                    torch.cuda.synchronize()
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record()
+                    for _ in range(reps):
+                        fn()
+                    e1.record()
+                    torch.cuda.synchronize()
+                    times.append(e0.elapsed_time(e1) / reps)
+                out[f"{op} m={m} {dist}"] = {"fwd_ms": round(times[0], 4), "vjp_ms": round(times[1], 4),
+                                             "fwd_GBs": round(8 * n / times[0] * 1e-6, 1)}
+            del idx, hb
+    return {"rbi_sweep_n2e26": out}
+
+
+def rbi_parity(b, np):
+    """Oracle (fp64, one thread) forward and adjoint on the whole workload:
+    its time is the cpu_baseline, its outputs gate the GPU's."""
+    import oracle
+    from oracle.gate import RTOL, gate
+    w = b["inputs"]
+    n, op, m = b["n"], b["cfg"]["op"], b["cfg"]["bins"]
+    h, vb = (t.cpu().numpy() for t in b["out"]())
+    t0 = time.perf_counter()
+    o = oracle.rbi_fwd(op, w["idx"], m, w["v"])
+    xb, cx = oracle.rbi_vjp(op, w["idx"], m, w["hbar"], w["v"])
+    dt = time.perf_counter() - t0
+    if op in ("min", "max"):
+        ok = bool(np.array_equal(h, o["hist"][:, 0].astype(np.float32)))
+        ok = ok and bool(np.array_equal(vb, xb[:, 0].astype(np.float32)))
+        par = dict(ok=ok, exact=True)
+    else:
+        rh = gate(h, o["hist"][:, 0], o["c"][:, 0], RTOL[op])
+        rv = gate(vb, xb[:, 0], cx[:, 0], RTOL[op])
+        par = dict(ok=rh["ok"] and rv["ok"], hist_max_rel=rh["max_rel"], vbar_max_rel=rv["max_rel"],
+                   range_exceeded=rh["n_range_exceeded"] + rv["n_range_exceeded"])
+    cpu = {"value": n / dt, "unit": "elem/s", "cores": 1, "kind": "oracle",
+           "sample": f"whole workload (n={n}, m={m}): oracle forward + adjoint, fp64, {dt:.2f} s"}
+    return cpu, par
 
 
 def bench_autograd(args, pcad, torch, np):
@@ -328,7 +433,12 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="segmented",
-                    choices=["segmented", "linrec", "mat2", "autograd"])
+                    choices=["segmented", "linrec", "mat2", "rbi", "autograd"])
+    ap.add_argument("--op", default="add", choices=["add", "mul", "min", "max"],
+                    help="operator of the rbi workload")
+    ap.add_argument("--bins", type=int, default=65536, help="bins of the rbi workload")
+    ap.add_argument("--dist", default="uniform", choices=["uniform", "zipf"],
+                    help="key distribution of the rbi workload")
     ap.add_argument("--mode", default="recompute", choices=["recompute", "checkpoint"],
                     help="saved-state form of the autograd workload's scan")
     ap.add_argument("--segments", type=int, default=4096, help="instances of the segmented workload")
@@ -351,7 +461,7 @@ def main():
 
     pcad.lib()
     b = {"linrec": bench_linrec, "mat2": bench_mat2, "segmented": bench_segmented,
-         "autograd": bench_autograd}[args.workload](args, pcad, torch, np)
+         "rbi": bench_rbi, "autograd": bench_autograd}[args.workload](args, pcad, torch, np)
     torch.cuda.synchronize()
 
     for _ in range(args.warmup):
@@ -393,12 +503,16 @@ def main():
         extras = segmented_extras(b, torch, np)
     if args.workload == "autograd" and not args.no_extras:
         extras = autograd_extras(b, torch, np)
+    if args.workload == "rbi" and not args.no_extras:
+        extras = rbi_sweep(torch)
     cpu, par = (None, None)
     if not args.no_cpu:
         if args.workload == "segmented":
             cpu, par = segmented_parity(b, torch, np)
         elif args.workload == "autograd":
             cpu, par = autograd_parity(b, torch, np)
+        elif args.workload == "rbi":
+            cpu, par = rbi_parity(b, np)
         else:
             cpu, par = cpu_baseline_and_parity(args.workload, b, np)
 

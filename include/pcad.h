@@ -190,10 +190,18 @@ int pcad_scan_vjp_checkpoint(int op, int64_t batch, int64_t n, const float *x0, 
  * Operators: ADD, MUL, MIN, MAX, and the ordered LINREC and MAT2, whose
  * per-bin fold takes the bin's elements in ascending index (the sequential
  * semantics of Section 4).  m >= 0, m <= 2^26; n at most 2^28.
- * Strategies: a private LDS histogram per block (ADD/MUL up to 8192 bins,
- * MIN/MAX up to 4096), an LDS hash table of the bins a block meets, or a
- * stable sort by bin followed by a segmented scan of each run (the rule
- * figure's sort; always for LINREC/MAT2 and for larger bin counts).
+ * Strategies (results agree up to the order in which + and * combine):
+ *   - a private LDS histogram per block (ADD/MUL up to 8192 bins, MIN/MAX
+ *     up to 4096);
+ *   - beyond that, for ADD/MUL/MIN/MAX: the elements are partitioned once by
+ *     bin range and each range gets its LDS histogram (the one-pass
+ *     relative of the multi-pass technique of Section 4.2; bin ranges of
+ *     16384 bins for ADD, 8192 otherwise, at most 2048 ranges), or, past
+ *     that or when knob rbi.partition is 0, an LDS hash table of the bins a
+ *     block meets with global atomics for the rest;
+ *   - for LINREC/MAT2 (and, by knob, large bin counts of the others) a
+ *     stable sort by bin followed by a segmented scan of each run (the rule
+ *     figure's sort).
  *   v: n floats per row; LINREC: n pairs (a, b) interleaved; MAT2: n
  *      row-major 2x2 matrices (4 floats).  hist: m entries of the same
  *      width per row.
@@ -223,7 +231,11 @@ int pcad_rbi_fwd(int op, int64_t batch, int64_t n, int64_t m, const int32_t *idx
  *            R_i the ordered folds of the bin's elements before and after i
  *            (the sort-based rule of Section 4, from the sort in `saved`)
  * with k = idx_i; out-of-range keys get 0.  v is required for MUL, LINREC
- * and MAT2; the ordered operators also need the workspace.
+ * and MAT2; the ordered operators also need the workspace.  For MUL, MIN
+ * and MAX the workspace is optional: given (of the queried size), large bin
+ * counts first pack what an element needs from its bin into one record per
+ * bin there, so each element makes one gather instead of one per array;
+ * with ws = NULL (or too small) the adjoint gathers from `saved` directly.
  */
 int pcad_rbi_vjp(int op, int64_t batch, int64_t n, int64_t m, const int32_t *idx,
                  const float *v, const void *saved, const float *hbar, float *vbar,

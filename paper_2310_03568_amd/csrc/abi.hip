@@ -277,7 +277,13 @@ int pcad_rbi_vjp(int op, int64_t batch, int64_t n, int64_t m, const int32_t *idx
   if (m > 0) PCAD_TRY(need(hbar));
   PCAD_TRY(need(vbar));
   PCAD_TRY(check_saved(PCAD_RBI, op, batch, n, m, saved));
-  if (ordered) PCAD_TRY(check_ws(PCAD_RBI, op, batch, n, m, ws, ws_bytes));
+  if (ordered) {
+    PCAD_TRY(check_ws(PCAD_RBI, op, batch, n, m, ws, ws_bytes));
+  } else if (ws != nullptr && check_ws(PCAD_RBI, op, batch, n, m, ws, ws_bytes) != PCAD_OK) {
+    // optional for + * min max: without a (sufficient) workspace the
+    // adjoint gathers from the saved arrays directly
+    ws = nullptr;
+  }
   return hip_status(rbi_vjp_launch(op, batch, n, m, idx, v, saved, hbar, vbar,
                                    (flags & PCAD_ACCUMULATE) != 0, ws, (hipStream_t)stream));
 }

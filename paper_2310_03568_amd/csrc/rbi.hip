@@ -254,7 +254,15 @@ __global__ __launch_bounds__(BLOCK) void k_rbi_fin(RbiArgs a, int64_t total) {
   }
 }
 
-// adjoint: one elementwise pass per row
+// adjoint: one elementwise pass per row.  What an element needs from its
+// bin comes from one place per element:
+//   GATHER -- the saved arrays and hbar directly (one gather per array);
+//   LDS    -- a per-bin record table the block builds in LDS (small m);
+//   TABLE  -- the same records built once in the workspace by k_rbi_vjp_tab
+//             (large m: one gather per element instead of one per array).
+// Records: + : hbar;  * : {y_pos, n0 | 2^31, hbar, 2^31};
+// min/max: {hbar, argk | 2^31}.  Every 8-byte word of a record left in the
+// workspace has its upper half >= 2^31.
 struct RbiVjpArgs {
   const int32_t *idx;
   const float *v;
@@ -263,17 +271,56 @@ struct RbiVjpArgs {
   const float *ypos;
   const int32_t *argk;
   float *vbar;
+  void *tab;
   int64_t n, m;
   int accumulate;
 };
 
+enum { VJP_GATHER = 0, VJP_LDS = 1, VJP_TABLE = 2 };
+constexpr uint32_t kRecHi = 0x80000000u;
+
 template <int OP>
+__device__ __forceinline__ uint4 vjp_rec(const RbiVjpArgs &a, int64_t t) {
+  uint4 r;
+  if (OP == MUL) {
+    r.x = __float_as_uint(a.ypos[t]); r.y = a.n0[t] | kRecHi;
+    r.z = __float_as_uint(a.hbar[t]); r.w = kRecHi;
+  } else {
+    r.x = __float_as_uint(a.hbar[t]); r.y = (uint32_t)a.argk[t] | kRecHi;
+    r.z = r.w = 0u;
+  }
+  return r;
+}
+
+template <int OP>
+__global__ __launch_bounds__(BLOCK) void k_rbi_vjp_tab(RbiVjpArgs a, int64_t total) {
+  for (int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * BLOCK) {
+    const uint4 r = vjp_rec<OP>(a, t);
+    if (OP == MUL) static_cast<uint4 *>(a.tab)[t] = r;
+    else static_cast<uint2 *>(a.tab)[t] = make_uint2(r.x, r.y);
+  }
+}
+
+template <int OP, int SRC>
 __global__ __launch_bounds__(BLOCK) void k_rbi_vjp(RbiVjpArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
   const int64_t row = blockIdx.y;
   const int32_t *ir = a.idx + row * a.n;
   const float *vr = a.v + row * a.n;
   float *ob = a.vbar + row * a.n;
   const int64_t gb = row * a.m;
+  if (SRC == VJP_LDS) {
+    for (int64_t k = threadIdx.x; k < a.m; k += BLOCK) {
+      if (OP == ADD) reinterpret_cast<float *>(smem)[k] = a.hbar[gb + k];
+      else if (OP == MUL) reinterpret_cast<uint4 *>(smem)[k] = vjp_rec<OP>(a, gb + k);
+      else {
+        const uint4 r = vjp_rec<OP>(a, gb + k);
+        reinterpret_cast<uint2 *>(smem)[k] = make_uint2(r.x, r.y);
+      }
+    }
+    __syncthreads();
+  }
   const bool vec_ok = ((row * a.n) & 3) == 0;
   const int64_t stride = (int64_t)gridDim.x * BLOCK * 4;
   for (int64_t i = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) * 4; i < a.n; i += stride) {
@@ -298,14 +345,31 @@ __global__ __launch_bounds__(BLOCK) void k_rbi_vjp(RbiVjpArgs a) {
       const int k = kk[j];
       float r = 0.0f;
       if (k >= 0 && k < a.m) {
-        const float h = a.hbar[gb + k];
-        if (OP == ADD) r = h;
-        if (OP == MUL) {
-          const uint32_t z = a.n0[gb + k];
-          const float p = a.ypos[gb + k];
+        if (OP == ADD) {
+          r = SRC == VJP_LDS ? reinterpret_cast<const float *>(smem)[k] : a.hbar[gb + k];
+        } else if (OP == MUL) {
+          uint32_t z;
+          float p, h;
+          if (SRC == VJP_GATHER) {
+            z = a.n0[gb + k]; p = a.ypos[gb + k]; h = a.hbar[gb + k];
+          } else {
+            const uint4 q = SRC == VJP_LDS ? reinterpret_cast<const uint4 *>(smem)[k]
+                                           : static_cast<const uint4 *>(a.tab)[gb + k];
+            p = __uint_as_float(q.x); z = q.y & ~kRecHi; h = __uint_as_float(q.z);
+          }
           r = z == 0 ? (p / vv[j]) * h : ((z == 1 && vv[j] == 0.0f) ? p * h : 0.0f);
+        } else {
+          int32_t ak;
+          float h;
+          if (SRC == VJP_GATHER) {
+            ak = a.argk[gb + k]; h = a.hbar[gb + k];
+          } else {
+            const uint2 q = SRC == VJP_LDS ? reinterpret_cast<const uint2 *>(smem)[k]
+                                           : static_cast<const uint2 *>(a.tab)[gb + k];
+            h = __uint_as_float(q.x); ak = (int32_t)(q.y & ~kRecHi);
+          }
+          r = ak == (int32_t)(i + j) ? h : 0.0f;
         }
-        if (OP == MIN || OP == MAX) r = (a.argk[gb + k] == (int32_t)(i + j)) ? h : 0.0f;
       }
       o[j] = r;
     }
@@ -366,8 +430,12 @@ static bool use_part(int op, int64_t n, int64_t m) {
   return n > 0 && part_may(op, m) && knob_rbi_partition() && !use_sorted(op, m);
 }
 
+// control block, then the per-bin region: min/max keys (forward) or
+// adjoint records (8 bytes per bin), * adjoint records (16 bytes per bin)
 static size_t base_ws_bytes(int op, int64_t batch, int64_t m) {
-  const size_t b = (op == MIN || op == MAX) ? kCtlBytes + (size_t)batch * m * 8 : kCtlBytes;
+  size_t b = kCtlBytes;
+  if (op == MIN || op == MAX) b += (size_t)batch * m * 8;
+  if (op == MUL) b += (size_t)batch * m * 16;
   return (b + 255) / 256 * 256;
 }
 
@@ -510,23 +578,50 @@ hipError_t rbi_vjp_launch(int op, int64_t batch, int64_t n, int64_t m, const int
   RbiVjpArgs a;
   a.idx = idx; a.v = v; a.hbar = hbar; a.vbar = vbar; a.n = n; a.m = m;
   a.accumulate = accumulate ? 1 : 0;
-  a.n0 = nullptr; a.ypos = nullptr; a.argk = nullptr;
+  a.n0 = nullptr; a.ypos = nullptr; a.argk = nullptr; a.tab = nullptr;
   const int64_t total = batch * m;
   if (op == MUL) {
     a.n0 = static_cast<const uint32_t *>(saved);
     a.ypos = reinterpret_cast<const float *>(static_cast<const uint32_t *>(saved) + total);
   }
   if (op == MIN || op == MAX) a.argk = static_cast<const int32_t *>(saved);
+  // bins per row up to which a block builds its record table in LDS (16 KB)
+  const int64_t lds_max = op == ADD ? 4096 : (op == MUL ? 1024 : 2048);
+  const size_t rec = op == ADD ? 4 : (op == MUL ? 16 : 8);
+  int src = VJP_GATHER;
+  if (m <= lds_max) src = VJP_LDS;
+  else if (op != ADD && ws != nullptr) src = VJP_TABLE;
   int64_t bx = (n + BLOCK * 4 * 4 - 1) / (BLOCK * 4 * 4);
-  if (bx > 65535) bx = 65535;
+  // an LDS table is built once per block: fewer, longer blocks
+  const int64_t bx_cap = src == VJP_LDS ? 2048 / (batch < 2048 ? batch : 2048) : 65535;
+  if (bx > bx_cap) bx = bx_cap;
+  if (bx < 1) bx = 1;
   const dim3 grid((unsigned)bx, (unsigned)batch);
+  const size_t shm = src == VJP_LDS ? (size_t)m * rec : 0;
+  if (src == VJP_TABLE) {
+    a.tab = static_cast<char *>(ws) + kCtlBytes;
+    const dim3 gi((unsigned)grid1d(total));
+    switch (op) {
+    case MUL: hipLaunchKernelGGL(k_rbi_vjp_tab<MUL>, gi, dim3(BLOCK), 0, s, a, total); break;
+    case MIN: hipLaunchKernelGGL(k_rbi_vjp_tab<MIN>, gi, dim3(BLOCK), 0, s, a, total); break;
+    case MAX: hipLaunchKernelGGL(k_rbi_vjp_tab<MAX>, gi, dim3(BLOCK), 0, s, a, total); break;
+    default: return hipErrorInvalidValue;
+    }
+  }
+#define PCAD_RBI_VJP(OPV)                                                                        \
+  case OPV:                                                                                      \
+    if (src == VJP_LDS) hipLaunchKernelGGL((k_rbi_vjp<OPV, VJP_LDS>), grid, dim3(BLOCK), shm, s, a); \
+    else if (src == VJP_TABLE) hipLaunchKernelGGL((k_rbi_vjp<OPV, VJP_TABLE>), grid, dim3(BLOCK), 0, s, a); \
+    else hipLaunchKernelGGL((k_rbi_vjp<OPV, VJP_GATHER>), grid, dim3(BLOCK), 0, s, a);          \
+    break;
   switch (op) {
-  case ADD: hipLaunchKernelGGL(k_rbi_vjp<ADD>, grid, dim3(BLOCK), 0, s, a); break;
-  case MUL: hipLaunchKernelGGL(k_rbi_vjp<MUL>, grid, dim3(BLOCK), 0, s, a); break;
-  case MIN: hipLaunchKernelGGL(k_rbi_vjp<MIN>, grid, dim3(BLOCK), 0, s, a); break;
-  case MAX: hipLaunchKernelGGL(k_rbi_vjp<MAX>, grid, dim3(BLOCK), 0, s, a); break;
+    PCAD_RBI_VJP(ADD)
+    PCAD_RBI_VJP(MUL)
+    PCAD_RBI_VJP(MIN)
+    PCAD_RBI_VJP(MAX)
   default: return hipErrorInvalidValue;
   }
+#undef PCAD_RBI_VJP
   return hipGetLastError();
 }
 

@@ -401,6 +401,34 @@ def test_rbi_many_bins(pcad, op, dist):
     check_rbi(pcad, op, 1, 999_999, 3 * 8192 + 5, seed=47, dist=dist)
 
 
+@pytest.mark.parametrize("op", SCALAR)
+@pytest.mark.parametrize("m", [700, 3000, 20_011])
+def test_rbi_vjp_without_workspace(pcad, op, m):
+    """The adjoint of + * min max may be called with ws = NULL (direct gathers
+    from the saved arrays); it must equal the call with a workspace (LDS or
+    packed per-bin records) bit for bit, and also accumulate the same way."""
+    rng = np.random.default_rng(m)
+    n = 50_001
+    v = rng.standard_normal(n).astype(np.float32)
+    if op == "mul":
+        v[rng.choice(n, 300, replace=False)] = 0.0
+    if op in ("min", "max"):
+        v = np.round(v * 16) / 16
+    idx = rng.integers(-3, m + 3, n).astype(np.int32)
+    I, V = dev(idx), dev(v)
+    hb = dev(rng.standard_normal(m).astype(np.float32))
+    h, saved = pcad.rbi_fwd(op, I, V, m)
+    ref = pcad.rbi_vjp(op, I, V, m, saved, hb)
+    for acc in (0, pcad.ACCUMULATE):
+        out = dev(np.ones(n, np.float32)) if acc else torch.empty_like(V)
+        pcad.check(pcad.lib().pcad_rbi_vjp(pcad.OPS[op], 1, n, m, I.data_ptr(), V.data_ptr(),
+                                           saved.data_ptr(), hb.data_ptr(), out.data_ptr(), acc,
+                                           None, 0, torch.cuda.current_stream().cuda_stream),
+                   "pcad_rbi_vjp")
+        expect = host(ref) + (1.0 if acc else 0.0)
+        np.testing.assert_array_equal(host(out), expect.astype(np.float32))
+
+
 def test_rbi_zero_bins(pcad):
     for op in SCALAR:
         I = dev(np.array([0, 3, -1], np.int32))
