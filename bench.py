@@ -39,19 +39,32 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "backward elems/s + % HBM peak, batched vs per-segment, at 1e-5 rel err"
 
 
+# the source files each timed kernel is built from (its own file and the
+# headers it includes): the traffic counters stay valid while these do
+KERNEL_SOURCES = {
+    "k_seg_bwd": ("batched.hip", "device.hpp", "adjoint.hpp"),
+    "k_scan_vjp": ("scan.hip", "device.hpp", "adjoint.hpp"),
+    "k_rbi_vjp": ("rbi.hip", "device.hpp"),
+}
+
+
+def sources_digest(kernel: str) -> str:
+    import hashlib
+    src = os.path.join(ROOT, "paper_2310_03568_amd", "csrc")
+    h = hashlib.sha1()
+    for f in KERNEL_SOURCES[kernel.split("<")[0]]:
+        h.update(open(os.path.join(src, f), "rb").read())
+    return h.hexdigest()[:12]
+
+
 def _traffic(kernel: str, workload: str):
     """HBM bytes per launch measured with rocprofv3 FETCH_SIZE/WRITE_SIZE,
-    scaled by a plain copy kernel; None when the kernel sources changed
+    scaled by a plain copy kernel; None when the kernel's sources changed
     since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "traffic.txt")
     if not os.path.exists(path):
         return None
-    import hashlib
-    src = os.path.join(ROOT, "paper_2310_03568_amd", "csrc")
-    h = hashlib.sha1()
-    for f in sorted(os.listdir(src)):
-        h.update(open(os.path.join(src, f), "rb").read())
-    digest = h.hexdigest()[:12]
+    digest = sources_digest(kernel)
     for line in open(path):
         parts = line.split()
         if len(parts) >= 4 and parts[0] == kernel and parts[1] == workload and parts[2] == digest:
@@ -516,6 +529,9 @@ def main():
         else:
             cpu, par = cpu_baseline_and_parity(args.workload, b, np)
 
+    wl_key = args.workload
+    if args.workload == "rbi":
+        wl_key = f"rbi-{args.op}-m{args.bins}-{args.dist}"
     out = {
         "metric": METRIC,
         "value": n / tb,
@@ -532,7 +548,7 @@ def main():
         "config": b["cfg"],
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": _traffic(b["kernel"], args.workload)},
+                     "traffic": _traffic(b["kernel"], wl_key)},
         "cpu_baseline": cpu,
         "bwd_ms": tb * 1e3,
         "fwd_ms": tf * 1e3,
