@@ -11,8 +11,11 @@ workload.  Every function widens its float32 inputs exactly to float64.
 
 Operators (names used throughout): ``add``, ``mul``, ``min``, ``max``,
 ``linrec`` (linear-function composition, Section 5.1 operator figure, with
-multiplier a and offset b, y_i = a_i*y_{i-1} + b_i) and ``mat2`` (row-major
-2x2 matrix product, Section 5.1 operator figure).
+multiplier a and offset b, y_i = a_i*y_{i-1} + b_i), ``mat2`` (row-major
+2x2 matrix product, Section 5.1 operator figure) and ``sumprod`` (the
+invertible operator sumOfProd of Section 3.3 on lifted pairs (p, s); the
+``sumprod_*`` functions below take the scalar inputs, lift each a to (0, a)
+and return the p component, as that section composes them).
 """
 from __future__ import annotations
 
@@ -26,8 +29,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-OPS = {"add": 0, "mul": 1, "min": 2, "max": 3, "linrec": 4, "mat2": 5}
-DIM = {"add": 1, "mul": 1, "min": 1, "max": 1, "linrec": 2, "mat2": 4}
+OPS = {"add": 0, "mul": 1, "min": 2, "max": 3, "linrec": 4, "mat2": 5, "sumprod": 6}
+DIM = {"add": 1, "mul": 1, "min": 1, "max": 1, "linrec": 2, "mat2": 4, "sumprod": 2}
 
 
 def build(force: bool = True) -> str:
@@ -81,6 +84,14 @@ def pack(op: str, x0, x1=None) -> np.ndarray:
     if op == "linrec":
         a, b = _f64(x0).reshape(-1), _f64(x1).reshape(-1)
         return np.ascontiguousarray(np.stack([a, b], axis=1))
+    if op == "sumprod":
+        # the lifting map of Section 3.3: a -> (0, a); a (n, 2) array is
+        # taken as already lifted
+        x = _f64(x0)
+        if x.ndim == 2 and x.shape[1] == 2:
+            return np.ascontiguousarray(x)
+        a = x.reshape(-1)
+        return np.ascontiguousarray(np.stack([np.zeros_like(a), a], axis=1))
     if d == 4:
         return _f64(x0).reshape(-1, 4)
     return _f64(x0).reshape(-1, 1)
@@ -283,3 +294,38 @@ def autograd_grad(a, b, v, idx, m: int, ybar=None):
     hb = (r["argk"] < n).astype(np.float64)
     vb, cv = rbi_vjp("max", idx, m, hb, v)
     return xb[:, 0], xb[:, 1], vb[:, 0], cx[:, 0], cx[:, 1], cv[:, 0]
+
+
+# -------------------------------------------------------------------------
+# sumOfProd: the invertible-operator example of Section 3.3 as the
+# composition lift -> fold with the lifted operator -> project to p, for
+# reduce and reduce-by-index (Section 4.2, Invertible Operators).  The
+# adjoints are the reverse sweep of that composition: the output adjoint
+# enters as (p_bar, 0) and an input's adjoint is the s component of its
+# lifted adjoint (the lifting a -> (0, a) passes only the s slot).
+# -------------------------------------------------------------------------
+def sumprod_reduce(a):
+    """Returns dict(y = p = sum_{i<j} a_i a_j, s = sum a_i, c = companion of p)."""
+    r = reduce_fwd("sumprod", a)
+    return dict(y=float(r["y"][0]), s=float(r["y"][1]), c=float(r["c"][0]))
+
+
+def sumprod_reduce_vjp(a, ybar: float):
+    """Returns (a_bar, c) for y = sum_{i<j} a_i a_j and output adjoint ybar."""
+    xb, c = reduce_vjp("sumprod", np.array([float(ybar), 0.0]), a)
+    return xb[:, 1].copy(), c[:, 1].copy()
+
+
+def sumprod_rbi_fwd(idx, m: int, a):
+    """Per bin: hist (p_k), s (sum of the bin's values), c (companion of p_k),
+    count."""
+    r = rbi_fwd("sumprod", idx, m, a)
+    return dict(hist=r["hist"][:, 0].copy(), s=r["hist"][:, 1].copy(), c=r["c"][:, 0].copy(),
+                count=r["count"])
+
+
+def sumprod_rbi_vjp(idx, m: int, hbar, a):
+    """Returns (v_bar, c): the adjoint of every value for bin adjoints hbar."""
+    hb = np.stack([_f64(hbar).reshape(-1), np.zeros(max(int(m), 0))], axis=1)
+    vb, c = rbi_vjp("sumprod", idx, m, hb, a)
+    return vb[:, 1].copy(), c[:, 1].copy()

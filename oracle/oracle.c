@@ -21,6 +21,12 @@
  *                        [[a,b],[c,d]]; the operator is the matrix product
  *                        P (.) M = P x M (Section 5.1, operator figure),
  *                        neutral I.
+ *   SUMPROD            : d = 2, the lifted pair (p, s) of the invertible
+ *                        operator sumOfProd (Section 3.3):
+ *                        (p1,s1) (.) (p2,s2) = (p1 + p2 + s1*s2, s1 + s2),
+ *                        neutral (0,0).  A scalar input a enters as (0, a)
+ *                        and the result is the p component, so a fold gives
+ *                        p = sum over i<j of a_i*a_j and s = sum of a_i.
  *
  * Forward results are the plain definitions:
  *   reduce : the left fold x_0 (.) x_1 (.) ... (.) x_{n-1} (Section 3.1);
@@ -56,11 +62,11 @@
 #include <stdlib.h>
 #include <string.h>
 
-enum { OP_ADD = 0, OP_MUL = 1, OP_MIN = 2, OP_MAX = 3, OP_LINREC = 4, OP_MAT2 = 5 };
+enum { OP_ADD = 0, OP_MUL = 1, OP_MIN = 2, OP_MAX = 3, OP_LINREC = 4, OP_MAT2 = 5, OP_SUMPROD = 6 };
 
-int orc_dim(int op) { return op == OP_LINREC ? 2 : (op == OP_MAT2 ? 4 : 1); }
+int orc_dim(int op) { return (op == OP_LINREC || op == OP_SUMPROD) ? 2 : (op == OP_MAT2 ? 4 : 1); }
 
-static int valid_op(int op) { return op >= OP_ADD && op <= OP_MAT2; }
+static int valid_op(int op) { return op >= OP_ADD && op <= OP_SUMPROD; }
 
 /* neutral element e of the operator */
 static void neutral(int op, double *e) {
@@ -71,6 +77,7 @@ static void neutral(int op, double *e) {
   case OP_MAX: e[0] = -INFINITY; break;
   case OP_LINREC: e[0] = 1.0; e[1] = 0.0; break;
   case OP_MAT2: e[0] = 1.0; e[1] = 0.0; e[2] = 0.0; e[3] = 1.0; break;
+  case OP_SUMPROD: e[0] = 0.0; e[1] = 0.0; break;
   }
 }
 
@@ -85,6 +92,11 @@ static void combine(int op, const double *acc, const double *x, double *out) {
   case OP_LINREC:
     t[0] = acc[0] * x[0];
     t[1] = x[0] * acc[1] + x[1];
+    out[0] = t[0]; out[1] = t[1];
+    break;
+  case OP_SUMPROD:
+    t[0] = acc[0] + x[0] + acc[1] * x[1];
+    t[1] = acc[1] + x[1];
     out[0] = t[0]; out[1] = t[1];
     break;
   case OP_MAT2:
@@ -133,6 +145,13 @@ static void partials(int op, const double *acc, const double *x, double *JA, dou
     JA[2] = 0.0;  JA[3] = x[0];
     JX[0] = acc[0]; JX[1] = 0.0;
     JX[2] = acc[1]; JX[3] = 1.0;
+    break;
+  case OP_SUMPROD:
+    /* out0 = P + p + S*s, out1 = S + s with acc = (P,S), x = (p,s) */
+    JA[0] = 1.0; JA[1] = x[1];
+    JA[2] = 0.0; JA[3] = 1.0;
+    JX[0] = 1.0; JX[1] = acc[1];
+    JX[2] = 0.0; JX[3] = 1.0;
     break;
   case OP_MAT2: {
     /* out[i][j] = sum_k P[i][k] M[k][j]; flat index 2*row + col */

@@ -187,7 +187,20 @@ def _f(v):
 def test_golden(g):
     op, comb = g["op"], g["combinator"]
     assert g.get("cite"), "every fixture cites the rule it follows"
-    if comb == "reduce":
+    if comb == "reduce" and op == "sumprod":
+        r = oracle.sumprod_reduce(np.array(g["x"]))
+        assert r["y"] == g["y"][0] and r["s"] == g["s"]
+        xb, _ = oracle.sumprod_reduce_vjp(np.array(g["x"]), g["ybar"][0])
+        np.testing.assert_array_equal(xb, g["xbar"])
+    elif comb == "rbi" and op == "sumprod":
+        idx = np.array(g["idx"], np.int32)
+        r = oracle.sumprod_rbi_fwd(idx, g["m"], np.array(g["v"]))
+        np.testing.assert_array_equal(r["hist"], g["hist"])
+        np.testing.assert_array_equal(r["s"], g["s"])
+        np.testing.assert_array_equal(r["count"], g["count"])
+        vb, _ = oracle.sumprod_rbi_vjp(idx, g["m"], np.array(g["hbar"]), np.array(g["v"]))
+        np.testing.assert_array_equal(vb, g["vbar"])
+    elif comb == "reduce":
         r = oracle.reduce_fwd(op, np.array(g["x"]))
         np.testing.assert_array_equal(r["y"], g["y"])
         if "k" in g:
@@ -721,3 +734,94 @@ def test_segmented_matches_per_instance():
             yt[j] += w["hbar"][s * 8 + k]
     xb, _ = oracle.scan_vjp("linrec", np.stack([np.zeros(hi - lo), yt], 1), w["a"][lo:hi], w["b"][lo:hi])
     np.testing.assert_allclose(bb[lo:hi], xb[:, 1], rtol=1e-13)
+
+
+# -------------------------------------------------------------------------
+# sumOfProd (Section 3.3; reduce-by-index: Section 4.2, Invertible Operators)
+# -------------------------------------------------------------------------
+def _sp_comb(a, b):
+    """The operator as Section 3.3 defines it, written independently."""
+    return (a[0] + b[0] + a[1] * b[1], a[1] + b[1])
+
+
+def _sp_inv(z, b):
+    """Its left inverse: z = a (.) b  =>  a = z inv b."""
+    return (z[0] - b[0] - (z[1] - b[1]) * b[1], z[1] - b[1])
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_sumprod_reduce_closed_forms(seed):
+    """Small integers keep float64 exact: p equals the brute-force pair sum
+    and (S^2 - sum a^2)/2, s equals S, a_bar equals (S - a) y_bar."""
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(1, 40))
+    a = rng.integers(-9, 10, n).astype(np.float64)
+    r = oracle.sumprod_reduce(a)
+    brute = sum(a[i] * a[j] for i in range(n) for j in range(i + 1, n))
+    S = a.sum()
+    assert r["y"] == brute == (S * S - (a * a).sum()) / 2
+    assert r["s"] == S
+    assert r["c"] >= abs(r["y"])
+    xb, c = oracle.sumprod_reduce_vjp(a, 3.0)
+    np.testing.assert_array_equal(xb, (S - a) * 3.0)
+    assert np.all(c >= np.abs(xb))
+
+
+def test_sumprod_reduce_fd_and_empty():
+    rng = np.random.default_rng(11)
+    a = rng.standard_normal(25)
+    xb, _ = oracle.sumprod_reduce_vjp(a, 1.0)
+    h = 1e-6
+    for k in range(0, 25, 4):
+        e = np.zeros_like(a)
+        e[k] = h
+        fd = (oracle.sumprod_reduce(a + e)["y"] - oracle.sumprod_reduce(a - e)["y"]) / (2 * h)
+        assert abs(fd - xb[k]) <= 1e-7 * (1 + abs(xb[k]))
+    r = oracle.sumprod_reduce(np.zeros(0))
+    assert r["y"] == 0.0 and r["s"] == 0.0
+    r = oracle.sumprod_reduce(np.array([7.0]))
+    assert r["y"] == 0.0 and r["s"] == 7.0
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_sumprod_rbi_against_brute_force_and_the_invertible_rule(seed):
+    """Per bin the pair sum and value sum by brute force; the adjoint by the
+    paper's invertible-operator rule (b_i = hist[k] inv (0, v_i), then the
+    derivative of b_i (.) (0, x) in x, which is b_i's s), written here
+    from the operator alone, and by its closed form (s_k - v_i) h_bar[k]."""
+    rng = np.random.default_rng(100 + seed)
+    n, m = 60, 7
+    v = rng.integers(-5, 6, n).astype(np.float64)
+    idx = rng.integers(-2, m + 2, n).astype(np.int32)
+    hb = rng.integers(-4, 5, m).astype(np.float64)
+    r = oracle.sumprod_rbi_fwd(idx, m, v)
+    for k in range(m):
+        vk = v[idx == k]
+        assert r["hist"][k] == sum(vk[i] * vk[j] for i in range(len(vk)) for j in range(i + 1, len(vk)))
+        assert r["s"][k] == vk.sum() and r["count"][k] == len(vk)
+    vb, c = oracle.sumprod_rbi_vjp(idx, m, hb, v)
+    for i in range(n):
+        k = idx[i]
+        if k < 0 or k >= m:
+            assert vb[i] == 0.0
+            continue
+        b = _sp_inv((r["hist"][k], r["s"][k]), (0.0, v[i]))
+        assert _sp_comb(b, (0.0, v[i])) == (r["hist"][k], r["s"][k])
+        assert vb[i] == b[1] * hb[k] == (r["s"][k] - v[i]) * hb[k]
+    assert np.all(c >= np.abs(vb))
+
+
+def test_sumprod_operator_is_associative_commutative_invertible():
+    rng = np.random.default_rng(5)
+    for _ in range(50):
+        x, y, z = (tuple(rng.integers(-20, 21, 2).astype(float)) for _ in range(3))
+        assert _sp_comb(_sp_comb(x, y), z) == _sp_comb(x, _sp_comb(y, z))
+        assert _sp_comb(x, y) == _sp_comb(y, x)
+        assert _sp_inv(_sp_comb(x, y), y) == x
+    # the oracle's fold agrees with the operator applied left to right
+    a = rng.integers(-9, 10, 12).astype(float)
+    acc = (0.0, 0.0)
+    for t in a:
+        acc = _sp_comb(acc, (0.0, t))
+    r = oracle.sumprod_reduce(a)
+    assert (r["y"], r["s"]) == acc
