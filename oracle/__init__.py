@@ -303,6 +303,14 @@ def autograd_grad(a, b, v, idx, m: int, ybar=None):
 # adjoints are the reverse sweep of that composition: the output adjoint
 # enters as (p_bar, 0) and an input's adjoint is the s component of its
 # lifted adjoint (the lifting a -> (0, a) passes only the s slot).
+#
+# Companions of the adjoints: the rule these adjoints specialise (Section
+# 3.3, and Section 4.2 for reduce-by-index) obtains the rest of the fold by
+# inverting the total with the element, i.e. it evaluates s - a_i with s the
+# total sum.  Rounding in s and in that subtraction is bounded relative to
+# sum_j |a_j| * |y_bar| (all elements, a_i included), not relative to the
+# reverse sweep's sum over j != i; the companions returned below are
+# therefore the sweep's plus |a_i| * |y_bar|.
 # -------------------------------------------------------------------------
 def sumprod_reduce(a):
     """Returns dict(y = p = sum_{i<j} a_i a_j, s = sum a_i, c = companion of p)."""
@@ -313,7 +321,8 @@ def sumprod_reduce(a):
 def sumprod_reduce_vjp(a, ybar: float):
     """Returns (a_bar, c) for y = sum_{i<j} a_i a_j and output adjoint ybar."""
     xb, c = reduce_vjp("sumprod", np.array([float(ybar), 0.0]), a)
-    return xb[:, 1].copy(), c[:, 1].copy()
+    av = np.abs(_f64(a).reshape(-1))
+    return xb[:, 1].copy(), c[:, 1] + av * abs(float(ybar))
 
 
 def sumprod_rbi_fwd(idx, m: int, a):
@@ -326,6 +335,11 @@ def sumprod_rbi_fwd(idx, m: int, a):
 
 def sumprod_rbi_vjp(idx, m: int, hbar, a):
     """Returns (v_bar, c): the adjoint of every value for bin adjoints hbar."""
-    hb = np.stack([_f64(hbar).reshape(-1), np.zeros(max(int(m), 0))], axis=1)
+    H = _f64(hbar).reshape(-1)
+    hb = np.stack([H, np.zeros(max(int(m), 0))], axis=1)
     vb, c = rbi_vjp("sumprod", idx, m, hb, a)
-    return vb[:, 1].copy(), c[:, 1].copy()
+    ix = np.asarray(idx, dtype=np.int64).reshape(-1)
+    ok = (ix >= 0) & (ix < m)
+    extra = np.zeros(ix.shape[0])
+    extra[ok] = np.abs(_f64(a).reshape(-1)[ok]) * np.abs(H[ix[ok]])
+    return vb[:, 1].copy(), c[:, 1] + extra

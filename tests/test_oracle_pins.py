@@ -764,6 +764,8 @@ def test_sumprod_reduce_closed_forms(seed):
     assert r["c"] >= abs(r["y"])
     xb, c = oracle.sumprod_reduce_vjp(a, 3.0)
     np.testing.assert_array_equal(xb, (S - a) * 3.0)
+    # the companion of the invertible rule's s - a_i: every |a_j| counts
+    np.testing.assert_array_equal(c, np.full(n, np.abs(a).sum() * 3.0))
     assert np.all(c >= np.abs(xb))
 
 
