@@ -173,8 +173,8 @@ def bench_rbi(args, pcad, torch, np):
     # compulsory bytes.  Forward: reads idx, v; writes the bins (+ saved per
     # bin: n0 and y_pos for *, argk for min/max).  Adjoint: reads idx (+ v
     # for *), writes v_bar, and reads each bin's hbar (+ saved) once
-    per_bin = {"add": 4, "mul": 12, "min": 8, "max": 8}[op]
-    per_elem_bwd = {"add": 8, "mul": 12, "min": 8, "max": 8}[op]
+    per_bin = {"add": 4, "mul": 12, "min": 8, "max": 8, "sumprod": 8}[op]
+    per_elem_bwd = {"add": 8, "mul": 12, "min": 8, "max": 8, "sumprod": 12}[op]
     return dict(n=n, fwd=fwd, bwd=bwd, inputs=w, bytes_fwd=8 * n + per_bin * m,
                 bytes_bwd=per_elem_bwd * n + per_bin * m, kernel=f"k_rbi_vjp<{op.upper()}>",
                 out=lambda: (state["h"], vb),
@@ -202,7 +202,7 @@ def rbi_sweep(torch, reps=3):
                 u = torch.rand(n, device="cuda:0", generator=g, dtype=torch.float64)
                 idx = torch.searchsorted(cdf, u, right=True).clamp_(max=m - 1).to(torch.int32)
             hb = torch.randn(m, device="cuda:0", generator=g)
-            for op in ("add", "mul", "min", "max"):
+            for op in ("add", "mul", "min", "max", "sumprod"):
                 h, saved = pcad.rbi_fwd(op, idx, v, m)
                 vb = pcad.rbi_vjp(op, idx, v, m, saved, hb)
                 times = []
@@ -220,6 +220,25 @@ def rbi_sweep(torch, reps=3):
                 out[f"{op} m={m} {dist}"] = {"fwd_ms": round(times[0], 4), "vjp_ms": round(times[1], 4),
                                              "fwd_GBs": round(8 * n / times[0] * 1e-6, 1)}
             del idx, hb
+    # reduce with the invertible operator sumOfProd (Section 3.3), same n
+    y, saved = pcad.reduce_fwd("sumprod", v)
+    yb = torch.ones(1, device="cuda:0")
+    g = pcad.reduce_vjp("sumprod", v, None, saved, yb)
+    times = []
+    for fn in (lambda: pcad.reduce_fwd("sumprod", v),
+               lambda: pcad.reduce_vjp("sumprod", v, None, saved, yb, out=(g,))):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1) / reps)
+    out["reduce sumprod"] = {"fwd_ms": round(times[0], 4), "vjp_ms": round(times[1], 4),
+                             "fwd_GBs": round(4 * n / times[0] * 1e-6, 1),
+                             "vjp_GBs": round(8 * n / times[1] * 1e-6, 1)}
     return {"rbi_sweep_n2e26": out}
 
 
@@ -231,11 +250,21 @@ def rbi_parity(b, np):
     w = b["inputs"]
     n, op, m = b["n"], b["cfg"]["op"], b["cfg"]["bins"]
     h, vb = (t.cpu().numpy() for t in b["out"]())
-    t0 = time.perf_counter()
-    o = oracle.rbi_fwd(op, w["idx"], m, w["v"])
-    xb, cx = oracle.rbi_vjp(op, w["idx"], m, w["hbar"], w["v"])
-    dt = time.perf_counter() - t0
-    if op in ("min", "max"):
+    if op != "sumprod":
+        t0 = time.perf_counter()
+        o = oracle.rbi_fwd(op, w["idx"], m, w["v"])
+        xb, cx = oracle.rbi_vjp(op, w["idx"], m, w["hbar"], w["v"])
+        dt = time.perf_counter() - t0
+    if op == "sumprod":
+        t0 = time.perf_counter()
+        o = oracle.sumprod_rbi_fwd(w["idx"], m, w["v"])
+        xb, cx = oracle.sumprod_rbi_vjp(w["idx"], m, w["hbar"], w["v"])
+        dt = time.perf_counter() - t0
+        rh = gate(h, o["hist"], o["c"], RTOL[op])
+        rv = gate(vb, xb, cx, RTOL[op])
+        par = dict(ok=rh["ok"] and rv["ok"], hist_max_rel=rh["max_rel"], vbar_max_rel=rv["max_rel"],
+                   range_exceeded=rh["n_range_exceeded"] + rv["n_range_exceeded"])
+    elif op in ("min", "max"):
         ok = bool(np.array_equal(h, o["hist"][:, 0].astype(np.float32)))
         ok = ok and bool(np.array_equal(vb, xb[:, 0].astype(np.float32)))
         par = dict(ok=ok, exact=True)
@@ -447,7 +476,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="segmented",
                     choices=["segmented", "linrec", "mat2", "rbi", "autograd"])
-    ap.add_argument("--op", default="add", choices=["add", "mul", "min", "max"],
+    ap.add_argument("--op", default="add", choices=["add", "mul", "min", "max", "sumprod"],
                     help="operator of the rbi workload")
     ap.add_argument("--bins", type=int, default=65536, help="bins of the rbi workload")
     ap.add_argument("--dist", default="uniform", choices=["uniform", "zipf"],

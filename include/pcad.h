@@ -85,7 +85,8 @@ typedef enum {
   PCAD_MIN = 2,
   PCAD_MAX = 3,
   PCAD_LINREC = 4, /* linear-function composition (a multiplier, b offset) */
-  PCAD_MAT2 = 5    /* 2x2 matrix product, row-major */
+  PCAD_MAT2 = 5,   /* 2x2 matrix product, row-major */
+  PCAD_SUMPROD = 6 /* sumOfProd (Section 3.3): reduce and reduce_by_index only */
 } pcad_op;
 
 enum {
@@ -118,7 +119,12 @@ int pcad_query(int combinator, int op, int64_t batch, int64_t n, int64_t m, unsi
  *             of the non-zero elements (Section 3.2 Multiplication);
  *     MIN/MAX: {int32 k} -- lowest index attaining the extremum, n if empty
  *             (Section 3.2 Min/Max);
- *     LINREC/MAT2: the exclusive prefix of every tile of the row (opaque).
+ *     LINREC/MAT2: the exclusive prefix of every tile of the row (opaque);
+ *     SUMPROD: {float s} -- the sum of the row.
+ * SUMPROD is the invertible operator of Section 3.3: elements a enter as
+ * pairs (0, a), pairs combine as (p1,s1) (.) (p2,s2) = (p1+p2+s1*s2, s1+s2),
+ * and y is the p of the result, i.e. y = sum over i<j of a_i*a_j (0 for
+ * n < 2).
  */
 int pcad_reduce_fwd(int op, int64_t batch, int64_t n, const float *x0, const float *x1,
                     float *y, void *saved, unsigned flags, void *ws, size_t ws_bytes,
@@ -130,7 +136,11 @@ int pcad_reduce_fwd(int op, int64_t batch, int64_t n, const float *x0, const flo
  * Addition); MUL uses the three zero cases (Section 3.2 Multiplication);
  * MIN/MAX write y_bar at index k only (Section 3.2 Min/Max); LINREC/MAT2 use
  * the general rule x_bar_i = d(l_i (.) x_i (.) r_i)/dx_i^T y_bar (Eq. 2) with
- * l_i, r_i the exclusive prefix and suffix (Section 3.1).
+ * l_i, r_i the exclusive prefix and suffix (Section 3.1); SUMPROD uses the
+ * invertible-operator rule of Section 3.3: the rest of the fold is
+ * (p, s) inverted by (0, x_i), whose s is s - x_i, so x_bar_i =
+ * (s - x_i) * y_bar (x0 required).  Scans of SUMPROD return
+ * PCAD_E_UNSUPPORTED.
  *   xbar0/xbar1: same layout as x0/x1 (LINREC: a_bar, b_bar).
  */
 int pcad_reduce_vjp(int op, int64_t batch, int64_t n, const float *x0, const float *x1,
@@ -190,10 +200,10 @@ int pcad_scan_vjp_checkpoint(int op, int64_t batch, int64_t n, const float *x0, 
  * Operators: ADD, MUL, MIN, MAX, and the ordered LINREC and MAT2, whose
  * per-bin fold takes the bin's elements in ascending index (the sequential
  * semantics of Section 4).  m >= 0, m <= 2^26; n at most 2^28.
- * Strategies (results agree up to the order in which + and * combine):
+ * Strategies (results agree up to the order in which + * SUMPROD combine):
  *   - a private LDS histogram per block (ADD/MUL up to 8192 bins, MIN/MAX
- *     up to 4096);
- *   - beyond that, for ADD/MUL/MIN/MAX: the elements are partitioned once by
+ *     and SUMPROD up to 4096);
+ *   - beyond that, for ADD/MUL/MIN/MAX/SUMPROD: the elements are partitioned once by
  *     bin range and each range gets its LDS histogram (the one-pass
  *     relative of the multi-pass technique of Section 4.2; bin ranges of
  *     16384 bins for ADD, 8192 otherwise, at most 2048 ranges), or, past
@@ -212,6 +222,8 @@ int pcad_scan_vjp_checkpoint(int op, int64_t batch, int64_t n, const float *x0, 
  *              product of the non-zeros per bin, Section 4.2 Multiplication);
  *     MIN/MAX: int32 argk[batch*m], the lowest index of the bin's extremum,
  *              n when the bin is empty (Section 4.2 Min/Max rule figure);
+ *     SUMPROD: float s[batch*m], the sum of the bin's values (its hist is
+ *              the sum of v_i*v_j over pairs i<j of the bin); m <= 2^24;
  *     then, wherever the sort-based path may run (LINREC, MAT2, and bin
  *     counts beyond the LDS histogram), 256-byte aligned, per row the sorted
  *     keys, the permutation and the sort's scratch (opaque), which the
@@ -227,6 +239,8 @@ int pcad_rbi_fwd(int op, int64_t batch, int64_t n, int64_t m, const int32_t *idx
  *   MUL    : v_bar_i = hbar[k]*(n0==0 ? y_pos/v_i : (n0==1 && v_i==0 ? y_pos : 0))
  *                                                      (Section 4.2 Multiplication)
  *   MIN/MAX: v_bar_i = hbar[k] if i == argk[k] else 0  (Section 4.2 Min/Max)
+ *   SUMPROD: v_bar_i = (s[k] - v_i) * hbar[k]   (Section 4.2 Invertible
+ *            Operators: hist[k] inverted by (0, v_i) leaves s[k] - v_i)
  *   LINREC/MAT2: v_bar_i = d(L_i (.) v_i (.) R_i)/dv_i^T hbar[k], with L_i and
  *            R_i the ordered folds of the bin's elements before and after i
  *            (the sort-based rule of Section 4, from the sort in `saved`)

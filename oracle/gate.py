@@ -25,7 +25,10 @@ import numpy as np
 FLT_MAX = float(np.finfo(np.float32).max)
 TINY = 2.0 ** -126
 
-RTOL = {"add": 1e-5, "min": 1e-5, "max": 1e-5, "mul": 1e-4, "linrec": 1e-4, "mat2": 1e-4}
+RTOL = {"add": 1e-5, "min": 1e-5, "max": 1e-5, "mul": 1e-4, "linrec": 1e-4, "mat2": 1e-4,
+        # sumOfProd accumulates pairwise products s1*s2 of partial sums: the
+        # error bound of a dot product, like the product-type folds above
+        "sumprod": 1e-4}
 
 
 def gate(g, r, c, rtol: float):

@@ -24,8 +24,10 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpcad.so")
 
-OPS = {"add": 0, "mul": 1, "min": 2, "max": 3, "linrec": 4, "mat2": 5}
-DIM = {"add": 1, "mul": 1, "min": 1, "max": 1, "linrec": 2, "mat2": 4}
+OPS = {"add": 0, "mul": 1, "min": 2, "max": 3, "linrec": 4, "mat2": 5, "sumprod": 6}
+# floats per element of the values and of the results (sumprod: scalar values,
+# scalar results -- the p of the lifted pair)
+DIM = {"add": 1, "mul": 1, "min": 1, "max": 1, "linrec": 2, "mat2": 4, "sumprod": 1}
 REDUCE, SCAN, RBI = 0, 1, 2
 ACCUMULATE = 1
 
@@ -292,7 +294,8 @@ def rbi_fwd(op: str, idx: torch.Tensor, v: torch.Tensor, m: int):
     """Returns (hist, saved).  idx (..., n); v (..., n) or (..., n, d) for
     linrec (pairs (a, b)) and mat2; hist (..., m) or (..., m, d).
     saved: mul -> uint32 n0[batch*m] then float y_pos[batch*m];
-    min/max -> int32 argk[batch*m]; then, where the sort-based path may run
+    min/max -> int32 argk[batch*m]; sumprod -> float s[batch*m] (bin sums);
+    then, where the sort-based path may run
     (the ordered operators always, the others beyond the LDS capacity),
     each row's sort (sorted keys and permutation) for the adjoint."""
     _dev_check(idx, v)

@@ -26,13 +26,14 @@ namespace {
 constexpr int64_t kMaxN = 2147483647LL;
 constexpr int64_t kMaxTotal = 1LL << 40;
 constexpr int64_t kMaxBins = 1LL << 26;
+constexpr int64_t kMaxBinsSumProd = 1LL << 24;  // LDS histogram or at most 2048 bin ranges
 constexpr unsigned kKnownFlags = PCAD_ACCUMULATE;
 
 
 bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 
 int check_common(int op, int64_t batch, int64_t n, unsigned flags) {
-  if (op < PCAD_ADD || op > PCAD_MAT2) return PCAD_E_INVALID_ARG;
+  if (op < PCAD_ADD || op > PCAD_SUMPROD) return PCAD_E_INVALID_ARG;
   if (flags & ~kKnownFlags) return PCAD_E_INVALID_ARG;
   if (batch < 0 || n < 0) return PCAD_E_INVALID_ARG;
   if (n > kMaxN) return PCAD_E_SIZE;
@@ -77,7 +78,8 @@ size_t reduce_saved(int op, int64_t batch, int64_t n) {
   case PCAD_ADD: return 0;
   case PCAD_MUL: return (size_t)batch * 8;
   case PCAD_MIN:
-  case PCAD_MAX: return (size_t)batch * 4;
+  case PCAD_MAX:
+  case PCAD_SUMPROD: return (size_t)batch * 4;
   default: return scan_saved(op, batch, n);
   }
 }
@@ -90,12 +92,13 @@ int query(int comb, int op, int64_t batch, int64_t n, int64_t m, size_t *saved, 
     w = reduce_ws_bytes(op, batch, n);
     break;
   case PCAD_SCAN:
+    if (op == PCAD_SUMPROD) return PCAD_E_UNSUPPORTED;
     s = scan_saved(op, batch, n);
     w = scan_ws(op, batch, n);
     break;
   case PCAD_RBI:
     if (m < 0) return PCAD_E_INVALID_ARG;
-    if (m > kMaxBins) return PCAD_E_SIZE;
+    if (m > (op == PCAD_SUMPROD ? kMaxBinsSumProd : kMaxBins)) return PCAD_E_SIZE;
     if (!sort_supported(n)) return PCAD_E_SIZE;
     s = rbi_saved_bytes(op, batch, n, m);
     w = rbi_ws_bytes(op, batch, n, m);
@@ -187,6 +190,7 @@ int pcad_scan_fwd(int op, int64_t batch, int64_t n, const float *x0, const float
                   float *y1, void *saved, unsigned flags, void *ws, size_t ws_bytes,
                   void *stream) {
   PCAD_TRY(check_common(op, batch, n, flags));
+  if (op == PCAD_SUMPROD) return PCAD_E_UNSUPPORTED;
   if (batch == 0 || n == 0) return PCAD_OK;
   if (scan_tiles(op, batch, n) > 2147483647LL) return PCAD_E_SIZE;
   PCAD_TRY(need(x0));
@@ -204,6 +208,7 @@ int pcad_scan_vjp(int op, int64_t batch, int64_t n, const float *x0, const float
                   const void *saved, const float *ybar0, const float *ybar1, float *xbar0,
                   float *xbar1, unsigned flags, void *ws, size_t ws_bytes, void *stream) {
   PCAD_TRY(check_common(op, batch, n, flags));
+  if (op == PCAD_SUMPROD) return PCAD_E_UNSUPPORTED;
   if (batch == 0 || n == 0) return PCAD_OK;
   if (scan_tiles(op, batch, n) > 2147483647LL) return PCAD_E_SIZE;
   PCAD_TRY(need(x0));
@@ -225,6 +230,7 @@ int pcad_scan_vjp_checkpoint(int op, int64_t batch, int64_t n, const float *x0, 
                              const float *ybar1, float *xbar0, float *xbar1, unsigned flags,
                              void *ws, size_t ws_bytes, void *stream) {
   PCAD_TRY(check_common(op, batch, n, flags));
+  if (op == PCAD_SUMPROD) return PCAD_E_UNSUPPORTED;
   if (batch == 0 || n == 0) return PCAD_OK;
   if (scan_tiles(op, batch, n) > 2147483647LL) return PCAD_E_SIZE;
   PCAD_TRY(need(x0));
@@ -252,7 +258,7 @@ int pcad_rbi_fwd(int op, int64_t batch, int64_t n, int64_t m, const int32_t *idx
                  void *stream) {
   PCAD_TRY(check_common(op, batch, n, flags));
   if (m < 0) return PCAD_E_INVALID_ARG;
-  if (m > kMaxBins) return PCAD_E_SIZE;
+  if (m > (op == PCAD_SUMPROD ? kMaxBinsSumProd : kMaxBins)) return PCAD_E_SIZE;
   if (batch == 0 || m == 0) return PCAD_OK;
   if (n > 0) {
     PCAD_TRY(need(idx));
@@ -269,11 +275,11 @@ int pcad_rbi_vjp(int op, int64_t batch, int64_t n, int64_t m, const int32_t *idx
                  size_t ws_bytes, void *stream) {
   PCAD_TRY(check_common(op, batch, n, flags));
   if (m < 0) return PCAD_E_INVALID_ARG;
-  if (m > kMaxBins) return PCAD_E_SIZE;
+  if (m > (op == PCAD_SUMPROD ? kMaxBinsSumProd : kMaxBins)) return PCAD_E_SIZE;
   if (batch == 0 || n == 0) return PCAD_OK;
   PCAD_TRY(need(idx));
   const bool ordered = op == PCAD_LINREC || op == PCAD_MAT2;
-  if (op == PCAD_MUL || ordered) PCAD_TRY(need(v));
+  if (op == PCAD_MUL || op == PCAD_SUMPROD || ordered) PCAD_TRY(need(v));
   if (m > 0) PCAD_TRY(need(hbar));
   PCAD_TRY(need(vbar));
   PCAD_TRY(check_saved(PCAD_RBI, op, batch, n, m, saved));

@@ -13,8 +13,9 @@ constexpr int BLOCK = 256;
 constexpr int WAVE = 64;
 constexpr int WAVES = BLOCK / WAVE;
 
-// operator ids (same values as the public enum)
-enum { ADD = 0, MUL = 1, MIN = 2, MAX = 3, LINREC = 4, MAT2 = 5 };
+// operator ids (same values as the public enum).  SUMPROD (Section 3.3's
+// invertible operator sumOfProd) exists for reduce and reduce-by-index only.
+enum { ADD = 0, MUL = 1, MIN = 2, MAX = 3, LINREC = 4, MAT2 = 5, SUMPROD = 6 };
 
 template <int N>
 struct Vec {
@@ -71,6 +72,59 @@ __device__ __forceinline__ void lds_add_f32(float *p, float v) {
                                             __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                             __HIP_MEMORY_SCOPE_WORKGROUP))
     atomicAdd(p, v);
+}
+
+// ---------------------------------------------------------------------------
+// sumOfProd (Section 3.3) on lifted pairs (p, s):
+//   (p1, s1) (.) (p2, s2) = (p1 + p2 + s1*s2, s1 + s2),  neutral (0, 0);
+// an input a enters as (0, a).  A pair packs into one 64-bit word
+// {s:32 | p:32} so that an update is one 64-bit compare-and-swap.
+// ---------------------------------------------------------------------------
+struct SP {
+  float p, s;
+};
+
+__device__ __forceinline__ SP sp_comb(const SP &a, const SP &b) {
+  return {a.p + b.p + a.s * b.s, a.s + b.s};
+}
+
+__device__ __forceinline__ uint64_t sp_pack(const SP &v) {
+  return ((uint64_t)__float_as_uint(v.s) << 32) | __float_as_uint(v.p);
+}
+
+__device__ __forceinline__ SP sp_unpack(uint64_t w) {
+  return {__uint_as_float((uint32_t)w), __uint_as_float((uint32_t)(w >> 32))};
+}
+
+// *w = *w (.) v, atomically; SCOPE: workgroup for LDS, agent for global
+template <int SCOPE>
+__device__ __forceinline__ void sp_atomic(uint64_t *w, const SP &v) {
+  uint64_t old = __hip_atomic_load(w, __ATOMIC_RELAXED, SCOPE);
+  for (;;) {
+    const uint64_t nw = sp_pack(sp_comb(sp_unpack(old), v));
+    if (__hip_atomic_compare_exchange_strong(w, &old, nw, __ATOMIC_RELAXED, __ATOMIC_RELAXED, SCOPE))
+      return;
+  }
+}
+
+// One wave's LDS update of table[bin] (.)= (0, x) for the lanes with ok.
+// The lanes whose bin equals the first active lane's fold their elements
+// with a butterfly first and make one update together (skewed keys would
+// otherwise retry the same word 64 ways); must be called by all 64 lanes.
+__device__ __forceinline__ void sp_wave_update(uint64_t *table, uint32_t bin, float x, bool ok) {
+  const uint64_t act = __ballot(ok);
+  if (act == 0) return;
+  const int first = __builtin_ctzll(act);
+  const uint32_t b0 = (uint32_t)__builtin_amdgcn_readlane((int)bin, first);
+  const bool hot = ok && bin == b0;
+  SP v = {0.0f, hot ? x : 0.0f};
+#pragma unroll
+  for (int d = 1; d < WAVE; d <<= 1) {
+    const SP o = {__shfl_xor(v.p, d, WAVE), __shfl_xor(v.s, d, WAVE)};
+    v = sp_comb(v, o);
+  }
+  if (lane_id() == first) sp_atomic<__HIP_MEMORY_SCOPE_WORKGROUP>(&table[b0], v);
+  if (ok && !hot) sp_atomic<__HIP_MEMORY_SCOPE_WORKGROUP>(&table[bin], SP{0.0f, x});
 }
 
 // ---------------------------------------------------------------------------

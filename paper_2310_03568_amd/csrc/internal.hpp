@@ -35,14 +35,14 @@ int64_t iscan_totals(int64_t ne);
 bool iscan_fits(int64_t ne);
 hipError_t iscan_u32(uint32_t *v, int64_t ne, uint32_t *tot, hipStream_t s);
 
-// partitioned reduce-by-index of one row for + * min max beyond the LDS
+// partitioned reduce-by-index of one row for + * min max sumOfProd beyond the LDS
 // histogram capacity (rbi_part.hip): `region` is the row's workspace part;
-// writes every bin and the saved state (n0/ypos, argk) directly
+// writes every bin and the saved state (n0/ypos, argk, ssum) directly
 bool rbi_part_may(int op, int64_t m);
 size_t rbi_part_ws_bytes(int op, int64_t n, int64_t m);
 hipError_t rbi_part_fwd_row(int op, int64_t n, int64_t m, const int32_t *idx, const float *v,
-                            float *hist, uint32_t *n0, float *ypos, int32_t *argk, void *region,
-                            hipStream_t s);
+                            float *hist, uint32_t *n0, float *ypos, int32_t *argk, float *ssum,
+                            void *region, hipStream_t s);
 
 // sort-based reduce-by-index of one row (rbi_sorted.hip): `ctl` is the
 // control block at the start of the call's workspace, `region` the row's

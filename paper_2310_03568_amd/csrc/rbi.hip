@@ -1,4 +1,5 @@
-// reduce_by_index (Section 4) for + * min max, and its adjoint (Section 4.2).
+// reduce_by_index (Section 4) for + * min max and sumOfProd, and its adjoint
+// (Section 4.2).
 //
 // Forward, three launches: neutral initialisation of the bins, the update
 // pass, and (min/max, *) a per-bin finalisation.
@@ -55,8 +56,9 @@ struct RbiArgs {
   float *hist;        // ADD: bins; MUL: finalised values
   uint32_t *n0;       // MUL: zero counts (saved)
   float *ypos;        // MUL: product of non-zeros (saved)
-  uint64_t *keys;     // MIN/MAX: packed keys (workspace)
+  uint64_t *keys;     // MIN/MAX: packed keys; SUMPROD: packed (p, s) pairs (workspace)
   int32_t *argk;      // MIN/MAX: saved
+  float *ssum;        // SUMPROD: sum of each bin's values (saved)
   int64_t n, m;
   int64_t chunk;      // elements per block (multiple of 4)
   int bpr;
@@ -145,6 +147,51 @@ __global__ __launch_bounds__(BLOCK) void k_rbi_lds(RbiArgs a) {
       const unsigned long long key = sk[k];
       if (key != key_init<MAX>()) atomicMax(reinterpret_cast<unsigned long long *>(&a.keys[gb + k]), key);
     }
+  }
+}
+
+// sumOfProd (Section 3.3) with an LDS table of packed (p, s) pairs per
+// block; the chunk is walked in rounds that every lane of the block takes
+// (sp_wave_update needs whole waves), then the table goes to the block's own
+// slot of the workspace (a global compare-and-swap merge of many blocks
+// into few bins would serialise on those bins)
+__global__ __launch_bounds__(BLOCK) void k_rbi_lds_sp(RbiArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  uint64_t *tab = reinterpret_cast<uint64_t *>(smem);
+  const int64_t row = blockIdx.y;
+  const int m = (int)a.m;
+  for (int k = threadIdx.x; k < m; k += BLOCK) tab[k] = 0ull;
+  __syncthreads();
+  const int64_t lo = (int64_t)blockIdx.x * a.chunk;
+  const int64_t hi = lo + a.chunk < a.n ? lo + a.chunk : a.n;
+  const int32_t *ir = a.idx + row * a.n;
+  const float *vr = a.v + row * a.n;
+  for (int64_t i = lo + threadIdx.x; i - threadIdx.x < hi; i += BLOCK) {
+    const bool in = i < hi;
+    const int32_t k = in ? ir[i] : -1;
+    const float x = in ? vr[i] : 0.0f;
+    const bool ok = k >= 0 && k < m;
+    sp_wave_update(tab, ok ? (uint32_t)k : 0u, x, ok);
+  }
+  __syncthreads();
+  uint64_t *slot = a.keys + (row * a.bpr + blockIdx.x) * a.m;
+  for (int k = threadIdx.x; k < m; k += BLOCK) slot[k] = tab[k];
+}
+
+// fold the blocks' tables of every bin in block order (the fold order is
+// fixed, so results repeat bit for bit), then zero them
+__global__ __launch_bounds__(BLOCK) void k_rbi_fold_sp(RbiArgs a, int64_t total) {
+  for (int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * BLOCK) {
+    const int64_t row = t / a.m, k = t - row * a.m;
+    SP r = {0.0f, 0.0f};
+    for (int j = 0; j < a.bpr; ++j) {
+      uint64_t *w = a.keys + (row * a.bpr + j) * a.m + k;
+      r = sp_comb(r, sp_unpack(*w));
+      *w = 0ull;
+    }
+    a.hist[t] = r.p;
+    a.ssum[t] = r.s;
   }
 }
 
@@ -270,6 +317,7 @@ struct RbiVjpArgs {
   const uint32_t *n0;
   const float *ypos;
   const int32_t *argk;
+  const float *ssum;
   float *vbar;
   void *tab;
   int64_t n, m;
@@ -285,6 +333,9 @@ __device__ __forceinline__ uint4 vjp_rec(const RbiVjpArgs &a, int64_t t) {
   if (OP == MUL) {
     r.x = __float_as_uint(a.ypos[t]); r.y = a.n0[t] | kRecHi;
     r.z = __float_as_uint(a.hbar[t]); r.w = kRecHi;
+  } else if (OP == SUMPROD) {
+    r.x = __float_as_uint(a.ssum[t]); r.y = __float_as_uint(a.hbar[t]);  // LDS only
+    r.z = r.w = 0u;
   } else {
     r.x = __float_as_uint(a.hbar[t]); r.y = (uint32_t)a.argk[t] | kRecHi;
     r.z = r.w = 0u;
@@ -330,14 +381,14 @@ __global__ __launch_bounds__(BLOCK) void k_rbi_vjp(RbiVjpArgs a) {
     if (full) {
       const int4 k4 = *reinterpret_cast<const int4 *>(ir + i);
       kk[0] = k4.x; kk[1] = k4.y; kk[2] = k4.z; kk[3] = k4.w;
-      if (OP == MUL) {
+      if (OP == MUL || OP == SUMPROD) {
         const float4 v4 = *reinterpret_cast<const float4 *>(vr + i);
         vv[0] = v4.x; vv[1] = v4.y; vv[2] = v4.z; vv[3] = v4.w;
       }
     } else {
       for (int j = 0; j < 4; ++j) {
         kk[j] = (i + j < a.n) ? ir[i + j] : -1;
-        if (OP == MUL && i + j < a.n) vv[j] = vr[i + j];
+        if ((OP == MUL || OP == SUMPROD) && i + j < a.n) vv[j] = vr[i + j];
       }
     }
 #pragma unroll
@@ -358,6 +409,16 @@ __global__ __launch_bounds__(BLOCK) void k_rbi_vjp(RbiVjpArgs a) {
             p = __uint_as_float(q.x); z = q.y & ~kRecHi; h = __uint_as_float(q.z);
           }
           r = z == 0 ? (p / vv[j]) * h : ((z == 1 && vv[j] == 0.0f) ? p * h : 0.0f);
+        } else if (OP == SUMPROD) {
+          float sk, h;
+          if (SRC == VJP_LDS) {
+            const uint2 q = reinterpret_cast<const uint2 *>(smem)[k];
+            sk = __uint_as_float(q.x); h = __uint_as_float(q.y);
+          } else {
+            sk = a.ssum[gb + k]; h = a.hbar[gb + k];
+          }
+          // the invertible-operator rule: the bin without v_i keeps s - v_i
+          r = (sk - vv[j]) * h;
         } else {
           int32_t ak;
           float h;
@@ -390,19 +451,20 @@ __global__ __launch_bounds__(BLOCK) void k_rbi_vjp(RbiVjpArgs a) {
 // host side
 // ---------------------------------------------------------------------------
 static bool use_lds(int op, int64_t m) {
+  if (op == SUMPROD) return m <= kLdsBinsU64;  // no hash path: the knob does not apply
   if (op == MIN || op == MAX) return m <= kLdsBinsU64 && m <= knob_rbi_lds_max_bins(true);
   return m <= kLdsBinsF32 && m <= knob_rbi_lds_max_bins(false);
 }
 
 static size_t lds_bytes(int op, int64_t m) {
-  if (op == MIN || op == MAX) return (size_t)m * 8;
+  if (op == MIN || op == MAX || op == SUMPROD) return (size_t)m * 8;
   if (op == MUL) return (size_t)m * 8;
   return (size_t)m * 4;
 }
 
 static size_t op_saved_bytes(int op, int64_t batch, int64_t m) {
   if (op == MUL) return (size_t)batch * m * 8;
-  if (op == MIN || op == MAX) return (size_t)batch * m * 4;
+  if (op == MIN || op == MAX || op == SUMPROD) return (size_t)batch * m * 4;
   return 0;
 }
 
@@ -410,6 +472,7 @@ static size_t op_saved_bytes(int op, int64_t batch, int64_t m) {
 // beyond the LDS capacity (a fixed bound, so the workspace size does not
 // depend on the knobs), from the knob's bin count on
 static bool sorted_may(int op, int64_t m) {
+  if (op == SUMPROD) return false;
   if (op == LINREC || op == MAT2) return true;
   return m > ((op == MIN || op == MAX) ? kLdsBinsU64 : kLdsBinsF32);
 }
@@ -423,18 +486,36 @@ static bool use_sorted(int op, int64_t m) {
 // (a fixed bound, like sorted_may), unless the knob picks the hash table
 static bool part_may(int op, int64_t m) {
   if (op == LINREC || op == MAT2) return false;
-  return m > ((op == MIN || op == MAX) ? kLdsBinsU64 : kLdsBinsF32) && rbi_part_may(op, m);
+  const bool u64 = op == MIN || op == MAX || op == SUMPROD;
+  return m > (u64 ? kLdsBinsU64 : kLdsBinsF32) && rbi_part_may(op, m);
 }
 
+// sumOfProd has no other path beyond the LDS histogram
 static bool use_part(int op, int64_t n, int64_t m) {
+  if (op == SUMPROD) return n > 0 && part_may(op, m);
   return n > 0 && part_may(op, m) && knob_rbi_partition() && !use_sorted(op, m);
 }
 
 // control block, then the per-bin region: min/max keys (forward) or
-// adjoint records (8 bytes per bin), * adjoint records (16 bytes per bin)
-static size_t base_ws_bytes(int op, int64_t batch, int64_t m) {
+// adjoint records (8 bytes per bin), * adjoint records (16 bytes per bin),
+// sumOfProd's per-block tables
+// sumOfProd with the LDS table: blocks per row, each writing its table to
+// its own slot of the workspace (at most 2^22 pairs, 32 MB, in all)
+static int64_t sp_blocks_per_row(int64_t batch, int64_t n, int64_t m) {
+  int64_t cap = ((int64_t)1 << 22) / (batch * m > 0 ? batch * m : 1);
+  if (cap > 1024) cap = 1024;
+  if (cap < 1) cap = 1;
+  int64_t bpr = (n + 16383) / 16384;
+  if (bpr > cap) bpr = cap;
+  if (bpr < 1) bpr = 1;
+  return bpr;
+}
+
+static size_t base_ws_bytes(int op, int64_t batch, int64_t n, int64_t m) {
   size_t b = kCtlBytes;
   if (op == MIN || op == MAX) b += (size_t)batch * m * 8;
+  if (op == SUMPROD && m <= kLdsBinsU64)
+    b += (size_t)(batch * sp_blocks_per_row(batch, n, m) * m) * 8;
   if (op == MUL) b += (size_t)batch * m * 16;
   return (b + 255) / 256 * 256;
 }
@@ -444,7 +525,7 @@ size_t rbi_ws_bytes(int op, int64_t batch, int64_t n, int64_t m) {
   // may run) after the operator's own workspace
   const size_t so = sorted_may(op, m) ? rbi_sorted_ws_bytes(op, n, m) : 0;
   const size_t pa = part_may(op, m) ? rbi_part_ws_bytes(op, n, m) : 0;
-  return base_ws_bytes(op, batch, m) + (so > pa ? so : pa);
+  return base_ws_bytes(op, batch, n, m) + (so > pa ? so : pa);
 }
 
 // saved state: the operator's own (zero counts and products; arg-extrema)
@@ -471,7 +552,7 @@ hipError_t rbi_fwd_launch(int op, int64_t batch, int64_t n, int64_t m, const int
   if (batch == 0 || m == 0) return hipSuccess;
   RbiArgs a;
   a.idx = idx; a.v = v; a.hist = hist; a.n = n; a.m = m;
-  a.n0 = nullptr; a.ypos = nullptr; a.keys = nullptr; a.argk = nullptr;
+  a.n0 = nullptr; a.ypos = nullptr; a.keys = nullptr; a.argk = nullptr; a.ssum = nullptr;
   const int64_t total = batch * m;
   if (op == MUL) {
     a.n0 = static_cast<uint32_t *>(saved);
@@ -481,9 +562,13 @@ hipError_t rbi_fwd_launch(int op, int64_t batch, int64_t n, int64_t m, const int
     a.keys = reinterpret_cast<uint64_t *>(static_cast<char *>(ws) + kCtlBytes);
     a.argk = static_cast<int32_t *>(saved);
   }
+  if (op == SUMPROD) {
+    a.keys = reinterpret_cast<uint64_t *>(static_cast<char *>(ws) + kCtlBytes);
+    a.ssum = static_cast<float *>(saved);
+  }
   if (use_sorted(op, m)) {
     const int d = op == LINREC ? 2 : (op == MAT2 ? 4 : 1);
-    void *sws = static_cast<char *>(ws) + base_ws_bytes(op, batch, m);
+    void *sws = static_cast<char *>(ws) + base_ws_bytes(op, batch, n, m);
     const dim3 gi((unsigned)grid1d(total));
 #define PCAD_RBI_INIT(OPV) \
   case OPV: hipLaunchKernelGGL(k_rbi_init<OPV>, gi, dim3(BLOCK), 0, s, a, total); break;
@@ -515,12 +600,13 @@ hipError_t rbi_fwd_launch(int op, int64_t batch, int64_t n, int64_t m, const int
     return hipGetLastError();
   }
   if (use_part(op, n, m)) {
-    void *region = static_cast<char *>(ws) + base_ws_bytes(op, batch, m);
+    void *region = static_cast<char *>(ws) + base_ws_bytes(op, batch, n, m);
     for (int64_t r = 0; r < batch; ++r) {
       hipError_t e = rbi_part_fwd_row(op, n, m, idx + r * n, v + r * n, hist + r * m,
                                       a.n0 ? a.n0 + r * m : nullptr,
                                       a.ypos ? a.ypos + r * m : nullptr,
-                                      a.argk ? a.argk + r * m : nullptr, region, s);
+                                      a.argk ? a.argk + r * m : nullptr,
+                                      a.ssum ? a.ssum + r * m : nullptr, region, s);
       if (e != hipSuccess) return e;
     }
     return hipGetLastError();
@@ -548,6 +634,16 @@ hipError_t rbi_fwd_launch(int op, int64_t batch, int64_t n, int64_t m, const int
     }                                                                               \
     if (OPV != ADD) hipLaunchKernelGGL(k_rbi_fin<OPV>, gi, dim3(BLOCK), 0, s, a, total); \
     break;
+  if (op == SUMPROD) {
+    // n > 0 beyond the LDS table took the partitioned path above
+    if (n > 0 && !lds) return hipErrorInvalidValue;
+    a.bpr = n > 0 ? (int)sp_blocks_per_row(batch, n, m) : 0;
+    a.chunk = n > 0 ? ((n + a.bpr - 1) / a.bpr + 3) / 4 * 4 : 0;
+    if (n > 0) hipLaunchKernelGGL(k_rbi_lds_sp, dim3((unsigned)a.bpr, (unsigned)batch), dim3(BLOCK),
+                                  shm, s, a);
+    hipLaunchKernelGGL(k_rbi_fold_sp, gi, dim3(BLOCK), 0, s, a, total);
+    return hipGetLastError();
+  }
   switch (op) {
     PCAD_RBI(ADD)
     PCAD_RBI(MUL)
@@ -565,7 +661,7 @@ hipError_t rbi_vjp_launch(int op, int64_t batch, int64_t n, int64_t m, const int
   if (batch == 0 || n == 0) return hipSuccess;
   if (op == LINREC || op == MAT2) {
     const int d = op == LINREC ? 2 : 4;
-    void *sws = static_cast<char *>(ws) + base_ws_bytes(op, batch, m);
+    void *sws = static_cast<char *>(ws) + base_ws_bytes(op, batch, n, m);
     const char *area = static_cast<const char *>(saved) + op_saved_aligned(op, batch, m);
     const size_t ab = rbi_sort_area_bytes(n, m);
     for (int64_t r = 0; r < batch; ++r) {
@@ -578,19 +674,20 @@ hipError_t rbi_vjp_launch(int op, int64_t batch, int64_t n, int64_t m, const int
   RbiVjpArgs a;
   a.idx = idx; a.v = v; a.hbar = hbar; a.vbar = vbar; a.n = n; a.m = m;
   a.accumulate = accumulate ? 1 : 0;
-  a.n0 = nullptr; a.ypos = nullptr; a.argk = nullptr; a.tab = nullptr;
+  a.n0 = nullptr; a.ypos = nullptr; a.argk = nullptr; a.ssum = nullptr; a.tab = nullptr;
   const int64_t total = batch * m;
   if (op == MUL) {
     a.n0 = static_cast<const uint32_t *>(saved);
     a.ypos = reinterpret_cast<const float *>(static_cast<const uint32_t *>(saved) + total);
   }
   if (op == MIN || op == MAX) a.argk = static_cast<const int32_t *>(saved);
+  if (op == SUMPROD) a.ssum = static_cast<const float *>(saved);
   // bins per row up to which a block builds its record table in LDS (16 KB)
   const int64_t lds_max = op == ADD ? 4096 : (op == MUL ? 1024 : 2048);
   const size_t rec = op == ADD ? 4 : (op == MUL ? 16 : 8);
   int src = VJP_GATHER;
   if (m <= lds_max) src = VJP_LDS;
-  else if (op != ADD && ws != nullptr) src = VJP_TABLE;
+  else if (op != ADD && op != SUMPROD && ws != nullptr) src = VJP_TABLE;
   int64_t bx = (n + BLOCK * 4 * 4 - 1) / (BLOCK * 4 * 4);
   // an LDS table is built once per block: fewer, longer blocks
   const int64_t bx_cap = src == VJP_LDS ? 2048 / (batch < 2048 ? batch : 2048) : 65535;
@@ -619,6 +716,10 @@ hipError_t rbi_vjp_launch(int op, int64_t batch, int64_t n, int64_t m, const int
     PCAD_RBI_VJP(MUL)
     PCAD_RBI_VJP(MIN)
     PCAD_RBI_VJP(MAX)
+  case SUMPROD:
+    if (src == VJP_LDS) hipLaunchKernelGGL((k_rbi_vjp<SUMPROD, VJP_LDS>), grid, dim3(BLOCK), shm, s, a);
+    else hipLaunchKernelGGL((k_rbi_vjp<SUMPROD, VJP_GATHER>), grid, dim3(BLOCK), 0, s, a);
+    break;
   default: return hipErrorInvalidValue;
   }
 #undef PCAD_RBI_VJP

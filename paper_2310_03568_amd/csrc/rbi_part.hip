@@ -1,4 +1,5 @@
-// Partitioned reduce-by-index (Section 4) for + * min max when the bins do
+// Partitioned reduce-by-index (Section 4) for + * min max and sumOfProd
+// (Section 3.3, applied to reduce-by-index in Section 4.2) when the bins do
 // not fit one LDS histogram.  The paper's construct handles large
 // histograms with a multi-pass technique: each pass re-reads the input and
 // updates one partition of the bins.  Here the input is partitioned once
@@ -46,7 +47,8 @@ constexpr uint32_t kHi = 0x80000000u;
 // log2 of the bucket width: 64 KB of LDS per bucket
 template <int OP>
 constexpr int part_lw() {
-  return OP == ADD ? 14 : 13;  // + : 16384 floats; * : 8192 (count, product); min/max: 8192 keys
+  return OP == ADD ? 14 : 13;  // + : 16384 floats; * : 8192 (count, product); min/max: 8192 keys;
+                               // sumOfProd: 8192 (p, s) pairs
 }
 
 int part_lw_rt(int op) { return op == ADD ? 14 : 13; }
@@ -68,6 +70,7 @@ struct PartArgs {
   uint32_t *n0;
   float *ypos;
   int32_t *argk;
+  float *ssum;
 };
 
 __device__ __forceinline__ uint64_t tword(uint32_t x) { return ((uint64_t)0xffffffffu << 32) | x; }
@@ -340,6 +343,11 @@ __device__ __forceinline__ void put_bin(const PartArgs &a, int64_t g, float f, u
     a.ypos[g] = f;
     a.hist[g] = cnt > 0u ? 0.0f : f;
   }
+  if (OP == SUMPROD) {
+    const SP r = sp_unpack(key);
+    a.hist[g] = r.p;
+    a.ssum[g] = r.s;
+  }
   if (OP == MIN || OP == MAX) {
     if (key == key_init<OP>()) {
       a.argk[g] = (int32_t)a.n;
@@ -444,6 +452,46 @@ __global__ __launch_bounds__(PH_TH) void k_part_hist(PartArgs a) {
   }
 }
 
+// sumOfProd: the bucket's LDS table of packed (p, s) pairs; every lane of
+// the block takes every round (sp_wave_update works on whole waves)
+__global__ __launch_bounds__(PH_TH) void k_part_hist_sp(PartArgs a) {
+  constexpr int LW = part_lw<SUMPROD>();
+  constexpr int W = 1 << LW;
+  __shared__ uint64_t s_t[W];
+  const uint32_t t = blockIdx.x;
+  if (t >= tval(a.tab, 0)) return;
+  const uint64_t *tb = a.tab + 1;
+  int lo = 0, hi = a.nbk - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (tval(tb, (int64_t)mid * 5 + 2) <= t) lo = mid;
+    else hi = mid - 1;
+  }
+  const int b = lo;
+  const uint32_t start = tval(tb, (int64_t)b * 5), cnt = tval(tb, (int64_t)b * 5 + 1);
+  const uint32_t j = t - tval(tb, (int64_t)b * 5 + 2), q = tval(tb, (int64_t)b * 5 + 3);
+  const uint32_t per = q > 1u ? (cnt + q - 1u) / q : cnt;
+  const int64_t e0 = (int64_t)start + (int64_t)j * per;
+  const int64_t e1 = e0 + per < (int64_t)start + cnt ? e0 + per : (int64_t)start + cnt;
+  for (int i = threadIdx.x; i < W; i += PH_TH) s_t[i] = 0ull;
+  __syncthreads();
+  for (int64_t p = e0 + threadIdx.x; p - threadIdx.x < e1; p += PH_TH) {
+    const bool ok = p < e1;
+    const uint64_t r = ok ? a.rec[p] : 0ull;
+    sp_wave_update(s_t, (uint32_t)(r >> 32) & (uint32_t)(W - 1), __uint_as_float((uint32_t)r), ok);
+  }
+  __syncthreads();
+  const int64_t g0 = (int64_t)b << LW;
+  const int nb = a.m - g0 < W ? (int)(a.m - g0) : W;
+  if (q == 1u) {
+    for (int i = threadIdx.x; i < nb; i += PH_TH) put_bin<SUMPROD>(a, g0 + i, 0.0f, 0u, s_t[i]);
+  } else {
+    const int64_t slot = (int64_t)tval(tb, (int64_t)b * 5 + 4) + j;
+    for (int i = threadIdx.x; i < nb; i += PH_TH)
+      static_cast<uint64_t *>(a.partial)[slot * W + i] = s_t[i];
+  }
+}
+
 // split buckets: fold the partial histograms in item order, then zero them
 template <int OP>
 __global__ __launch_bounds__(PC_TH) void k_part_fold(PartArgs a) {
@@ -459,7 +507,7 @@ __global__ __launch_bounds__(PC_TH) void k_part_fold(PartArgs a) {
     const int64_t s0 = tval(tb, (int64_t)b * 5 + 4);
     float f = OP == MUL ? 1.0f : 0.0f;
     uint32_t c = 0;
-    uint64_t key = key_init<OP>();
+    uint64_t key = OP == SUMPROD ? 0ull : key_init<OP>();
     for (uint32_t j = 0; j < q; ++j) {
       const int64_t e = (s0 + j) * W + i;
       if (OP == ADD) {
@@ -478,6 +526,11 @@ __global__ __launch_bounds__(PC_TH) void k_part_fold(PartArgs a) {
         uint64_t *p = static_cast<uint64_t *>(a.partial);
         const uint64_t k = p[e];
         key = OP == MIN ? (k < key ? k : key) : (k > key ? k : key);
+        p[e] = 0ull;
+      }
+      if (OP == SUMPROD) {
+        uint64_t *p = static_cast<uint64_t *>(a.partial);
+        key = sp_pack(sp_comb(sp_unpack(key), sp_unpack(p[e])));
         p[e] = 0ull;
       }
     }
@@ -519,7 +572,7 @@ PartCfg part_cfg(int op, int64_t n, int64_t m) {
 }  // namespace
 
 bool rbi_part_may(int op, int64_t m) {
-  if (op != ADD && op != MUL && op != MIN && op != MAX) return false;
+  if (op != ADD && op != MUL && op != MIN && op != MAX && op != SUMPROD) return false;
   const int lw = part_lw_rt(op);
   return m > 0 && ((m + ((int64_t)1 << lw) - 1) >> lw) <= PT_NB_MAX;
 }
@@ -531,8 +584,8 @@ size_t rbi_part_ws_bytes(int op, int64_t n, int64_t m) {
 }
 
 hipError_t rbi_part_fwd_row(int op, int64_t n, int64_t m, const int32_t *idx, const float *v,
-                            float *hist, uint32_t *n0, float *ypos, int32_t *argk, void *region,
-                            hipStream_t s) {
+                            float *hist, uint32_t *n0, float *ypos, int32_t *argk, float *ssum,
+                            void *region, hipStream_t s) {
   if (n <= 0 || !rbi_part_may(op, m)) return hipErrorInvalidValue;
   const PartCfg c = part_cfg(op, n, m);
   PartArgs a;
@@ -545,7 +598,7 @@ hipError_t rbi_part_fwd_row(int op, int64_t n, int64_t m, const int32_t *idx, co
   uint32_t *tot = reinterpret_cast<uint32_t *>(w + c.rec_b + c.cnt_b);
   a.tab = reinterpret_cast<uint64_t *>(w + c.rec_b + c.cnt_b + c.tot_b);
   a.partial = w + c.rec_b + c.cnt_b + c.tot_b + c.tab_b;
-  a.hist = hist; a.n0 = n0; a.ypos = ypos; a.argk = argk;
+  a.hist = hist; a.n0 = n0; a.ypos = ypos; a.argk = argk; a.ssum = ssum;
   const int64_t ne = (int64_t)c.nbk * c.nb1 + 1;
   if (!iscan_fits(ne)) return hipErrorInvalidValue;
   const int64_t items_max = c.nbk + (n + c.T - 1) / c.T;
@@ -566,6 +619,11 @@ hipError_t rbi_part_fwd_row(int op, int64_t n, int64_t m, const int32_t *idx, co
     PCAD_PART(MUL)
     PCAD_PART(MIN)
     PCAD_PART(MAX)
+  case SUMPROD:
+    hipLaunchKernelGGL(k_part_scatter<SUMPROD>, dim3(c.nb1), dim3(PT_TH), 0, s, a, c.lw);
+    hipLaunchKernelGGL(k_part_hist_sp, dim3((unsigned)items_max), dim3(PH_TH), 0, s, a);
+    hipLaunchKernelGGL(k_part_fold<SUMPROD>, gf, dim3(PC_TH), 0, s, a);
+    break;
   default: return hipErrorInvalidValue;
   }
 #undef PCAD_PART

@@ -1,9 +1,10 @@
 // reduce (Section 3) and its adjoint.
 //
-// + * min max: a lifted grid reduction.  Each block folds a contiguous chunk
+// + * min max and sumOfProd: a lifted grid reduction.  Each block folds a contiguous chunk
 // of a row into one lifted partial -- the sum; (zero count, product of the
 // non-zeros) for * (Section 3.2 Multiplication); (value, lowest index) for
-// min/max (Section 3.2 Min/Max) -- and a second, stream-ordered launch
+// min/max (Section 3.2 Min/Max); (p, s) for sumOfProd (Section 3.3) --
+// and a second, stream-ordered launch
 // folds each row's partials.  The
 // adjoints are single elementwise passes (broadcast, the three zero cases,
 // the one-hot at k).
@@ -61,6 +62,17 @@ struct Lift<MAX> {
   __device__ static LV elem(float x, uint32_t i) { return {x, i}; }
   __device__ static LV comb(const LV &a, const LV &b) {
     return (b.f > a.f || (b.f == a.f && b.u < a.u)) ? b : a;
+  }
+};
+
+// sumOfProd (Section 3.3): f = p, u = the bits of s
+template <>
+struct Lift<SUMPROD> {
+  __device__ static LV id() { return {0.0f, 0u}; }
+  __device__ static LV elem(float x, uint32_t) { return {0.0f, __float_as_uint(x)}; }
+  __device__ static LV comb(const LV &a, const LV &b) {
+    const SP r = sp_comb(SP{a.f, __uint_as_float(a.u)}, SP{b.f, __uint_as_float(b.u)});
+    return {r.p, __float_as_uint(r.s)};
   }
 };
 
@@ -140,6 +152,9 @@ __global__ __launch_bounds__(BLOCK) void k_reduce_fold(RedArgs a) {
   if (threadIdx.x == 0) {
     if (OP == ADD) {
       a.y[row] = r.f;
+    } else if (OP == SUMPROD) {
+      a.y[row] = r.f;
+      reinterpret_cast<float *>(a.saved)[row] = __uint_as_float(r.u);  // s = sum of the row
     } else if (OP == MUL) {
       a.y[row] = r.u > 0 ? 0.0f : r.f;
       uint32_t *sv = reinterpret_cast<uint32_t *>(a.saved) + row * 2;
@@ -175,6 +190,10 @@ __global__ void k_reduce_empty(int op, int64_t batch, int d, float *y, void *sav
   case MAT2:
     y[4 * r] = 1.0f; y[4 * r + 1] = 0.0f; y[4 * r + 2] = 0.0f; y[4 * r + 3] = 1.0f;
     break;
+  case SUMPROD:
+    y[r] = 0.0f;
+    reinterpret_cast<float *>(saved)[r] = 0.0f;
+    break;
   }
   (void)d;
 }
@@ -194,6 +213,9 @@ __global__ __launch_bounds__(BLOCK) void k_reduce_vjp(const float *x, const void
     ypos = reinterpret_cast<const float *>(saved)[2 * row + 1];
   }
   if (OP == MIN || OP == MAX) k = reinterpret_cast<const int32_t *>(saved)[row];
+  // sumOfProd: d p / d x_i = s - x_i (the invertible-operator rule of
+  // Section 3.3: the rest of the fold is s - x_i)
+  const float ssum = OP == SUMPROD ? reinterpret_cast<const float *>(saved)[row] : 0.0f;
   const float *xr = x + row * n;
   float *xbr = xb + row * n;
   const bool vec_ok = ((row * n) & 3) == 0;
@@ -201,7 +223,7 @@ __global__ __launch_bounds__(BLOCK) void k_reduce_vjp(const float *x, const void
   for (int64_t i = ((int64_t)blockIdx.x * BLOCK + threadIdx.x) * 4; i < n; i += stride) {
     float v[4], o[4];
     const bool full = vec_ok && i + 4 <= n;
-    if (OP == MUL) {
+    if (OP == MUL || OP == SUMPROD) {
       if (full) {
         const float4 t = *reinterpret_cast<const float4 *>(xr + i);
         v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
@@ -215,6 +237,7 @@ __global__ __launch_bounds__(BLOCK) void k_reduce_vjp(const float *x, const void
       if (OP == MUL)
         o[j] = n0 == 0 ? (ypos / v[j]) * yb : ((n0 == 1 && v[j] == 0.0f) ? ypos * yb : 0.0f);
       if (OP == MIN || OP == MAX) o[j] = (i + j == k) ? yb : 0.0f;
+      if (OP == SUMPROD) o[j] = (ssum - v[j]) * yb;
     }
     if (accumulate) {
       for (int j = 0; j < 4; ++j)
@@ -468,6 +491,7 @@ hipError_t reduce_fwd_launch(int op, int64_t batch, int64_t n, const float *x0, 
     PCAD_RED(MUL)
     PCAD_RED(MIN)
     PCAD_RED(MAX)
+    PCAD_RED(SUMPROD)
   default: return hipErrorInvalidValue;
   }
 #undef PCAD_RED
@@ -500,6 +524,7 @@ hipError_t reduce_vjp_launch(int op, int64_t batch, int64_t n, const float *x0, 
   case MUL: hipLaunchKernelGGL(k_reduce_vjp<MUL>, grid, dim3(BLOCK), 0, s, x0, saved, ybar, xb0, n, acc); break;
   case MIN: hipLaunchKernelGGL(k_reduce_vjp<MIN>, grid, dim3(BLOCK), 0, s, x0, saved, ybar, xb0, n, acc); break;
   case MAX: hipLaunchKernelGGL(k_reduce_vjp<MAX>, grid, dim3(BLOCK), 0, s, x0, saved, ybar, xb0, n, acc); break;
+  case SUMPROD: hipLaunchKernelGGL(k_reduce_vjp<SUMPROD>, grid, dim3(BLOCK), 0, s, x0, saved, ybar, xb0, n, acc); break;
   default: return hipErrorInvalidValue;
   }
   (void)x1; (void)xb1;

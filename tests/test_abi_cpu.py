@@ -76,6 +76,23 @@ def test_query(L):
     assert st2 == 0 and s2 == 3 * s
 
 
+def test_sumprod_queries(L):
+    SP = 6
+    # reduce: the row sum s per row is saved
+    assert q(L, 0, SP, 3, 1000)[:2] == (0, 12)
+    # scans of sumOfProd are not offered
+    assert q(L, 1, SP, 1, 1000)[0] == 2  # PCAD_E_UNSUPPORTED
+    # reduce-by-index: s per bin saved, (p, s) pairs in the workspace
+    st, s, w = q(L, 2, SP, 2, 5000, 300)
+    assert st == 0 and s == 2 * 300 * 4 and w >= 256 + 2 * 300 * 8
+    # beyond the LDS table the partition's records are in the workspace
+    st, s, w = q(L, 2, SP, 1, 100_000, 70_000)
+    assert st == 0 and s == 70_000 * 4 and w >= 100_000 * 8
+    assert q(L, 2, SP, 1, 10, (1 << 24) + 1)[0] == 5  # PCAD_E_SIZE
+    assert q(L, 2, SP, 1, 10, 1 << 24)[0] == 0
+    assert q(L, 0, 7, 1, 10)[0] == 1  # no operator 7
+
+
 def test_validation(L):
     P = ctypes.c_void_p
     good = P(1 << 20)        # aligned, never dereferenced: validation fails first

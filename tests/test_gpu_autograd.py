@@ -247,3 +247,29 @@ def test_reduce_by_index_function(ag, op):
             np.testing.assert_array_equal(host(out[1]).astype(np.int64), r["argk"])
     else:
         assert_gate(g, vb[:, 0], cv[:, 0], RTOL[op], what="rbi mul")
+
+
+def test_sumprod_functions(ag):
+    """sumOfProd through the autograd Functions: the gradient of
+    sum_{i<j} a_i a_j is S - a (Section 3.3), and of sum_k w_k hist_k over a
+    reduce-by-index it is (s_k - v_i) w_k (Section 4.2); both against the
+    oracle's reverse sweep."""
+    rng = np.random.default_rng(17)
+    a_np = rng.standard_normal(30_001).astype(np.float32)
+    a = torch.from_numpy(a_np).cuda().requires_grad_(True)
+    y = ag.reduce("sumprod", a)
+    y.backward()
+    o = oracle.sumprod_reduce(a_np)
+    assert_gate([y.item()], [o["y"]], [o["c"]], RTOL["sumprod"], what="sumprod y")
+    xb, cx = oracle.sumprod_reduce_vjp(a_np, 1.0)
+    assert_gate(a.grad.cpu().numpy(), xb, cx, RTOL["sumprod"], what="sumprod grad")
+
+    m = 5000
+    v_np = rng.standard_normal(40_000).astype(np.float32)
+    idx_np = rng.integers(-1, m + 1, 40_000).astype(np.int32)
+    w_np = rng.standard_normal(m).astype(np.float32)
+    v = torch.from_numpy(v_np).cuda().requires_grad_(True)
+    h = ag.reduce_by_index("sumprod", torch.from_numpy(idx_np).cuda(), v, m)
+    (h * torch.from_numpy(w_np).cuda()).sum().backward()
+    vb, cv = oracle.sumprod_rbi_vjp(idx_np, m, w_np, v_np)
+    assert_gate(v.grad.cpu().numpy(), vb, cv, RTOL["sumprod"], what="sumprod rbi grad")

@@ -490,3 +490,80 @@ def test_rbi_ordered(pcad, op, n, m):
 def test_rbi_ordered_batched_and_skewed(pcad, op):
     check_rbi_ordered(pcad, op, 3, 7001, 129, seed=44)
     check_rbi_ordered(pcad, op, 1, 100_000, 1000, seed=45, dist="zipf")
+
+
+# ---------------------------------------------------------------------------
+# sumOfProd (Section 3.3) for reduce and reduce-by-index (Section 4.2,
+# Invertible Operators)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("batch,n", [(1, 0), (1, 1), (1, 2), (1, 1000), (1, 100_003), (3, 70_001),
+                                     (1, 1 << 20)])
+def test_reduce_sumprod(pcad, batch, n):
+    rng = np.random.default_rng(n + 7 * batch)
+    x = rng.standard_normal((batch, n)).astype(np.float32)
+    yb = rng.standard_normal(batch).astype(np.float32)
+    X = dev(x if batch > 1 else x[0])
+    y, saved = pcad.reduce_fwd("sumprod", X)
+    g = pcad.reduce_vjp("sumprod", X, None, saved, dev(yb if batch > 1 else yb[:1]))
+    y = host(y).reshape(batch)
+    g = host(g).reshape(batch, n)
+    s = host(saved)[: 4 * batch].view(np.float32)
+    for r in range(batch):
+        o = oracle.sumprod_reduce(x[r])
+        assert_gate([y[r]], [o["y"]], [o["c"]], RTOL["sumprod"], what=f"sumprod row {r}")
+        assert_gate([s[r]], [o["s"]], [np.abs(x[r].astype(np.float64)).sum()], RTOL["add"],
+                    what="sumprod s")
+        xb, cx = oracle.sumprod_reduce_vjp(x[r], float(yb[r]))
+        assert_gate(g[r], xb, cx, RTOL["sumprod"], what=f"sumprod vjp row {r}")
+    with pytest.raises(pcad.PcadError):
+        pcad.scan_fwd("sumprod", X)
+
+
+@pytest.mark.parametrize("dist", ["uniform", "zipf"])
+@pytest.mark.parametrize("n,m", [(0, 9), (1000, 7), (100_000, 256), (100_000, 4096),
+                                 (100_000, 4097), (300_000, 65536), (200_000, 1 << 20)])
+def test_rbi_sumprod(pcad, n, m, dist):
+    """LDS table of (p, s) pairs up to 4096 bins, the partitioned path
+    beyond; out-of-range keys; skew puts most elements into a few bins."""
+    rng = np.random.default_rng(n + m)
+    v = rng.standard_normal(n).astype(np.float32)
+    if dist == "zipf":
+        from workloads import zipf_keys
+        idx = zipf_keys(rng, n, m) if n else np.zeros(0, np.int32)
+    else:
+        idx = rng.integers(0, m, n).astype(np.int32)
+    if n:
+        k = rng.choice(n, max(n // 97, 1), replace=False)
+        idx[k] = rng.choice([-1, m, m + 5], k.size)
+    hb = rng.standard_normal(m).astype(np.float32)
+    I, V = dev(idx), dev(v)
+    h, saved = pcad.rbi_fwd("sumprod", I, V, m)
+    vb = pcad.rbi_vjp("sumprod", I, V, m, saved, dev(hb))
+    h, vb, s = host(h), host(vb), host(saved)[: 4 * m].view(np.float32)
+    o = oracle.sumprod_rbi_fwd(idx, m, v)
+    assert_gate(h, o["hist"], o["c"], RTOL["sumprod"], what="rbi sumprod hist")
+    cs = np.zeros(m)
+    ok = (idx >= 0) & (idx < m)
+    np.add.at(cs, idx[ok], np.abs(v[ok].astype(np.float64)))
+    assert_gate(s, o["s"], cs, RTOL["add"], what="rbi sumprod s")
+    xb, cx = oracle.sumprod_rbi_vjp(idx, m, hb, v)
+    assert_gate(vb, xb, cx, RTOL["sumprod"], what="rbi sumprod vjp")
+    assert ws_error() == 0
+
+
+def test_rbi_sumprod_batched_and_accumulate(pcad):
+    rng = np.random.default_rng(3)
+    batch, n, m = 3, 50_001, 9000
+    v = rng.standard_normal((batch, n)).astype(np.float32)
+    idx = rng.integers(-1, m + 1, (batch, n)).astype(np.int32)
+    hb = rng.standard_normal((batch, m)).astype(np.float32)
+    I, V = dev(idx), dev(v)
+    h, saved = pcad.rbi_fwd("sumprod", I, V, m)
+    base = dev(np.full((batch, n), 0.5, np.float32))
+    pcad.rbi_vjp("sumprod", I, V, m, saved, dev(hb), out=base, accumulate=True)
+    h, vb = host(h), host(base)
+    for r in range(batch):
+        o = oracle.sumprod_rbi_fwd(idx[r], m, v[r])
+        assert_gate(h[r], o["hist"], o["c"], RTOL["sumprod"], what=f"row {r}")
+        xb, cx = oracle.sumprod_rbi_vjp(idx[r], m, hb[r], v[r])
+        assert_gate(vb[r], xb + 0.5, cx + 0.5, RTOL["sumprod"], what=f"vjp row {r}")
