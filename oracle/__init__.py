@@ -343,3 +343,61 @@ def sumprod_rbi_vjp(idx, m: int, hbar, a):
     extra = np.zeros(ix.shape[0])
     extra[ok] = np.abs(_f64(a).reshape(-1)[ok]) * np.abs(H[ix[ok]])
     return vb[:, 1].copy(), c[:, 1] + extra
+
+
+# -------------------------------------------------------------------------
+# vectorised operators (Sections 3.2, 4.2 and 5.3, Vectorized Operators):
+# elements are vectors of d values combined component-wise (map2 (.)).  A
+# component-wise operator folds, scans or histograms each component on its
+# own, so every function below applies the scalar definition to each column
+# of an (n, d) array; the adjoints are per column as well (the Jacobian of a
+# component-wise program is block-diagonal by component).
+# -------------------------------------------------------------------------
+def _cols(a):
+    a = _f64(a)
+    return a.reshape(a.shape[0], -1) if a.ndim > 1 else a.reshape(-1, 1)
+
+
+def vreduce_fwd(op: str, X):
+    """X (n, d) -> dict(y (d,), c (d,), k (d,) int, n0 (d,) int, ypos (d,))."""
+    X = _cols(X)
+    rs = [reduce_fwd(op, X[:, j]) for j in range(X.shape[1])]
+    return dict(y=np.array([r["y"][0] for r in rs]), c=np.array([r["c"][0] for r in rs]),
+                k=np.array([r["k"] for r in rs], np.int64), n0=np.array([r["n0"] for r in rs], np.int64),
+                ypos=np.array([r["ypos"] for r in rs]))
+
+
+def vreduce_vjp(op: str, ybar, X):
+    X = _cols(X)
+    yb = _f64(ybar).reshape(-1)
+    out = [reduce_vjp(op, yb[j:j + 1], X[:, j]) for j in range(X.shape[1])]
+    return (np.stack([o[0][:, 0] for o in out], 1) if out else np.zeros(X.shape),
+            np.stack([o[1][:, 0] for o in out], 1) if out else np.zeros(X.shape))
+
+
+def vscan_fwd(op: str, X):
+    X = _cols(X)
+    out = [scan_fwd(op, X[:, j]) for j in range(X.shape[1])]
+    return np.stack([o[0][:, 0] for o in out], 1), np.stack([o[1][:, 0] for o in out], 1)
+
+
+def vscan_vjp(op: str, Ybar, X):
+    X = _cols(X)
+    Y = _cols(Ybar)
+    out = [scan_vjp(op, Y[:, j], X[:, j]) for j in range(X.shape[1])]
+    return np.stack([o[0][:, 0] for o in out], 1), np.stack([o[1][:, 0] for o in out], 1)
+
+
+def vrbi_fwd(op: str, idx, m: int, V):
+    """idx (n,), V (n, d) -> dict(hist (m, d), c, argk (m, d), n0 (m, d), ypos (m, d))."""
+    V = _cols(V)
+    rs = [rbi_fwd(op, idx, m, V[:, j]) for j in range(V.shape[1])]
+    return {key: np.stack([(r[key][:, 0] if r[key].ndim > 1 else r[key]) for r in rs], 1)
+            for key in ("hist", "c", "argk", "n0", "ypos", "count")}
+
+
+def vrbi_vjp(op: str, idx, m: int, Hbar, V):
+    V = _cols(V)
+    H = _f64(Hbar).reshape(max(int(m), 0), V.shape[1])
+    out = [rbi_vjp(op, idx, m, H[:, j], V[:, j]) for j in range(V.shape[1])]
+    return np.stack([o[0][:, 0] for o in out], 1), np.stack([o[1][:, 0] for o in out], 1)

@@ -827,3 +827,61 @@ def test_sumprod_operator_is_associative_commutative_invertible():
         acc = _sp_comb(acc, (0.0, t))
     r = oracle.sumprod_reduce(a)
     assert (r["y"], r["s"]) == acc
+
+
+# -------------------------------------------------------------------------
+# vectorised operators (Sections 3.2, 4.2, 5.3 Vectorized Operators)
+# -------------------------------------------------------------------------
+def test_vectorised_forwards_against_numpy_axis0():
+    """Small integers keep float64 exact: column folds, scans and histograms
+    against numpy's axis-0 reductions and scatter-updates."""
+    rng = np.random.default_rng(21)
+    n, d, m = 23, 5, 6
+    X = rng.integers(-4, 5, (n, d)).astype(float)
+    X[X == 0] = 1.0
+    idx = rng.integers(-1, m + 1, n).astype(np.int32)
+    for op, red, acc in (("add", np.sum, np.add.accumulate), ("mul", np.prod, np.multiply.accumulate),
+                         ("min", np.min, np.minimum.accumulate), ("max", np.max, np.maximum.accumulate)):
+        r = oracle.vreduce_fwd(op, X)
+        np.testing.assert_array_equal(r["y"], red(X, axis=0))
+        if op in ("min", "max"):
+            ref = np.argmin(X, axis=0) if op == "min" else np.argmax(X, axis=0)
+            np.testing.assert_array_equal(r["k"], ref)  # numpy returns the first extremum
+        Y, _ = oracle.vscan_fwd(op, X)
+        np.testing.assert_array_equal(Y, acc(X, axis=0))
+        h = oracle.vrbi_fwd(op, idx, m, X)["hist"]
+        ref = np.full((m, d), {"add": 0.0, "mul": 1.0, "min": np.inf, "max": -np.inf}[op])
+        ok = (idx >= 0) & (idx < m)
+        {"add": np.add, "mul": np.multiply, "min": np.minimum, "max": np.maximum}[op].at(ref, idx[ok], X[ok])
+        np.testing.assert_array_equal(h, ref)
+
+
+def test_vectorised_adjoints_are_per_component():
+    """Perturbing one component column leaves the other columns' adjoints
+    unchanged, and central differences of the forward match the adjoint."""
+    rng = np.random.default_rng(22)
+    n, d, m = 17, 4, 5
+    X = rng.uniform(0.5, 1.5, (n, d))
+    yb = rng.standard_normal(d)
+    Yb = rng.standard_normal((n, d))
+    idx = rng.integers(0, m, n).astype(np.int32)
+    Hb = rng.standard_normal((m, d))
+    for op in ("add", "mul"):
+        g, _ = oracle.vreduce_vjp(op, yb, X)
+        gs, _ = oracle.vscan_vjp(op, Yb, X)
+        gr, _ = oracle.vrbi_vjp(op, idx, m, Hb, X)
+        X2 = X.copy()
+        X2[:, 1] *= 1.3
+        np.testing.assert_array_equal(oracle.vreduce_vjp(op, yb, X2)[0][:, 0], g[:, 0])
+        np.testing.assert_array_equal(oracle.vscan_vjp(op, Yb, X2)[0][:, 2], gs[:, 2])
+        np.testing.assert_array_equal(oracle.vrbi_vjp(op, idx, m, Hb, X2)[0][:, 3], gr[:, 3])
+        h = 1e-6
+        for (i, j) in ((0, 0), (5, 2), (16, 3)):
+            E = np.zeros_like(X)
+            E[i, j] = h
+            f = lambda Z: float(oracle.vreduce_fwd(op, Z)["y"] @ yb)
+            assert abs((f(X + E) - f(X - E)) / (2 * h) - g[i, j]) <= 1e-7 * (1 + abs(g[i, j]))
+            fs = lambda Z: float((oracle.vscan_fwd(op, Z)[0] * Yb).sum())
+            assert abs((fs(X + E) - fs(X - E)) / (2 * h) - gs[i, j]) <= 1e-7 * (1 + abs(gs[i, j]))
+            fr = lambda Z: float((oracle.vrbi_fwd(op, idx, m, Z)["hist"] * Hb).sum())
+            assert abs((fr(X + E) - fr(X - E)) / (2 * h) - gr[i, j]) <= 1e-7 * (1 + abs(gr[i, j]))
