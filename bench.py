@@ -15,6 +15,8 @@ Workloads:
   rbi     -- reduce-by-index, n = 2^26 values into --bins bins (uniform or
              Zipf(1.1) keys), operator --op; extras: a sweep over
              m in {256, 65536, 2^22} x both key distributions x + * min max.
+  vec     -- vectorised scan (map2 --op) over 2^20 rows of 64 floats, with
+             vectorised reduce and reduce-by-index timings as extras.
   autograd -- 64 x 2^16 loss forward + backward through torch.autograd.
 
 `value` is backward elements/s: n / (mean duration of the adjoint kernel,
@@ -278,6 +280,91 @@ def rbi_parity(b, np):
     return cpu, par
 
 
+def bench_vec(args, pcad, torch, np):
+    """Vectorised scan (map2 op over vectors of d = 64 floats, n = 2^20 rows,
+    2^26 values; N(0,1), or U[0.5, 2) for *): forward and adjoint through
+    the transposed scalar form (the ISWIM rule)."""
+    n, d = (args.n or (1 << 20)), 64
+    op = args.op
+    g = np.random.default_rng(231003568 + 7)
+    x = g.standard_normal((n, d)).astype(np.float32) if op != "mul" else \
+        g.uniform(0.5, 2.0, (n, d)).astype(np.float32)
+    yb = g.standard_normal((n, d)).astype(np.float32)
+    dev = torch.device("cuda:0")
+    X, YB = torch.from_numpy(x).to(dev), torch.from_numpy(yb).to(dev)
+    xb = torch.empty_like(X)
+    state = {}
+
+    def fwd():
+        y, saved = pcad.vscan_fwd(op, X)
+        state["y"] = y
+        return None, None, saved
+
+    def bwd(saved):
+        pcad.vscan_vjp(op, X, saved, YB, out=xb)
+
+    N = n * d
+    # the scalar scan's algorithmic bytes; the rule's transposes add
+    # 2 x 8 B (forward) and 3 x 8 B (adjoint) per value on top
+    per_bwd = 8 if op == "add" else 12
+    return dict(n=N, fwd=fwd, bwd=bwd, bytes_fwd=8 * N, bytes_bwd=per_bwd * N,
+                kernel="k_scan_vjp<vec>", inputs={"x": x, "ybar": yb, "n": n, "d": d},
+                out=lambda: (state["y"], xb),
+                cfg={"workload": f"vectorised scan ({op} over vectors of {d}), {n} rows, fp32",
+                     "rows": n, "d": d, "op": op, "combinator": "scan (map2)"})
+
+
+def vec_extras(b, torch, np, reps=5):
+    """Vectorised reduce and reduce-by-index (1024 bins) on the same values."""
+    import paper_2310_03568_amd as pcad
+    x = torch.from_numpy(b["inputs"]["x"]).cuda()
+    n, d = b["inputs"]["n"], b["inputs"]["d"]
+    op = b["cfg"]["op"]
+    idx = torch.randint(0, 1024, (n,), device="cuda", dtype=torch.int32,
+                        generator=torch.Generator(device="cuda").manual_seed(5))
+    hb = torch.randn(1024, d, device="cuda")
+    yb = torch.randn(d, device="cuda")
+    out = {}
+    y, sv = pcad.vreduce_fwd(op, x)
+    h, sh = pcad.vrbi_fwd(op, idx, x, 1024)
+    gx = torch.empty_like(x)
+    for name, fn in (("vreduce_fwd", lambda: pcad.vreduce_fwd(op, x)),
+                     ("vreduce_vjp", lambda: pcad.vreduce_vjp(op, x, sv, yb, out=gx)),
+                     ("vrbi_fwd", lambda: pcad.vrbi_fwd(op, idx, x, 1024)),
+                     ("vrbi_vjp", lambda: pcad.vrbi_vjp(op, idx, x, 1024, sh, hb, out=gx))):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        out[name + "_ms"] = e0.elapsed_time(e1) / reps
+    return out
+
+
+def vec_parity(b, np):
+    """Oracle (fp64, one thread) on the whole workload: the vectorised scan
+    and its adjoint, column by column."""
+    import oracle
+    from oracle.gate import RTOL, gate
+    w = b["inputs"]
+    op = b["cfg"]["op"]
+    y, xb = (t.cpu().numpy() for t in b["out"]())
+    t0 = time.perf_counter()
+    Y, CY = oracle.vscan_fwd(op, w["x"])
+    XB, CX = oracle.vscan_vjp(op, w["ybar"], w["x"])
+    dt = time.perf_counter() - t0
+    r1 = gate(y, Y, CY, RTOL[op])
+    r2 = gate(xb, XB, CX, RTOL[op])
+    par = dict(ok=r1["ok"] and r2["ok"], y_max_rel=r1["max_rel"], xbar_max_rel=r2["max_rel"],
+               range_exceeded=r1["n_range_exceeded"] + r2["n_range_exceeded"])
+    cpu = {"value": b["n"] / dt, "unit": "elem/s", "cores": 1, "kind": "oracle",
+           "sample": f"whole workload ({b['n']} values): oracle scan + adjoint per column, fp64, {dt:.2f} s"}
+    return cpu, par
+
+
 def bench_autograd(args, pcad, torch, np):
     """64 sequences of 2^16: loss = sum log|linrec scan| + sum over non-empty
     bins of max-by-index (65536 bins); a step is the loss forward and its
@@ -475,7 +562,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="segmented",
-                    choices=["segmented", "linrec", "mat2", "rbi", "autograd"])
+                    choices=["segmented", "linrec", "mat2", "rbi", "vec", "autograd"])
     ap.add_argument("--op", default="add", choices=["add", "mul", "min", "max", "sumprod"],
                     help="operator of the rbi workload")
     ap.add_argument("--bins", type=int, default=65536, help="bins of the rbi workload")
@@ -503,7 +590,7 @@ def main():
 
     pcad.lib()
     b = {"linrec": bench_linrec, "mat2": bench_mat2, "segmented": bench_segmented,
-         "rbi": bench_rbi, "autograd": bench_autograd}[args.workload](args, pcad, torch, np)
+         "rbi": bench_rbi, "vec": bench_vec, "autograd": bench_autograd}[args.workload](args, pcad, torch, np)
     torch.cuda.synchronize()
 
     for _ in range(args.warmup):
@@ -547,6 +634,8 @@ def main():
         extras = autograd_extras(b, torch, np)
     if args.workload == "rbi" and not args.no_extras:
         extras = rbi_sweep(torch)
+    if args.workload == "vec" and not args.no_extras:
+        extras = vec_extras(b, torch, np)
     cpu, par = (None, None)
     if not args.no_cpu:
         if args.workload == "segmented":
@@ -555,6 +644,8 @@ def main():
             cpu, par = autograd_parity(b, torch, np)
         elif args.workload == "rbi":
             cpu, par = rbi_parity(b, np)
+        elif args.workload == "vec":
+            cpu, par = vec_parity(b, np)
         else:
             cpu, par = cpu_baseline_and_parity(args.workload, b, np)
 

@@ -306,6 +306,51 @@ void pcad_plan_destroy(pcad_plan *plan);
 int pcad_plan_last_hip_error(void);
 
 /*
+ * Vectorised operators (Sections 3.2, 4.2 and 5.3, Vectorized Operators):
+ * reduce, scan and reduce_by_index whose elements are vectors of d floats
+ * combined component-wise (map2 of ADD, MUL, MIN or MAX; other operators
+ * return PCAD_E_UNSUPPORTED).  Layouts, row-major:
+ *   vreduce: x[batch][n][d] -> y[batch][d];
+ *   vscan  : x[batch][n][d] -> y[batch][n][d] (inclusive, along n);
+ *   vrbi   : idx[batch][n], v[batch][n][d] -> hist[batch][m][d], bin k of
+ *            component c folding v[i][c] over the i with idx[i] == k.
+ * Each runs the paper's rewrite of the vectorised form into the scalar one
+ * over the transposed array (the IRWIM, ISWIM and IRBIWIM rules): the
+ * operands are transposed into [d][n] and the scalar batched kernels run
+ * over batch*d rows, row (b, c) holding component c of batch row b.
+ * Saved state and workspace are those of the scalar call with batch*d rows
+ * (its layouts, rows in that order); pcad_vquery reports them and the bytes
+ * of `tmp`.
+ *   tmp: caller-owned device scratch (256-byte aligned, not overlapping ws)
+ *        for the transposed copies; its contents after a call are
+ *        unspecified and it needs no initialisation.
+ *   Adjoints follow the scalar rules per component; PCAD_ACCUMULATE adds
+ *   into xbar / vbar.  Errors as for the scalar calls, plus
+ *   PCAD_E_WORKSPACE / PCAD_E_NULLPTR / PCAD_E_MISALIGNED for `tmp`.
+ */
+int pcad_vquery(int combinator, int op, int64_t batch, int64_t n, int64_t d, int64_t m,
+                unsigned flags, size_t *saved_bytes, size_t *workspace_bytes, size_t *tmp_bytes);
+int pcad_vreduce_fwd(int op, int64_t batch, int64_t n, int64_t d, const float *x, float *y,
+                     void *saved, unsigned flags, void *ws, size_t ws_bytes, void *tmp,
+                     size_t tmp_bytes, void *stream);
+int pcad_vreduce_vjp(int op, int64_t batch, int64_t n, int64_t d, const float *x, const void *saved,
+                     const float *ybar, float *xbar, unsigned flags, void *ws, size_t ws_bytes,
+                     void *tmp, size_t tmp_bytes, void *stream);
+int pcad_vscan_fwd(int op, int64_t batch, int64_t n, int64_t d, const float *x, float *y,
+                   void *saved, unsigned flags, void *ws, size_t ws_bytes, void *tmp,
+                   size_t tmp_bytes, void *stream);
+int pcad_vscan_vjp(int op, int64_t batch, int64_t n, int64_t d, const float *x, const void *saved,
+                   const float *ybar, float *xbar, unsigned flags, void *ws, size_t ws_bytes,
+                   void *tmp, size_t tmp_bytes, void *stream);
+int pcad_vrbi_fwd(int op, int64_t batch, int64_t n, int64_t d, int64_t m, const int32_t *idx,
+                  const float *v, float *hist, void *saved, unsigned flags, void *ws,
+                  size_t ws_bytes, void *tmp, size_t tmp_bytes, void *stream);
+int pcad_vrbi_vjp(int op, int64_t batch, int64_t n, int64_t d, int64_t m, const int32_t *idx,
+                  const float *v, const void *saved, const float *hbar, float *vbar,
+                  unsigned flags, void *ws, size_t ws_bytes, void *tmp, size_t tmp_bytes,
+                  void *stream);
+
+/*
  * Tuning knobs: launch parameters an autotuner may set (the block size of the
  * scan kernels per operator and direction, the bin count up to which
  * reduce-by-index keeps private LDS histograms, elements per histogram

@@ -68,6 +68,13 @@ def lib():
             "pcad_plan_run_per_segment": ([P, I, P], I),
             "pcad_plan_destroy": ([P], None),
             "pcad_plan_last_hip_error": ([], I),
+            "pcad_vquery": ([I, I, I64, I64, I64, I64, U, PSZ, PSZ, PSZ], I),
+            "pcad_vreduce_fwd": ([I, I64, I64, I64, P, P, P, U, P, SZ, P, SZ, P], I),
+            "pcad_vreduce_vjp": ([I, I64, I64, I64, P, P, P, P, U, P, SZ, P, SZ, P], I),
+            "pcad_vscan_fwd": ([I, I64, I64, I64, P, P, P, U, P, SZ, P, SZ, P], I),
+            "pcad_vscan_vjp": ([I, I64, I64, I64, P, P, P, P, U, P, SZ, P, SZ, P], I),
+            "pcad_vrbi_fwd": ([I, I64, I64, I64, I64, P, P, P, P, U, P, SZ, P, SZ, P], I),
+            "pcad_vrbi_vjp": ([I, I64, I64, I64, I64, P, P, P, P, P, U, P, SZ, P, SZ, P], I),
             "pcad_knob_count": ([], I),
             "pcad_knob_name": ([I], ctypes.c_char_p),
             "pcad_knob_get": ([ctypes.c_char_p, ctypes.POINTER(I64)], I),
@@ -331,6 +338,128 @@ def saved_mul(saved: torch.Tensor, batch: int, m: int):
     n0 = saved[: batch * m * 4].view(torch.int32).view(batch, m)
     yp = saved[batch * m * 4: batch * m * 8].view(torch.float32).view(batch, m)
     return n0, yp
+
+
+# ---------------------------------------------------------------------------
+# vectorised operators: elements are vectors of d floats (the last axis),
+# combined component-wise; the library transposes into the scalar form
+# ---------------------------------------------------------------------------
+_tmp = {}
+
+
+def scratch(nbytes: int, device: torch.device, stream=None) -> torch.Tensor:
+    """The `tmp` buffer of the vectorised calls (no initialisation needed),
+    one per (device, stream), grown on demand."""
+    stream = stream if stream is not None else torch.cuda.current_stream(device)
+    key = (device.index, stream.cuda_stream)
+    buf = _tmp.get(key)
+    if buf is None or buf.numel() < nbytes:
+        size = 1 << (max(int(nbytes), 4096) - 1).bit_length()
+        buf = torch.empty(size, dtype=torch.uint8, device=device)
+        _tmp[key] = buf
+    return buf
+
+
+def vquery(comb: int, op: str, batch: int, n: int, d: int, m: int = 0):
+    s, w, t = ctypes.c_size_t(0), ctypes.c_size_t(0), ctypes.c_size_t(0)
+    check(lib().pcad_vquery(comb, OPS[op], batch, n, d, m, 0, ctypes.byref(s), ctypes.byref(w),
+                            ctypes.byref(t)), "pcad_vquery")
+    return s.value, w.value, t.value
+
+
+def _vshape(x: torch.Tensor):
+    """(batch, n, d, lead) of a tensor (..., n, d)."""
+    if x.dim() < 2:
+        raise PcadError("vectorised calls expect values of shape (..., n, d)")
+    lead = tuple(x.shape[:-2])
+    batch = 1
+    for t in lead:
+        batch *= t
+    return batch, x.shape[-2], x.shape[-1], lead
+
+
+def vreduce_fwd(op: str, x: torch.Tensor):
+    """x (..., n, d) -> (y (..., d), saved): reduce with map2 op."""
+    _dev_check(x)
+    batch, n, d, lead = _vshape(x)
+    s_b, w_b, t_b = vquery(REDUCE, op, batch, n, d)
+    dev = x.device
+    y = torch.empty(lead + (d,), dtype=torch.float32, device=dev)
+    saved = torch.empty(max(s_b, 16), dtype=torch.uint8, device=dev)
+    ws, tmp = workspace(w_b, dev), scratch(t_b, dev)
+    check(lib().pcad_vreduce_fwd(OPS[op], batch, n, d, _ptr(x), _ptr(y), _ptr(saved), 0, _ptr(ws),
+                                 ws.numel(), _ptr(tmp), tmp.numel(), _stream(dev)),
+          "pcad_vreduce_fwd")
+    return y, saved
+
+
+def vreduce_vjp(op: str, x, saved, ybar, out=None, accumulate: bool = False):
+    _dev_check(x, ybar)
+    batch, n, d, lead = _vshape(x)
+    s_b, w_b, t_b = vquery(REDUCE, op, batch, n, d)
+    dev = x.device
+    out = torch.empty_like(x) if out is None else out
+    ws, tmp = workspace(w_b, dev), scratch(t_b, dev)
+    check(lib().pcad_vreduce_vjp(OPS[op], batch, n, d, _ptr(x), _ptr(saved), _ptr(ybar.contiguous()),
+                                 _ptr(out), ACCUMULATE if accumulate else 0, _ptr(ws), ws.numel(),
+                                 _ptr(tmp), tmp.numel(), _stream(dev)), "pcad_vreduce_vjp")
+    return out
+
+
+def vscan_fwd(op: str, x: torch.Tensor):
+    """x (..., n, d) -> (y (..., n, d), saved): inclusive scan with map2 op."""
+    _dev_check(x)
+    batch, n, d, lead = _vshape(x)
+    s_b, w_b, t_b = vquery(SCAN, op, batch, n, d)
+    dev = x.device
+    y = torch.empty_like(x)
+    saved = torch.empty(max(s_b, 16), dtype=torch.uint8, device=dev)
+    ws, tmp = workspace(w_b, dev), scratch(t_b, dev)
+    check(lib().pcad_vscan_fwd(OPS[op], batch, n, d, _ptr(x), _ptr(y), _ptr(saved), 0, _ptr(ws),
+                               ws.numel(), _ptr(tmp), tmp.numel(), _stream(dev)), "pcad_vscan_fwd")
+    return y, saved
+
+
+def vscan_vjp(op: str, x, saved, ybar, out=None, accumulate: bool = False):
+    _dev_check(x, ybar)
+    batch, n, d, lead = _vshape(x)
+    s_b, w_b, t_b = vquery(SCAN, op, batch, n, d)
+    dev = x.device
+    out = torch.empty_like(x) if out is None else out
+    ws, tmp = workspace(w_b, dev), scratch(t_b, dev)
+    check(lib().pcad_vscan_vjp(OPS[op], batch, n, d, _ptr(x), _ptr(saved), _ptr(ybar.contiguous()),
+                               _ptr(out), ACCUMULATE if accumulate else 0, _ptr(ws), ws.numel(),
+                               _ptr(tmp), tmp.numel(), _stream(dev)), "pcad_vscan_vjp")
+    return out
+
+
+def vrbi_fwd(op: str, idx: torch.Tensor, v: torch.Tensor, m: int):
+    """idx (..., n), v (..., n, d) -> (hist (..., m, d), saved)."""
+    _dev_check(idx, v)
+    batch, n, d, lead = _vshape(v)
+    s_b, w_b, t_b = vquery(RBI, op, batch, n, d, m)
+    dev = v.device
+    hist = torch.empty(lead + (m, d), dtype=torch.float32, device=dev)
+    saved = torch.empty(max(s_b, 16), dtype=torch.uint8, device=dev)
+    ws, tmp = workspace(w_b, dev), scratch(t_b, dev)
+    check(lib().pcad_vrbi_fwd(OPS[op], batch, n, d, m, _ptr(idx), _ptr(v), _ptr(hist), _ptr(saved),
+                              0, _ptr(ws), ws.numel(), _ptr(tmp), tmp.numel(), _stream(dev)),
+          "pcad_vrbi_fwd")
+    return hist, saved
+
+
+def vrbi_vjp(op: str, idx, v, m: int, saved, hbar, out=None, accumulate: bool = False):
+    _dev_check(idx, v, hbar)
+    batch, n, d, lead = _vshape(v)
+    s_b, w_b, t_b = vquery(RBI, op, batch, n, d, m)
+    dev = v.device
+    out = torch.empty_like(v) if out is None else out
+    ws, tmp = workspace(w_b, dev), scratch(t_b, dev)
+    check(lib().pcad_vrbi_vjp(OPS[op], batch, n, d, m, _ptr(idx), _ptr(v), _ptr(saved),
+                              _ptr(hbar.contiguous()), _ptr(out), ACCUMULATE if accumulate else 0,
+                              _ptr(ws), ws.numel(), _ptr(tmp), tmp.numel(), _stream(dev)),
+          "pcad_vrbi_vjp")
+    return out
 
 
 # ---------------------------------------------------------------------------

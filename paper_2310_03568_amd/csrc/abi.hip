@@ -128,6 +128,35 @@ int check_saved(int comb, int op, int64_t batch, int64_t n, int64_t m, const voi
   return PCAD_OK;
 }
 
+// vectorised calls: + * min max over vectors of d floats; the scalar
+// batched call they run has batch*d rows
+int check_vec(int comb, int op, int64_t batch, int64_t n, int64_t d, int64_t m, unsigned flags) {
+  if (op < PCAD_ADD || op > PCAD_SUMPROD) return PCAD_E_INVALID_ARG;
+  if (op > PCAD_MAX) return PCAD_E_UNSUPPORTED;
+  if (comb < PCAD_REDUCE || comb > PCAD_RBI) return PCAD_E_INVALID_ARG;
+  if (d < 1 || batch < 0 || n < 0 || m < 0) return PCAD_E_INVALID_ARG;
+  if (batch > 0 && d > kMaxTotal / batch) return PCAD_E_SIZE;
+  PCAD_TRY(check_common(op, batch * d, n, flags));
+  if (comb == PCAD_RBI && batch > 0 && m > kMaxTotal / (batch * d)) return PCAD_E_SIZE;
+  return PCAD_OK;
+}
+
+int vquery(int comb, int op, int64_t batch, int64_t n, int64_t d, int64_t m, size_t *saved,
+           size_t *ws, size_t *tmp) {
+  PCAD_TRY(query(comb, op, batch * d, n, m, saved, ws));
+  if (tmp) *tmp = vec_tmp_bytes(comb, batch, n, d, m);
+  return PCAD_OK;
+}
+
+int check_tmp(int comb, int64_t batch, int64_t n, int64_t d, int64_t m, const void *tmp,
+              size_t tmp_bytes) {
+  const size_t need_tmp = vec_tmp_bytes(comb, batch, n, d, m);
+  if (tmp_bytes < need_tmp) return PCAD_E_WORKSPACE;
+  if (need_tmp > 0 && !tmp) return PCAD_E_NULLPTR;
+  if (tmp && ((uintptr_t)tmp & 255u)) return PCAD_E_MISALIGNED;
+  return PCAD_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -292,6 +321,110 @@ int pcad_rbi_vjp(int op, int64_t batch, int64_t n, int64_t m, const int32_t *idx
   }
   return hip_status(rbi_vjp_launch(op, batch, n, m, idx, v, saved, hbar, vbar,
                                    (flags & PCAD_ACCUMULATE) != 0, ws, (hipStream_t)stream));
+}
+
+}  // extern "C"
+
+extern "C" {
+
+int pcad_vquery(int combinator, int op, int64_t batch, int64_t n, int64_t d, int64_t m,
+                unsigned flags, size_t *saved_bytes, size_t *workspace_bytes, size_t *tmp_bytes) {
+  PCAD_TRY(check_vec(combinator, op, batch, n, d, m, flags));
+  return vquery(combinator, op, batch, n, d, m, saved_bytes, workspace_bytes, tmp_bytes);
+}
+
+int pcad_vreduce_fwd(int op, int64_t batch, int64_t n, int64_t d, const float *x, float *y,
+                     void *saved, unsigned flags, void *ws, size_t ws_bytes, void *tmp,
+                     size_t tmp_bytes, void *stream) {
+  PCAD_TRY(check_vec(PCAD_REDUCE, op, batch, n, d, 0, flags));
+  if (batch == 0) return PCAD_OK;
+  if (n > 0) PCAD_TRY(need(x));
+  PCAD_TRY(need(y));
+  PCAD_TRY(check_saved(PCAD_REDUCE, op, batch * d, n, 0, saved));
+  PCAD_TRY(check_ws(PCAD_REDUCE, op, batch * d, n, 0, ws, ws_bytes));
+  PCAD_TRY(check_tmp(PCAD_REDUCE, batch, n, d, 0, tmp, tmp_bytes));
+  return hip_status(vreduce_fwd_launch(op, batch, n, d, x, y, saved, ws, tmp, (hipStream_t)stream));
+}
+
+int pcad_vreduce_vjp(int op, int64_t batch, int64_t n, int64_t d, const float *x, const void *saved,
+                     const float *ybar, float *xbar, unsigned flags, void *ws, size_t ws_bytes,
+                     void *tmp, size_t tmp_bytes, void *stream) {
+  PCAD_TRY(check_vec(PCAD_REDUCE, op, batch, n, d, 0, flags));
+  if (batch == 0 || n == 0) return PCAD_OK;
+  if (op != PCAD_ADD) PCAD_TRY(need(x));
+  PCAD_TRY(need(ybar));
+  PCAD_TRY(need(xbar));
+  PCAD_TRY(check_saved(PCAD_REDUCE, op, batch * d, n, 0, saved));
+  PCAD_TRY(check_ws(PCAD_REDUCE, op, batch * d, n, 0, ws, ws_bytes));
+  PCAD_TRY(check_tmp(PCAD_REDUCE, batch, n, d, 0, tmp, tmp_bytes));
+  return hip_status(vreduce_vjp_launch(op, batch, n, d, x, saved, ybar, xbar,
+                                       (flags & PCAD_ACCUMULATE) != 0, ws, tmp, (hipStream_t)stream));
+}
+
+int pcad_vscan_fwd(int op, int64_t batch, int64_t n, int64_t d, const float *x, float *y,
+                   void *saved, unsigned flags, void *ws, size_t ws_bytes, void *tmp,
+                   size_t tmp_bytes, void *stream) {
+  PCAD_TRY(check_vec(PCAD_SCAN, op, batch, n, d, 0, flags));
+  if (batch == 0 || n == 0) return PCAD_OK;
+  if (scan_tiles(op, batch * d, n) > 2147483647LL) return PCAD_E_SIZE;
+  PCAD_TRY(need(x));
+  PCAD_TRY(need(y));
+  PCAD_TRY(check_saved(PCAD_SCAN, op, batch * d, n, 0, saved));
+  PCAD_TRY(check_ws(PCAD_SCAN, op, batch * d, n, 0, ws, ws_bytes));
+  PCAD_TRY(check_tmp(PCAD_SCAN, batch, n, d, 0, tmp, tmp_bytes));
+  return hip_status(vscan_fwd_launch(op, batch, n, d, x, y, saved, ws, tmp, (hipStream_t)stream));
+}
+
+int pcad_vscan_vjp(int op, int64_t batch, int64_t n, int64_t d, const float *x, const void *saved,
+                   const float *ybar, float *xbar, unsigned flags, void *ws, size_t ws_bytes,
+                   void *tmp, size_t tmp_bytes, void *stream) {
+  PCAD_TRY(check_vec(PCAD_SCAN, op, batch, n, d, 0, flags));
+  if (batch == 0 || n == 0) return PCAD_OK;
+  if (scan_tiles(op, batch * d, n) > 2147483647LL) return PCAD_E_SIZE;
+  PCAD_TRY(need(x));
+  PCAD_TRY(need(ybar));
+  PCAD_TRY(need(xbar));
+  PCAD_TRY(check_saved(PCAD_SCAN, op, batch * d, n, 0, saved));
+  PCAD_TRY(check_ws(PCAD_SCAN, op, batch * d, n, 0, ws, ws_bytes));
+  PCAD_TRY(check_tmp(PCAD_SCAN, batch, n, d, 0, tmp, tmp_bytes));
+  return hip_status(vscan_vjp_launch(op, batch, n, d, x, saved, ybar, xbar,
+                                     (flags & PCAD_ACCUMULATE) != 0, ws, tmp, (hipStream_t)stream));
+}
+
+int pcad_vrbi_fwd(int op, int64_t batch, int64_t n, int64_t d, int64_t m, const int32_t *idx,
+                  const float *v, float *hist, void *saved, unsigned flags, void *ws,
+                  size_t ws_bytes, void *tmp, size_t tmp_bytes, void *stream) {
+  PCAD_TRY(check_vec(PCAD_RBI, op, batch, n, d, m, flags));
+  if (m > kMaxBins) return PCAD_E_SIZE;
+  if (batch == 0 || m == 0) return PCAD_OK;
+  if (n > 0) {
+    PCAD_TRY(need(idx));
+    PCAD_TRY(need(v));
+  }
+  PCAD_TRY(need(hist));
+  PCAD_TRY(check_saved(PCAD_RBI, op, batch * d, n, m, saved));
+  PCAD_TRY(check_ws(PCAD_RBI, op, batch * d, n, m, ws, ws_bytes));
+  PCAD_TRY(check_tmp(PCAD_RBI, batch, n, d, m, tmp, tmp_bytes));
+  return hip_status(vrbi_fwd_launch(op, batch, n, d, m, idx, v, hist, saved, ws, tmp,
+                                    (hipStream_t)stream));
+}
+
+int pcad_vrbi_vjp(int op, int64_t batch, int64_t n, int64_t d, int64_t m, const int32_t *idx,
+                  const float *v, const void *saved, const float *hbar, float *vbar,
+                  unsigned flags, void *ws, size_t ws_bytes, void *tmp, size_t tmp_bytes,
+                  void *stream) {
+  PCAD_TRY(check_vec(PCAD_RBI, op, batch, n, d, m, flags));
+  if (m > kMaxBins) return PCAD_E_SIZE;
+  if (batch == 0 || n == 0) return PCAD_OK;
+  PCAD_TRY(need(idx));
+  if (op == PCAD_MUL) PCAD_TRY(need(v));
+  if (m > 0) PCAD_TRY(need(hbar));
+  PCAD_TRY(need(vbar));
+  PCAD_TRY(check_saved(PCAD_RBI, op, batch * d, n, m, saved));
+  PCAD_TRY(check_ws(PCAD_RBI, op, batch * d, n, m, ws, ws_bytes));
+  PCAD_TRY(check_tmp(PCAD_RBI, batch, n, d, m, tmp, tmp_bytes));
+  return hip_status(vrbi_vjp_launch(op, batch, n, d, m, idx, v, saved, hbar, vbar,
+                                    (flags & PCAD_ACCUMULATE) != 0, ws, tmp, (hipStream_t)stream));
 }
 
 }  // extern "C"

@@ -58,6 +58,29 @@ hipError_t rbi_sorted_vjp_row(int op, int64_t n, int64_t m, const float *v, cons
                               float *vbar, bool accumulate, void *ctl, void *region,
                               const void *area, hipStream_t s);
 
+// vectorised operators (vec.hip): transposes around the batched kernels;
+// comb 0 reduce, 1 scan, 2 reduce-by-index
+hipError_t transpose_launch(const float *in, float *out, int64_t batch, int64_t rows, int64_t cols,
+                            bool accumulate, hipStream_t s);
+size_t vec_tmp_bytes(int comb, int64_t batch, int64_t n, int64_t d, int64_t m);
+hipError_t vreduce_fwd_launch(int op, int64_t batch, int64_t n, int64_t d, const float *x,
+                              float *y, void *saved, void *ws, void *tmp, hipStream_t s);
+hipError_t vreduce_vjp_launch(int op, int64_t batch, int64_t n, int64_t d, const float *x,
+                              const void *saved, const float *ybar, float *xbar, bool accumulate,
+                              void *ws, void *tmp, hipStream_t s);
+hipError_t vscan_fwd_launch(int op, int64_t batch, int64_t n, int64_t d, const float *x, float *y,
+                            void *saved, void *ws, void *tmp, hipStream_t s);
+hipError_t vscan_vjp_launch(int op, int64_t batch, int64_t n, int64_t d, const float *x,
+                            const void *saved, const float *ybar, float *xbar, bool accumulate,
+                            void *ws, void *tmp, hipStream_t s);
+hipError_t vrbi_fwd_launch(int op, int64_t batch, int64_t n, int64_t d, int64_t m,
+                           const int32_t *idx, const float *v, float *hist, void *saved, void *ws,
+                           void *tmp, hipStream_t s);
+hipError_t vrbi_vjp_launch(int op, int64_t batch, int64_t n, int64_t d, int64_t m,
+                           const int32_t *idx, const float *v, const void *saved,
+                           const float *hbar, float *vbar, bool accumulate, void *ws, void *tmp,
+                           hipStream_t s);
+
 // scan
 int scan_tile_size(int op);
 int scan_elem_floats(int op);

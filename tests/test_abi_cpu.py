@@ -131,3 +131,23 @@ def test_validation(L):
     assert L.pcad_scan_vjp(3, 0, 10, None, None, None, None, None, None, None, 0, None, 0, None) == 0
     assert L.pcad_rbi_fwd(0, 1, 10, 0, None, None, None, None, 0, None, 0, None) == 0
     assert L.pcad_reduce_vjp(2, 1, 0, None, None, None, None, None, None, 0, None, 0, None) == 0
+
+
+def test_vectorised_queries(L):
+    def vq(comb, op, batch, n, d, m=0):
+        s, w, t = ctypes.c_size_t(0), ctypes.c_size_t(0), ctypes.c_size_t(0)
+        st = L.pcad_vquery(comb, op, batch, n, d, m, 0, ctypes.byref(s), ctypes.byref(w), ctypes.byref(t))
+        return st, s.value, w.value, t.value
+    # reduce of vectors = the scalar reduce of batch*d rows
+    st, s, w, t = vq(0, 1, 2, 1000, 3)
+    assert st == 0 and s == 2 * 3 * 8 and t >= 2 * 2 * 3 * 1000 * 4
+    assert vq(0, 1, 2, 1000, 3)[1:3] == q(L, 0, 1, 6, 1000)[1:]
+    # scan: xT, yT / y_barT, x_barT
+    st, s, w, t = vq(1, 0, 1, 5000, 4)
+    assert st == 0 and (s, w) == q(L, 1, 0, 4, 5000)[1:] and t >= 3 * 4 * 5000 * 4
+    # reduce-by-index: saved/workspace of batch*d rows, tmp holds hist^T too
+    st, s, w, t = vq(2, 2, 1, 100, 8, 50)
+    assert st == 0 and (s, w) == q(L, 2, 2, 8, 100, 50)[1:] and t >= 3 * 8 * 100 * 4 + 8 * 50 * 4
+    assert vq(0, 4, 1, 10, 2)[0] == 2   # LINREC: unsupported
+    assert vq(0, 0, 1, 10, 0)[0] == 1   # d = 0
+    assert vq(0, 9, 1, 10, 2)[0] == 1   # no operator 9

@@ -567,3 +567,90 @@ def test_rbi_sumprod_batched_and_accumulate(pcad):
         assert_gate(h[r], o["hist"], o["c"], RTOL["sumprod"], what=f"row {r}")
         xb, cx = oracle.sumprod_rbi_vjp(idx[r], m, hb[r], v[r])
         assert_gate(vb[r], xb + 0.5, cx + 0.5, RTOL["sumprod"], what=f"vjp row {r}")
+
+
+# ---------------------------------------------------------------------------
+# vectorised operators (Sections 3.2, 4.2, 5.3, Vectorized Operators)
+# ---------------------------------------------------------------------------
+VEC_SHAPES = [(1, 5000, 1), (1, 20_011, 3), (2, 9001, 16), (1, 3000, 100), (1, 70_000, 64)]
+
+
+def _vec_values(op, shape, rng):
+    x = rng.standard_normal(shape)
+    if op == "mul":
+        x = rng.uniform(0.9, 1.1, shape) * np.sign(x)
+        x.reshape(-1)[rng.choice(x.size, max(x.size // 500, 1), replace=False)] = 0.0
+    if op in ("min", "max"):
+        x = np.round(x * 64) / 64
+    return x.astype(np.float32)
+
+
+def _check_cols(g, r, c, op, what):
+    if op in ("min", "max"):
+        np.testing.assert_array_equal(g, r.astype(np.float32), err_msg=what)
+    else:
+        assert_gate(g, r, c, RTOL[op], max_range_exceeded=g.size if op == "mul" else 0, what=what)
+
+
+@pytest.mark.parametrize("op", SCALAR)
+@pytest.mark.parametrize("batch,n,d", VEC_SHAPES)
+def test_vreduce(pcad, op, batch, n, d):
+    rng = np.random.default_rng(n + d + batch)
+    x = _vec_values(op, (batch, n, d), rng)
+    yb = rng.standard_normal((batch, d)).astype(np.float32)
+    X = dev(x)
+    y, saved = pcad.vreduce_fwd(op, X)
+    g = pcad.vreduce_vjp(op, X, saved, dev(yb))
+    y, g = host(y), host(g)
+    for b in range(batch):
+        o = oracle.vreduce_fwd(op, x[b])
+        _check_cols(y[b], o["y"], o["c"], op, f"vreduce {op}")
+        xb, cx = oracle.vreduce_vjp(op, yb[b], x[b])
+        _check_cols(g[b], xb, cx, op, f"vreduce_vjp {op}")
+
+
+@pytest.mark.parametrize("op", SCALAR)
+@pytest.mark.parametrize("batch,n,d", VEC_SHAPES)
+def test_vscan(pcad, op, batch, n, d):
+    rng = np.random.default_rng(2 * n + d + batch)
+    x = _vec_values(op, (batch, n, d), rng)
+    yb = rng.standard_normal((batch, n, d)).astype(np.float32)
+    X = dev(x)
+    y, saved = pcad.vscan_fwd(op, X)
+    base = dev(np.full((batch, n, d), 0.25, np.float32))
+    pcad.vscan_vjp(op, X, saved, dev(yb), out=base, accumulate=True)
+    y, g = host(y), host(base)
+    for b in range(batch):
+        Y, CY = oracle.vscan_fwd(op, x[b])
+        _check_cols(y[b], Y, CY, op, f"vscan {op}")
+        xb, cx = oracle.vscan_vjp(op, yb[b], x[b])
+        # min/max adjoints of a scan are sums of y_bar (the running extremum
+        # collects them), so every operator goes through the gate here
+        assert_gate(g[b], xb + 0.25, cx + 0.25, RTOL[op], max_range_exceeded=g[b].size if op == "mul" else 0,
+                    what=f"vscan_vjp {op}")
+
+
+@pytest.mark.parametrize("op", SCALAR)
+@pytest.mark.parametrize("batch,n,d,m", [(1, 5000, 1, 7), (1, 20_011, 3, 300), (2, 9001, 16, 1000),
+                                         (1, 40_000, 8, 20_000), (1, 3000, 100, 64)])
+def test_vrbi(pcad, op, batch, n, d, m):
+    rng = np.random.default_rng(n + d + m)
+    v = _vec_values(op, (batch, n, d), rng)
+    idx = rng.integers(-2, m + 2, (batch, n)).astype(np.int32)
+    hb = rng.standard_normal((batch, m, d)).astype(np.float32)
+    I, V = dev(idx), dev(v)
+    h, saved = pcad.vrbi_fwd(op, I, V, m)
+    g = pcad.vrbi_vjp(op, I, V, m, saved, dev(hb))
+    h, g = host(h), host(g)
+    for b in range(batch):
+        o = oracle.vrbi_fwd(op, idx[b], m, v[b])
+        _check_cols(h[b], o["hist"], o["c"], op, f"vrbi {op}")
+        xb, cx = oracle.vrbi_vjp(op, idx[b], m, hb[b], v[b])
+        _check_cols(g[b], xb, cx, op, f"vrbi_vjp {op}")
+    assert ws_error() == 0
+
+
+def test_vectorised_rejects_other_operators(pcad):
+    X = dev(np.ones((10, 4), np.float32))
+    with pytest.raises(pcad.PcadError):
+        pcad.vreduce_fwd("linrec", X)
