@@ -9,14 +9,15 @@
 // digit-major, block-minor order, and a stable scatter in which every block
 // walks its chunk in rounds of one element per thread, ranking each element
 // among the round's equal digits with eight ballots (lanes of a wave whose
-// digit bits all agree) and a per-digit prefix over the block's waves.
+// digit bits all agree) and a per-digit prefix over the block's waves; the
+// chunk is staged in LDS in digit order and written out run by run.
 #include "device.hpp"
 #include "internal.hpp"
 
 namespace pcad {
 
 constexpr int SORT_TH = 256;                // threads per block
-constexpr int SORT_CH = 4096;               // elements per block and pass
+constexpr int SORT_CH = 8192;               // elements per block and pass (staged in LDS)
 constexpr int SORT_D = 256;                 // digit values
 constexpr int SORT_W = SORT_TH / WAVE;
 constexpr int SCAN_TH = 1024, SCAN_PER = 4; // integer scan: entries per block = 4096
@@ -145,17 +146,44 @@ hipError_t iscan_u32(uint32_t *v, int64_t ne, uint32_t *tot, hipStream_t s) {
 }
 
 // stable scatter of (key, perm) by digit; perm_in == nullptr means the
-// identity (first pass)
+// identity (first pass).  The block's chunk is staged in LDS in digit order
+// first (its digit counts follow from the scanned offsets), then written
+// out slot by slot, so each digit's elements leave as one contiguous run
+// instead of single scattered words.
 __global__ __launch_bounds__(SORT_TH) void k_sort_scatter(const int32_t *keys_in,
                                                           const int32_t *perm_in, int64_t n,
                                                           int64_t m, bool first, int shift, int nb,
                                                           const uint32_t *offsets,
                                                           int32_t *keys_out, int32_t *perm_out) {
   __shared__ uint32_t s_base[SORT_D];          // block's first output position per digit
+  __shared__ uint32_t s_rb[SORT_D];            // first stage slot per digit
   __shared__ uint32_t s_cnt[SORT_W][SORT_D];   // this round's count per wave and digit
-  __shared__ uint32_t s_off[SORT_W][SORT_D];   // this round's output offset per wave and digit
+  __shared__ uint32_t s_off[SORT_W][SORT_D];   // this round's offset per wave and digit
+  __shared__ uint32_t s_w[SORT_W];
+  __shared__ int32_t s_k[SORT_CH];
+  __shared__ int32_t s_p[SORT_CH];
   const int tid = threadIdx.x, lane = lane_id(), wave = tid / WAVE;
-  s_base[tid] = offsets[(int64_t)tid * nb + blockIdx.x];
+  const int64_t ne = (int64_t)SORT_D * nb;
+  {
+    // digit tid: the block's output base and count; stage bases by an
+    // exclusive scan of the counts over the digits
+    const int64_t e = (int64_t)tid * nb + blockIdx.x;
+    const uint32_t base = offsets[e];
+    const uint32_t cnt = (e + 1 < ne ? offsets[e + 1] : (uint32_t)n) - base;
+    s_base[tid] = base;
+    uint32_t inc = cnt;
+#pragma unroll
+    for (int dd = 1; dd < WAVE; dd <<= 1) {
+      const uint32_t o = __shfl_up(inc, dd, WAVE);
+      if (lane >= dd) inc += o;
+    }
+    if (lane == WAVE - 1) s_w[wave] = inc;
+    __syncthreads();
+    uint32_t before = 0;
+#pragma unroll
+    for (int w = 0; w < SORT_W; ++w) before += w < wave ? s_w[w] : 0u;
+    s_rb[tid] = before + inc - cnt;
+  }
 #pragma unroll
   for (int w = 0; w < SORT_W; ++w) s_cnt[w][tid] = 0u;
   uint32_t run = 0;  // thread `tid` tracks digit `tid`: elements placed in earlier rounds
@@ -195,10 +223,19 @@ __global__ __launch_bounds__(SORT_TH) void k_sort_scatter(const int32_t *keys_in
     }
     __syncthreads();
     if (valid) {
-      const uint32_t pos = s_base[d] + s_off[wave][d] + rank;
-      keys_out[pos] = k;
-      perm_out[pos] = p;
+      const uint32_t slot = s_rb[d] + s_off[wave][d] + rank;
+      s_k[slot] = k;
+      s_p[slot] = p;
     }
+  }
+  __syncthreads();
+  const int len = (int)(hi - lo);
+  for (int t = tid; t < len; t += SORT_TH) {
+    const int32_t k = s_k[t];
+    const int d = (k >> shift) & (SORT_D - 1);
+    const uint32_t pos = s_base[d] + (uint32_t)t - s_rb[d];
+    keys_out[pos] = k;
+    perm_out[pos] = s_p[t];
   }
 }
 
