@@ -15,7 +15,8 @@ multiplier a and offset b, y_i = a_i*y_{i-1} + b_i), ``mat2`` (row-major
 2x2 matrix product, Section 5.1 operator figure) and ``sumprod`` (the
 invertible operator sumOfProd of Section 3.3 on lifted pairs (p, s); the
 ``sumprod_*`` functions below take the scalar inputs, lift each a to (0, a)
-and return the p component, as that section composes them).
+and return the p component, as that section composes them) and ``satadd``
+(saturated addition at 1e6, the evaluation's operator figure).
 """
 from __future__ import annotations
 
@@ -29,8 +30,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-OPS = {"add": 0, "mul": 1, "min": 2, "max": 3, "linrec": 4, "mat2": 5, "sumprod": 6}
-DIM = {"add": 1, "mul": 1, "min": 1, "max": 1, "linrec": 2, "mat2": 4, "sumprod": 2}
+OPS = {"add": 0, "mul": 1, "min": 2, "max": 3, "linrec": 4, "mat2": 5, "sumprod": 6, "satadd": 7}
+DIM = {"add": 1, "mul": 1, "min": 1, "max": 1, "linrec": 2, "mat2": 4, "sumprod": 2, "satadd": 1}
+SAT_CAP = 1e6
 
 
 def build(force: bool = True) -> str:

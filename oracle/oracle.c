@@ -21,6 +21,15 @@
  *                        [[a,b],[c,d]]; the operator is the matrix product
  *                        P (.) M = P x M (Section 5.1, operator figure),
  *                        neutral I.
+ *   SATADD             : d = 1, saturated addition (the evaluation's operator
+ *                        figure): acc (.) x = C if acc + x > C, else acc + x,
+ *                        with C = 1e6 and neutral 0; its partials are 0 where
+ *                        the sum saturates and 1 elsewhere.  Associative and
+ *                        commutative on values in [0, C]; the derivative of a
+ *                        fold depends on the bracketing where a bracket lands
+ *                        exactly on C (a kink: a zero prefix meeting a
+ *                        saturated suffix, or a partial sum equal to C), and
+ *                        this oracle takes the sequential loop's.
  *   SUMPROD            : d = 2, the lifted pair (p, s) of the invertible
  *                        operator sumOfProd (Section 3.3):
  *                        (p1,s1) (.) (p2,s2) = (p1 + p2 + s1*s2, s1 + s2),
@@ -62,11 +71,14 @@
 #include <stdlib.h>
 #include <string.h>
 
-enum { OP_ADD = 0, OP_MUL = 1, OP_MIN = 2, OP_MAX = 3, OP_LINREC = 4, OP_MAT2 = 5, OP_SUMPROD = 6 };
+enum { OP_ADD = 0, OP_MUL = 1, OP_MIN = 2, OP_MAX = 3, OP_LINREC = 4, OP_MAT2 = 5, OP_SUMPROD = 6,
+       OP_SATADD = 7 };
+
+static const double SAT_CAP = 1e6;
 
 int orc_dim(int op) { return (op == OP_LINREC || op == OP_SUMPROD) ? 2 : (op == OP_MAT2 ? 4 : 1); }
 
-static int valid_op(int op) { return op >= OP_ADD && op <= OP_SUMPROD; }
+static int valid_op(int op) { return op >= OP_ADD && op <= OP_SATADD; }
 
 /* neutral element e of the operator */
 static void neutral(int op, double *e) {
@@ -78,6 +90,7 @@ static void neutral(int op, double *e) {
   case OP_LINREC: e[0] = 1.0; e[1] = 0.0; break;
   case OP_MAT2: e[0] = 1.0; e[1] = 0.0; e[2] = 0.0; e[3] = 1.0; break;
   case OP_SUMPROD: e[0] = 0.0; e[1] = 0.0; break;
+  case OP_SATADD: e[0] = 0.0; break;
   }
 }
 
@@ -94,6 +107,7 @@ static void combine(int op, const double *acc, const double *x, double *out) {
     t[1] = x[0] * acc[1] + x[1];
     out[0] = t[0]; out[1] = t[1];
     break;
+  case OP_SATADD: out[0] = (acc[0] + x[0] > SAT_CAP) ? SAT_CAP : acc[0] + x[0]; break;
   case OP_SUMPROD:
     t[0] = acc[0] + x[0] + acc[1] * x[1];
     t[1] = acc[1] + x[1];
@@ -117,6 +131,7 @@ static void combine_abs(int op, const double *cacc, const double *cx,
   case OP_MIN: out[0] = (acc[0] <= x[0]) ? cacc[0] : cx[0]; break;
   case OP_MAX: out[0] = (acc[0] >= x[0]) ? cacc[0] : cx[0]; break;
   case OP_MAT2: out[0] = out[1] = out[2] = out[3] = cacc[0] * cx[0]; break;
+  case OP_SATADD: out[0] = (acc[0] + x[0] > SAT_CAP) ? SAT_CAP : cacc[0] + cx[0]; break;
   default: combine(op, cacc, cx, out); break;
   }
 }
@@ -145,6 +160,10 @@ static void partials(int op, const double *acc, const double *x, double *JA, dou
     JA[2] = 0.0;  JA[3] = x[0];
     JX[0] = acc[0]; JX[1] = 0.0;
     JX[2] = acc[1]; JX[3] = 1.0;
+    break;
+  case OP_SATADD:
+    /* the saturated branch is a constant */
+    JA[0] = JX[0] = (acc[0] + x[0] > SAT_CAP) ? 0.0 : 1.0;
     break;
   case OP_SUMPROD:
     /* out0 = P + p + S*s, out1 = S + s with acc = (P,S), x = (p,s) */
@@ -177,7 +196,7 @@ static void partials(int op, const double *acc, const double *x, double *JA, dou
  * computed prefixes).  For min/max the 0/1 decision of the real run is used. */
 static void partials_abs(int op, const double *acc, const double *x, const double *cacc,
                          const double *ax, double *JA, double *JX) {
-  if (op == OP_MIN || op == OP_MAX) partials(op, acc, x, JA, JX);
+  if (op == OP_MIN || op == OP_MAX || op == OP_SATADD) partials(op, acc, x, JA, JX);
   else partials(op, cacc, ax, JA, JX);
 }
 

@@ -885,3 +885,92 @@ def test_vectorised_adjoints_are_per_component():
             assert abs((fs(X + E) - fs(X - E)) / (2 * h) - gs[i, j]) <= 1e-7 * (1 + abs(gs[i, j]))
             fr = lambda Z: float((oracle.vrbi_fwd(op, idx, m, Z)["hist"] * Hb).sum())
             assert abs((fr(X + E) - fr(X - E)) / (2 * h) - gr[i, j]) <= 1e-7 * (1 + abs(gr[i, j]))
+
+
+# -------------------------------------------------------------------------
+# saturated addition (the evaluation's operator figure, Section 6.1)
+# -------------------------------------------------------------------------
+CAP = 1e6
+
+
+def _sat_loop_with_jacobian(x):
+    """Sequential saturated sums and their Jacobian by forward-mode
+    derivative vectors, written from the operator's definition alone."""
+    n = len(x)
+    ys, J = [], np.zeros((n, n))
+    acc, dacc = 0.0, np.zeros(n)
+    for i, v in enumerate(x):
+        e = np.zeros(n)
+        e[i] = 1.0
+        if i == 0:
+            acc, dacc = v, e
+        elif acc + v > CAP:
+            acc, dacc = CAP, np.zeros(n)
+        else:
+            acc, dacc = acc + v, dacc + e
+        ys.append(acc)
+        J[i] = dacc
+    return np.array(ys), J
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_satadd_scan_and_reduce_against_brute_force(seed):
+    rng = np.random.default_rng(300 + seed)
+    n = int(rng.integers(1, 30))
+    x = rng.integers(0, 4, n).astype(float) * rng.choice([1.0, 1e5, 3e5], n)
+    yb = rng.standard_normal(n)
+    Y, J = _sat_loop_with_jacobian(x)
+    rs, c = oracle.scan_fwd("satadd", x)
+    np.testing.assert_array_equal(rs[:, 0], Y)
+    assert np.all(c[:, 0] >= np.abs(Y))
+    xb, _ = oracle.scan_vjp("satadd", yb, x)
+    np.testing.assert_allclose(xb[:, 0], J.T @ yb, rtol=1e-12, atol=1e-12)
+    r = oracle.reduce_fwd("satadd", x)
+    assert r["y"][0] == Y[-1]
+    g, _ = oracle.reduce_vjp("satadd", np.array([1.5]), x)
+    np.testing.assert_allclose(g[:, 0], 1.5 * J[-1], rtol=1e-12, atol=1e-12)
+
+
+def test_satadd_reduce_general_rule():
+    """The general reduce rule (Section 3.1): x_bar_i = d(l_i (.) x_i (.) r_i)/d x_i
+    y_bar with exclusive prefix l_i and suffix r_i.  For non-negative values
+    the operator is associative, but its derivative depends on the
+    bracketing where a bracket lands exactly on the cap (a kink: a zero
+    prefix meeting a saturated suffix, or a partial sum equal to 1e6).  The
+    values here are positive multiples of 3e5, whose sums never equal 1e6,
+    and then the rule equals the reverse sweep."""
+    rng = np.random.default_rng(9)
+    for _ in range(20):
+        n = int(rng.integers(2, 25))
+        x = rng.integers(1, 4, n).astype(float) * 3e5
+        sat = lambda a, b: CAP if a + b > CAP else a + b
+        g, _ = oracle.reduce_vjp("satadd", np.array([1.0]), x)
+        for i in range(n):
+            l = 0.0
+            for t in x[:i]:
+                l = sat(l, t)
+            r = 0.0
+            for t in x[i + 1:][::-1]:
+                r = sat(t, r)
+            lx = sat(l, x[i])
+            d = (0.0 if l + x[i] > CAP else 1.0) * (0.0 if lx + r > CAP else 1.0)
+            assert g[i, 0] == d, (x, i)
+
+
+def test_satadd_rbi_against_per_bin_loops():
+    rng = np.random.default_rng(10)
+    n, m = 80, 5
+    v = rng.integers(0, 4, n).astype(float) * 2e5
+    idx = rng.integers(-1, m + 1, n).astype(np.int32)
+    hb = rng.standard_normal(m)
+    r = oracle.rbi_fwd("satadd", idx, m, v)
+    vb, _ = oracle.rbi_vjp("satadd", idx, m, hb, v)
+    for k in range(m):
+        sel = np.flatnonzero(idx == k)
+        if sel.size == 0:
+            assert r["hist"][k, 0] == 0.0
+            continue
+        Y, J = _sat_loop_with_jacobian(v[sel])
+        assert r["hist"][k, 0] == Y[-1]
+        np.testing.assert_allclose(vb[sel, 0], hb[k] * J[-1], rtol=1e-12, atol=1e-12)
+    assert np.all(vb[(idx < 0) | (idx >= m), 0] == 0.0)
