@@ -86,7 +86,8 @@ typedef enum {
   PCAD_MAX = 3,
   PCAD_LINREC = 4, /* linear-function composition (a multiplier, b offset) */
   PCAD_MAT2 = 5,   /* 2x2 matrix product, row-major */
-  PCAD_SUMPROD = 6 /* sumOfProd (Section 3.3): reduce and reduce_by_index only */
+  PCAD_SUMPROD = 6, /* sumOfProd (Section 3.3): reduce and reduce_by_index only */
+  PCAD_SATADD = 7   /* saturated addition at 1e6 (the evaluation's operator figure) */
 } pcad_op;
 
 enum {
@@ -119,7 +120,8 @@ int pcad_query(int combinator, int op, int64_t batch, int64_t n, int64_t m, unsi
  *             of the non-zero elements (Section 3.2 Multiplication);
  *     MIN/MAX: {int32 k} -- lowest index attaining the extremum, n if empty
  *             (Section 3.2 Min/Max);
- *     LINREC/MAT2: the exclusive prefix of every tile of the row (opaque);
+ *     LINREC/MAT2/SATADD: the exclusive prefix of every tile of the row
+ *             (opaque);
  *     SUMPROD: {float s} -- the sum of the row.
  * SUMPROD is the invertible operator of Section 3.3: elements a enter as
  * pairs (0, a), pairs combine as (p1,s1) (.) (p2,s2) = (p1+p2+s1*s2, s1+s2),
@@ -136,7 +138,8 @@ int pcad_reduce_fwd(int op, int64_t batch, int64_t n, const float *x0, const flo
  * Addition); MUL uses the three zero cases (Section 3.2 Multiplication);
  * MIN/MAX write y_bar at index k only (Section 3.2 Min/Max); LINREC/MAT2 use
  * the general rule x_bar_i = d(l_i (.) x_i (.) r_i)/dx_i^T y_bar (Eq. 2) with
- * l_i, r_i the exclusive prefix and suffix (Section 3.1); SUMPROD uses the
+ * l_i, r_i the exclusive prefix and suffix (Section 3.1), which SATADD uses
+ * too (its partials are 0 on a saturated step); SUMPROD uses the
  * invertible-operator rule of Section 3.3: the rest of the fold is
  * (p, s) inverted by (0, x_i), whose s is s - x_i, so x_bar_i =
  * (s - x_i) * y_bar (x0 required).  Scans of SUMPROD return
@@ -166,6 +169,7 @@ int pcad_scan_fwd(int op, int64_t batch, int64_t n, const float *x0, const float
  * lam_i = ybar_i + J_i^T lam_{i+1}, J_i = d(rs_i (.) x_{i+1})/d rs_i, solved
  * by a right-to-left decoupled look-back scan of adjoint affine maps, fused
  * with x_bar_i = d(rs_{i-1} (.) x_i)/d x_i^T lam_i (x_bar_0 = lam_0).
+ * SATADD: both partials are [rs_{i-1} + x_i <= 1e6] (0 on a saturated step).
  * Forward prefixes are recomputed inside each tile from `saved`.
  *   ybar0: adjoint of y0 (x-layout; MAT2 4 floats per element).
  *   ybar1: LINREC only, optional adjoint of A (NULL = zero).
@@ -209,9 +213,9 @@ int pcad_scan_vjp_checkpoint(int op, int64_t batch, int64_t n, const float *x0, 
  *     16384 bins for ADD, 8192 otherwise, at most 2048 ranges), or, past
  *     that or when knob rbi.partition is 0, an LDS hash table of the bins a
  *     block meets with global atomics for the rest;
- *   - for LINREC/MAT2 (and, by knob, large bin counts of the others) a
- *     stable sort by bin followed by a segmented scan of each run (the rule
- *     figure's sort).
+ *   - for LINREC/MAT2/SATADD (and, by knob, large bin counts of + * min
+ *     max) a stable sort by bin followed by a segmented scan of each run
+ *     (the rule figure's sort); their adjoints are the general rule.
  *   v: n floats per row; LINREC: n pairs (a, b) interleaved; MAT2: n
  *      row-major 2x2 matrices (4 floats).  hist: m entries of the same
  *      width per row.

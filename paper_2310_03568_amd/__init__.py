@@ -24,10 +24,10 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpcad.so")
 
-OPS = {"add": 0, "mul": 1, "min": 2, "max": 3, "linrec": 4, "mat2": 5, "sumprod": 6}
+OPS = {"add": 0, "mul": 1, "min": 2, "max": 3, "linrec": 4, "mat2": 5, "sumprod": 6, "satadd": 7}
 # floats per element of the values and of the results (sumprod: scalar values,
 # scalar results -- the p of the lifted pair)
-DIM = {"add": 1, "mul": 1, "min": 1, "max": 1, "linrec": 2, "mat2": 4, "sumprod": 1}
+DIM = {"add": 1, "mul": 1, "min": 1, "max": 1, "linrec": 2, "mat2": 4, "sumprod": 1, "satadd": 1}
 REDUCE, SCAN, RBI = 0, 1, 2
 ACCUMULATE = 1
 

@@ -33,7 +33,7 @@ constexpr unsigned kKnownFlags = PCAD_ACCUMULATE;
 bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 
 int check_common(int op, int64_t batch, int64_t n, unsigned flags) {
-  if (op < PCAD_ADD || op > PCAD_SUMPROD) return PCAD_E_INVALID_ARG;
+  if (op < PCAD_ADD || op > PCAD_SATADD) return PCAD_E_INVALID_ARG;
   if (flags & ~kKnownFlags) return PCAD_E_INVALID_ARG;
   if (batch < 0 || n < 0) return PCAD_E_INVALID_ARG;
   if (n > kMaxN) return PCAD_E_SIZE;
@@ -131,7 +131,7 @@ int check_saved(int comb, int op, int64_t batch, int64_t n, int64_t m, const voi
 // vectorised calls: + * min max over vectors of d floats; the scalar
 // batched call they run has batch*d rows
 int check_vec(int comb, int op, int64_t batch, int64_t n, int64_t d, int64_t m, unsigned flags) {
-  if (op < PCAD_ADD || op > PCAD_SUMPROD) return PCAD_E_INVALID_ARG;
+  if (op < PCAD_ADD || op > PCAD_SATADD) return PCAD_E_INVALID_ARG;
   if (op > PCAD_MAX) return PCAD_E_UNSUPPORTED;
   if (comb < PCAD_REDUCE || comb > PCAD_RBI) return PCAD_E_INVALID_ARG;
   if (d < 1 || batch < 0 || n < 0 || m < 0) return PCAD_E_INVALID_ARG;
@@ -307,7 +307,9 @@ int pcad_rbi_vjp(int op, int64_t batch, int64_t n, int64_t m, const int32_t *idx
   if (m > (op == PCAD_SUMPROD ? kMaxBinsSumProd : kMaxBins)) return PCAD_E_SIZE;
   if (batch == 0 || n == 0) return PCAD_OK;
   PCAD_TRY(need(idx));
-  const bool ordered = op == PCAD_LINREC || op == PCAD_MAT2;
+  // the general rule (ordered operators, saturated addition) reads the values
+  // and the sort's status words in the workspace
+  const bool ordered = op == PCAD_LINREC || op == PCAD_MAT2 || op == PCAD_SATADD;
   if (op == PCAD_MUL || op == PCAD_SUMPROD || ordered) PCAD_TRY(need(v));
   if (m > 0) PCAD_TRY(need(hbar));
   PCAD_TRY(need(vbar));

@@ -186,6 +186,31 @@ struct Adj<MIN, ABAR> : AdjMinMax<MIN, ABAR> {};
 template <bool ABAR>
 struct Adj<MAX, ABAR> : AdjMinMax<MAX, ABAR> {};
 
+// saturated addition: both partials of rs_{i-1} (.) x_i are [rs_{i-1} + x_i
+// <= cap] (0 on a saturated step), the same sum and test the forward made;
+// the row's first element takes its own adjoint
+template <bool ABAR>
+struct Adj<SATADD, ABAR> {
+  using M = MapScal;
+  using FT = Fwd<SATADD>::T;
+  static constexpr bool NEEDS_PREFIX = true;
+  static constexpr int NY = 1, NXB = 1;
+  __device__ static bool pass(const FT &p, const FT &x, bool first) {
+    return first || !(p.f[0] + x.f[0] > kSatCap);
+  }
+  __device__ static M::T make(const FT &p, const FT &x, const float *yb, bool first) {
+    const bool k = !first && pass(p, x, false);
+    return {{k ? yb[0] : 0.0f, k ? 1.0f : 0.0f}};
+  }
+  __device__ static void step(const FT &p, const FT &x, const float *yb, bool first, M::P &rho,
+                              float *xb) {
+    const float lam = yb[0] + rho.f[0];
+    const bool k = pass(p, x, first);
+    xb[0] = k ? lam : 0.0f;
+    rho.f[0] = (!first && k) ? lam : 0.0f;
+  }
+};
+
 // linear recurrence, element x = (a, b), prefix p = (A_{i-1}, y_{i-1});
 // adjoint inputs (ybar_i[, Abar_i]); outputs (a_bar_i, b_bar_i):
 //   b_bar = lam_y,  a_bar = lam_y*y_{i-1} + lam_A*A_{i-1},  rho = a*lam

@@ -15,7 +15,11 @@ constexpr int WAVES = BLOCK / WAVE;
 
 // operator ids (same values as the public enum).  SUMPROD (Section 3.3's
 // invertible operator sumOfProd) exists for reduce and reduce-by-index only.
-enum { ADD = 0, MUL = 1, MIN = 2, MAX = 3, LINREC = 4, MAT2 = 5, SUMPROD = 6 };
+// SATADD is the saturated addition of the evaluation's operator figure.
+enum { ADD = 0, MUL = 1, MIN = 2, MAX = 3, LINREC = 4, MAT2 = 5, SUMPROD = 6, SATADD = 7 };
+
+// the saturation level of SATADD
+constexpr float kSatCap = 1000000.0f;
 
 template <int N>
 struct Vec {
@@ -193,6 +197,19 @@ struct Fwd<MAX> {
   __device__ static T comb(const T &a, const T &b) { return {{b.f[0] > a.f[0] ? b.f[0] : a.f[0]}}; }
 };
 
+// saturated addition: the sum, or the cap when the sum exceeds it
+// (associative and commutative on values in [0, cap])
+template <>
+struct Fwd<SATADD> {
+  static constexpr int N = 1;
+  using T = Vec<1>;
+  __device__ static T id() { return {{0.0f}}; }
+  __device__ static T comb(const T &a, const T &b) {
+    const float t = a.f[0] + b.f[0];
+    return {{t > kSatCap ? kSatCap : t}};
+  }
+};
+
 // linear-function composition, element (A = multiplier, B = offset):
 // (A1,B1) then (A2,B2) = (A1*A2, A2*B1 + B2)
 template <>
@@ -355,6 +372,8 @@ template <>
 struct IO<MIN> : IOScalar<MIN> {};
 template <>
 struct IO<MAX> : IOScalar<MAX> {};
+template <>
+struct IO<SATADD> : IOScalar<SATADD> {};
 
 template <>
 struct IO<LINREC> {

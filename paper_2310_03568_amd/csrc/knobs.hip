@@ -59,7 +59,10 @@ Knob *find(const char *name) {
 
 }  // namespace
 
-int knob_scan_threads(int op, int dir) { return (int)g_knobs[(dir ? 6 : 0) + op].value; }
+// saturated addition has the shape of + and shares its block sizes
+int knob_scan_threads(int op, int dir) {
+  return (int)g_knobs[(dir ? 6 : 0) + (op == PCAD_SATADD ? PCAD_ADD : op)].value;
+}
 int64_t knob_rbi_lds_max_bins(bool u64) { return g_knobs[u64 ? kRbiU64 : kRbiF32].value; }
 int64_t knob_rbi_elems_per_block() { return g_knobs[kRbiEpb].value; }
 int64_t knob_rbi_sort_min_bins() { return g_knobs[kRbiSort].value; }

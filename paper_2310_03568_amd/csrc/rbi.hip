@@ -73,6 +73,7 @@ __global__ __launch_bounds__(BLOCK) void k_rbi_init(RbiArgs a, int64_t total) {
     if (OP == MUL) { a.n0[k] = 0u; a.ypos[k] = 1.0f; }
     if (OP == MIN || OP == MAX) a.keys[k] = key_init<OP>();
     if (OP == LINREC) { a.hist[2 * k] = 1.0f; a.hist[2 * k + 1] = 0.0f; }
+    if (OP == SATADD) a.hist[k] = 0.0f;
     if (OP == MAT2) {
       a.hist[4 * k] = 1.0f; a.hist[4 * k + 1] = 0.0f;
       a.hist[4 * k + 2] = 0.0f; a.hist[4 * k + 3] = 1.0f;
@@ -471,21 +472,25 @@ static size_t op_saved_bytes(int op, int64_t batch, int64_t m) {
 // the sort-based path: always for the ordered operators; for the others
 // beyond the LDS capacity (a fixed bound, so the workspace size does not
 // depend on the knobs), from the knob's bin count on
+// (the general rule: the ordered operators and saturated addition, which has
+// no specialised rule)
+static bool general_rule(int op) { return op == LINREC || op == MAT2 || op == SATADD; }
+
 static bool sorted_may(int op, int64_t m) {
   if (op == SUMPROD) return false;
-  if (op == LINREC || op == MAT2) return true;
+  if (general_rule(op)) return true;
   return m > ((op == MIN || op == MAX) ? kLdsBinsU64 : kLdsBinsF32);
 }
 
 static bool use_sorted(int op, int64_t m) {
-  if (op == LINREC || op == MAT2) return true;
+  if (general_rule(op)) return true;
   return sorted_may(op, m) && m >= knob_rbi_sort_min_bins();
 }
 
 // the partitioned path: the commutative operators beyond the LDS capacity
 // (a fixed bound, like sorted_may), unless the knob picks the hash table
 static bool part_may(int op, int64_t m) {
-  if (op == LINREC || op == MAT2) return false;
+  if (general_rule(op)) return false;
   const bool u64 = op == MIN || op == MAX || op == SUMPROD;
   return m > (u64 ? kLdsBinsU64 : kLdsBinsF32) && rbi_part_may(op, m);
 }
@@ -579,6 +584,7 @@ hipError_t rbi_fwd_launch(int op, int64_t batch, int64_t n, int64_t m, const int
       PCAD_RBI_INIT(MAX)
       PCAD_RBI_INIT(LINREC)
       PCAD_RBI_INIT(MAT2)
+      PCAD_RBI_INIT(SATADD)
     default: return hipErrorInvalidValue;
     }
 #undef PCAD_RBI_INIT
@@ -659,8 +665,8 @@ hipError_t rbi_vjp_launch(int op, int64_t batch, int64_t n, int64_t m, const int
                           const float *v, const void *saved, const float *hbar, float *vbar,
                           bool accumulate, void *ws, hipStream_t s) {
   if (batch == 0 || n == 0) return hipSuccess;
-  if (op == LINREC || op == MAT2) {
-    const int d = op == LINREC ? 2 : 4;
+  if (general_rule(op)) {
+    const int d = op == LINREC ? 2 : (op == MAT2 ? 4 : 1);
     void *sws = static_cast<char *>(ws) + base_ws_bytes(op, batch, n, m);
     const char *area = static_cast<const char *>(saved) + op_saved_aligned(op, batch, m);
     const size_t ab = rbi_sort_area_bytes(n, m);

@@ -81,6 +81,18 @@ struct RsBase<MIN> : RsMinMax<MIN> {};
 template <>
 struct RsBase<MAX> : RsMinMax<MAX> {};
 
+// saturated addition (the evaluation's operator figure)
+template <>
+struct RsBase<SATADD> {
+  static constexpr int N = 1;
+  __device__ static void id(float *p) { p[0] = 0.0f; }
+  __device__ static void comb(const float *a, const float *b, float *r) {
+    const float t = a[0] + b[0];
+    r[0] = t > kSatCap ? kSatCap : t;
+  }
+  __device__ static void lift(const float *v, int64_t e, float *p) { p[0] = v[e]; }
+};
+
 template <>
 struct RsBase<LINREC> {
   static constexpr int N = 2;  // (A, y); elements (a, b) interleaved in v
@@ -227,7 +239,7 @@ __global__ __launch_bounds__(RS_TH) void k_rbi_sorted(RsArgs a) {
       if (p + 1 < a.n && key[j + 1] == key[j]) continue;  // not the run's end
       const T r = Tr::comb(full, loc[j]);
       const int64_t k = key[j];
-      if (OP == ADD) a.hist[k] = r.f[1];
+      if (OP == ADD || OP == SATADD) a.hist[k] = r.f[1];
       if (OP == MUL) { a.n0[k] = __float_as_uint(r.f[1]); a.ypos[k] = r.f[2]; }
       if (OP == MIN || OP == MAX) a.keys[k] = RsMinMax<OP>::join(r.f + 1);
       if (OP == LINREC || OP == MAT2) {
@@ -256,7 +268,12 @@ __global__ __launch_bounds__(RS_TH) void k_rbi_sorted(RsArgs a) {
 template <int OP>
 __device__ __forceinline__ void rs_local_vjp(const float *l, const float *x, const float *r,
                                              const float *hb, float *xb) {
-  if (OP == LINREC) {
+  if (OP == SATADD) {
+    // out = (l (.) x) (.) r: both steps' partials in x, 0 where saturated
+    const float lx = l[0] + x[0];
+    const float lxs = lx > kSatCap ? kSatCap : lx;
+    xb[0] = (!(lx > kSatCap) && !(lxs + r[0] > kSatCap)) ? hb[0] : 0.0f;
+  } else if (OP == LINREC) {
     // out = (l (.) x) (.) r = (A_l a A_r, (y_l a + b) A_r + y_r)
     xb[0] = (hb[0] * l[0] + hb[1] * l[1]) * r[0];
     xb[1] = hb[1] * r[0];
@@ -381,6 +398,7 @@ static int rs_words(int op) {
   case MIN: case MAX: return 2 * (1 + 2);
   case LINREC: return 2 * (1 + RsBase<LINREC>::N);
   case MAT2: return 2 * (1 + RsBase<MAT2>::N);
+  case SATADD: return 2 * (1 + RsBase<SATADD>::N);
   }
   return 0;
 }
@@ -400,7 +418,8 @@ size_t rbi_sorted_ws_bytes(int op, int64_t n, int64_t m) {
   (void)m;
   const int64_t nt = (n + RS_TILE - 1) / RS_TILE;
   size_t b = al256((size_t)(nt > 0 ? nt : 1) * rs_words(op) * 8);
-  if (op == LINREC || op == MAT2) b += al256((size_t)n * (op == LINREC ? 2 : 4) * 4);
+  if (op == LINREC || op == MAT2 || op == SATADD)
+    b += al256((size_t)n * (op == LINREC ? 2 : (op == MAT2 ? 4 : 1)) * 4);
   return b;
 }
 
@@ -433,19 +452,20 @@ hipError_t rbi_sorted_fwd_row(int op, int64_t n, int64_t m, const int32_t *idx, 
   case MAX: hipLaunchKernelGGL((k_rbi_sorted<MAX, 0>), g, dim3(RS_TH), 0, s, a); break;
   case LINREC: hipLaunchKernelGGL((k_rbi_sorted<LINREC, 0>), g, dim3(RS_TH), 0, s, a); break;
   case MAT2: hipLaunchKernelGGL((k_rbi_sorted<MAT2, 0>), g, dim3(RS_TH), 0, s, a); break;
+  case SATADD: hipLaunchKernelGGL((k_rbi_sorted<SATADD, 0>), g, dim3(RS_TH), 0, s, a); break;
   default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-// adjoint of one row of an ordered operator (LINREC, MAT2), from the sort the
+// adjoint of one row by the general rule (LINREC, MAT2, SATADD), from the sort the
 // forward left in `area`
 hipError_t rbi_sorted_vjp_row(int op, int64_t n, int64_t m, const float *v, const float *hbar,
                               float *vbar, bool accumulate, void *ctl, void *region,
                               const void *area, hipStream_t s) {
   if (n == 0) return hipSuccess;
   const char *ar = static_cast<const char *>(area);
-  const int d = op == LINREC ? 2 : 4;
+  const int d = op == LINREC ? 2 : (op == MAT2 ? 4 : 1);
   const int64_t nt = (n + RS_TILE - 1) / RS_TILE;
   RsArgs a{};
   a.sk = reinterpret_cast<const int32_t *>(ar);
@@ -465,6 +485,9 @@ hipError_t rbi_sorted_vjp_row(int op, int64_t n, int64_t m, const float *v, cons
   } else if (op == MAT2) {
     hipLaunchKernelGGL((k_rbi_sorted<MAT2, 1>), g, dim3(RS_TH), 0, s, a);
     hipLaunchKernelGGL(k_rbi_sorted_vjp<MAT2>, g, dim3(RS_TH), 0, s, a);
+  } else if (op == SATADD) {
+    hipLaunchKernelGGL((k_rbi_sorted<SATADD, 1>), g, dim3(RS_TH), 0, s, a);
+    hipLaunchKernelGGL(k_rbi_sorted_vjp<SATADD>, g, dim3(RS_TH), 0, s, a);
   } else {
     return hipErrorInvalidValue;
   }

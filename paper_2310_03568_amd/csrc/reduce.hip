@@ -9,7 +9,8 @@
 // adjoints are single elementwise passes (broadcast, the three zero cases,
 // the one-hot at k).
 //
-// linear recurrence / 2x2 matrix product: the general rule of Section 3.1
+// linear recurrence / 2x2 matrix product / saturated addition: the general
+// rule of Section 3.1
 // (reduce rule figure).  The forward is the look-back scan kernel run without
 // per-element outputs; it saves every tile's exclusive prefix l_t.  The
 // adjoint takes tiles right to left, recomputes in registers the in-tile
@@ -194,6 +195,7 @@ __global__ void k_reduce_empty(int op, int64_t batch, int d, float *y, void *sav
     y[r] = 0.0f;
     reinterpret_cast<float *>(saved)[r] = 0.0f;
     break;
+  case SATADD: y[r] = 0.0f; break;
   }
   (void)d;
 }
@@ -293,6 +295,19 @@ struct LocalVjp<MAT2> {
     MapMat::mm(lt, yb, t);
     MapMat::mm(t, rt, xb);
     (void)x;
+  }
+};
+
+template <>
+struct LocalVjp<SATADD> {
+  using T = Fwd<SATADD>::T;
+  // out = (l (.) x) (.) r: the two steps' partials in x, each 0 if saturated
+  __device__ static void apply(const T &l, const T &x, const T &r, const float *yb, float *xb) {
+    const float lx = l.f[0] + x.f[0];
+    const float lxs = lx > kSatCap ? kSatCap : lx;
+    const bool pass = !(lx > kSatCap) && !(lxs + r.f[0] > kSatCap);
+    xb[0] = pass ? yb[0] : 0.0f;
+    xb[1] = 0.0f;
   }
 };
 
@@ -454,7 +469,7 @@ int reduce_blocks_per_row(int64_t batch, int64_t n) {
 }
 
 size_t reduce_ws_bytes(int op, int64_t batch, int64_t n) {
-  if (op == LINREC || op == MAT2) {
+  if (op == LINREC || op == MAT2 || op == SATADD) {
     const int tile = scan_tile_size(op);
     const int64_t tiles = batch * ((n + tile - 1) / tile);
     return kCtlBytes + (size_t)tiles * 2 * scan_elem_floats(op) * sizeof(uint64_t);
@@ -471,7 +486,7 @@ hipError_t reduce_fwd_launch(int op, int64_t batch, int64_t n, const float *x0, 
                        op, batch, scan_elem_floats(op), y, saved);
     return hipGetLastError();
   }
-  if (op == LINREC || op == MAT2)
+  if (op == LINREC || op == MAT2 || op == SATADD)
     return scan_fwd_launch(op, batch, n, x0, x1, nullptr, nullptr, static_cast<float *>(saved), y,
                            true, ws, s);
   RedArgs a;
@@ -502,7 +517,7 @@ hipError_t reduce_vjp_launch(int op, int64_t batch, int64_t n, const float *x0, 
                              const void *saved, const float *ybar, float *xb0, float *xb1,
                              bool accumulate, void *ws, hipStream_t s) {
   if (batch == 0 || n == 0) return hipSuccess;
-  if (op == LINREC || op == MAT2) {
+  if (op == LINREC || op == MAT2 || op == SATADD) {
     const int tile = scan_tile_size(op);
     const int tpr = (int)((n + tile - 1) / tile);
     RedGenArgs a;
@@ -512,6 +527,7 @@ hipError_t reduce_vjp_launch(int op, int64_t batch, int64_t n, const float *x0, 
     a.status = reinterpret_cast<uint64_t *>(static_cast<char *>(ws) + kCtlBytes);
     const dim3 grid((unsigned)(batch * tpr));
     if (op == LINREC) hipLaunchKernelGGL(k_reduce_vjp_gen<LINREC>, grid, dim3(Shape<LINREC>::THREADS), 0, s, a);
+    else if (op == SATADD) hipLaunchKernelGGL(k_reduce_vjp_gen<SATADD>, grid, dim3(Shape<SATADD>::THREADS), 0, s, a);
     else hipLaunchKernelGGL(k_reduce_vjp_gen<MAT2>, grid, dim3(Shape<MAT2>::THREADS), 0, s, a);
     return hipGetLastError();
   }

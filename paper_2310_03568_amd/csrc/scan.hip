@@ -506,6 +506,7 @@ int scan_tile_size(int op) {
   case MUL: return Shape<MUL>::TILE;
   case MIN: return Shape<MIN>::TILE;
   case MAX: return Shape<MAX>::TILE;
+  case SATADD: return Shape<SATADD>::TILE;
   case LINREC: return Shape<LINREC>::TILE;
   case MAT2: return Shape<MAT2>::TILE;
   }
@@ -518,7 +519,7 @@ int scan_elem_floats(int op) { return op == LINREC ? 2 : (op == MAT2 ? 4 : 1); }
 int scan_status_words(int op, bool abar) {
   switch (op) {
   case ADD: return 2;
-  case MUL: case MIN: case MAX: return 3;
+  case MUL: case MIN: case MAX: case SATADD: return 3;
   case LINREC: return abar ? 5 : 4;
   case MAT2: return 12;
   }
@@ -597,6 +598,7 @@ hipError_t scan_fwd_launch(int op, int64_t batch, int64_t n, const float *x0, co
     PCAD_FWD(MUL)
     PCAD_FWD(MIN)
     PCAD_FWD(MAX)
+    PCAD_FWD(SATADD)
     PCAD_FWD(LINREC)
     PCAD_FWD(MAT2)
   }
@@ -624,6 +626,8 @@ hipError_t scan_vjp_launch(int op, int64_t batch, int64_t n, const float *x0, co
   case MUL: return ck ? launch_vjp<MUL, false, true>(a, s) : launch_vjp<MUL, false, false>(a, s);
   case MIN: return ck ? launch_vjp<MIN, false, true>(a, s) : launch_vjp<MIN, false, false>(a, s);
   case MAX: return ck ? launch_vjp<MAX, false, true>(a, s) : launch_vjp<MAX, false, false>(a, s);
+  case SATADD:
+    return ck ? launch_vjp<SATADD, false, true>(a, s) : launch_vjp<SATADD, false, false>(a, s);
   case LINREC:
     if (yb1)
       return ck ? launch_vjp<LINREC, true, true>(a, s) : launch_vjp<LINREC, true, false>(a, s);

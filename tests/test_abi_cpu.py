@@ -90,7 +90,7 @@ def test_sumprod_queries(L):
     assert st == 0 and s == 70_000 * 4 and w >= 100_000 * 8
     assert q(L, 2, SP, 1, 10, (1 << 24) + 1)[0] == 5  # PCAD_E_SIZE
     assert q(L, 2, SP, 1, 10, 1 << 24)[0] == 0
-    assert q(L, 0, 7, 1, 10)[0] == 1  # no operator 7
+    assert q(L, 0, 8, 1, 10)[0] == 1  # no operator 8
 
 
 def test_validation(L):

@@ -654,3 +654,70 @@ def test_vectorised_rejects_other_operators(pcad):
     X = dev(np.ones((10, 4), np.float32))
     with pytest.raises(pcad.PcadError):
         pcad.vreduce_fwd("linrec", X)
+
+
+# ---------------------------------------------------------------------------
+# saturated addition (the evaluation's operator figure): scan (both adjoint
+# forms), reduce (the general rule) and reduce-by-index (the sort-based
+# general rule).  Values are positive multiples of 3: every partial sum is
+# an exact float32 integer and none equals the cap 1e6, so the saturation
+# decisions, and the bracketing-independent derivatives, agree exactly with
+# the oracle's.
+# ---------------------------------------------------------------------------
+def _sat_values(rng, shape, hi):
+    return (3 * rng.integers(1, hi, shape)).astype(np.float32)
+
+
+@pytest.mark.parametrize("batch,n,hi", [(1, 1, 10), (1, 100_003, 11), (3, 30_001, 40), (2, 9000, 30_000),
+                                        (1, 1 << 20, 3)])
+def test_scan_satadd(pcad, batch, n, hi):
+    rng = np.random.default_rng(n + hi)
+    x = _sat_values(rng, (batch, n), hi)
+    yb = rng.standard_normal((batch, n)).astype(np.float32)
+    X = dev(x)
+    y, _, saved = pcad.scan_fwd("satadd", X)
+    g = pcad.scan_vjp("satadd", X, None, saved, dev(yb))
+    gc = pcad.scan_vjp_checkpoint("satadd", X, None, y, None, dev(yb))
+    y, g, gc = host(y), host(g), host(gc)
+    for r in range(batch):
+        rs, _ = oracle.scan_fwd("satadd", x[r])
+        np.testing.assert_array_equal(y[r], rs[:, 0].astype(np.float32))
+        xb, cx = oracle.scan_vjp("satadd", yb[r], x[r])
+        assert_gate(g[r], xb[:, 0], cx[:, 0], RTOL["add"], what="scan satadd vjp")
+        assert_gate(gc[r], xb[:, 0], cx[:, 0], RTOL["add"], what="scan satadd vjp checkpoint")
+    assert ws_error() == 0
+
+
+@pytest.mark.parametrize("batch,n,hi", [(1, 1, 10), (1, 50_000, 11), (1, 100_003, 5), (4, 20_001, 9)])
+def test_reduce_satadd(pcad, batch, n, hi):
+    """n*hi*3/2 against 1e6 puts some rows below the cap and some above."""
+    rng = np.random.default_rng(7 * n + hi)
+    x = _sat_values(rng, (batch, n), hi)
+    yb = rng.standard_normal(batch).astype(np.float32)
+    X = dev(x)
+    y, saved = pcad.reduce_fwd("satadd", X)
+    g = pcad.reduce_vjp("satadd", X, None, saved, dev(yb))
+    y, g = host(y).reshape(batch), host(g).reshape(batch, n)
+    for r in range(batch):
+        o = oracle.reduce_fwd("satadd", x[r])
+        assert y[r] == np.float32(o["y"][0])
+        xb, _ = oracle.reduce_vjp("satadd", yb[r:r + 1], x[r])
+        np.testing.assert_array_equal(g[r], xb[:, 0].astype(np.float32))
+
+
+@pytest.mark.parametrize("n,m,hi", [(1000, 7, 30_000), (100_000, 64, 40), (200_003, 5000, 3_000),
+                                    (100_000, 1 << 20, 300_000)])
+def test_rbi_satadd(pcad, n, m, hi):
+    rng = np.random.default_rng(n + m)
+    v = _sat_values(rng, n, hi)
+    idx = rng.integers(-2, m + 2, n).astype(np.int32)
+    hb = rng.standard_normal(m).astype(np.float32)
+    I, V = dev(idx), dev(v)
+    h, saved = pcad.rbi_fwd("satadd", I, V, m)
+    vb = pcad.rbi_vjp("satadd", I, V, m, saved, dev(hb))
+    h, vb = host(h), host(vb)
+    o = oracle.rbi_fwd("satadd", idx, m, v)
+    np.testing.assert_array_equal(h, o["hist"][:, 0].astype(np.float32))
+    xb, _ = oracle.rbi_vjp("satadd", idx, m, hb, v)
+    np.testing.assert_array_equal(vb, xb[:, 0].astype(np.float32))
+    assert ws_error() == 0
