@@ -327,6 +327,22 @@ def sumprod_reduce_vjp(a, ybar: float):
     return xb[:, 1].copy(), c[:, 1] + av * abs(float(ybar))
 
 
+def sumprod_scan(a):
+    """Inclusive scan with sumOfProd (Section 3.3's operator under the scan of
+    Section 5.1): returns (y, c) with y_i = sum over j<k<=i of a_j a_k."""
+    rs, c = scan_fwd("sumprod", a)
+    return rs[:, 0].copy(), c[:, 0].copy()
+
+
+def sumprod_scan_vjp(a, ybar):
+    """Adjoint of sumprod_scan: the reverse sweep of the lifted scan with
+    output adjoints (ybar_i, 0); an input's adjoint is the s slot."""
+    yb = _f64(ybar).reshape(-1)
+    yl = np.stack([yb, np.zeros_like(yb)], axis=1)
+    xb, c = scan_vjp("sumprod", yl, a)
+    return xb[:, 1].copy(), c[:, 1].copy()
+
+
 def sumprod_rbi_fwd(idx, m: int, a):
     """Per bin: hist (p_k), s (sum of the bin's values), c (companion of p_k),
     count."""

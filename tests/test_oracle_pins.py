@@ -974,3 +974,22 @@ def test_satadd_rbi_against_per_bin_loops():
         assert r["hist"][k, 0] == Y[-1]
         np.testing.assert_allclose(vb[sel, 0], hb[k] * J[-1], rtol=1e-12, atol=1e-12)
     assert np.all(vb[(idx < 0) | (idx >= m), 0] == 0.0)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_sumprod_scan_closed_forms(seed):
+    """y_i = sum_{j<k<=i} a_j a_k by brute force, and the adjoint
+    d/da_m sum_i ybar_i y_i = sum_{i>=m} ybar_i (S_i - a_m), S_i = a_0+..+a_i."""
+    rng = np.random.default_rng(500 + seed)
+    n = int(rng.integers(1, 30))
+    a = rng.integers(-6, 7, n).astype(float)
+    yb = rng.integers(-3, 4, n).astype(float)
+    y, c = oracle.sumprod_scan(a)
+    for i in range(n):
+        assert y[i] == sum(a[j] * a[k] for j in range(i + 1) for k in range(j + 1, i + 1))
+    assert np.all(c >= np.abs(y))
+    S = np.cumsum(a)
+    xb, cx = oracle.sumprod_scan_vjp(a, yb)
+    ref = np.array([sum(yb[i] * (S[i] - a[m_]) for i in range(m_, n)) for m_ in range(n)])
+    np.testing.assert_array_equal(xb, ref)
+    assert np.all(cx >= np.abs(xb))
