@@ -86,7 +86,7 @@ typedef enum {
   PCAD_MAX = 3,
   PCAD_LINREC = 4, /* linear-function composition (a multiplier, b offset) */
   PCAD_MAT2 = 5,   /* 2x2 matrix product, row-major */
-  PCAD_SUMPROD = 6, /* sumOfProd (Section 3.3): reduce and reduce_by_index only */
+  PCAD_SUMPROD = 6, /* sumOfProd (Section 3.3), scalar inputs lifted to (0, a) */
   PCAD_SATADD = 7   /* saturated addition at 1e6 (the evaluation's operator figure) */
 } pcad_op;
 
@@ -142,8 +142,7 @@ int pcad_reduce_fwd(int op, int64_t batch, int64_t n, const float *x0, const flo
  * too (its partials are 0 on a saturated step); SUMPROD uses the
  * invertible-operator rule of Section 3.3: the rest of the fold is
  * (p, s) inverted by (0, x_i), whose s is s - x_i, so x_bar_i =
- * (s - x_i) * y_bar (x0 required).  Scans of SUMPROD return
- * PCAD_E_UNSUPPORTED.
+ * (s - x_i) * y_bar (x0 required).
  *   xbar0/xbar1: same layout as x0/x1 (LINREC: a_bar, b_bar).
  */
 int pcad_reduce_vjp(int op, int64_t batch, int64_t n, const float *x0, const float *x1,
@@ -170,6 +169,10 @@ int pcad_scan_fwd(int op, int64_t batch, int64_t n, const float *x0, const float
  * by a right-to-left decoupled look-back scan of adjoint affine maps, fused
  * with x_bar_i = d(rs_{i-1} (.) x_i)/d x_i^T lam_i (x_bar_0 = lam_0).
  * SATADD: both partials are [rs_{i-1} + x_i <= 1e6] (0 on a saturated step).
+ * SUMPROD: inputs a_i lift to (0, a_i) and y_i is the p of the prefix, the
+ * sum over j<k<=i of a_j a_k; the adjoint maps act on (lam_p, lam_s) through
+ * J^T = [[1, 0], [a_i, 1]] and a_bar_i = S_{i-1} lam_p + lam_s (S the prefix
+ * sum), recompute form only (pcad_scan_vjp_checkpoint: PCAD_E_UNSUPPORTED).
  * Forward prefixes are recomputed inside each tile from `saved`.
  *   ybar0: adjoint of y0 (x-layout; MAT2 4 floats per element).
  *   ybar1: LINREC only, optional adjoint of A (NULL = zero).

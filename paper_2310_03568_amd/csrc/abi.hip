@@ -92,7 +92,6 @@ int query(int comb, int op, int64_t batch, int64_t n, int64_t m, size_t *saved, 
     w = reduce_ws_bytes(op, batch, n);
     break;
   case PCAD_SCAN:
-    if (op == PCAD_SUMPROD) return PCAD_E_UNSUPPORTED;
     s = scan_saved(op, batch, n);
     w = scan_ws(op, batch, n);
     break;
@@ -219,7 +218,6 @@ int pcad_scan_fwd(int op, int64_t batch, int64_t n, const float *x0, const float
                   float *y1, void *saved, unsigned flags, void *ws, size_t ws_bytes,
                   void *stream) {
   PCAD_TRY(check_common(op, batch, n, flags));
-  if (op == PCAD_SUMPROD) return PCAD_E_UNSUPPORTED;
   if (batch == 0 || n == 0) return PCAD_OK;
   if (scan_tiles(op, batch, n) > 2147483647LL) return PCAD_E_SIZE;
   PCAD_TRY(need(x0));
@@ -237,7 +235,6 @@ int pcad_scan_vjp(int op, int64_t batch, int64_t n, const float *x0, const float
                   const void *saved, const float *ybar0, const float *ybar1, float *xbar0,
                   float *xbar1, unsigned flags, void *ws, size_t ws_bytes, void *stream) {
   PCAD_TRY(check_common(op, batch, n, flags));
-  if (op == PCAD_SUMPROD) return PCAD_E_UNSUPPORTED;
   if (batch == 0 || n == 0) return PCAD_OK;
   if (scan_tiles(op, batch, n) > 2147483647LL) return PCAD_E_SIZE;
   PCAD_TRY(need(x0));
@@ -259,7 +256,7 @@ int pcad_scan_vjp_checkpoint(int op, int64_t batch, int64_t n, const float *x0, 
                              const float *ybar1, float *xbar0, float *xbar1, unsigned flags,
                              void *ws, size_t ws_bytes, void *stream) {
   PCAD_TRY(check_common(op, batch, n, flags));
-  if (op == PCAD_SUMPROD) return PCAD_E_UNSUPPORTED;
+  if (op == PCAD_SUMPROD) return PCAD_E_UNSUPPORTED;  // needs the s of every prefix
   if (batch == 0 || n == 0) return PCAD_OK;
   if (scan_tiles(op, batch, n) > 2147483647LL) return PCAD_E_SIZE;
   PCAD_TRY(need(x0));

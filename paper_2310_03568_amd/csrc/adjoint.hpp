@@ -113,6 +113,26 @@ struct MapMat {
   __device__ static P apply0(const T &t) { return {{t.f[0], t.f[1], t.f[2], t.f[3]}}; }
 };
 
+// sumOfProd scans: rho is the pair (rho_p, rho_s) and J_{i-1}^T =
+// [[1, 0], [a_i, 1]] acts on it; composed maps stay lower triangular,
+// r -> o + W r with W = [[w0, 0], [w1, w2]] (constant maps have W = 0)
+struct MapSP {
+  using T = Vec<5>;  // o_p, o_s, w0, w1, w2
+  using P = Vec<2>;
+  static constexpr int NA = 5, NP = 2;
+  __device__ static T id() { return {{0.0f, 0.0f, 1.0f, 0.0f, 1.0f}}; }
+  __device__ static T comb(const T &e, const T &l) {
+    // l o e: o = l.o + W_l e.o, W = W_l W_e
+    return {{__builtin_fmaf(l.f[2], e.f[0], l.f[0]),
+             __builtin_fmaf(l.f[3], e.f[0], __builtin_fmaf(l.f[4], e.f[1], l.f[1])),
+             l.f[2] * e.f[2],
+             __builtin_fmaf(l.f[3], e.f[2], l.f[4] * e.f[3]),
+             l.f[4] * e.f[4]}};
+  }
+  __device__ static T from_pre(const P &p) { return {{p.f[0], p.f[1], 0.0f, 0.0f, 0.0f}}; }
+  __device__ static P apply0(const T &t) { return {{t.f[0], t.f[1]}}; }
+};
+
 // ---------------------------------------------------------------------------
 // Per-operator local rules.  `p` is rs_{i-1} (the forward exclusive prefix,
 // the neutral element at a row start), `first` marks the row's first
@@ -208,6 +228,28 @@ struct Adj<SATADD, ABAR> {
     const bool k = pass(p, x, first);
     xb[0] = k ? lam : 0.0f;
     rho.f[0] = (!first && k) ? lam : 0.0f;
+  }
+};
+
+// sumOfProd scans: element x = (0, a_i), prefix p = (P_{i-1}, S_{i-1}); the
+// output adjoint is (ybar_i, 0):
+//   lam = ybar + rho,  a_bar = S_{i-1} lam_p + lam_s,  rho = (lam_p, a lam_p + lam_s)
+template <bool ABAR>
+struct Adj<SUMPROD, ABAR> {
+  using M = MapSP;
+  using FT = Fwd<SUMPROD>::T;
+  static constexpr bool NEEDS_PREFIX = true;
+  static constexpr int NY = 1, NXB = 1;
+  __device__ static M::T make(const FT &, const FT &x, const float *yb, bool) {
+    const float a = x.f[1];
+    return {{yb[0], a * yb[0], 1.0f, a, 1.0f}};
+  }
+  __device__ static void step(const FT &p, const FT &x, const float *yb, bool, M::P &rho,
+                              float *xb) {
+    const float lp = yb[0] + rho.f[0], ls = rho.f[1];
+    xb[0] = __builtin_fmaf(p.f[1], lp, ls);
+    rho.f[0] = lp;
+    rho.f[1] = __builtin_fmaf(x.f[1], lp, ls);
   }
 };
 

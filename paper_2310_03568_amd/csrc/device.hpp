@@ -13,8 +13,8 @@ constexpr int BLOCK = 256;
 constexpr int WAVE = 64;
 constexpr int WAVES = BLOCK / WAVE;
 
-// operator ids (same values as the public enum).  SUMPROD (Section 3.3's
-// invertible operator sumOfProd) exists for reduce and reduce-by-index only.
+// operator ids (same values as the public enum).  SUMPROD is Section 3.3's
+// invertible operator sumOfProd (reduce, scan, reduce-by-index).
 // SATADD is the saturated addition of the evaluation's operator figure.
 enum { ADD = 0, MUL = 1, MIN = 2, MAX = 3, LINREC = 4, MAT2 = 5, SUMPROD = 6, SATADD = 7 };
 
@@ -197,6 +197,18 @@ struct Fwd<MAX> {
   __device__ static T comb(const T &a, const T &b) { return {{b.f[0] > a.f[0] ? b.f[0] : a.f[0]}}; }
 };
 
+// sumOfProd (Section 3.3) on lifted pairs (p, s); scans lift an input a to
+// (0, a) and write p
+template <>
+struct Fwd<SUMPROD> {
+  static constexpr int N = 2;
+  using T = Vec<2>;
+  __device__ static T id() { return {{0.0f, 0.0f}}; }
+  __device__ static T comb(const T &a, const T &b) {
+    return {{__builtin_fmaf(a.f[1], b.f[1], a.f[0] + b.f[0]), a.f[1] + b.f[1]}};
+  }
+};
+
 // saturated addition: the sum, or the cap when the sum exceeds it
 // (associative and commutative on values in [0, cap])
 template <>
@@ -374,6 +386,15 @@ template <>
 struct IO<MAX> : IOScalar<MAX> {};
 template <>
 struct IO<SATADD> : IOScalar<SATADD> {};
+
+// sumOfProd: one scalar stream, each value lifted to (0, a)
+template <>
+struct IO<SUMPROD> {
+  static constexpr int NIN = 1, S = 1;
+  using FT = Fwd<SUMPROD>::T;
+  __device__ static float4 fill(int) { return make_float4(0, 0, 0, 0); }
+  __device__ static FT elem(const float4 (&in)[NIN], int j) { return {{0.0f, f4get(in[0], j)}}; }
+};
 
 template <>
 struct IO<LINREC> {

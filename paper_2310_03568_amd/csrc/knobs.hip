@@ -59,9 +59,11 @@ Knob *find(const char *name) {
 
 }  // namespace
 
-// saturated addition has the shape of + and shares its block sizes
+// saturated addition has the shape of + and shares its block sizes;
+// sumOfProd scans (two floats per element) share the linear recurrence's
 int knob_scan_threads(int op, int dir) {
-  return (int)g_knobs[(dir ? 6 : 0) + (op == PCAD_SATADD ? PCAD_ADD : op)].value;
+  const int o = op == PCAD_SATADD ? PCAD_ADD : (op == PCAD_SUMPROD ? PCAD_LINREC : op);
+  return (int)g_knobs[(dir ? 6 : 0) + o].value;
 }
 int64_t knob_rbi_lds_max_bins(bool u64) { return g_knobs[u64 ? kRbiU64 : kRbiF32].value; }
 int64_t knob_rbi_elems_per_block() { return g_knobs[kRbiEpb].value; }

@@ -507,13 +507,14 @@ int scan_tile_size(int op) {
   case MIN: return Shape<MIN>::TILE;
   case MAX: return Shape<MAX>::TILE;
   case SATADD: return Shape<SATADD>::TILE;
+  case SUMPROD: return Shape<SUMPROD>::TILE;
   case LINREC: return Shape<LINREC>::TILE;
   case MAT2: return Shape<MAT2>::TILE;
   }
   return 0;
 }
 
-int scan_elem_floats(int op) { return op == LINREC ? 2 : (op == MAT2 ? 4 : 1); }
+int scan_elem_floats(int op) { return (op == LINREC || op == SUMPROD) ? 2 : (op == MAT2 ? 4 : 1); }
 
 // status words per tile: forward (N + N); adjoint maps (NA + NP)
 int scan_status_words(int op, bool abar) {
@@ -522,6 +523,7 @@ int scan_status_words(int op, bool abar) {
   case MUL: case MIN: case MAX: case SATADD: return 3;
   case LINREC: return abar ? 5 : 4;
   case MAT2: return 12;
+  case SUMPROD: return 7;
   }
   return 0;
 }
@@ -599,6 +601,7 @@ hipError_t scan_fwd_launch(int op, int64_t batch, int64_t n, const float *x0, co
     PCAD_FWD(MIN)
     PCAD_FWD(MAX)
     PCAD_FWD(SATADD)
+    PCAD_FWD(SUMPROD)
     PCAD_FWD(LINREC)
     PCAD_FWD(MAT2)
   }
@@ -628,6 +631,8 @@ hipError_t scan_vjp_launch(int op, int64_t batch, int64_t n, const float *x0, co
   case MAX: return ck ? launch_vjp<MAX, false, true>(a, s) : launch_vjp<MAX, false, false>(a, s);
   case SATADD:
     return ck ? launch_vjp<SATADD, false, true>(a, s) : launch_vjp<SATADD, false, false>(a, s);
+  case SUMPROD:  // recompute form only: the checkpoint form would need s as well
+    return ck ? hipErrorInvalidValue : launch_vjp<SUMPROD, false, false>(a, s);
   case LINREC:
     if (yb1)
       return ck ? launch_vjp<LINREC, true, true>(a, s) : launch_vjp<LINREC, true, false>(a, s);

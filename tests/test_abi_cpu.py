@@ -80,8 +80,8 @@ def test_sumprod_queries(L):
     SP = 6
     # reduce: the row sum s per row is saved
     assert q(L, 0, SP, 3, 1000)[:2] == (0, 12)
-    # scans of sumOfProd are not offered
-    assert q(L, 1, SP, 1, 1000)[0] == 2  # PCAD_E_UNSUPPORTED
+    # scans of sumOfProd: two floats per tile prefix, like the linear recurrence
+    assert q(L, 1, SP, 1, 8192)[:2] == (0, 2 * 4)
     # reduce-by-index: s per bin saved, (p, s) pairs in the workspace
     st, s, w = q(L, 2, SP, 2, 5000, 300)
     assert st == 0 and s == 2 * 300 * 4 and w >= 256 + 2 * 300 * 8

@@ -515,8 +515,6 @@ def test_reduce_sumprod(pcad, batch, n):
                     what="sumprod s")
         xb, cx = oracle.sumprod_reduce_vjp(x[r], float(yb[r]))
         assert_gate(g[r], xb, cx, RTOL["sumprod"], what=f"sumprod vjp row {r}")
-    with pytest.raises(pcad.PcadError):
-        pcad.scan_fwd("sumprod", X)
 
 
 @pytest.mark.parametrize("dist", ["uniform", "zipf"])
@@ -721,3 +719,25 @@ def test_rbi_satadd(pcad, n, m, hi):
     xb, _ = oracle.rbi_vjp("satadd", idx, m, hb, v)
     np.testing.assert_array_equal(vb, xb[:, 0].astype(np.float32))
     assert ws_error() == 0
+
+
+@pytest.mark.parametrize("batch,n", [(1, 1), (1, 5000), (1, 100_003), (3, 30_001), (1, 1 << 20)])
+def test_scan_sumprod(pcad, batch, n):
+    """Scans with sumOfProd (Section 3.3's operator, lifted pairs (p, s)):
+    y_i = sum over j<k<=i of x_j x_k, and the adjoint by the right-to-left
+    scan of lower-triangular adjoint maps."""
+    rng = np.random.default_rng(n + batch)
+    x = (rng.standard_normal((batch, n)) / np.sqrt(max(n, 1)) * 8).astype(np.float32)
+    yb = rng.standard_normal((batch, n)).astype(np.float32)
+    X = dev(x)
+    y, _, saved = pcad.scan_fwd("sumprod", X)
+    g = pcad.scan_vjp("sumprod", X, None, saved, dev(yb))
+    y, g = host(y), host(g)
+    for r in range(batch):
+        Y, CY = oracle.sumprod_scan(x[r])
+        assert_gate(y[r], Y, CY, RTOL["sumprod"], what="scan sumprod")
+        xb, cx = oracle.sumprod_scan_vjp(x[r], yb[r])
+        assert_gate(g[r], xb, cx, RTOL["sumprod"], what="scan sumprod vjp")
+    assert ws_error() == 0
+    with pytest.raises(pcad.PcadError):
+        pcad.scan_vjp_checkpoint("sumprod", X, None, dev(y), None, dev(yb))
