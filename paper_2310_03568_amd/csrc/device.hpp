@@ -283,6 +283,24 @@ struct ShapeT {
   static_assert(K >= 1 && K * THREADS * EPL == TILE, "tile must be whole groups of the block");
 };
 
+// Element layout of a tile over the threads: group-major (group g of all
+// threads, then group g+1) or lane-major (a thread's K groups are
+// consecutive elements, so a tile needs one serial pass and one wave scan
+// per thread instead of one per group).  Lane-major cuts the scan work
+// where it dominates -- the adjoint of the 2x2 matrix product -- but its
+// loads are strided by K groups, so it pays only with few groups per thread
+// (1024-thread blocks); the forward kernels (DIR 0) stay group-major.
+template <int OP, int DIR>
+constexpr bool lane_major() {
+  return DIR == 1 && OP == MAT2;
+}
+
+// first element of group g of thread tid within a tile
+template <bool LM, int K, int TH, int EPL>
+__device__ __forceinline__ int group_el(int g, int tid) {
+  return LM ? (tid * K + g) * EPL : g * TH * EPL + tid * EPL;
+}
+
 template <int OP, int DIR = 0>
 struct Shape {
   static constexpr int EPL = (OP == MAT2) ? 1 : 4;

@@ -51,6 +51,7 @@ __global__ __launch_bounds__(TH_) void k_scan_fwd(ScanFwdArgs a) {
   constexpr int EPL = Sh::EPL, K = Sh::K, TILE = Sh::TILE;
   constexpr int TH = Sh::THREADS, W = Sh::W;
   constexpr int NIN = Io::NIN, S = Io::S, N = Fwd<OP>::N;
+  constexpr bool LM = lane_major<OP, 0>();
 
   __shared__ T s_tot[K][W];
   __shared__ T s_pre[K][W];
@@ -63,7 +64,7 @@ __global__ __launch_bounds__(TH_) void k_scan_fwd(ScanFwdArgs a) {
     const TileInfo ti = tile_info(t, a.n, a.tpr, TILE);
 #pragma unroll
     for (int g = 0; g < K; ++g) {
-      const int el = g * TH * EPL + tid * EPL;
+      const int el = group_el<LM, K, TH, EPL>(g, tid);
 #pragma unroll
       for (int s = 0; s < NIN; ++s)
         buf[g][s] = load_group<S>(src[s], ti.base, el, ti.valid - el, ti.vec_ok, Io::fill(s));
@@ -84,6 +85,34 @@ __global__ __launch_bounds__(TH_) void k_scan_fwd(ScanFwdArgs a) {
   // publishes it as its inclusive prefix).
   auto phase1 = [&](int64_t tt, T (&thr)[K], T (&lc)[K][EPL], T &ag) {
     const TileInfo ti = tile_info(tt, a.n, a.tpr, TILE);
+    if constexpr (LM) {
+      // a thread's K groups are consecutive elements: one serial pass, one
+      // wave scan, one block prefix
+      T acc = Io::elem(cur[0], 0);
+#pragma unroll
+      for (int g = 0; g < K; ++g) {
+#pragma unroll
+        for (int j = 0; j < EPL; ++j) {
+          if (g > 0 || j > 0) acc = Op::comb(acc, Io::elem(cur[g], j));
+          lc[g][j] = acc;
+        }
+      }
+      const T inc = wave_scan_fwd<Op>(acc);
+      if (lane == WAVE - 1) s_tot[0][wave] = inc;
+      __syncthreads();
+      if (wave == 0) {
+        ag = wave0_block_prefix<Op, 1, W, false>(s_tot, s_pre, Op::id());
+        uint64_t *st = a.status + ti.tile * (Op::NA + Op::NP);
+        if (lane == 0) publish<N>(ti.lt == 0 ? st + Op::NA : st, tag, ag);
+      }
+      __syncthreads();
+      T ex = shift_up1(inc);
+      if (lane == 0) ex = Op::id();
+      const T tp = Op::comb(s_pre[0][wave], ex);
+#pragma unroll
+      for (int g = 0; g < K; ++g) thr[g] = tp;
+      return;
+    }
     T incl[K];
 #pragma unroll
     for (int g = 0; g < K; ++g) {
@@ -165,7 +194,7 @@ __global__ __launch_bounds__(TH_) void k_scan_fwd(ScanFwdArgs a) {
 #pragma unroll
       for (int g = 0; g < K; ++g) {
         const T full = Op::comb(carry, pthr[g]);
-        const int el = g * TH * EPL + tid * EPL;
+        const int el = group_el<LM, K, TH, EPL>(g, tid);
         const int v = ti.valid - el;
         if constexpr (OP == MAT2) {
           const T o = Op::comb(full, ploc[g][0]);
@@ -234,6 +263,7 @@ __global__ __launch_bounds__(TH_) void k_scan_vjp(ScanVjpArgs a) {
   constexpr int EPL = Sh::EPL, K = Sh::K, TILE = Sh::TILE;
   constexpr int TH = Sh::THREADS, W = Sh::W;
   constexpr int NIN = Io::NIN, S = Io::S, N = Fwd<OP>::N;
+  constexpr bool LM = lane_major<OP, 1>();
   constexpr bool RECOMP = A::NEEDS_PREFIX && !CKPT;
   constexpr bool TAPE = A::NEEDS_PREFIX && CKPT;
   // streams per group: x...; y_bar; [A_bar]; [tape y; [tape A]]
@@ -266,7 +296,7 @@ __global__ __launch_bounds__(TH_) void k_scan_vjp(ScanVjpArgs a) {
     const TileInfo ti = tile_info(t, a.n, a.tpr, TILE);
 #pragma unroll
     for (int g = 0; g < K; ++g) {
-      const int el = g * TH * EPL + tid * EPL;
+      const int el = group_el<LM, K, TH, EPL>(g, tid);
       const int v = ti.valid - el;
 #pragma unroll
       for (int s = 0; s < NX; ++s)
@@ -317,7 +347,20 @@ __global__ __launch_bounds__(TH_) void k_scan_vjp(ScanVjpArgs a) {
   // the forward prefixes rs_{i-1} of the EPL slots of group g, ascending
   auto prefixes = [&](int g, FT (&p)[EPL]) {
     if (TAPE) {
-      if (S == 4) {
+      if (S == 4 && LM) {
+        // the element before group g: the same thread's group g-1, or for
+        // g = 0 the left neighbour's last group (lane 0: loaded with pv)
+        Vec<4> up;
+        if (g > 0) {
+          up = Vec<4>{{cur[g - 1][IT].x, cur[g - 1][IT].y, cur[g - 1][IT].z, cur[g - 1][IT].w}};
+        } else {
+          Vec<4> q = {{cur[K - 1][IT].x, cur[K - 1][IT].y, cur[K - 1][IT].z, cur[K - 1][IT].w}};
+          up = shift_up1(q);
+          if (lane == 0) up = Vec<4>{{cpv[0][0].x, cpv[0][0].y, cpv[0][0].z, cpv[0][0].w}};
+        }
+#pragma unroll
+        for (int i = 0; i < N; ++i) p[0].f[i] = up.f[i];
+      } else if (S == 4) {
         Vec<4> q = {{cur[g][IT].x, cur[g][IT].y, cur[g][IT].z, cur[g][IT].w}};
         Vec<4> up = shift_up1(q);
         if (lane == 0) up = Vec<4>{{cpv[g][0].x, cpv[g][0].y, cpv[g][0].z, cpv[g][0].w}};
@@ -354,6 +397,73 @@ __global__ __launch_bounds__(TH_) void k_scan_vjp(ScanVjpArgs a) {
 
   auto phase1 = [&](int64_t kk) {
     const TileInfo ti = tile_info(tile_of(kk), a.n, a.tpr, TILE);
+    if constexpr (LM) {
+      // a thread's K groups are consecutive elements: one serial pass and
+      // one wave scan each way
+      if (RECOMP) {
+        FT gagg[K];
+#pragma unroll
+        for (int g = 0; g < K; ++g) {
+          FT e = x_of(cur, g, 0);
+#pragma unroll
+          for (int j = 1; j < EPL; ++j) e = Op::comb(e, x_of(cur, g, j));
+          gagg[g] = e;
+        }
+        FT acc = gagg[0];
+#pragma unroll
+        for (int g = 1; g < K; ++g) acc = Op::comb(acc, gagg[g]);
+        const FT fin = wave_scan_fwd<Op>(acc);
+        if (lane == WAVE - 1) s_ftot[0][wave] = fin;
+        __syncthreads();
+        if (wave == 0) {
+          FT c;
+#pragma unroll
+          for (int i = 0; i < N; ++i) c.f[i] = a.saved[ti.tile * N + i];
+          wave0_block_prefix<Op, 1, W, false>(s_ftot, s_fpre, c);
+        }
+        __syncthreads();
+        FT ex = shift_up1(fin);
+        if (lane == 0) ex = Op::id();
+        thr_f[0] = Op::comb(s_fpre[0][wave], ex);
+#pragma unroll
+        for (int g = 1; g < K; ++g) thr_f[g] = Op::comb(thr_f[g - 1], gagg[g - 1]);
+      } else {
+#pragma unroll
+        for (int g = 0; g < K; ++g) thr_f[g] = Op::id();
+      }
+      MT acc = M::id();
+#pragma unroll
+      for (int g = K - 1; g >= 0; --g) {
+        FT p[EPL];
+        prefixes(g, p);
+#pragma unroll
+        for (int j = EPL - 1; j >= 0; --j) {
+          float yb[4];
+          ybar_of(cur, g, j, yb);
+          const bool first = ti.lt == 0 && g == 0 && tid == 0 && j == 0;
+          const MT h = A::make(p[j], x_of(cur, g, j), yb, first);
+          acc = (g == K - 1 && j == EPL - 1) ? h : M::comb(acc, h);
+        }
+      }
+      mincl[0] = wave_scan_rev<M>(acc);
+      if (lane == 0) s_mtot[0][wave] = mincl[0];
+      __syncthreads();
+      if (wave == 0) {
+        agg = wave0_block_prefix<M, 1, W, true>(s_mtot, s_mpre, M::id());
+        uint64_t *st = a.status + ti.tile * (M::NA + M::NP);
+        if (lane == 0) {
+          if (ti.lt == a.tpr - 1) {
+            typename M::P zero;
+#pragma unroll
+            for (int i = 0; i < M::NP; ++i) zero.f[i] = 0.0f;
+            publish<M::NP>(st + M::NA, tag, M::apply0(M::comb(M::from_pre(zero), agg)));
+          } else {
+            publish<M::NA>(st, tag, agg);
+          }
+        }
+      }
+      return;
+    }
     if (RECOMP) {
       FT fincl[K];
 #pragma unroll
@@ -446,11 +556,24 @@ __global__ __launch_bounds__(TH_) void k_scan_vjp(ScanVjpArgs a) {
     const MT carry = s_carry;
 
     // thread-serial sweep, right to left
-#pragma unroll
-    for (int g = 0; g < K; ++g) {
-      MT ex = shift_down1(mincl[g]);
+    typename M::P rho_lm;
+    if constexpr (LM) {
+      MT ex = shift_down1(mincl[0]);
       if (lane == WAVE - 1) ex = M::id();
-      typename M::P rho = M::apply0(M::comb(M::comb(carry, s_mpre[g][wave]), ex));
+      rho_lm = M::apply0(M::comb(M::comb(carry, s_mpre[0][wave]), ex));
+    }
+#pragma unroll
+    for (int gi = 0; gi < K; ++gi) {
+      // lane-major threads sweep their groups from the last one
+      const int g = LM ? K - 1 - gi : gi;
+      typename M::P rho;
+      if constexpr (LM) {
+        rho = rho_lm;
+      } else {
+        MT ex = shift_down1(mincl[g]);
+        if (lane == WAVE - 1) ex = M::id();
+        rho = M::apply0(M::comb(M::comb(carry, s_mpre[g][wave]), ex));
+      }
       FT p[EPL];
       prefixes(g, p);
       float4 o[2];
@@ -470,7 +593,8 @@ __global__ __launch_bounds__(TH_) void k_scan_vjp(ScanVjpArgs a) {
           if (A::NXB == 2) f4set(o[1], j, xb[1]);
         }
       }
-      const int el = g * TH * EPL + tid * EPL;
+      if constexpr (LM) rho_lm = rho;
+      const int el = group_el<LM, K, TH, EPL>(g, tid);
       const int v = ti.valid - el;
       float *dst[2] = {a.xb0, a.xb1};
 #pragma unroll
