@@ -419,3 +419,51 @@ def vrbi_vjp(op: str, idx, m: int, Hbar, V):
     H = _f64(Hbar).reshape(max(int(m), 0), V.shape[1])
     out = [rbi_vjp(op, idx, m, H[:, j], V[:, j]) for j in range(V.shape[1])]
     return np.stack([o[0][:, 0] for o in out], 1), np.stack([o[1][:, 0] for o in out], 1)
+
+
+# -------------------------------------------------------------------------
+# d x d matrix-product scans, d >= 3 (the evaluation's matMul3x3 and
+# matMul5x5, Section 6.1 operator figure; their adjoint by the redundant
+# block-diagonal sparsity of Section 5.3): plain float64 loops.
+#   forward : P_0 = M_0, P_i = P_{i-1} M_i;
+#   adjoint : the reverse sweep of that loop -- Rbar_{n-1} = Pbar_{n-1},
+#             Rbar_i = Pbar_i + Rbar_{i+1} M_{i+1}^T, Mbar_i = P_{i-1}^T Rbar_i
+#             with P_{-1} = I (the adjoint of P_i = P_{i-1} M_i with respect
+#             to both factors).
+# Companions are norm-wise, as for the 2x2 product: every entry of a product
+# chain is bounded by the product of the factors' Frobenius norms.
+# -------------------------------------------------------------------------
+def matd_scan(M):
+    """M (n, d, d) -> (P (n, d, d), c (n,)): inclusive products and the
+    companion prod_{j<=i} ||M_j||_F."""
+    M = _f64(M)
+    n, d = M.shape[0], M.shape[1]
+    P = np.empty_like(M)
+    c = np.empty(n)
+    acc, ca = np.eye(d), 1.0
+    for i in range(n):
+        acc = M[i].copy() if i == 0 else acc @ M[i]
+        ca = (np.linalg.norm(M[i]) if i == 0 else ca * np.linalg.norm(M[i]))
+        P[i], c[i] = acc, ca
+    return P, c
+
+
+def matd_scan_vjp(M, Pbar):
+    """M, Pbar (n, d, d) -> (Mbar (n, d, d), c (n,)) with the norm-wise
+    companion ||P_{i-1}|| * (sum_{j>=i} ||Pbar_j|| prod_{i<k<=j} ||M_k||)."""
+    M, Pb = _f64(M), _f64(Pbar)
+    n, d = M.shape[0], M.shape[1]
+    P, cP = matd_scan(M)
+    Mb = np.empty_like(M)
+    c = np.empty(n)
+    R, cR = None, 0.0
+    for i in range(n - 1, -1, -1):
+        if i == n - 1:
+            R, cR = Pb[i].copy(), np.linalg.norm(Pb[i])
+        else:
+            R = Pb[i] + R @ M[i + 1].T
+            cR = np.linalg.norm(Pb[i]) + cR * np.linalg.norm(M[i + 1])
+        prev = P[i - 1] if i > 0 else np.eye(d)
+        Mb[i] = prev.T @ R
+        c[i] = (cP[i - 1] if i > 0 else 1.0) * cR
+    return Mb, c

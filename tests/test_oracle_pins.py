@@ -993,3 +993,54 @@ def test_sumprod_scan_closed_forms(seed):
     ref = np.array([sum(yb[i] * (S[i] - a[m_]) for i in range(m_, n)) for m_ in range(n)])
     np.testing.assert_array_equal(xb, ref)
     assert np.all(cx >= np.abs(xb))
+
+
+# -------------------------------------------------------------------------
+# d x d matrix-product scans (the evaluation's matMul3x3 / matMul5x5)
+# -------------------------------------------------------------------------
+@pytest.mark.parametrize("d", [2, 3, 5])
+def test_matd_scan_against_products_and_the_2x2_oracle(d):
+    rng = np.random.default_rng(40 + d)
+    n = 9
+    M = rng.integers(-2, 3, (n, d, d)).astype(float)
+    P, c = oracle.matd_scan(M)
+    for i in range(n):
+        np.testing.assert_array_equal(P[i], np.linalg.multi_dot(list(M[: i + 1])) if i > 0 else M[0])
+        assert c[i] >= np.abs(P[i]).max() - 1e-12
+    if d == 2:
+        rs, _ = oracle.scan_fwd("mat2", M.reshape(n, 4))
+        np.testing.assert_array_equal(P.reshape(n, 4), rs)
+        Pb = rng.integers(-2, 3, (n, 2, 2)).astype(float)
+        xb, _ = oracle.scan_vjp("mat2", Pb.reshape(n, 4), M.reshape(n, 4))
+        Mb, _ = oracle.matd_scan_vjp(M, Pb)
+        np.testing.assert_array_equal(Mb.reshape(n, 4), xb)
+
+
+@pytest.mark.parametrize("d", [3, 5])
+def test_matd_scan_vjp_central_differences_and_embedding(d):
+    rng = np.random.default_rng(50 + d)
+    n = 7
+    M = rng.standard_normal((n, d, d)) * 0.6
+    Pb = rng.standard_normal((n, d, d))
+    Mb, c = oracle.matd_scan_vjp(M, Pb)
+    assert np.all(c >= np.abs(Mb).max(axis=(1, 2)) - 1e-12)
+    f = lambda Z: float((oracle.matd_scan(Z)[0] * Pb).sum())
+    h = 1e-6
+    for (i, a, b) in ((0, 0, 1), (3, d - 1, 0), (6, 1, 2)):
+        E = np.zeros_like(M)
+        E[i, a, b] = h
+        fd = (f(M + E) - f(M - E)) / (2 * h)
+        assert abs(fd - Mb[i, a, b]) <= 1e-6 * (1 + abs(fd))
+    # a 2x2 block embedded with an identity block scans (and adjoints) as the 2x2 product
+    M2 = rng.standard_normal((n, 2, 2))
+    Pb2 = rng.standard_normal((n, 2, 2))
+    Me = np.tile(np.eye(d), (n, 1, 1))
+    Me[:, :2, :2] = M2
+    Pbe = np.zeros((n, d, d))
+    Pbe[:, :2, :2] = Pb2
+    Pe, _ = oracle.matd_scan(Me)
+    rs, _ = oracle.scan_fwd("mat2", M2.reshape(n, 4))
+    np.testing.assert_allclose(Pe[:, :2, :2].reshape(n, 4), rs, rtol=1e-13, atol=1e-13)
+    Mbe, _ = oracle.matd_scan_vjp(Me, Pbe)
+    xb, _ = oracle.scan_vjp("mat2", Pb2.reshape(n, 4), M2.reshape(n, 4))
+    np.testing.assert_allclose(Mbe[:, :2, :2].reshape(n, 4), xb, rtol=1e-12, atol=1e-12)
