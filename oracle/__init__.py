@@ -430,12 +430,14 @@ def vrbi_vjp(op: str, idx, m: int, Hbar, V):
 #             Rbar_i = Pbar_i + Rbar_{i+1} M_{i+1}^T, Mbar_i = P_{i-1}^T Rbar_i
 #             with P_{-1} = I (the adjoint of P_i = P_{i-1} M_i with respect
 #             to both factors).
-# Companions are norm-wise, as for the 2x2 product: every entry of a product
-# chain is bounded by the product of the factors' Frobenius norms.
+# Companions are norm-wise: every entry of a product chain is bounded by the
+# product of the factors' spectral norms (Frobenius norms would grow as
+# sqrt(d) per factor even for orthogonal factors and leave the float range).
 # -------------------------------------------------------------------------
 def matd_scan(M):
     """M (n, d, d) -> (P (n, d, d), c (n,)): inclusive products and the
-    companion prod_{j<=i} ||M_j||_F."""
+    companion prod_{j<=i} ||M_j||_2 (spectral norm: it bounds ||P_i||_2 and
+    so every entry, and it stays 1 along chains of orthogonal factors)."""
     M = _f64(M)
     n, d = M.shape[0], M.shape[1]
     P = np.empty_like(M)
@@ -443,14 +445,15 @@ def matd_scan(M):
     acc, ca = np.eye(d), 1.0
     for i in range(n):
         acc = M[i].copy() if i == 0 else acc @ M[i]
-        ca = (np.linalg.norm(M[i]) if i == 0 else ca * np.linalg.norm(M[i]))
+        ca = (np.linalg.norm(M[i], 2) if i == 0 else ca * np.linalg.norm(M[i], 2))
         P[i], c[i] = acc, ca
     return P, c
 
 
 def matd_scan_vjp(M, Pbar):
     """M, Pbar (n, d, d) -> (Mbar (n, d, d), c (n,)) with the norm-wise
-    companion ||P_{i-1}|| * (sum_{j>=i} ||Pbar_j|| prod_{i<k<=j} ||M_k||)."""
+    companion ||P_{i-1}|| * (sum_{j>=i} ||Pbar_j|| prod_{i<k<=j} ||M_k||),
+    spectral norms throughout."""
     M, Pb = _f64(M), _f64(Pbar)
     n, d = M.shape[0], M.shape[1]
     P, cP = matd_scan(M)
@@ -459,10 +462,10 @@ def matd_scan_vjp(M, Pbar):
     R, cR = None, 0.0
     for i in range(n - 1, -1, -1):
         if i == n - 1:
-            R, cR = Pb[i].copy(), np.linalg.norm(Pb[i])
+            R, cR = Pb[i].copy(), np.linalg.norm(Pb[i], 2)
         else:
             R = Pb[i] + R @ M[i + 1].T
-            cR = np.linalg.norm(Pb[i]) + cR * np.linalg.norm(M[i + 1])
+            cR = np.linalg.norm(Pb[i], 2) + cR * np.linalg.norm(M[i + 1], 2)
         prev = P[i - 1] if i > 0 else np.eye(d)
         Mb[i] = prev.T @ R
         c[i] = (cP[i - 1] if i > 0 else 1.0) * cR

@@ -218,3 +218,32 @@ def autograd(B: int = 64, T: int = 1 << 16, m: int = 65536, seed: int = BASE_SEE
         idx=r[3].integers(0, m, (B, T), dtype=np.int64).astype(np.int32),
         m=m,
     )
+
+
+# --------------------------------------------------------------------------
+# workload: d x d matrix-product scans (3x3, 5x5)
+# --------------------------------------------------------------------------
+def orthogonal_matrices(rng, n: int, d: int) -> np.ndarray:
+    """n Haar-random orthogonal d x d matrices (n, d, d), float32: the Q of
+    a QR factorisation of a Gaussian matrix, columns signed so that R has a
+    positive diagonal."""
+    G = rng.standard_normal((n, d, d))
+    Q, R = np.linalg.qr(G)
+    sgn = np.sign(np.diagonal(R, axis1=1, axis2=2))
+    sgn[sgn == 0] = 1.0
+    return f32(Q * sgn[:, None, :])
+
+
+def matd(d: int, n: int, batch: int = 1, seed: int = BASE_SEED + 6, ensemble: str = "orth"):
+    """M (batch, n, d, d) and an output adjoint Pbar ~ N(0, 1) of the same
+    shape.  ``orth``: Haar-orthogonal factors (products keep unit spectral
+    norm); ``near``: orthogonal factors times (1 + 0.01 N(0, 1)) entrywise
+    perturbations, so that the products drift slowly in norm."""
+    r = _streams(seed + 100 * d, 3)
+    M = orthogonal_matrices(r[0], batch * n, d).astype(np.float64)
+    if ensemble == "near":
+        M = M * (1.0 + 0.01 * r[2].standard_normal(M.shape))
+    elif ensemble != "orth":
+        raise ValueError(ensemble)
+    return dict(M=f32(M).reshape(batch, n, d, d),
+                Pbar=f32(r[1].standard_normal((batch, n, d, d))))
