@@ -358,6 +358,35 @@ int pcad_vrbi_vjp(int op, int64_t batch, int64_t n, int64_t d, int64_t m, const 
                   void *stream);
 
 /*
+ * Scans of d x d matrix products, d = 3 or 5 (the 3x3 and 5x5 matrix
+ * multiplication operators of the evaluation), and their adjoints (Section
+ * 5.3, redundant block-diagonal sparsity: the adjoint of P_i is a d x d
+ * matrix and the map that carries it, r -> Pbar_i + r M_{i+1}^T, has a d x d
+ * multiplier, so an adjoint map is 2 d^2 floats).
+ *   M   : [batch][n][d*d] row-major d x d matrices, 16-byte aligned.
+ *   P   : [batch][n][d*d], P_i = M_0 M_1 ... M_i per row.
+ *   saved: the exclusive prefix product of every tile (pcad_matd_query),
+ *          from which the adjoint recomputes the forward prefixes.
+ *   Pbar / Mbar: adjoints in the layout of P / M; Mbar_i = P_{i-1}^T Rbar_i
+ *          with Rbar_i = Pbar_i + Rbar_{i+1} M_{i+1}^T, P_{-1} = I;
+ *          PCAD_ACCUMULATE adds into Mbar.
+ *   ws  : workspace of pcad_matd_query's size, 256-byte aligned; it may be
+ *         shared with the other calls on the same stream (between calls it
+ *         holds only zeros past the control block).
+ * Errors: PCAD_E_INVALID_ARG for d other than 3 or 5, negative sizes or
+ * unknown flags; PCAD_E_SIZE for n > 2^31-1 or more than 2^31-1 tiles;
+ * PCAD_E_NULLPTR / PCAD_E_MISALIGNED / PCAD_E_WORKSPACE as for the scans.
+ * No compute happens on an error; batch == 0 or n == 0 is a no-op.
+ */
+int pcad_matd_query(int d, int64_t batch, int64_t n, unsigned flags, size_t *saved_bytes,
+                    size_t *workspace_bytes);
+int pcad_matd_scan_fwd(int d, int64_t batch, int64_t n, const float *M, float *P, void *saved,
+                       unsigned flags, void *ws, size_t ws_bytes, void *stream);
+int pcad_matd_scan_vjp(int d, int64_t batch, int64_t n, const float *M, const void *saved,
+                       const float *Pbar, float *Mbar, unsigned flags, void *ws, size_t ws_bytes,
+                       void *stream);
+
+/*
  * Tuning knobs: launch parameters an autotuner may set (the block size of the
  * scan kernels per operator and direction, the bin count up to which
  * reduce-by-index keeps private LDS histograms, elements per histogram

@@ -75,6 +75,9 @@ def lib():
             "pcad_vscan_vjp": ([I, I64, I64, I64, P, P, P, P, U, P, SZ, P, SZ, P], I),
             "pcad_vrbi_fwd": ([I, I64, I64, I64, I64, P, P, P, P, U, P, SZ, P, SZ, P], I),
             "pcad_vrbi_vjp": ([I, I64, I64, I64, I64, P, P, P, P, P, U, P, SZ, P, SZ, P], I),
+            "pcad_matd_query": ([I, I64, I64, U, PSZ, PSZ], I),
+            "pcad_matd_scan_fwd": ([I, I64, I64, P, P, P, U, P, SZ, P], I),
+            "pcad_matd_scan_vjp": ([I, I64, I64, P, P, P, P, U, P, SZ, P], I),
             "pcad_knob_count": ([], I),
             "pcad_knob_name": ([I], ctypes.c_char_p),
             "pcad_knob_get": ([ctypes.c_char_p, ctypes.POINTER(I64)], I),
@@ -430,6 +433,56 @@ def vscan_vjp(op: str, x, saved, ybar, out=None, accumulate: bool = False):
     check(lib().pcad_vscan_vjp(OPS[op], batch, n, d, _ptr(x), _ptr(saved), _ptr(ybar.contiguous()),
                                _ptr(out), ACCUMULATE if accumulate else 0, _ptr(ws), ws.numel(),
                                _ptr(tmp), tmp.numel(), _stream(dev)), "pcad_vscan_vjp")
+    return out
+
+
+# ---------------------------------------------------------------------------
+# scans of d x d matrix products (d = 3, 5)
+# ---------------------------------------------------------------------------
+def matd_query(d: int, batch: int, n: int):
+    s, w = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    check(lib().pcad_matd_query(d, batch, n, 0, ctypes.byref(s), ctypes.byref(w)),
+          "pcad_matd_query")
+    return s.value, w.value
+
+
+def _mdshape(M: torch.Tensor):
+    """(d, batch, n, lead) of matrices (..., n, d, d)."""
+    if M.dim() < 3 or M.shape[-1] != M.shape[-2]:
+        raise PcadError("matd calls expect matrices of shape (..., n, d, d)")
+    lead = tuple(M.shape[:-3])
+    batch = 1
+    for t in lead:
+        batch *= t
+    return M.shape[-1], batch, M.shape[-3], lead
+
+
+def matd_scan_fwd(M: torch.Tensor):
+    """M (..., n, d, d) -> (P, saved), P_i = M_0 ... M_i along n."""
+    _dev_check(M)
+    d, batch, n, lead = _mdshape(M)
+    s_b, w_b = matd_query(d, batch, n)
+    dev = M.device
+    P = torch.empty_like(M)
+    saved = torch.empty(max(s_b, 16), dtype=torch.uint8, device=dev)
+    ws = workspace(w_b, dev)
+    check(lib().pcad_matd_scan_fwd(d, batch, n, _ptr(M), _ptr(P), _ptr(saved), 0, _ptr(ws),
+                                   ws.numel(), _stream(dev)), "pcad_matd_scan_fwd")
+    return P, saved
+
+
+def matd_scan_vjp(M, saved, Pbar, out=None, accumulate: bool = False):
+    """Adjoint of matd_scan_fwd: returns M_bar (shape of M)."""
+    _dev_check(M)
+    d, batch, n, lead = _mdshape(M)
+    s_b, w_b = matd_query(d, batch, n)
+    dev = M.device
+    out = torch.empty_like(M) if out is None else out
+    _dev_check(out)
+    ws = workspace(w_b, dev)
+    check(lib().pcad_matd_scan_vjp(d, batch, n, _ptr(M), _ptr(saved), _ptr(Pbar.contiguous()),
+                                   _ptr(out), ACCUMULATE if accumulate else 0, _ptr(ws),
+                                   ws.numel(), _stream(dev)), "pcad_matd_scan_vjp")
     return out
 
 

@@ -427,3 +427,62 @@ int pcad_vrbi_vjp(int op, int64_t batch, int64_t n, int64_t d, int64_t m, const 
 }
 
 }  // extern "C"
+
+namespace {
+
+int check_matd(int d, int64_t batch, int64_t n, unsigned flags) {
+  if (d != 3 && d != 5) return PCAD_E_INVALID_ARG;
+  if (flags & ~kKnownFlags) return PCAD_E_INVALID_ARG;
+  if (batch < 0 || n < 0) return PCAD_E_INVALID_ARG;
+  if (n > kMaxN) return PCAD_E_SIZE;
+  if (batch > 0 && n > 0 && batch > kMaxTotal / n) return PCAD_E_SIZE;
+  if (matd_tiles(d, batch, n) > 2147483647LL) return PCAD_E_SIZE;
+  return PCAD_OK;
+}
+
+int check_matd_ws(int d, int64_t batch, int64_t n, const void *ws, size_t ws_bytes) {
+  if (ws_bytes < matd_ws_bytes(d, batch, n)) return PCAD_E_WORKSPACE;
+  if (!ws) return PCAD_E_NULLPTR;
+  if ((uintptr_t)ws & 255u) return PCAD_E_MISALIGNED;
+  return PCAD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pcad_matd_query(int d, int64_t batch, int64_t n, unsigned flags, size_t *saved_bytes,
+                    size_t *workspace_bytes) {
+  PCAD_TRY(check_matd(d, batch, n, flags));
+  if (saved_bytes) *saved_bytes = matd_saved_bytes(d, batch, n);
+  if (workspace_bytes) *workspace_bytes = matd_ws_bytes(d, batch, n);
+  return PCAD_OK;
+}
+
+int pcad_matd_scan_fwd(int d, int64_t batch, int64_t n, const float *M, float *P, void *saved,
+                       unsigned flags, void *ws, size_t ws_bytes, void *stream) {
+  PCAD_TRY(check_matd(d, batch, n, flags));
+  if (batch == 0 || n == 0) return PCAD_OK;
+  PCAD_TRY(need(M));
+  PCAD_TRY(need(P));
+  PCAD_TRY(need(saved));
+  PCAD_TRY(check_matd_ws(d, batch, n, ws, ws_bytes));
+  return hip_status(matd_fwd_launch(d, batch, n, M, P, static_cast<float *>(saved), ws,
+                                    (hipStream_t)stream));
+}
+
+int pcad_matd_scan_vjp(int d, int64_t batch, int64_t n, const float *M, const void *saved,
+                       const float *Pbar, float *Mbar, unsigned flags, void *ws, size_t ws_bytes,
+                       void *stream) {
+  PCAD_TRY(check_matd(d, batch, n, flags));
+  if (batch == 0 || n == 0) return PCAD_OK;
+  PCAD_TRY(need(M));
+  PCAD_TRY(need(saved));
+  PCAD_TRY(need(Pbar));
+  PCAD_TRY(need(Mbar));
+  PCAD_TRY(check_matd_ws(d, batch, n, ws, ws_bytes));
+  return hip_status(matd_vjp_launch(d, batch, n, M, static_cast<const float *>(saved), Pbar, Mbar,
+                                    (flags & PCAD_ACCUMULATE) != 0, ws, (hipStream_t)stream));
+}
+
+}  // extern "C"

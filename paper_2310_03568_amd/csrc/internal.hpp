@@ -81,6 +81,16 @@ hipError_t vrbi_vjp_launch(int op, int64_t batch, int64_t n, int64_t d, int64_t 
                            const float *hbar, float *vbar, bool accumulate, void *ws, void *tmp,
                            hipStream_t s);
 
+// d x d matrix-product scans, d = 3 or 5 (matd.hip)
+int64_t matd_tiles(int d, int64_t batch, int64_t n);
+size_t matd_saved_bytes(int d, int64_t batch, int64_t n);
+size_t matd_ws_bytes(int d, int64_t batch, int64_t n);
+hipError_t matd_fwd_launch(int d, int64_t batch, int64_t n, const float *x, float *y,
+                           float *saved, void *ws, hipStream_t s);
+hipError_t matd_vjp_launch(int d, int64_t batch, int64_t n, const float *x, const float *saved,
+                           const float *ybar, float *xbar, bool accumulate, void *ws,
+                           hipStream_t s);
+
 // scan
 int scan_tile_size(int op);
 int scan_elem_floats(int op);

@@ -151,3 +151,33 @@ def test_vectorised_queries(L):
     assert vq(0, 4, 1, 10, 2)[0] == 2   # LINREC: unsupported
     assert vq(0, 0, 1, 10, 0)[0] == 1   # d = 0
     assert vq(0, 9, 1, 10, 2)[0] == 1   # no operator 9
+
+
+def test_matd_queries_and_validation(L):
+    def mq(d, batch, n, flags=0):
+        s, w = ctypes.c_size_t(0), ctypes.c_size_t(0)
+        st = L.pcad_matd_query(d, batch, n, flags, ctypes.byref(s), ctypes.byref(w))
+        return st, s.value, w.value
+    # 3x3: tiles of 1024 elements, one 3x3 prefix saved per tile; the
+    # workspace holds the tile values (2 d^2 floats) and the tile adjoints
+    st, s, w = mq(3, 2, 3000)
+    assert st == 0 and s == 2 * 3 * 9 * 4 and w >= 256 + 6 * 18 * 4 + 6 * 9 * 4
+    # 5x5: tiles of 512 elements
+    st, s, w = mq(5, 1, 1025)
+    assert st == 0 and s == 3 * 25 * 4 and w >= 256 + 3 * 50 * 4 + 3 * 25 * 4
+    assert mq(2, 1, 10)[0] == 1 and mq(4, 1, 10)[0] == 1   # only d = 3 and 5
+    assert mq(3, -1, 10)[0] == 1 and mq(3, 1, -1)[0] == 1
+    assert mq(3, 1, 10, flags=0x100)[0] == 1
+    assert mq(5, 1, 1 << 31)[0] == 5                         # n beyond 2^31 - 1
+    st, s, w = mq(3, 0, 100)
+    assert st == 0 and s == 0
+    # host checks before any launch: null operands, small workspace, no-ops
+    assert L.pcad_matd_scan_fwd(3, 1, 10, None, None, None, 0, None, 0, None) == 3
+    assert L.pcad_matd_scan_fwd(3, 0, 10, None, None, None, 0, None, 0, None) == 0
+    assert L.pcad_matd_scan_vjp(5, 1, 0, None, None, None, None, 0, None, 0, None) == 0
+    assert L.pcad_matd_scan_vjp(4, 1, 10, None, None, None, None, 0, None, 0, None) == 1
+    buf = (ctypes.c_float * 4096)()
+    p = ctypes.addressof(buf)
+    p16 = (p + 15) & ~15
+    assert L.pcad_matd_scan_fwd(3, 1, 10, p16, p16, p16, 0, p16, 8, None) == 6
+    assert L.pcad_matd_scan_vjp(3, 1, 10, p16 + 4, p16, p16, p16, 0, None, 0, None) == 4

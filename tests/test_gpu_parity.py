@@ -741,3 +741,63 @@ def test_scan_sumprod(pcad, batch, n):
     assert ws_error() == 0
     with pytest.raises(pcad.PcadError):
         pcad.scan_vjp_checkpoint("sumprod", X, None, dev(y), None, dev(yb))
+
+
+# ---------------------------------------------------------------------------
+# scans of d x d matrix products (3x3, 5x5)
+# ---------------------------------------------------------------------------
+def _matd_gate(g, r, c, what):
+    d = r.shape[-1]
+    cc = np.repeat(c[:, None], d * d, axis=1).reshape(r.shape)
+    assert_gate(g, r, cc, RTOL["mat2"], what=what)
+
+
+def _ws_tail_zero(pcad, d, batch, n):
+    _, w_b = pcad.matd_query(d, batch, n)
+    torch.cuda.synchronize()
+    for buf in pcad._ws.values():
+        assert int(buf[256:w_b].count_nonzero().item()) == 0
+
+
+@pytest.mark.parametrize("d", [3, 5])
+@pytest.mark.parametrize("batch,n,ens", [(1, 1, "orth"), (1, 700, "near"), (2, 3 * 1024 + 37, "orth"),
+                                         (3, 2 * 512 + 1, "near"), (1, 257 * 512 + 11, "orth")])
+def test_matd_scan(pcad, d, batch, n, ens):
+    """P_i = M_0 ... M_i and M_bar_i = P_{i-1}^T R_bar_i against the float64
+    loops, over several tiles, a ragged tail and (last case) more tiles per
+    row than one block of the tile scan holds."""
+    from workloads import matd
+    w = matd(d, n, batch, ensemble=ens)
+    print(f"matd d={d} batch={batch} n={n} {ens}", flush=True)
+    M = dev(w["M"])
+    P, saved = pcad.matd_scan_fwd(M)
+    Mb = pcad.matd_scan_vjp(M, saved, dev(w["Pbar"]))
+    P, Mb = host(P), host(Mb)
+    for r in range(batch):
+        rs, c = oracle.matd_scan(w["M"][r])
+        _matd_gate(P[r], rs, c, f"matd{d} scan row {r}")
+        xb, cx = oracle.matd_scan_vjp(w["M"][r], w["Pbar"][r])
+        _matd_gate(Mb[r], xb, cx, f"matd{d} vjp row {r}")
+    _ws_tail_zero(pcad, d, batch, n)
+
+
+@pytest.mark.parametrize("d", [3, 5])
+def test_matd_scan_accumulate_and_empty(pcad, d):
+    from workloads import matd
+    w = matd(d, 1500, 2, ensemble="near")
+    M = dev(w["M"])
+    P, saved = pcad.matd_scan_fwd(M)
+    base = np.random.default_rng(d).standard_normal(w["M"].shape).astype(np.float32)
+    out = dev(base)
+    pcad.matd_scan_vjp(M, saved, dev(w["Pbar"]), out=out, accumulate=True)
+    g = host(out) - base
+    for r in range(2):
+        xb, cx = oracle.matd_scan_vjp(w["M"][r], w["Pbar"][r])
+        cc = np.repeat(cx[:, None], d * d, axis=1).reshape(xb.shape) + np.abs(base[r])
+        assert_gate(g[r], xb, cc, RTOL["mat2"], what=f"matd{d} accumulate")
+    E = torch.empty((3, 0, d, d), device="cuda")
+    P0, s0 = pcad.matd_scan_fwd(E)
+    assert P0.shape == E.shape
+    assert pcad.matd_scan_vjp(E, s0, E).shape == E.shape
+    with pytest.raises(pcad.PcadError):
+        pcad.matd_scan_fwd(torch.empty((4, 4, 4), device="cuda"))
