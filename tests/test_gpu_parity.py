@@ -761,12 +761,15 @@ def _ws_tail_zero(pcad, d, batch, n):
 
 @pytest.mark.parametrize("d", [3, 5])
 @pytest.mark.parametrize("batch,n,ens", [(1, 1, "orth"), (1, 700, "near"), (2, 3 * 1024 + 37, "orth"),
-                                         (3, 2 * 512 + 1, "near"), (1, 257 * 512 + 11, "orth")])
+                                         (3, 2 * 512 + 1, "near"), (1, -1, "orth"), (2, -2, "orth")])
 def test_matd_scan(pcad, d, batch, n, ens):
     """P_i = M_0 ... M_i and M_bar_i = P_{i-1}^T R_bar_i against the float64
-    loops, over several tiles, a ragged tail and (last case) more tiles per
-    row than one block of the tile scan holds."""
+    loops, over several tiles, a ragged tail and (n < 0) more tiles per row
+    than one chunk of the tile scan holds (256 tiles of 1024 3x3 or 512 5x5
+    elements)."""
     from workloads import matd
+    if n < 0:
+        n = (256 * -n + 1) * (1024 if d == 3 else 512) + 11
     w = matd(d, n, batch, ensemble=ens)
     print(f"matd d={d} batch={batch} n={n} {ens}", flush=True)
     M = dev(w["M"])
