@@ -18,6 +18,8 @@ Workloads:
   vec     -- vectorised scan (map2 --op) over 2^20 rows of 64 floats, with
              vectorised reduce and reduce-by-index timings as extras.
   autograd -- 64 x 2^16 loss forward + backward through torch.autograd.
+  matd    -- scan of --d x --d matrix products (3 or 5), n = 10^7
+             (the evaluation's smaller dataset), Haar-orthogonal factors.
 
 `value` is backward elements/s: n / (mean duration of the adjoint kernel,
 HIP events on the stream the kernel runs on).  `roofline` prices that kernel
@@ -47,6 +49,7 @@ KERNEL_SOURCES = {
     "k_seg_bwd": ("batched.hip", "device.hpp", "adjoint.hpp"),
     "k_scan_vjp": ("scan.hip", "device.hpp", "adjoint.hpp"),
     "k_rbi_vjp": ("rbi.hip", "device.hpp"),
+    "k_md_vapply": ("matd.hip", "device.hpp"),
 }
 
 
@@ -119,6 +122,60 @@ def bench_mat2(args, pcad, torch, np):
                 kernel="k_scan_vjp<MAT2>", inputs=w, out=lambda: (mb,),
                 cfg={"workload": "2x2 matrix-product scan, n=2^24, fp32 (entries ~N(0,0.5))",
                      "n": n, "op": "mat2", "combinator": "scan"})
+
+
+def bench_matd(args, pcad, torch, np):
+    from workloads import matd
+    d = args.d
+    n = args.n or 10_000_000
+    w = matd(d, n)
+    dev = torch.device("cuda:0")
+    M = torch.from_numpy(w["M"][0]).to(dev)
+    PB = torch.from_numpy(w["Pbar"][0]).to(dev)
+    mb = torch.empty_like(M)
+
+    def fwd():
+        P, saved = pcad.matd_scan_fwd(M)
+        return P, None, saved
+
+    def bwd(saved):
+        pcad.matd_scan_vjp(M, saved, PB, out=mb)
+
+    e = 4 * d * d
+    return dict(n=n, fwd=fwd, bwd=bwd, bytes_fwd=2 * e * n, bytes_bwd=3 * e * n,
+                kernel=f"k_md_vapply<{d}>", inputs=w, out=lambda: (mb,), dev=(M, PB),
+                cfg={"workload": f"{d}x{d} matrix-product scan, n={n}, fp32 (Haar-orthogonal factors)",
+                     "n": n, "op": f"mat{d}", "combinator": "scan"})
+
+
+def matd_parity(b, torch, np, sample: int = 1 << 14):
+    """Forward: the timed run's first `sample` outputs against the oracle on
+    that prefix (a scan prefix depends on nothing after it).  Adjoint: the
+    library on the prefix alone against the oracle.  The oracle's adjoint
+    time on the prefix is the cpu_baseline."""
+    import oracle
+    import paper_2310_03568_amd as pcad
+    from oracle.gate import RTOL, gate
+    M, PB = b["dev"]
+    w = b["inputs"]
+    Mh, Pbh = w["M"][0][:sample], w["Pbar"][0][:sample]
+    P, _, _ = b["fwd"]()
+    P = P[:sample].cpu().numpy()
+    Ms = M[:sample].contiguous()
+    _, saved = pcad.matd_scan_fwd(Ms)
+    g = pcad.matd_scan_vjp(Ms, saved, PB[:sample].contiguous()).cpu().numpy()
+    rs, c = oracle.matd_scan(Mh)
+    t0 = time.perf_counter()
+    xb, cx = oracle.matd_scan_vjp(Mh, Pbh)
+    dt = time.perf_counter() - t0
+    d2 = Mh.shape[-1] ** 2
+    r1 = gate(P, rs, np.repeat(c, d2).reshape(rs.shape), RTOL["mat2"])
+    r2 = gate(g, xb, np.repeat(cx, d2).reshape(xb.shape), RTOL["mat2"])
+    cpu = {"value": sample / dt, "unit": "elem/s", "cores": 1, "kind": "oracle",
+           "sample": f"first {sample} elements of the row: oracle adjoint incl. its forward, fp64, {dt:.2f} s"}
+    par = dict(ok=r1["ok"] and r2["ok"] and r1["n_range_exceeded"] == 0 and r2["n_range_exceeded"] == 0,
+               max_rel_fwd=r1["max_rel"], max_rel_bwd=r2["max_rel"], sample=sample)
+    return cpu, par
 
 
 def bench_segmented(args, pcad, torch, np):
@@ -562,9 +619,10 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="segmented",
-                    choices=["segmented", "linrec", "mat2", "rbi", "vec", "autograd"])
+                    choices=["segmented", "linrec", "mat2", "rbi", "vec", "autograd", "matd"])
     ap.add_argument("--op", default="add", choices=["add", "mul", "min", "max", "sumprod"],
                     help="operator of the rbi workload")
+    ap.add_argument("--d", type=int, default=3, choices=[3, 5], help="matrix size of the matd workload")
     ap.add_argument("--bins", type=int, default=65536, help="bins of the rbi workload")
     ap.add_argument("--dist", default="uniform", choices=["uniform", "zipf"],
                     help="key distribution of the rbi workload")
@@ -590,7 +648,8 @@ def main():
 
     pcad.lib()
     b = {"linrec": bench_linrec, "mat2": bench_mat2, "segmented": bench_segmented,
-         "rbi": bench_rbi, "vec": bench_vec, "autograd": bench_autograd}[args.workload](args, pcad, torch, np)
+         "rbi": bench_rbi, "vec": bench_vec, "autograd": bench_autograd,
+         "matd": bench_matd}[args.workload](args, pcad, torch, np)
     torch.cuda.synchronize()
 
     for _ in range(args.warmup):
@@ -646,12 +705,16 @@ def main():
             cpu, par = rbi_parity(b, np)
         elif args.workload == "vec":
             cpu, par = vec_parity(b, np)
+        elif args.workload == "matd":
+            cpu, par = matd_parity(b, torch, np)
         else:
             cpu, par = cpu_baseline_and_parity(args.workload, b, np)
 
     wl_key = args.workload
     if args.workload == "rbi":
         wl_key = f"rbi-{args.op}-m{args.bins}-{args.dist}"
+    if args.workload == "matd":
+        wl_key = f"matd{args.d}-n{n}"
     out = {
         "metric": METRIC,
         "value": n / tb,
