@@ -752,7 +752,17 @@ def _matd_gate(g, r, c, what):
     assert_gate(g, r, cc, RTOL["mat2"], what=what)
 
 
+def _ws_clear(pcad):
+    """Zero every cached workspace (other calls leave tagged status words
+    there, which the product scans may overwrite but need not clear)."""
+    torch.cuda.synchronize()
+    for buf in pcad._ws.values():
+        buf.zero_()
+    torch.cuda.synchronize()
+
+
 def _ws_tail_zero(pcad, d, batch, n):
+    """The product scans leave no temporaries behind them."""
     _, w_b = pcad.matd_query(d, batch, n)
     torch.cuda.synchronize()
     for buf in pcad._ws.values():
@@ -773,6 +783,7 @@ def test_matd_scan(pcad, d, batch, n, ens):
     w = matd(d, n, batch, ensemble=ens)
     print(f"matd d={d} batch={batch} n={n} {ens}", flush=True)
     M = dev(w["M"])
+    _ws_clear(pcad)
     P, saved = pcad.matd_scan_fwd(M)
     Mb = pcad.matd_scan_vjp(M, saved, dev(w["Pbar"]))
     P, Mb = host(P), host(Mb)
