@@ -470,3 +470,42 @@ def matd_scan_vjp(M, Pbar):
         Mb[i] = prev.T @ R
         c[i] = (cP[i - 1] if i > 0 else 1.0) * cR
     return Mb, c
+
+
+def matd_reduce(M):
+    """M (n, d, d) -> (Y = M_0 M_1 ... M_{n-1}, c = prod ||M_j||_2); the
+    identity (c = 1) for n = 0 (the operator's neutral element)."""
+    M = _f64(M)
+    n, d = M.shape[0], M.shape[1]
+    Y, c = np.eye(d), 1.0
+    for i in range(n):
+        Y = Y @ M[i]
+        c *= np.linalg.norm(M[i], 2)
+    return Y, c
+
+
+def matd_reduce_vjp(M, Ybar):
+    """Section 3.1's rule for a general associative operator, written out for
+    the matrix product: with L_i = M_0 ... M_{i-1} and R_i = M_{i+1} ... M_{n-1}
+    (identities when empty), Mbar_i = L_i^T Ybar R_i^T; companion
+    ||L_i|| ||Ybar|| ||R_i|| (spectral norms, each bounded by the product of
+    its factors' norms)."""
+    M, Yb = _f64(M), _f64(Ybar)
+    n, d = M.shape[0], M.shape[1]
+    L = np.empty((n, d, d))
+    cL = np.empty(n)
+    acc, ca = np.eye(d), 1.0
+    for i in range(n):
+        L[i], cL[i] = acc, ca
+        acc = acc @ M[i]
+        ca *= np.linalg.norm(M[i], 2)
+    Mb = np.empty_like(M)
+    c = np.empty(n)
+    acc, ca = np.eye(d), 1.0
+    yn = np.linalg.norm(Yb, 2)
+    for i in range(n - 1, -1, -1):
+        Mb[i] = L[i].T @ Yb @ acc.T
+        c[i] = cL[i] * yn * ca
+        acc = M[i] @ acc
+        ca *= np.linalg.norm(M[i], 2)
+    return Mb, c

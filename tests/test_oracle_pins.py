@@ -1044,3 +1044,41 @@ def test_matd_scan_vjp_central_differences_and_embedding(d):
     Mbe, _ = oracle.matd_scan_vjp(Me, Pbe)
     xb, _ = oracle.scan_vjp("mat2", Pb2.reshape(n, 4), M2.reshape(n, 4))
     np.testing.assert_allclose(Mbe[:, :2, :2].reshape(n, 4), xb, rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("d", [2, 3, 5])
+def test_matd_reduce_against_products_scan_and_differences(d):
+    """The reduce is the scan's last prefix; its adjoint is the scan adjoint
+    seeded at the last element only (Section 3.1's rule and Section 5's
+    recurrence must agree); central differences; the 2x2 case against the
+    2x2 reduce oracle; the empty reduce is the identity."""
+    rng = np.random.default_rng(60 + d)
+    n = 8
+    M = rng.integers(-2, 3, (n, d, d)).astype(float)
+    Y, c = oracle.matd_reduce(M)
+    np.testing.assert_array_equal(Y, np.linalg.multi_dot(list(M)))
+    assert c >= np.abs(Y).max() - 1e-12
+    Yb = rng.integers(-2, 3, (d, d)).astype(float)
+    Mb, cm = oracle.matd_reduce_vjp(M, Yb)
+    Pb = np.zeros((n, d, d))
+    Pb[-1] = Yb
+    Ms, _ = oracle.matd_scan_vjp(M, Pb)
+    np.testing.assert_array_equal(Mb, Ms)
+    assert np.all(cm >= np.abs(Mb).max(axis=(1, 2)) - 1e-12)
+    Mg = rng.standard_normal((n, d, d)) * 0.7
+    Mbg, _ = oracle.matd_reduce_vjp(Mg, Yb)
+    f = lambda Z: float((oracle.matd_reduce(Z)[0] * Yb).sum())
+    h = 1e-6
+    for (i, a, b) in ((0, 1, 0), (4, 0, d - 1), (7, d - 1, 1)):
+        E = np.zeros_like(Mg)
+        E[i, a, b] = h
+        fd = (f(Mg + E) - f(Mg - E)) / (2 * h)
+        assert abs(fd - Mbg[i, a, b]) <= 1e-6 * (1 + abs(fd))
+    if d == 2:
+        y2 = oracle.reduce_fwd("mat2", M.reshape(n, 4))["y"]
+        np.testing.assert_array_equal(y2.reshape(2, 2), Y)
+        xb, _ = oracle.reduce_vjp("mat2", Yb.reshape(4), M.reshape(n, 4))
+        np.testing.assert_array_equal(xb.reshape(n, 2, 2), Mb)
+    Y0, c0 = oracle.matd_reduce(np.zeros((0, d, d)))
+    np.testing.assert_array_equal(Y0, np.eye(d))
+    assert c0 == 1.0
