@@ -387,6 +387,21 @@ int pcad_matd_scan_vjp(int d, int64_t batch, int64_t n, const float *M, const vo
                        void *stream);
 
 /*
+ * Reduce of d x d matrix products, d = 3 or 5: Y = M_0 M_1 ... M_{n-1} per row
+ * (the identity for n == 0), and its adjoint by the general rule of Section
+ * 3.1, Mbar_i = L_i^T Ybar R_i^T with L_i = M_0 ... M_{i-1} and
+ * R_i = M_{i+1} ... M_{n-1}.
+ *   Y, Ybar: [batch][d*d].  M, Mbar, flags as for the scan.
+ *   saved / ws: the sizes pcad_matd_query reports (the same as the scan's).
+ * Errors as for the scans; batch == 0 is a no-op.
+ */
+int pcad_matd_reduce_fwd(int d, int64_t batch, int64_t n, const float *M, float *Y, void *saved,
+                         unsigned flags, void *ws, size_t ws_bytes, void *stream);
+int pcad_matd_reduce_vjp(int d, int64_t batch, int64_t n, const float *M, const void *saved,
+                         const float *Ybar, float *Mbar, unsigned flags, void *ws,
+                         size_t ws_bytes, void *stream);
+
+/*
  * Tuning knobs: launch parameters an autotuner may set (the block size of the
  * scan kernels per operator and direction, the bin count up to which
  * reduce-by-index keeps private LDS histograms, elements per histogram

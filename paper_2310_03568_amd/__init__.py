@@ -78,6 +78,8 @@ def lib():
             "pcad_matd_query": ([I, I64, I64, U, PSZ, PSZ], I),
             "pcad_matd_scan_fwd": ([I, I64, I64, P, P, P, U, P, SZ, P], I),
             "pcad_matd_scan_vjp": ([I, I64, I64, P, P, P, P, U, P, SZ, P], I),
+            "pcad_matd_reduce_fwd": ([I, I64, I64, P, P, P, U, P, SZ, P], I),
+            "pcad_matd_reduce_vjp": ([I, I64, I64, P, P, P, P, U, P, SZ, P], I),
             "pcad_knob_count": ([], I),
             "pcad_knob_name": ([I], ctypes.c_char_p),
             "pcad_knob_get": ([ctypes.c_char_p, ctypes.POINTER(I64)], I),
@@ -483,6 +485,35 @@ def matd_scan_vjp(M, saved, Pbar, out=None, accumulate: bool = False):
     check(lib().pcad_matd_scan_vjp(d, batch, n, _ptr(M), _ptr(saved), _ptr(Pbar.contiguous()),
                                    _ptr(out), ACCUMULATE if accumulate else 0, _ptr(ws),
                                    ws.numel(), _stream(dev)), "pcad_matd_scan_vjp")
+    return out
+
+
+def matd_reduce_fwd(M: torch.Tensor):
+    """M (..., n, d, d) -> (Y (..., d, d), saved), Y = M_0 ... M_{n-1}."""
+    _dev_check(M)
+    d, batch, n, lead = _mdshape(M)
+    s_b, w_b = matd_query(d, batch, n)
+    dev = M.device
+    Y = torch.empty(lead + (d, d), dtype=torch.float32, device=dev)
+    saved = torch.empty(max(s_b, 16), dtype=torch.uint8, device=dev)
+    ws = workspace(w_b, dev)
+    check(lib().pcad_matd_reduce_fwd(d, batch, n, _ptr(M), _ptr(Y), _ptr(saved), 0, _ptr(ws),
+                                     ws.numel(), _stream(dev)), "pcad_matd_reduce_fwd")
+    return Y, saved
+
+
+def matd_reduce_vjp(M, saved, Ybar, out=None, accumulate: bool = False):
+    """Adjoint of matd_reduce_fwd: returns M_bar (shape of M)."""
+    _dev_check(M)
+    d, batch, n, lead = _mdshape(M)
+    s_b, w_b = matd_query(d, batch, n)
+    dev = M.device
+    out = torch.empty_like(M) if out is None else out
+    _dev_check(out)
+    ws = workspace(w_b, dev)
+    check(lib().pcad_matd_reduce_vjp(d, batch, n, _ptr(M), _ptr(saved), _ptr(Ybar.contiguous()),
+                                     _ptr(out), ACCUMULATE if accumulate else 0, _ptr(ws),
+                                     ws.numel(), _stream(dev)), "pcad_matd_reduce_vjp")
     return out
 
 

@@ -485,4 +485,33 @@ int pcad_matd_scan_vjp(int d, int64_t batch, int64_t n, const float *M, const vo
                                     (flags & PCAD_ACCUMULATE) != 0, ws, (hipStream_t)stream));
 }
 
+int pcad_matd_reduce_fwd(int d, int64_t batch, int64_t n, const float *M, float *Y, void *saved,
+                         unsigned flags, void *ws, size_t ws_bytes, void *stream) {
+  PCAD_TRY(check_matd(d, batch, n, flags));
+  if (batch == 0) return PCAD_OK;
+  PCAD_TRY(need(Y));
+  if (n > 0) {
+    PCAD_TRY(need(M));
+    PCAD_TRY(need(saved));
+    PCAD_TRY(check_matd_ws(d, batch, n, ws, ws_bytes));
+  }
+  return hip_status(matd_reduce_fwd_launch(d, batch, n, M, Y, static_cast<float *>(saved), ws,
+                                           (hipStream_t)stream));
+}
+
+int pcad_matd_reduce_vjp(int d, int64_t batch, int64_t n, const float *M, const void *saved,
+                         const float *Ybar, float *Mbar, unsigned flags, void *ws,
+                         size_t ws_bytes, void *stream) {
+  PCAD_TRY(check_matd(d, batch, n, flags));
+  if (batch == 0 || n == 0) return PCAD_OK;
+  PCAD_TRY(need(M));
+  PCAD_TRY(need(saved));
+  PCAD_TRY(need(Ybar));
+  PCAD_TRY(need(Mbar));
+  PCAD_TRY(check_matd_ws(d, batch, n, ws, ws_bytes));
+  return hip_status(matd_reduce_vjp_launch(d, batch, n, M, static_cast<const float *>(saved),
+                                           Ybar, Mbar, (flags & PCAD_ACCUMULATE) != 0, ws,
+                                           (hipStream_t)stream));
+}
+
 }  // extern "C"

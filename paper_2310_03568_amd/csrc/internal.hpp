@@ -90,6 +90,11 @@ hipError_t matd_fwd_launch(int d, int64_t batch, int64_t n, const float *x, floa
 hipError_t matd_vjp_launch(int d, int64_t batch, int64_t n, const float *x, const float *saved,
                            const float *ybar, float *xbar, bool accumulate, void *ws,
                            hipStream_t s);
+hipError_t matd_reduce_fwd_launch(int d, int64_t batch, int64_t n, const float *x, float *y,
+                                  float *saved, void *ws, hipStream_t s);
+hipError_t matd_reduce_vjp_launch(int d, int64_t batch, int64_t n, const float *x,
+                                  const float *saved, const float *ybar, float *xbar,
+                                  bool accumulate, void *ws, hipStream_t s);
 
 // scan
 int scan_tile_size(int op);

@@ -23,7 +23,10 @@
 // in registers through DPP (wave) and a 4-entry LDS table (waves).
 //
 // The forward saves the exclusive prefix product of every tile; the adjoint
-// recomputes the forward prefixes inside each tile from it.  Workspace
+// recomputes the forward prefixes inside each tile from it.  The reduce runs
+// passes 1-3 (the row product falls out of pass 3) and its adjoint is the
+// scan adjoint seeded with Ybar at the last element only, which is Section
+// 3.1's rule L_i^T Ybar R_i^T.  Workspace
 // temporaries are zeroed by the pass that consumes them (the last one by a
 // small fill kernel), so the workspace holds only zeros between calls.
 #include "device.hpp"
@@ -151,6 +154,9 @@ struct MdArgs {
   float *agg;         // workspace: tile values [tiles][2 d*d]
   float *cagg;        // workspace: chunk values [chunks][2 d*d]
   float *cvec;        // workspace: chunk entry values [chunks][d*d]
+  float *total;       // reduce: the product of each row [rows][d*d] (else null)
+  const float *ybar_last;  // reduce adjoint: Ybar per row; Pbar_i = Ybar at
+                           // i = n-1, else 0 (pbar unused)
   int64_t n;
   int64_t tpr;        // tiles per row
   int64_t cpr;        // chunks per row
@@ -192,6 +198,24 @@ __device__ __forceinline__ void stage_out(float *__restrict__ dst, int cnt, cons
   for (int f = threadIdx.x; f < cnt; f += MD_TH) {
     const float v = lds[f + f / C::GF];
     dst[f] = accumulate ? dst[f] + v : v;
+  }
+}
+
+// the adjoint input of a tile: Pbar from memory, or for the reduce adjoint
+// Ybar at the row's last element and zeros elsewhere
+template <int D>
+__device__ __forceinline__ void stage_pbar(const MdArgs &a, const TileRange &t, float *lds) {
+  using C = MD<D>;
+  if (!a.ybar_last) {
+    stage_in<D>(a.pbar + t.base * C::D2, t.valid * C::D2, lds);
+    return;
+  }
+  const int cnt = t.valid * C::D2;
+  const int64_t last = a.n - 1 - t.lt * C::TILE;  // the row's last element, tile-relative
+  const float *yb = a.ybar_last + t.row * C::D2;
+  for (int f = threadIdx.x; f < cnt; f += MD_TH) {
+    const int e = f / C::D2;
+    lds[f + f / C::GF] = (e == last) ? yb[f - e * C::D2] : 0.0f;
   }
 }
 
@@ -301,7 +325,7 @@ __global__ __launch_bounds__(MD_TH) void k_md_vagg(MdArgs a) {
 #pragma unroll
   for (int j = 0; j < C::TPT; ++j) copy_in(m[j], lds_el<D>(s_t, j));
   __syncthreads();
-  stage_in<D>(a.pbar + t.base * C::D2, t.valid * C::D2, s_t);
+  stage_pbar<D>(a, t, s_t);
   __syncthreads();
   const Map<D> inc = wave_scan_rev<Tr>(thread_map<D>(m, s_t, t.valid));
   if (lane_id() == 0) s_w[threadIdx.x / WAVE] = inc;
@@ -399,6 +423,7 @@ __global__ __launch_bounds__(MD_TH) void k_md_scan_chunks(MdArgs a) {
       for (int w = 0; w < MD_W; ++w) carry = Tr::comb(carry, s_w[w]);
       __syncthreads();
     }
+    if (a.total && threadIdx.x == 0) put(a.total + row * C::D2, carry);
   } else {
     using Tr = TrMap<D>;
     __shared__ Map<D> s_w[MD_W];
@@ -492,7 +517,7 @@ __global__ __launch_bounds__(MD_TH) void k_md_vapply(MdArgs a) {
 #pragma unroll
   for (int j = 0; j < C::TPT; ++j) copy_in(m[j], lds_el<D>(s_t, j));
   __syncthreads();
-  stage_in<D>(a.pbar + t.base * C::D2, t.valid * C::D2, s_t);
+  stage_pbar<D>(a, t, s_t);
   __syncthreads();
 
   // reverse side: rho entering this thread's last element from the right
@@ -558,6 +583,31 @@ __global__ __launch_bounds__(MD_TH) void k_md_vapply(MdArgs a) {
   stage_out<D>(a.y + t.base * C::D2, t.valid * C::D2, s_t, a.accumulate != 0);
 }
 
+// reduce forward: complete the saved tile prefixes (chunk prefix times the
+// chunk-local prefix), which the scan forward does in its last pass
+template <int D>
+__global__ __launch_bounds__(256) void k_md_fix_pre(MdArgs a, int64_t tiles) {
+  using Tr = TrMat<D>;
+  constexpr int D2 = D * D;
+  for (int64_t tile = (int64_t)blockIdx.x * 256 + threadIdx.x; tile < tiles;
+       tile += (int64_t)gridDim.x * 256) {
+    const int64_t row = tile / a.tpr, lt = tile - row * a.tpr;
+    Mat<D> loc, cv;
+    copy_in(loc, a.pre + tile * D2);
+    copy_in(cv, a.cvec + (row * a.cpr + lt / MD_CH) * D2);
+    put(a.pre + tile * D2, Tr::comb(cv, loc));
+  }
+}
+
+// reduce of empty rows: the identity
+__global__ __launch_bounds__(256) void k_md_eye(float *y, int64_t count, int d) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * 256) {
+    const int k = (int)(i % (d * d));
+    y[i] = (k % (d + 1) == 0) ? 1.0f : 0.0f;
+  }
+}
+
 __global__ __launch_bounds__(256) void k_md_zero(float *p, int64_t count) {
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < count;
        i += (int64_t)gridDim.x * 256)
@@ -592,15 +642,20 @@ size_t matd_ws_bytes(int d, int64_t batch, int64_t n) {
          al256(chunks * d * d * 4);
 }
 
+// reduce (forward): y = null, total = the row products; reduce (adjoint):
+// pbar = null, ybar_last = Ybar per row
 template <int D>
 static hipError_t matd_run(bool vjp, int64_t batch, int64_t n, const float *x, const float *pbar,
-                           float *y, float *saved, bool accumulate, void *ws, hipStream_t s) {
+                           float *y, float *saved, bool accumulate, void *ws, hipStream_t s,
+                           float *total = nullptr, const float *ybar_last = nullptr) {
   constexpr int D2 = D * D;
   MdArgs a;
   a.x = x;
   a.pbar = pbar;
   a.y = y;
   a.pre = saved;
+  a.total = total;
+  a.ybar_last = ybar_last;
   a.n = n;
   a.tpr = (n + MD<D>::TILE - 1) / MD<D>::TILE;
   a.cpr = (a.tpr + MD_CH - 1) / MD_CH;
@@ -619,7 +674,13 @@ static hipError_t matd_run(bool vjp, int64_t batch, int64_t n, const float *x, c
     hipLaunchKernelGGL(k_md_agg<D>, gt, th, 0, s, a);
     hipLaunchKernelGGL((k_md_scan_tiles<D, false>), gc, th, 0, s, a);
     hipLaunchKernelGGL((k_md_scan_chunks<D, false>), gr, th, 0, s, a);
-    hipLaunchKernelGGL(k_md_apply<D>, gt, th, 0, s, a);
+    if (total) {
+      const int64_t fb = (tiles + 255) / 256;
+      hipLaunchKernelGGL(k_md_fix_pre<D>, dim3((unsigned)(fb < 4096 ? fb : 4096)), dim3(256), 0,
+                         s, a, tiles);
+    } else {
+      hipLaunchKernelGGL(k_md_apply<D>, gt, th, 0, s, a);
+    }
   } else {
     hipLaunchKernelGGL(k_md_vagg<D>, gt, th, 0, s, a);
     hipLaunchKernelGGL((k_md_scan_tiles<D, true>), gc, th, 0, s, a);
@@ -648,6 +709,32 @@ hipError_t matd_vjp_launch(int d, int64_t batch, int64_t n, const float *x, cons
   float *sv = const_cast<float *>(saved);  // read only in the adjoint passes
   if (d == 3) return matd_run<3>(true, batch, n, x, ybar, xbar, sv, accumulate, ws, s);
   if (d == 5) return matd_run<5>(true, batch, n, x, ybar, xbar, sv, accumulate, ws, s);
+  return hipErrorInvalidValue;
+}
+
+hipError_t matd_reduce_fwd_launch(int d, int64_t batch, int64_t n, const float *x, float *y,
+                                  float *saved, void *ws, hipStream_t s) {
+  if (batch == 0) return hipSuccess;
+  if (n == 0) {
+    const int64_t cnt = batch * d * d, nb = (cnt + 255) / 256;
+    hipLaunchKernelGGL(k_md_eye, dim3((unsigned)(nb < 4096 ? nb : 4096)), dim3(256), 0, s, y, cnt,
+                       d);
+    return hipGetLastError();
+  }
+  if (d == 3) return matd_run<3>(false, batch, n, x, nullptr, nullptr, saved, false, ws, s, y);
+  if (d == 5) return matd_run<5>(false, batch, n, x, nullptr, nullptr, saved, false, ws, s, y);
+  return hipErrorInvalidValue;
+}
+
+hipError_t matd_reduce_vjp_launch(int d, int64_t batch, int64_t n, const float *x,
+                                  const float *saved, const float *ybar, float *xbar,
+                                  bool accumulate, void *ws, hipStream_t s) {
+  if (batch == 0 || n == 0) return hipSuccess;
+  float *sv = const_cast<float *>(saved);
+  if (d == 3)
+    return matd_run<3>(true, batch, n, x, nullptr, xbar, sv, accumulate, ws, s, nullptr, ybar);
+  if (d == 5)
+    return matd_run<5>(true, batch, n, x, nullptr, xbar, sv, accumulate, ws, s, nullptr, ybar);
   return hipErrorInvalidValue;
 }
 

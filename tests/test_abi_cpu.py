@@ -181,3 +181,9 @@ def test_matd_queries_and_validation(L):
     p16 = (p + 15) & ~15
     assert L.pcad_matd_scan_fwd(3, 1, 10, p16, p16, p16, 0, p16, 8, None) == 6
     assert L.pcad_matd_scan_vjp(3, 1, 10, p16 + 4, p16, p16, p16, 0, None, 0, None) == 4
+    # reduce: same validation; the empty reduce still needs Y (identity out)
+    assert L.pcad_matd_reduce_fwd(3, 1, 0, None, None, None, 0, None, 0, None) == 3
+    assert L.pcad_matd_reduce_fwd(3, 0, 10, None, None, None, 0, None, 0, None) == 0
+    assert L.pcad_matd_reduce_fwd(5, 1, 10, p16, p16, p16, 0, p16, 8, None) == 6
+    assert L.pcad_matd_reduce_vjp(5, 2, 0, None, None, None, None, 0, None, 0, None) == 0
+    assert L.pcad_matd_reduce_vjp(3, 1, 10, p16, p16, None, p16, 0, None, 0, None) == 3

@@ -815,3 +815,32 @@ def test_matd_scan_accumulate_and_empty(pcad, d):
     assert pcad.matd_scan_vjp(E, s0, E).shape == E.shape
     with pytest.raises(pcad.PcadError):
         pcad.matd_scan_fwd(torch.empty((4, 4, 4), device="cuda"))
+
+
+@pytest.mark.parametrize("d", [3, 5])
+@pytest.mark.parametrize("batch,n", [(1, 1), (2, 777), (3, 2 * 1024 + 5), (1, -1)])
+def test_matd_reduce(pcad, d, batch, n):
+    """Y = M_0 ... M_{n-1} and Mbar_i = L_i^T Ybar R_i^T (Section 3.1's rule)
+    against the float64 oracle; n < 0: more tiles than one chunk holds."""
+    from workloads import matd
+    if n < 0:
+        n = 257 * (1024 if d == 3 else 512) + 3
+    w = matd(d, n, batch, ensemble="orth")
+    print(f"matd reduce d={d} batch={batch} n={n}", flush=True)
+    yb = np.random.default_rng(n + d).standard_normal((batch, d, d)).astype(np.float32)
+    M = dev(w["M"])
+    _ws_clear(pcad)
+    Y, saved = pcad.matd_reduce_fwd(M)
+    base = np.random.default_rng(d).standard_normal(w["M"].shape).astype(np.float32)
+    out = dev(base)
+    pcad.matd_reduce_vjp(M, saved, dev(yb), out=out, accumulate=True)
+    Y, g = host(Y), host(out) - base
+    for r in range(batch):
+        ry, cy = oracle.matd_reduce(w["M"][r])
+        assert_gate(Y[r], ry, np.full(ry.shape, cy), RTOL["mat2"], what=f"matd{d} reduce row {r}")
+        xb, cx = oracle.matd_reduce_vjp(w["M"][r], yb[r])
+        cc = np.repeat(cx[:, None], d * d, axis=1).reshape(xb.shape) + np.abs(base[r])
+        assert_gate(g[r], xb, cc, RTOL["mat2"], what=f"matd{d} reduce vjp row {r}")
+    _ws_tail_zero(pcad, d, batch, n)
+    Y0, s0 = pcad.matd_reduce_fwd(torch.empty((2, 0, d, d), device="cuda"))
+    np.testing.assert_array_equal(host(Y0), np.broadcast_to(np.eye(d, dtype=np.float32), (2, d, d)))
