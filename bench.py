@@ -148,6 +148,33 @@ def bench_matd(args, pcad, torch, np):
                      "n": n, "op": f"mat{d}", "combinator": "scan"})
 
 
+def matd_extras(b, torch, np, reps=5):
+    """Reduce of the same matrices: forward and adjoint times."""
+    import paper_2310_03568_amd as pcad
+    M, _ = b["dev"]
+    d = M.shape[-1]
+    yb = torch.randn(d, d, device=M.device)
+    out = torch.empty_like(M)
+    Y, saved = pcad.matd_reduce_fwd(M)
+    pcad.matd_reduce_vjp(M, saved, yb, out=out)
+    torch.cuda.synchronize()
+    tf, tb = [], []
+    s = torch.cuda.current_stream()
+    for _ in range(reps):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        e[0].record(s)
+        Y, saved = pcad.matd_reduce_fwd(M)
+        e[1].record(s)
+        pcad.matd_reduce_vjp(M, saved, yb, out=out)
+        e[2].record(s)
+        torch.cuda.synchronize()
+        tf.append(e[0].elapsed_time(e[1]))
+        tb.append(e[1].elapsed_time(e[2]))
+    n = b["n"]
+    return {"reduce_fwd_ms": float(np.mean(tf)), "reduce_bwd_ms": float(np.mean(tb)),
+            "reduce_fwd_GBs": 4 * d * d * n / (np.mean(tf) * 1e-3) / 1e9}
+
+
 def matd_parity(b, torch, np, sample: int = 1 << 14):
     """Forward: the timed run's first `sample` outputs against the oracle on
     that prefix (a scan prefix depends on nothing after it).  Adjoint: the
@@ -695,6 +722,8 @@ def main():
         extras = rbi_sweep(torch)
     if args.workload == "vec" and not args.no_extras:
         extras = vec_extras(b, torch, np)
+    if args.workload == "matd" and not args.no_extras:
+        extras = matd_extras(b, torch, np)
     cpu, par = (None, None)
     if not args.no_cpu:
         if args.workload == "segmented":
