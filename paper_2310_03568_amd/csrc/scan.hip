@@ -557,6 +557,8 @@ __global__ __launch_bounds__(TH_) void k_scan_vjp(ScanVjpArgs a) {
 
     // thread-serial sweep, right to left
     typename M::P rho_lm;
+    float4 o_lm[LM ? K : 1];  // lane-major: a thread's groups are adjacent in
+                              // memory; they are stored together after the sweep
     if constexpr (LM) {
       MT ex = shift_down1(mincl[0]);
       if (lane == WAVE - 1) ex = M::id();
@@ -593,7 +595,11 @@ __global__ __launch_bounds__(TH_) void k_scan_vjp(ScanVjpArgs a) {
           if (A::NXB == 2) f4set(o[1], j, xb[1]);
         }
       }
-      if constexpr (LM) rho_lm = rho;
+      if constexpr (LM) {
+        rho_lm = rho;
+        o_lm[g] = o[0];
+        continue;
+      }
       const int el = group_el<LM, K, TH, EPL>(g, tid);
       const int v = ti.valid - el;
       float *dst[2] = {a.xb0, a.xb1};
@@ -605,6 +611,25 @@ __global__ __launch_bounds__(TH_) void k_scan_vjp(ScanVjpArgs a) {
           val.x += old.x; val.y += old.y; val.z += old.z; val.w += old.w;
         }
         store_group<S>(dst[s], ti.base, el, v, ti.vec_ok, val);
+      }
+    }
+    if constexpr (LM) {
+      // back-to-back ordinary (not streaming) stores of the thread's
+      // consecutive groups, so that L2 merges them into whole lines; the
+      // streaming stores of one group per sweep step left half-written lines
+      // (twice the output bytes in the write counter)
+      static_assert(S == 4 && A::NXB == 4, "lane-major tiles hold 2x2 matrices");
+#pragma unroll
+      for (int g = 0; g < K; ++g) {
+        const int el = group_el<LM, K, TH, EPL>(g, tid);
+        if (el >= ti.valid) break;
+        float4 *q = reinterpret_cast<float4 *>(a.xb0 + (ti.base + el) * 4);
+        float4 val = o_lm[g];
+        if (a.accumulate) {
+          const float4 old = *q;
+          val.x += old.x; val.y += old.y; val.z += old.z; val.w += old.w;
+        }
+        *q = val;
       }
     }
     if (!more) break;
