@@ -258,9 +258,10 @@ def bench_rbi(args, pcad, torch, np):
 
     # compulsory bytes.  Forward: reads idx, v; writes the bins (+ saved per
     # bin: n0 and y_pos for *, argk for min/max).  Adjoint: reads idx (+ v
-    # for *), writes v_bar, and reads each bin's hbar (+ saved) once
+    # for *), writes v_bar, and reads each bin's hbar (+ saved) once; min/max
+    # need no keys (v_bar is zero except at each bin's arg-extremum)
     per_bin = {"add": 4, "mul": 12, "min": 8, "max": 8, "sumprod": 8}[op]
-    per_elem_bwd = {"add": 8, "mul": 12, "min": 8, "max": 8, "sumprod": 12}[op]
+    per_elem_bwd = {"add": 8, "mul": 12, "min": 4, "max": 4, "sumprod": 12}[op]
     return dict(n=n, fwd=fwd, bwd=bwd, inputs=w, bytes_fwd=8 * n + per_bin * m,
                 bytes_bwd=per_elem_bwd * n + per_bin * m, kernel=f"k_rbi_vjp<{op.upper()}>",
                 out=lambda: (state["h"], vb),

@@ -245,18 +245,22 @@ int pcad_rbi_fwd(int op, int64_t batch, int64_t n, int64_t m, const int32_t *idx
  *   ADD    : v_bar_i = hbar[idx_i] (gather)            (Section 4.2 Addition)
  *   MUL    : v_bar_i = hbar[k]*(n0==0 ? y_pos/v_i : (n0==1 && v_i==0 ? y_pos : 0))
  *                                                      (Section 4.2 Multiplication)
- *   MIN/MAX: v_bar_i = hbar[k] if i == argk[k] else 0  (Section 4.2 Min/Max)
+ *   MIN/MAX: v_bar_i = hbar[k] if i == argk[k] else 0  (Section 4.2 Min/Max),
+ *            computed as the paper's rule states it: v_bar filled with zeros
+ *            (skipped under PCAD_ACCUMULATE), then each bin's adjoint
+ *            scattered to argk[k]; idx is not read
  *   SUMPROD: v_bar_i = (s[k] - v_i) * hbar[k]   (Section 4.2 Invertible
  *            Operators: hist[k] inverted by (0, v_i) leaves s[k] - v_i)
  *   LINREC/MAT2: v_bar_i = d(L_i (.) v_i (.) R_i)/dv_i^T hbar[k], with L_i and
  *            R_i the ordered folds of the bin's elements before and after i
  *            (the sort-based rule of Section 4, from the sort in `saved`)
  * with k = idx_i; out-of-range keys get 0.  v is required for MUL, LINREC
- * and MAT2; the ordered operators also need the workspace.  For MUL, MIN
- * and MAX the workspace is optional: given (of the queried size), large bin
- * counts first pack what an element needs from its bin into one record per
- * bin there, so each element makes one gather instead of one per array;
- * with ws = NULL (or too small) the adjoint gathers from `saved` directly.
+ * and MAT2; the ordered operators also need the workspace.  For the other
+ * operators the workspace is optional: for MUL, given (of the queried size),
+ * large bin counts first pack what an element needs from its bin into one
+ * record per bin there, so each element makes one gather instead of one per
+ * array; with ws = NULL (or too small) the adjoint gathers from `saved`
+ * directly.
  */
 int pcad_rbi_vjp(int op, int64_t batch, int64_t n, int64_t m, const int32_t *idx,
                  const float *v, const void *saved, const float *hbar, float *vbar,

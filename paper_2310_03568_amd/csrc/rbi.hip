@@ -334,11 +334,8 @@ __device__ __forceinline__ uint4 vjp_rec(const RbiVjpArgs &a, int64_t t) {
   if (OP == MUL) {
     r.x = __float_as_uint(a.ypos[t]); r.y = a.n0[t] | kRecHi;
     r.z = __float_as_uint(a.hbar[t]); r.w = kRecHi;
-  } else if (OP == SUMPROD) {
+  } else {  // SUMPROD
     r.x = __float_as_uint(a.ssum[t]); r.y = __float_as_uint(a.hbar[t]);  // LDS only
-    r.z = r.w = 0u;
-  } else {
-    r.x = __float_as_uint(a.hbar[t]); r.y = (uint32_t)a.argk[t] | kRecHi;
     r.z = r.w = 0u;
   }
   return r;
@@ -348,9 +345,33 @@ template <int OP>
 __global__ __launch_bounds__(BLOCK) void k_rbi_vjp_tab(RbiVjpArgs a, int64_t total) {
   for (int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x; t < total;
        t += (int64_t)gridDim.x * BLOCK) {
-    const uint4 r = vjp_rec<OP>(a, t);
-    if (OP == MUL) static_cast<uint4 *>(a.tab)[t] = r;
-    else static_cast<uint2 *>(a.tab)[t] = make_uint2(r.x, r.y);
+    static_cast<uint4 *>(a.tab)[t] = vjp_rec<OP>(a, t);  // MUL
+  }
+}
+
+// min/max adjoint as the min rule figure of Section 4.2 states it: the bin
+// adjoint goes to the bin's arg-extremum by a scatter (positions are unique
+// within a row, and an empty bin's sentinel n selects nothing); every other
+// element's adjoint is zero (a fill first unless accumulating).  The keys are
+// never read.
+__global__ __launch_bounds__(BLOCK) void k_rbi_vjp_fill0(float *vbar, int64_t total) {
+  const int64_t t4 = total / 4;
+  for (int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x; t < t4;
+       t += (int64_t)gridDim.x * BLOCK)
+    reinterpret_cast<float4 *>(vbar)[t] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  const int64_t r = t4 * 4 + (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (r < total) vbar[r] = 0.0f;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_rbi_vjp_scatter(RbiVjpArgs a, int64_t total) {
+  for (int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * BLOCK) {
+    const int64_t row = t / a.m;
+    const int32_t k = a.argk[t];
+    if (k >= 0 && k < a.n) {
+      float *o = a.vbar + row * a.n + k;
+      *o = a.accumulate ? *o + a.hbar[t] : a.hbar[t];
+    }
   }
 }
 
@@ -366,7 +387,7 @@ __global__ __launch_bounds__(BLOCK) void k_rbi_vjp(RbiVjpArgs a) {
     for (int64_t k = threadIdx.x; k < a.m; k += BLOCK) {
       if (OP == ADD) reinterpret_cast<float *>(smem)[k] = a.hbar[gb + k];
       else if (OP == MUL) reinterpret_cast<uint4 *>(smem)[k] = vjp_rec<OP>(a, gb + k);
-      else {
+      else {  // SUMPROD: (s, hbar)
         const uint4 r = vjp_rec<OP>(a, gb + k);
         reinterpret_cast<uint2 *>(smem)[k] = make_uint2(r.x, r.y);
       }
@@ -420,17 +441,6 @@ __global__ __launch_bounds__(BLOCK) void k_rbi_vjp(RbiVjpArgs a) {
           }
           // the invertible-operator rule: the bin without v_i keeps s - v_i
           r = (sk - vv[j]) * h;
-        } else {
-          int32_t ak;
-          float h;
-          if (SRC == VJP_GATHER) {
-            ak = a.argk[gb + k]; h = a.hbar[gb + k];
-          } else {
-            const uint2 q = SRC == VJP_LDS ? reinterpret_cast<const uint2 *>(smem)[k]
-                                           : static_cast<const uint2 *>(a.tab)[gb + k];
-            h = __uint_as_float(q.x); ak = (int32_t)(q.y & ~kRecHi);
-          }
-          r = ak == (int32_t)(i + j) ? h : 0.0f;
         }
       }
       o[j] = r;
@@ -688,12 +698,23 @@ hipError_t rbi_vjp_launch(int op, int64_t batch, int64_t n, int64_t m, const int
   }
   if (op == MIN || op == MAX) a.argk = static_cast<const int32_t *>(saved);
   if (op == SUMPROD) a.ssum = static_cast<const float *>(saved);
+  if (op == MIN || op == MAX) {
+    if (!accumulate) {
+      const int64_t nt = batch * n;
+      hipLaunchKernelGGL(k_rbi_vjp_fill0, dim3((unsigned)grid1d((nt + 3) / 4)), dim3(BLOCK), 0, s,
+                         vbar, nt);
+    }
+    if (total > 0)
+      hipLaunchKernelGGL(k_rbi_vjp_scatter, dim3((unsigned)grid1d(total)), dim3(BLOCK), 0, s, a,
+                         total);
+    return hipGetLastError();
+  }
   // bins per row up to which a block builds its record table in LDS (16 KB)
   const int64_t lds_max = op == ADD ? 4096 : (op == MUL ? 1024 : 2048);
-  const size_t rec = op == ADD ? 4 : (op == MUL ? 16 : 8);
+  const size_t rec = op == ADD ? 4 : (op == MUL ? 16 : 8);  // SUMPROD: 8
   int src = VJP_GATHER;
   if (m <= lds_max) src = VJP_LDS;
-  else if (op != ADD && op != SUMPROD && ws != nullptr) src = VJP_TABLE;
+  else if (op == MUL && ws != nullptr) src = VJP_TABLE;
   int64_t bx = (n + BLOCK * 4 * 4 - 1) / (BLOCK * 4 * 4);
   // an LDS table is built once per block: fewer, longer blocks
   const int64_t bx_cap = src == VJP_LDS ? 2048 / (batch < 2048 ? batch : 2048) : 65535;
@@ -706,8 +727,6 @@ hipError_t rbi_vjp_launch(int op, int64_t batch, int64_t n, int64_t m, const int
     const dim3 gi((unsigned)grid1d(total));
     switch (op) {
     case MUL: hipLaunchKernelGGL(k_rbi_vjp_tab<MUL>, gi, dim3(BLOCK), 0, s, a, total); break;
-    case MIN: hipLaunchKernelGGL(k_rbi_vjp_tab<MIN>, gi, dim3(BLOCK), 0, s, a, total); break;
-    case MAX: hipLaunchKernelGGL(k_rbi_vjp_tab<MAX>, gi, dim3(BLOCK), 0, s, a, total); break;
     default: return hipErrorInvalidValue;
     }
   }
@@ -720,8 +739,6 @@ hipError_t rbi_vjp_launch(int op, int64_t batch, int64_t n, int64_t m, const int
   switch (op) {
     PCAD_RBI_VJP(ADD)
     PCAD_RBI_VJP(MUL)
-    PCAD_RBI_VJP(MIN)
-    PCAD_RBI_VJP(MAX)
   case SUMPROD:
     if (src == VJP_LDS) hipLaunchKernelGGL((k_rbi_vjp<SUMPROD, VJP_LDS>), grid, dim3(BLOCK), shm, s, a);
     else hipLaunchKernelGGL((k_rbi_vjp<SUMPROD, VJP_GATHER>), grid, dim3(BLOCK), 0, s, a);
