@@ -349,6 +349,81 @@ __global__ __launch_bounds__(BLOCK) void k_rbi_vjp_tab(RbiVjpArgs a, int64_t tot
   }
 }
 
+// + and sumOfProd adjoints beyond the 16 KB tables: 1024-thread blocks (one
+// per CU, 16 waves) keep the records of the first up to kBigBins bins in
+// 144 KB of LDS and gather the rest from memory, so that at m = 65536 most
+// lookups stay out of the L2 -> L1 path (a random 4-byte gather moves a
+// whole line there)
+constexpr int VJP_BIG_TH = 1024;
+constexpr int kBigLdsBytes = 147456;
+
+template <int OP>
+__global__ __launch_bounds__(VJP_BIG_TH) void k_rbi_vjp_big(RbiVjpArgs a, int64_t lm) {
+  constexpr int REC = OP == ADD ? 4 : 8;  // ADD: hbar; SUMPROD: (s, hbar)
+  __shared__ __align__(16) unsigned char s_tab[kBigLdsBytes];
+  const int64_t row = blockIdx.y;
+  const int32_t *ir = a.idx + row * a.n;
+  const float *vr = a.v + row * a.n;
+  float *ob = a.vbar + row * a.n;
+  const int64_t gb = row * a.m;
+  for (int64_t k = threadIdx.x; k < lm; k += VJP_BIG_TH) {
+    if (OP == ADD) reinterpret_cast<float *>(s_tab)[k] = a.hbar[gb + k];
+    else reinterpret_cast<float2 *>(s_tab)[k] = make_float2(a.ssum[gb + k], a.hbar[gb + k]);
+  }
+  __syncthreads();
+  static_assert(REC == 4 || REC == 8, "record size");
+  const bool vec_ok = ((row * a.n) & 3) == 0;
+  const int64_t stride = (int64_t)gridDim.x * VJP_BIG_TH * 4;
+  for (int64_t i = ((int64_t)blockIdx.x * VJP_BIG_TH + threadIdx.x) * 4; i < a.n; i += stride) {
+    const bool full = vec_ok && i + 4 <= a.n;
+    int kk[4];
+    float vv[4] = {0.0f, 0.0f, 0.0f, 0.0f}, o[4];
+    if (full) {
+      const int4 k4 = *reinterpret_cast<const int4 *>(ir + i);
+      kk[0] = k4.x; kk[1] = k4.y; kk[2] = k4.z; kk[3] = k4.w;
+      if (OP == SUMPROD) {
+        const float4 v4 = *reinterpret_cast<const float4 *>(vr + i);
+        vv[0] = v4.x; vv[1] = v4.y; vv[2] = v4.z; vv[3] = v4.w;
+      }
+    } else {
+      for (int j = 0; j < 4; ++j) {
+        kk[j] = (i + j < a.n) ? ir[i + j] : -1;
+        if (OP == SUMPROD && i + j < a.n) vv[j] = vr[i + j];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int k = kk[j];
+      float r = 0.0f;
+      if (k >= 0 && k < a.m) {
+        if (OP == ADD) {
+          r = k < lm ? reinterpret_cast<const float *>(s_tab)[k] : a.hbar[gb + k];
+        } else {
+          float sk, h;
+          if (k < lm) {
+            const float2 q = reinterpret_cast<const float2 *>(s_tab)[k];
+            sk = q.x; h = q.y;
+          } else {
+            sk = a.ssum[gb + k]; h = a.hbar[gb + k];
+          }
+          r = (sk - vv[j]) * h;  // the invertible-operator rule
+        }
+      }
+      o[j] = r;
+    }
+    if (a.accumulate) {
+      for (int j = 0; j < 4; ++j)
+        if (i + j < a.n) o[j] += ob[i + j];
+    }
+    if (full) {
+      *reinterpret_cast<float4 *>(ob + i) = make_float4(o[0], o[1], o[2], o[3]);
+    } else {
+      for (int j = 0; j < 4; ++j)
+        if (i + j < a.n) ob[i + j] = o[j];
+    }
+  }
+}
+
 // min/max adjoint as the min rule figure of Section 4.2 states it: the bin
 // adjoint goes to the bin's arg-extremum by a scatter (positions are unique
 // within a row, and an empty bin's sentinel n selects nothing); every other
@@ -711,6 +786,22 @@ hipError_t rbi_vjp_launch(int op, int64_t batch, int64_t n, int64_t m, const int
   }
   // bins per row up to which a block builds its record table in LDS (16 KB)
   const int64_t lds_max = op == ADD ? 4096 : (op == MUL ? 1024 : 2048);
+  if ((op == ADD || op == SUMPROD) && m > lds_max) {
+    const int64_t lm_cap = kBigLdsBytes / (op == ADD ? 4 : 8);
+    const int64_t lm = m < lm_cap ? m : lm_cap;
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      return hipErrorInvalidDevice;
+    int64_t bx = (cus + batch - 1) / batch;
+    const int64_t need = (n + VJP_BIG_TH * 4 - 1) / (VJP_BIG_TH * 4);
+    if (bx > need) bx = need;
+    if (bx < 1) bx = 1;
+    const dim3 grid((unsigned)bx, (unsigned)batch);
+    if (op == ADD) hipLaunchKernelGGL(k_rbi_vjp_big<ADD>, grid, dim3(VJP_BIG_TH), 0, s, a, lm);
+    else hipLaunchKernelGGL(k_rbi_vjp_big<SUMPROD>, grid, dim3(VJP_BIG_TH), 0, s, a, lm);
+    return hipGetLastError();
+  }
   const size_t rec = op == ADD ? 4 : (op == MUL ? 16 : 8);  // SUMPROD: 8
   int src = VJP_GATHER;
   if (m <= lds_max) src = VJP_LDS;
