@@ -210,7 +210,12 @@ int pcad_scan_vjp_checkpoint(int op, int64_t batch, int64_t n, const float *x0, 
  * Strategies (results agree up to the order in which + * SUMPROD combine):
  *   - a private LDS histogram per block (ADD/MUL up to 8192 bins, MIN/MAX
  *     and SUMPROD up to 4096);
- *   - beyond that, for ADD/MUL/MIN/MAX/SUMPROD: the elements are partitioned once by
+ *   - beyond that, one row (batch == 1) of ADD up to 131072 bins or of
+ *     MIN/MAX up to 65536: the bins are split into at most four 128 KB
+ *     LDS tables, one block per (table, chunk of elements) with the blocks
+ *     of a chunk on one XCD, and the per-chunk tables folded in chunk order
+ *     (knob rbi.parts = 0 turns this off);
+ *   - otherwise, for ADD/MUL/MIN/MAX/SUMPROD: the elements are partitioned once by
  *     bin range and each range gets its LDS histogram (the one-pass
  *     relative of the multi-pass technique of Section 4.2; bin ranges of
  *     16384 bins for ADD, 8192 otherwise, at most 2048 ranges), or, past
@@ -409,8 +414,9 @@ int pcad_matd_reduce_vjp(int d, int64_t batch, int64_t n, const float *M, const 
  * Tuning knobs: launch parameters an autotuner may set (the block size of the
  * scan kernels per operator and direction, the bin count up to which
  * reduce-by-index keeps private LDS histograms, elements per histogram
- * block, and the bin count from which the commutative operators sort by bin
- * rather than use the LDS hash table).  Knobs never change the sizes or
+ * block, the bin count from which the commutative operators sort by bin
+ * rather than use the LDS hash table, and whether the partition, the hash
+ * table or the split LDS tables handle large bin counts).  Knobs never change the sizes or
  * layouts of saved states and workspaces; they change speed and, for + and
  * *, the order in which floating-point values are combined (results stay
  * within the same error bound; min/max values, arg-extrema and zero counts

@@ -20,6 +20,7 @@ int64_t knob_rbi_lds_max_bins(bool u64);
 int64_t knob_rbi_elems_per_block();
 int64_t knob_rbi_sort_min_bins();
 bool knob_rbi_partition();
+bool knob_rbi_parts();
 
 // stable sort of element indices by bin (sort.hip): keys outside [0, m)
 // sort last as m

@@ -46,9 +46,14 @@ Knob g_knobs[] = {
     // beyond the LDS histogram: 1 partitions the elements by bin range and
     // builds LDS histograms per range, 0 uses the LDS hash table
     {"rbi.partition", 1, 0, 1, false, 1},
+    // bin counts of at most four 128 KB LDS tables (+: 131072, min/max:
+    // 65536), one row: 1 splits the bins into those tables, one block per
+    // (table, chunk of elements); 0 leaves them to the partition / hash path
+    {"rbi.parts", 1, 0, 1, false, 1},
 };
 constexpr int kNumKnobs = (int)(sizeof(g_knobs) / sizeof(g_knobs[0]));
-constexpr int kRbiF32 = 12, kRbiU64 = 13, kRbiEpb = 14, kRbiSort = 15, kRbiPart = 16;
+constexpr int kRbiF32 = 12, kRbiU64 = 13, kRbiEpb = 14, kRbiSort = 15, kRbiPart = 16,
+              kRbiParts = 17;
 
 Knob *find(const char *name) {
   if (!name) return nullptr;
@@ -69,6 +74,7 @@ int64_t knob_rbi_lds_max_bins(bool u64) { return g_knobs[u64 ? kRbiU64 : kRbiF32
 int64_t knob_rbi_elems_per_block() { return g_knobs[kRbiEpb].value; }
 int64_t knob_rbi_sort_min_bins() { return g_knobs[kRbiSort].value; }
 bool knob_rbi_partition() { return g_knobs[kRbiPart].value != 0; }
+bool knob_rbi_parts() { return g_knobs[kRbiParts].value != 0; }
 
 }  // namespace pcad
 

@@ -534,6 +534,121 @@ __global__ __launch_bounds__(BLOCK) void k_rbi_vjp(RbiVjpArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Bin counts of a few LDS tables: the bins are split into P <= 4 parts of
+// one 128 KB table each, and one 1024-thread block per CU owns a (part,
+// chunk of elements) pair, keeping only the keys of its part.  Blocks are
+// dealt to the XCDs round robin, so the P blocks of a chunk are placed on
+// one XCD: the chunk comes from HBM about once and from that XCD's L2 for
+// the other parts.  Each block writes its table to its own slot; a fold
+// combines a bin's chunks in chunk order (deterministic) and clears the
+// slots.  For one row; the slots live where the partition's records would.
+// ---------------------------------------------------------------------------
+constexpr int PARTS_TH = 1024;
+constexpr int kPartsLdsBytes = 131072;
+constexpr int kPartsMax = 4;
+constexpr int kXcds = 8;  // gfx950: blocks go to the 8 XCDs round robin
+
+template <int OP>
+constexpr int parts_bins() {
+  return OP == ADD ? kPartsLdsBytes / 4 : kPartsLdsBytes / 8;
+}
+
+struct PartsArgs {
+  const int32_t *idx;
+  const float *v;
+  float *hist;
+  int32_t *argk;
+  void *slots;
+  int64_t n, m, chunk;
+  int P, C;
+};
+
+template <int OP>
+__global__ __launch_bounds__(PARTS_TH) void k_rbi_parts(PartsArgs a) {
+  constexpr int L = parts_bins<OP>();
+  constexpr bool KEYS = OP == MIN || OP == MAX;
+  __shared__ __align__(16) unsigned char s_raw[kPartsLdsBytes];
+  static_assert(OP == ADD || KEYS, "+ and min/max only");
+  float *sf = reinterpret_cast<float *>(s_raw);                    // + values
+  unsigned long long *sk = reinterpret_cast<unsigned long long *>(s_raw);  // min/max keys
+  const int b = blockIdx.x;
+  const int xcd = b % kXcds, slot = b / kXcds;
+  const int c = xcd + kXcds * (slot / a.P), p = slot % a.P;
+  for (int k = threadIdx.x; k < L; k += PARTS_TH) {
+    if (OP == ADD) sf[k] = 0.0f;
+    if (KEYS) sk[k] = key_init<OP>();
+  }
+  __syncthreads();
+  const int64_t lo = (int64_t)c * a.chunk;
+  const int64_t hi = lo + a.chunk < a.n ? lo + a.chunk : a.n;
+  const int64_t kb0 = (int64_t)p * L;
+  auto upd = [&](int32_t key, float v, uint32_t i) {
+    const int64_t k = (int64_t)key - kb0;
+    if (key < 0 || key >= a.m || k < 0 || k >= L) return;
+    if (OP == ADD) lds_add_f32(&sf[k], v);
+    if (OP == MIN) atomicMin(&sk[k], (unsigned long long)key_of<MIN>(v, i));
+    if (OP == MAX) atomicMax(&sk[k], (unsigned long long)key_of<MAX>(v, i));
+  };
+  for (int64_t i = lo + (int64_t)threadIdx.x * 4; i < hi; i += (int64_t)PARTS_TH * 4) {
+    if (i + 4 <= hi) {  // lo, chunk and the row start are multiples of 4
+      const int4 k4 = *reinterpret_cast<const int4 *>(a.idx + i);
+      const float4 v4 = *reinterpret_cast<const float4 *>(a.v + i);
+      upd(k4.x, v4.x, (uint32_t)i);
+      upd(k4.y, v4.y, (uint32_t)(i + 1));
+      upd(k4.z, v4.z, (uint32_t)(i + 2));
+      upd(k4.w, v4.w, (uint32_t)(i + 3));
+    } else {
+      for (int64_t j = i; j < hi; ++j) upd(a.idx[j], a.v[j], (uint32_t)j);
+    }
+  }
+  __syncthreads();
+  // only the part's bins below m: the fold clears exactly what was written
+  const int64_t base = ((int64_t)p * a.C + c) * L;
+  const int lim = (int)(a.m - kb0 < L ? a.m - kb0 : L);
+  for (int k = threadIdx.x; k < lim; k += PARTS_TH) {
+    if (OP == ADD) static_cast<float *>(a.slots)[base + k] = sf[k];
+    if (KEYS) static_cast<uint64_t *>(a.slots)[base + k] = sk[k];
+  }
+}
+
+template <int OP>
+__global__ __launch_bounds__(BLOCK) void k_rbi_parts_fold(PartsArgs a) {
+  constexpr int L = parts_bins<OP>();
+  for (int64_t g = (int64_t)blockIdx.x * BLOCK + threadIdx.x; g < a.m;
+       g += (int64_t)gridDim.x * BLOCK) {
+    const int64_t p = g / L, k = g - p * L;
+    float f = 0.0f;
+    uint64_t key = key_init<OP == MAX ? MAX : MIN>();
+    for (int c = 0; c < a.C; ++c) {
+      const int64_t e = (p * a.C + c) * L + k;
+      if (OP == ADD) {
+        float *s = static_cast<float *>(a.slots);
+        f += s[e];
+        s[e] = 0.0f;
+      }
+      if (OP == MIN || OP == MAX) {
+        uint64_t *s = static_cast<uint64_t *>(a.slots);
+        const uint64_t q = s[e];
+        key = OP == MIN ? (q < key ? q : key) : (q > key ? q : key);
+        s[e] = 0ull;
+      }
+    }
+    if (OP == ADD) a.hist[g] = f;
+    if (OP == MIN || OP == MAX) {
+      if (key == key_init<OP>()) {
+        a.argk[g] = (int32_t)a.n;
+        a.hist[g] = OP == MIN ? __builtin_inff() : -__builtin_inff();
+      } else {
+        const uint32_t lo = (uint32_t)key;
+        const uint32_t i = OP == MIN ? lo : ~lo;
+        a.argk[g] = (int32_t)i;
+        a.hist[g] = a.v[i];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
 static bool use_lds(int op, int64_t m) {
@@ -584,6 +699,41 @@ static bool part_may(int op, int64_t m) {
 static bool use_part(int op, int64_t n, int64_t m) {
   if (op == SUMPROD) return n > 0 && part_may(op, m);
   return n > 0 && part_may(op, m) && knob_rbi_partition() && !use_sorted(op, m);
+}
+
+// the LDS-table parts (see k_rbi_parts): one row, at most kPartsMax tables
+struct PartsCfg {
+  int P = 0, C = 0;
+  int64_t chunk = 0;
+  size_t bytes = 0;
+};
+
+static PartsCfg parts_cfg(int op, int64_t n, int64_t m) {
+  PartsCfg c;
+  const int64_t L = op == ADD ? kPartsLdsBytes / 4 : kPartsLdsBytes / 8;
+  const int64_t P = (m + L - 1) / L;
+  if (P < 1 || P > kPartsMax) return c;
+  // chunks per XCD: fill the 256 CUs, but give every block at least 64K elements
+  int64_t cl = 32 / P;
+  const int64_t want = (n + (int64_t)kXcds * 65536 - 1) / ((int64_t)kXcds * 65536);
+  if (cl > want) cl = want;
+  if (cl < 1) cl = 1;
+  c.P = (int)P;
+  c.C = (int)(kXcds * cl);
+  c.chunk = ((n + c.C - 1) / c.C + 3) / 4 * 4;
+  c.bytes = (size_t)P * c.C * L * (op == ADD ? 4 : 8);
+  return c;
+}
+
+// (not for *: its LDS product is a compare-and-swap loop, which hot bins of
+// skewed keys serialise in these large blocks -- 2.7 ms against the
+// partition's 1.0 ms at m = 65536 with Zipf keys)
+static bool use_parts(int op, int64_t batch, int64_t n, int64_t m) {
+  if (op != ADD && op != MIN && op != MAX) return false;
+  if (batch != 1 || n <= 0 || !knob_rbi_parts() || !part_may(op, m) || use_sorted(op, m))
+    return false;
+  const PartsCfg c = parts_cfg(op, n, m);
+  return c.P > 0 && c.bytes <= rbi_part_ws_bytes(op, n, m);
 }
 
 // control block, then the per-bin region: min/max keys (forward) or
@@ -688,6 +838,27 @@ hipError_t rbi_fwd_launch(int op, int64_t batch, int64_t n, int64_t m, const int
     case MAX: hipLaunchKernelGGL(k_rbi_fin<MAX>, gi, dim3(BLOCK), 0, s, a, total); break;
     default: break;
     }
+    return hipGetLastError();
+  }
+  if (use_parts(op, batch, n, m)) {
+    const PartsCfg c = parts_cfg(op, n, m);
+    PartsArgs q;
+    q.idx = idx; q.v = v; q.hist = hist; q.argk = a.argk;
+    q.slots = static_cast<char *>(ws) + base_ws_bytes(op, batch, n, m);
+    q.n = n; q.m = m; q.chunk = c.chunk; q.P = c.P; q.C = c.C;
+    const dim3 gp((unsigned)(c.P * c.C)), gf((unsigned)grid1d(m));
+#define PCAD_PARTS(OPV)                                                              \
+  case OPV:                                                                          \
+    hipLaunchKernelGGL(k_rbi_parts<OPV>, gp, dim3(PARTS_TH), 0, s, q);               \
+    hipLaunchKernelGGL(k_rbi_parts_fold<OPV>, gf, dim3(BLOCK), 0, s, q);             \
+    break;
+    switch (op) {
+      PCAD_PARTS(ADD)
+      PCAD_PARTS(MIN)
+      PCAD_PARTS(MAX)
+    default: return hipErrorInvalidValue;
+    }
+#undef PCAD_PARTS
     return hipGetLastError();
   }
   if (use_part(op, n, m)) {

@@ -35,19 +35,26 @@ def test_scan_block_sizes(pcad, op, threads):
     check_scan(pcad, op, 2, 9_000, seed=threads + 7, ckpt=op != "add")
 
 
-@pytest.mark.parametrize("strategy", ["lds", "global", "partition", "hash_large", "sorted"])
+@pytest.mark.parametrize("strategy", ["lds", "global", "parts", "parts4", "partition", "hash_large",
+                                      "sorted"])
 @pytest.mark.parametrize("op", ["add", "mul", "min", "max"])
 def test_rbi_strategies(pcad, op, strategy):
     """lds: private LDS histograms; global: the hash path forced at a small
-    bin count; partition / hash_large / sorted: beyond the LDS capacity, the
-    partition by bin range (default), the hash table, or the sort by bin
-    with a segmented scan"""
+    bin count; parts / parts4: beyond the LDS capacity, bins split into one
+    to four 128 KB LDS tables (default up to four tables; * takes the
+    partition there); partition /
+    hash_large / sorted: the partition by bin range, the hash table, or the
+    sort by bin with a segmented scan"""
     m = 300
     if strategy == "global":
         pcad.set_knob("rbi.lds_max_bins_f32", 0)
         pcad.set_knob("rbi.lds_max_bins_u64", 0)
-    if strategy in ("partition", "hash_large", "sorted"):
+    if strategy in ("parts", "partition", "hash_large", "sorted"):
         m = 20_011
+    if strategy == "parts4":
+        m = 131_072 if op == "add" else 65_536
+    if strategy in ("partition", "hash_large", "sorted"):
+        pcad.set_knob("rbi.parts", 0)
     if strategy == "hash_large":
         pcad.set_knob("rbi.partition", 0)
     if strategy == "sorted":
