@@ -371,7 +371,8 @@ def check_rbi(pcad, op, batch, n, m, seed, dist="uniform", oob=True, ties=False)
 
 
 RBI_CASES = [(0, 5), (1, 1), (1000, 7), (10_000, 1), (100_000, 1024), (100_000, 4096),
-             (100_000, 4097), (100_000, 8192), (100_000, 8193), (300_000, 65536), (70_000, 1 << 20)]
+             (100_000, 4097), (100_000, 8192), (100_000, 8193), (300_000, 65536), (200_003, 100_000),
+             (70_000, 1 << 20)]
 
 
 @pytest.mark.parametrize("op", SCALAR)
