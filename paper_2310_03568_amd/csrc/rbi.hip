@@ -992,22 +992,17 @@ hipError_t rbi_vjp_launch(int op, int64_t batch, int64_t n, int64_t m, const int
     default: return hipErrorInvalidValue;
     }
   }
-#define PCAD_RBI_VJP(OPV)                                                                        \
-  case OPV:                                                                                      \
-    if (src == VJP_LDS) hipLaunchKernelGGL((k_rbi_vjp<OPV, VJP_LDS>), grid, dim3(BLOCK), shm, s, a); \
-    else if (src == VJP_TABLE) hipLaunchKernelGGL((k_rbi_vjp<OPV, VJP_TABLE>), grid, dim3(BLOCK), 0, s, a); \
-    else hipLaunchKernelGGL((k_rbi_vjp<OPV, VJP_GATHER>), grid, dim3(BLOCK), 0, s, a);          \
-    break;
+  // here + and sumOfProd have m <= lds_max (the 144 KB tables took the rest)
   switch (op) {
-    PCAD_RBI_VJP(ADD)
-    PCAD_RBI_VJP(MUL)
-  case SUMPROD:
-    if (src == VJP_LDS) hipLaunchKernelGGL((k_rbi_vjp<SUMPROD, VJP_LDS>), grid, dim3(BLOCK), shm, s, a);
-    else hipLaunchKernelGGL((k_rbi_vjp<SUMPROD, VJP_GATHER>), grid, dim3(BLOCK), 0, s, a);
+  case ADD: hipLaunchKernelGGL((k_rbi_vjp<ADD, VJP_LDS>), grid, dim3(BLOCK), shm, s, a); break;
+  case SUMPROD: hipLaunchKernelGGL((k_rbi_vjp<SUMPROD, VJP_LDS>), grid, dim3(BLOCK), shm, s, a); break;
+  case MUL:
+    if (src == VJP_LDS) hipLaunchKernelGGL((k_rbi_vjp<MUL, VJP_LDS>), grid, dim3(BLOCK), shm, s, a);
+    else if (src == VJP_TABLE) hipLaunchKernelGGL((k_rbi_vjp<MUL, VJP_TABLE>), grid, dim3(BLOCK), 0, s, a);
+    else hipLaunchKernelGGL((k_rbi_vjp<MUL, VJP_GATHER>), grid, dim3(BLOCK), 0, s, a);
     break;
   default: return hipErrorInvalidValue;
   }
-#undef PCAD_RBI_VJP
   return hipGetLastError();
 }
 
