@@ -4,6 +4,9 @@
     scan(op, x0, x1=None, mode="auto")      -> y            (linrec: y, or (y, A))
     scan_linrec(a, b, mode, return_A=False) / scan_mat2(M, mode)
     reduce_by_index(op, idx, v, m, return_argk=False) -> hist (, argk)
+    scan_matd(M) / reduce_matd(M)           3x3 or 5x5 matrix products (..., n, d, d)
+    vscan(op, x) / vreduce(op, x) / vreduce_by_index(op, idx, v, m)
+                                            vectorised operators, x (..., n, d)
 
 Each forward runs the HIP forward kernel and keeps what the adjoint kernel
 needs; each backward runs the adjoint kernel (the rules of Sections 3 to 5,
@@ -29,8 +32,10 @@ from typing import Optional
 
 import torch
 
-from . import (DIM, PcadError, reduce_fwd, reduce_vjp, rbi_fwd, rbi_vjp, saved_argk,
-               scan_fwd, scan_vjp, scan_vjp_checkpoint)
+from . import (DIM, PcadError, matd_reduce_fwd, matd_reduce_vjp, matd_scan_fwd, matd_scan_vjp,
+               reduce_fwd, reduce_vjp, rbi_fwd, rbi_vjp, saved_argk, scan_fwd, scan_vjp,
+               scan_vjp_checkpoint, vrbi_fwd, vrbi_vjp, vreduce_fwd, vreduce_vjp, vscan_fwd,
+               vscan_vjp)
 
 MODES = ("auto", "recompute", "checkpoint")
 CHECKPOINT_BUDGET_BYTES = 256 << 20
@@ -157,5 +162,109 @@ def reduce_by_index(op: str, idx: torch.Tensor, v: torch.Tensor, m: int,
     return _Rbi.apply(op, int(m), bool(return_argk), idx, v)
 
 
+class _MatdScan(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, M):
+        M = M.contiguous()
+        P, saved = matd_scan_fwd(M)
+        ctx.save_for_backward(M, saved)
+        return P
+
+    @staticmethod
+    def backward(ctx, gP):
+        M, saved = ctx.saved_tensors
+        return matd_scan_vjp(M, saved, gP.contiguous())
+
+
+class _MatdReduce(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, M):
+        M = M.contiguous()
+        Y, saved = matd_reduce_fwd(M)
+        ctx.save_for_backward(M, saved)
+        return Y
+
+    @staticmethod
+    def backward(ctx, gY):
+        M, saved = ctx.saved_tensors
+        return matd_reduce_vjp(M, saved, gY.contiguous())
+
+
+def scan_matd(M: torch.Tensor):
+    """P[..., i, :, :] = M[..., 0, :, :] @ ... @ M[..., i, :, :] for 3x3 or 5x5
+    matrices M (..., n, d, d); the adjoint recomputes the forward prefixes
+    from the saved tile prefixes (Section 5.3's redundant block-diagonal
+    form)."""
+    return _MatdScan.apply(M)
+
+
+def reduce_matd(M: torch.Tensor):
+    """Y[...] = M[..., 0, :, :] @ ... @ M[..., n-1, :, :] (identity for n = 0)."""
+    return _MatdReduce.apply(M)
+
+
+class _VScan(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, op: str, x):
+        x = x.contiguous()
+        y, saved = vscan_fwd(op, x)
+        ctx.op = op
+        ctx.save_for_backward(x, saved)
+        return y
+
+    @staticmethod
+    def backward(ctx, gy):
+        x, saved = ctx.saved_tensors
+        return None, vscan_vjp(ctx.op, x, saved, gy.contiguous())
+
+
+class _VReduce(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, op: str, x):
+        x = x.contiguous()
+        y, saved = vreduce_fwd(op, x)
+        ctx.op = op
+        ctx.save_for_backward(x, saved)
+        return y
+
+    @staticmethod
+    def backward(ctx, gy):
+        x, saved = ctx.saved_tensors
+        return None, vreduce_vjp(ctx.op, x, saved, gy.contiguous())
+
+
+class _VRbi(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, op: str, m: int, idx, v):
+        idx, v = _c(idx), _c(v)
+        hist, saved = vrbi_fwd(op, idx, v, m)
+        ctx.op, ctx.m = op, m
+        ctx.save_for_backward(idx, v, saved)
+        return hist
+
+    @staticmethod
+    def backward(ctx, gh):
+        idx, v, saved = ctx.saved_tensors
+        return None, None, None, vrbi_vjp(ctx.op, idx, v, ctx.m, saved, gh.contiguous())
+
+
+def vscan(op: str, x: torch.Tensor):
+    """Inclusive scan along n of x (..., n, d) with map2 op (+ * min max)."""
+    return _VScan.apply(op, x)
+
+
+def vreduce(op: str, x: torch.Tensor):
+    """Fold of x (..., n, d) along n with map2 op -> (..., d)."""
+    return _VReduce.apply(op, x)
+
+
+def vreduce_by_index(op: str, idx: torch.Tensor, v: torch.Tensor, m: int):
+    """hist[..., k, c] = fold of v[..., i, c] over idx[..., i] == k."""
+    if idx.dtype != torch.int32:
+        raise PcadError("keys must be int32")
+    return _VRbi.apply(op, int(m), idx, v)
+
+
 __all__ = ["MODES", "CHECKPOINT_BUDGET_BYTES", "pick_mode", "scan", "scan_linrec", "scan_mat2",
-           "reduce", "reduce_by_index", "DIM"]
+           "reduce", "reduce_by_index", "scan_matd", "reduce_matd", "vscan", "vreduce",
+           "vreduce_by_index", "DIM"]

@@ -273,3 +273,57 @@ def test_sumprod_functions(ag):
     (h * torch.from_numpy(w_np).cuda()).sum().backward()
     vb, cv = oracle.sumprod_rbi_vjp(idx_np, m, w_np, v_np)
     assert_gate(v.grad.cpu().numpy(), vb, cv, RTOL["sumprod"], what="sumprod rbi grad")
+
+
+@pytest.mark.parametrize("d", [3, 5])
+def test_matd_functions(ag, d):
+    """3x3 / 5x5 products through autograd: the gradient of sum(W * P) for the
+    scan and of sum(V * Y) for the reduce against the oracle's reverse
+    sweeps, on orthogonal factors."""
+    from workloads import matd
+    w = matd(d, 3001, 2, ensemble="near")
+    M = torch.from_numpy(w["M"]).cuda().requires_grad_(True)
+    W = torch.from_numpy(w["Pbar"]).cuda()
+    (ag.scan_matd(M) * W).sum().backward()
+    g = host(M.grad)
+    for r in range(2):
+        xb, cx = oracle.matd_scan_vjp(w["M"][r], w["Pbar"][r])
+        cc = np.repeat(cx[:, None], d * d, axis=1).reshape(xb.shape)
+        assert_gate(g[r], xb, cc, RTOL["mat2"], what=f"matd{d} scan grad")
+    M.grad = None
+    V = np.random.default_rng(d).standard_normal((2, d, d)).astype(np.float32)
+    (ag.reduce_matd(M) * torch.from_numpy(V).cuda()).sum().backward()
+    g = host(M.grad)
+    for r in range(2):
+        xb, cx = oracle.matd_reduce_vjp(w["M"][r], V[r])
+        cc = np.repeat(cx[:, None], d * d, axis=1).reshape(xb.shape)
+        assert_gate(g[r], xb, cc, RTOL["mat2"], what=f"matd{d} reduce grad")
+
+
+@pytest.mark.parametrize("op", ["add", "mul", "min", "max"])
+def test_vectorised_functions(ag, op):
+    """map2 operators through autograd against the oracle's per-component
+    adjoints."""
+    rng = np.random.default_rng(len(op) + 40)
+    n, d, m = 5000, 7, 300
+    x = rng.uniform(0.5, 2.0, (n, d)).astype(np.float32)
+    if op in ("min", "max"):
+        x = np.floor(x * 8) / 8
+    X = dev(x, True)
+    wy = rng.standard_normal((n, d)).astype(np.float32)
+    (ag.vscan(op, X) * dev(wy)).sum().backward()
+    # products of thousands of factors in [0.5, 2) leave the float32 range
+    rx = n * d if op == "mul" else 0
+    xb, cx = oracle.vscan_vjp(op, wy, x)
+    assert_gate(host(X.grad), xb, cx, RTOL[op], max_range_exceeded=rx, what=f"vscan {op}")
+    X.grad = None
+    wr = rng.standard_normal(d).astype(np.float32)
+    (ag.vreduce(op, X) * dev(wr)).sum().backward()
+    xb, cx = oracle.vreduce_vjp(op, wr, x)
+    assert_gate(host(X.grad), xb, cx, RTOL[op], max_range_exceeded=rx, what=f"vreduce {op}")
+    X.grad = None
+    idx = rng.integers(-1, m + 1, n).astype(np.int32)
+    wh = rng.standard_normal((m, d)).astype(np.float32)
+    (ag.vreduce_by_index(op, torch.from_numpy(idx).cuda(), X, m) * dev(wh)).sum().backward()
+    xb, cx = oracle.vrbi_vjp(op, idx, m, wh, x)
+    assert_gate(host(X.grad), xb, cx, RTOL[op], what=f"vrbi {op}")
