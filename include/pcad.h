@@ -212,9 +212,10 @@ int pcad_scan_vjp_checkpoint(int op, int64_t batch, int64_t n, const float *x0, 
  *     and SUMPROD up to 4096);
  *   - beyond that, one row (batch == 1) of ADD up to 131072 bins or of
  *     MIN/MAX up to 65536: the bins are split into at most four 128 KB
- *     LDS tables, one block per (table, chunk of elements) with the blocks
- *     of a chunk on one XCD, and the per-chunk tables folded in chunk order
- *     (knob rbi.parts = 0 turns this off);
+ *     LDS tables (ADD: bin g in table g mod P; MIN/MAX: contiguous ranges),
+ *     one block per (table, chunk of elements) with the blocks of a chunk
+ *     on one XCD, and the per-chunk tables folded in chunk order (knob
+ *     rbi.parts = 0 turns this off);
  *   - otherwise, for ADD/MUL/MIN/MAX/SUMPROD: the elements are partitioned once by
  *     bin range and each range gets its LDS histogram (the one-pass
  *     relative of the multi-pass technique of Section 4.2; bin ranges of
