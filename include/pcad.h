@@ -11,7 +11,11 @@
  *   reduce_by_index hist (.) e ks vs                   (Section 4)
  * Operators are +, *, min, max and two generic associative operators:
  * linear-function composition and the 2x2 matrix product (Section 5.1,
- * operator figure).
+ * operator figure), plus the evaluation's sumOfProd (an invertible lifted
+ * operator, Section 3.3) and saturated addition (non-invertible).  Further
+ * entry points cover scans and reduces of 3x3 and 5x5 matrix products
+ * (pcad_matd_*) and the vectorised operators (pcad_v*: map2 of + * min max
+ * over vectors of d floats).
  *
  * Conventions shared by every call
  * --------------------------------
