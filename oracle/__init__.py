@@ -509,3 +509,57 @@ def matd_reduce_vjp(M, Ybar):
         acc = M[i] @ acc
         ca *= np.linalg.norm(M[i], 2)
     return Mb, c
+
+
+# -------------------------------------------------------------------------
+# int32 forward combinators for + * min max, results wrapping mod 2^32 (the
+# evaluation's integer element types; forward only, as integer arithmetic
+# has no derivative).  Plain loops over Python integers, reduced mod 2^32 and
+# read back in two's complement after every step: exact by construction.
+# -------------------------------------------------------------------------
+_I32_NEUTRAL = {"add": 0, "mul": 1, "min": 2**31 - 1, "max": -2**31}
+
+
+def _wrap32(x: int) -> int:
+    x &= 0xFFFFFFFF
+    return x - (1 << 32) if x >= (1 << 31) else x
+
+
+def _i32_comb(op: str, a: int, b: int) -> int:
+    if op == "add":
+        return _wrap32(a + b)
+    if op == "mul":
+        return _wrap32(a * b)
+    if op == "min":
+        return a if a <= b else b
+    if op == "max":
+        return a if a >= b else b
+    raise ValueError(op)
+
+
+def i32_reduce(op: str, x) -> int:
+    """Left fold of x (int32) from the neutral element."""
+    acc = _I32_NEUTRAL[op]
+    for v in np.asarray(x, dtype=np.int64).reshape(-1).tolist():
+        acc = _i32_comb(op, acc, v)
+    return acc
+
+
+def i32_scan(op: str, x) -> np.ndarray:
+    """Inclusive scan of x (int32)."""
+    out = np.empty(len(x), dtype=np.int32)
+    acc = _I32_NEUTRAL[op]
+    for i, v in enumerate(np.asarray(x, dtype=np.int64).reshape(-1).tolist()):
+        acc = _i32_comb(op, acc, v)
+        out[i] = acc
+    return out
+
+
+def i32_rbi(op: str, idx, m: int, v) -> np.ndarray:
+    """hist[k] = fold of v[i] over idx[i] == k from the neutral element; keys
+    outside [0, m) are skipped (Section 4's sequential loop)."""
+    h = [_I32_NEUTRAL[op]] * max(int(m), 0)
+    for k, x in zip(np.asarray(idx).reshape(-1).tolist(), np.asarray(v, dtype=np.int64).reshape(-1).tolist()):
+        if 0 <= k < m:
+            h[k] = _i32_comb(op, h[k], x)
+    return np.array(h, dtype=np.int32)

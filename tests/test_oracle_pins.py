@@ -1082,3 +1082,42 @@ def test_matd_reduce_against_products_scan_and_differences(d):
     Y0, c0 = oracle.matd_reduce(np.zeros((0, d, d)))
     np.testing.assert_array_equal(Y0, np.eye(d))
     assert c0 == 1.0
+
+
+# -------------------------------------------------------------------------
+# int32 forward combinators (wrapping mod 2^32)
+# -------------------------------------------------------------------------
+@pytest.mark.parametrize("op", ["add", "mul", "min", "max"])
+def test_i32_against_numpy_wrapping_arithmetic(op):
+    """numpy's int32 arithmetic wraps mod 2^32 (two's complement): its
+    accumulate and ufunc.at must agree with the oracle's loops, including
+    on values that overflow."""
+    rng = np.random.default_rng(70 + len(op))
+    x = rng.integers(-2**31, 2**31, 500, dtype=np.int64).astype(np.int32)
+    if op == "mul":
+        x = rng.integers(-7, 8, 500).astype(np.int32)  # products wrap many times
+    uf = {"add": np.add, "mul": np.multiply, "min": np.minimum, "max": np.maximum}[op]
+    with np.errstate(over="ignore"):
+        ref_scan = uf.accumulate(x, dtype=np.int32)
+    np.testing.assert_array_equal(oracle.i32_scan(op, x), ref_scan)
+    assert oracle.i32_reduce(op, x) == int(ref_scan[-1])
+    m = 37
+    idx = rng.integers(-3, m + 3, 500).astype(np.int32)
+    h = np.full(m, oracle._I32_NEUTRAL[op], dtype=np.int32)
+    ok = (idx >= 0) & (idx < m)
+    with np.errstate(over="ignore"):
+        uf.at(h, idx[ok], x[ok])
+    np.testing.assert_array_equal(oracle.i32_rbi(op, idx, m, x), h)
+
+
+def test_i32_closed_forms():
+    n = 100_000
+    x = np.arange(n, dtype=np.int32)
+    assert oracle.i32_reduce("add", x) == (n * (n - 1) // 2 + 2**31) % 2**32 - 2**31
+    assert oracle.i32_reduce("add", np.zeros(0, np.int32)) == 0
+    assert oracle.i32_reduce("mul", np.zeros(0, np.int32)) == 1
+    assert oracle.i32_reduce("min", np.zeros(0, np.int32)) == 2**31 - 1
+    assert oracle.i32_reduce("max", np.array([-2**31, -5], np.int32)) == -5
+    # 2^31 wraps to -2^31; 2^32 wraps to 0
+    assert oracle.i32_reduce("mul", np.array([2**16, 2**15], np.int32)) == -2**31
+    assert oracle.i32_reduce("mul", np.array([2**16, 2**16], np.int32)) == 0
