@@ -416,6 +416,27 @@ int pcad_matd_reduce_vjp(int d, int64_t batch, int64_t n, const float *M, const 
                          size_t ws_bytes, void *stream);
 
 /*
+ * int32 forward combinators for ADD, MUL, MIN, MAX (the evaluation's integer
+ * element types; integer arithmetic has no adjoint).  ADD and MUL wrap mod
+ * 2^32 (two's complement); every result is exact, whatever the order of
+ * combination.  combinator: PCAD_REDUCE (y[batch]), PCAD_SCAN (inclusive,
+ * y[batch][n]) or PCAD_RBI (hist y[batch][m] from the neutral element: 0,
+ * 1, INT32_MAX, INT32_MIN; keys outside [0, m) skipped).
+ *   x: int32 [batch][n]; idx: int32 [batch][n] (PCAD_RBI only, else NULL).
+ *   ws: PCAD_SCAN only (pcad_i32_query's size, zero-filled before first
+ *       use, same contract as every workspace of this library); others
+ *       need none (ws may be NULL).
+ * Errors: PCAD_E_UNSUPPORTED for the other operators; PCAD_E_SIZE for
+ * batch > 65535 (reduce, reduce-by-index) or the sizes of the float calls;
+ * pointer and workspace errors as for those.
+ */
+int pcad_i32_query(int combinator, int op, int64_t batch, int64_t n, int64_t m,
+                   size_t *workspace_bytes);
+int pcad_i32_fwd(int combinator, int op, int64_t batch, int64_t n, int64_t m,
+                 const int32_t *idx, const int32_t *x, int32_t *y, void *ws, size_t ws_bytes,
+                 void *stream);
+
+/*
  * Tuning knobs: launch parameters an autotuner may set (the block size of the
  * scan kernels per operator and direction, the bin count up to which
  * reduce-by-index keeps private LDS histograms, elements per histogram

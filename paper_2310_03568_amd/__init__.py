@@ -80,6 +80,8 @@ def lib():
             "pcad_matd_scan_vjp": ([I, I64, I64, P, P, P, P, U, P, SZ, P], I),
             "pcad_matd_reduce_fwd": ([I, I64, I64, P, P, P, U, P, SZ, P], I),
             "pcad_matd_reduce_vjp": ([I, I64, I64, P, P, P, P, U, P, SZ, P], I),
+            "pcad_i32_query": ([I, I, I64, I64, I64, PSZ], I),
+            "pcad_i32_fwd": ([I, I, I64, I64, I64, P, P, P, P, SZ, P], I),
             "pcad_knob_count": ([], I),
             "pcad_knob_name": ([I], ctypes.c_char_p),
             "pcad_knob_get": ([ctypes.c_char_p, ctypes.POINTER(I64)], I),
@@ -515,6 +517,30 @@ def matd_reduce_vjp(M, saved, Ybar, out=None, accumulate: bool = False):
                                      _ptr(out), ACCUMULATE if accumulate else 0, _ptr(ws),
                                      ws.numel(), _stream(dev)), "pcad_matd_reduce_vjp")
     return out
+
+
+# ---------------------------------------------------------------------------
+# int32 forward combinators (+ * min max, wrapping mod 2^32)
+# ---------------------------------------------------------------------------
+def i32_fwd(comb: int, op: str, x: torch.Tensor, idx: Optional[torch.Tensor] = None, m: int = 0):
+    """x int32 (..., n).  REDUCE -> (...,); SCAN -> (..., n); RBI -> (..., m)."""
+    _dev_check(x, idx)
+    if x.dtype != torch.int32 or (idx is not None and idx.dtype != torch.int32):
+        raise PcadError("i32 calls take int32 tensors")
+    lead = tuple(x.shape[:-1])
+    n = x.shape[-1] if x.dim() else 1
+    batch = 1
+    for t in lead:
+        batch *= t
+    w = ctypes.c_size_t(0)
+    check(lib().pcad_i32_query(comb, OPS[op], batch, n, m, ctypes.byref(w)), "pcad_i32_query")
+    dev = x.device
+    shape = {REDUCE: lead, SCAN: lead + (n,), RBI: lead + (m,)}[comb]
+    y = torch.empty(shape, dtype=torch.int32, device=dev)
+    ws = workspace(w.value, dev) if w.value else None
+    check(lib().pcad_i32_fwd(comb, OPS[op], batch, n, m, _ptr(idx), _ptr(x), _ptr(y), _ptr(ws),
+                             ws.numel() if ws is not None else 0, _stream(dev)), "pcad_i32_fwd")
+    return y
 
 
 def vrbi_fwd(op: str, idx: torch.Tensor, v: torch.Tensor, m: int):

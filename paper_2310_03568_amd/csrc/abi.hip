@@ -514,4 +514,48 @@ int pcad_matd_reduce_vjp(int d, int64_t batch, int64_t n, const float *M, const 
                                            (hipStream_t)stream));
 }
 
+namespace {
+
+int check_i32(int comb, int op, int64_t batch, int64_t n, int64_t m) {
+  if (comb < PCAD_REDUCE || comb > PCAD_RBI) return PCAD_E_INVALID_ARG;
+  if (op < PCAD_ADD || op > PCAD_SATADD) return PCAD_E_INVALID_ARG;
+  if (op > PCAD_MAX) return PCAD_E_UNSUPPORTED;
+  PCAD_TRY(check_common(op, batch, n, 0));
+  if (comb != PCAD_SCAN && batch > 65535) return PCAD_E_SIZE;
+  if (comb == PCAD_RBI) {
+    if (m < 0) return PCAD_E_INVALID_ARG;
+    if (m > kMaxBins) return PCAD_E_SIZE;
+  }
+  return PCAD_OK;
+}
+
+}  // namespace
+
+int pcad_i32_query(int combinator, int op, int64_t batch, int64_t n, int64_t m,
+                   size_t *workspace_bytes) {
+  PCAD_TRY(check_i32(combinator, op, batch, n, m));
+  if (workspace_bytes) *workspace_bytes = i32_ws_bytes(combinator, batch, n);
+  return PCAD_OK;
+}
+
+int pcad_i32_fwd(int combinator, int op, int64_t batch, int64_t n, int64_t m,
+                 const int32_t *idx, const int32_t *x, int32_t *y, void *ws, size_t ws_bytes,
+                 void *stream) {
+  PCAD_TRY(check_i32(combinator, op, batch, n, m));
+  if (batch == 0) return PCAD_OK;
+  if (combinator == PCAD_SCAN && n == 0) return PCAD_OK;
+  if (combinator == PCAD_RBI && m == 0) return PCAD_OK;
+  if (n > 0) PCAD_TRY(need(x));
+  if (combinator == PCAD_RBI && n > 0) PCAD_TRY(need(idx));
+  PCAD_TRY(need(y));
+  const size_t need_ws = i32_ws_bytes(combinator, batch, n);
+  if (need_ws > 0) {
+    if (ws_bytes < need_ws) return PCAD_E_WORKSPACE;
+    if (!ws) return PCAD_E_NULLPTR;
+    if ((uintptr_t)ws & 255u) return PCAD_E_MISALIGNED;
+  }
+  return hip_status(i32_fwd_launch(combinator, op, batch, n, m, idx, x, y, ws,
+                                   (hipStream_t)stream));
+}
+
 }  // extern "C"

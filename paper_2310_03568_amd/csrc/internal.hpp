@@ -97,6 +97,13 @@ hipError_t matd_reduce_vjp_launch(int d, int64_t batch, int64_t n, const float *
                                   const float *saved, const float *ybar, float *xbar,
                                   bool accumulate, void *ws, hipStream_t s);
 
+// int32 forward combinators for + * min max (i32.hip); comb 0 reduce, 1 scan,
+// 2 reduce-by-index
+size_t i32_ws_bytes(int comb, int64_t batch, int64_t n);
+hipError_t i32_fwd_launch(int comb, int op, int64_t batch, int64_t n, int64_t m,
+                          const int32_t *idx, const int32_t *x, int32_t *y, void *ws,
+                          hipStream_t s);
+
 // scan
 int scan_tile_size(int op);
 int scan_elem_floats(int op);

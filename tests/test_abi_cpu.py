@@ -187,3 +187,28 @@ def test_matd_queries_and_validation(L):
     assert L.pcad_matd_reduce_fwd(5, 1, 10, p16, p16, p16, 0, p16, 8, None) == 6
     assert L.pcad_matd_reduce_vjp(5, 2, 0, None, None, None, None, 0, None, 0, None) == 0
     assert L.pcad_matd_reduce_vjp(3, 1, 10, p16, p16, None, p16, 0, None, 0, None) == 3
+
+
+def test_i32_queries_and_validation(L):
+    def iq(comb, op, batch, n, m=0):
+        w = ctypes.c_size_t(0)
+        return L.pcad_i32_query(comb, op, batch, n, m, ctypes.byref(w)), w.value
+    # scan: one int per tile of 4096 after the control block; reduce and
+    # reduce-by-index need no workspace
+    st, w = iq(1, 0, 2, 10_000)
+    assert st == 0 and w >= 256 + 2 * 3 * 4
+    assert iq(0, 1, 3, 10_000) == (0, 0)
+    assert iq(2, 3, 1, 10_000, 50) == (0, 0)
+    assert iq(0, 4, 1, 10)[0] == 2          # LINREC: unsupported
+    assert iq(0, 9, 1, 10)[0] == 1          # no operator 9
+    assert iq(3, 0, 1, 10)[0] == 1          # no combinator 3
+    assert iq(2, 0, 1, 10, -1)[0] == 1
+    assert iq(0, 0, 70_000, 10)[0] == 5     # rows beyond 65535 for reduce
+    assert iq(1, 0, 70_000, 10)[0] == 0     # the scan has no such limit
+    assert L.pcad_i32_fwd(0, 0, 1, 10, 0, None, None, None, None, 0, None) == 3
+    assert L.pcad_i32_fwd(1, 0, 1, 0, 0, None, None, None, None, 0, None) == 0
+    assert L.pcad_i32_fwd(2, 0, 1, 10, 0, None, None, None, None, 0, None) == 0
+    buf = (ctypes.c_int32 * 4096)()
+    p16 = (ctypes.addressof(buf) + 15) & ~15
+    assert L.pcad_i32_fwd(1, 0, 1, 10, 0, None, p16, p16, None, 0, None) == 6
+    assert L.pcad_i32_fwd(2, 2, 1, 10, 5, None, p16, p16, None, 0, None) == 3

@@ -845,3 +845,50 @@ def test_matd_reduce(pcad, d, batch, n):
     _ws_tail_zero(pcad, d, batch, n)
     Y0, s0 = pcad.matd_reduce_fwd(torch.empty((2, 0, d, d), device="cuda"))
     np.testing.assert_array_equal(host(Y0), np.broadcast_to(np.eye(d, dtype=np.float32), (2, d, d)))
+
+
+# ---------------------------------------------------------------------------
+# int32 forward combinators (+ * min max wrapping mod 2^32): bit-exact
+# ---------------------------------------------------------------------------
+def _i32_inputs(op, shape, rng):
+    if op == "mul":  # small factors: products wrap many times without going to 0
+        x = rng.choice(np.array([-3, -1, 1, 3, 5, 7], np.int64), size=shape)
+    else:
+        x = rng.integers(-2**31, 2**31, size=shape, dtype=np.int64)
+    return x.astype(np.int32)
+
+
+@pytest.mark.parametrize("op", SCALAR)
+@pytest.mark.parametrize("batch,n", [(1, 1), (1, 4095), (2, 4097), (3, 50_001), (1, 1_050_011)])
+def test_i32_reduce_and_scan(pcad, op, batch, n):
+    rng = np.random.default_rng(n + len(op))
+    x = _i32_inputs(op, (batch, n), rng)
+    X = dev(x)
+    y = host(pcad.i32_fwd(pcad.REDUCE, op, X))
+    s = host(pcad.i32_fwd(pcad.SCAN, op, X))
+    for r in range(batch):
+        assert int(y[r]) == oracle.i32_reduce(op, x[r])
+        if n <= 60_000 or r == 0:
+            np.testing.assert_array_equal(s[r], oracle.i32_scan(op, x[r]))
+    assert ws_error() == 0
+
+
+@pytest.mark.parametrize("op", SCALAR)
+@pytest.mark.parametrize("batch,n,m", [(1, 0, 5), (1, 1, 1), (2, 30_001, 300), (1, 100_000, 8192),
+                                       (1, 100_000, 8193), (1, 60_000, 1 << 20)])
+def test_i32_rbi(pcad, op, batch, n, m):
+    rng = np.random.default_rng(n + m + len(op))
+    x = _i32_inputs(op, (batch, n), rng)
+    idx = rng.integers(-2, m + 2, size=(batch, n)).astype(np.int32)
+    h = host(pcad.i32_fwd(pcad.RBI, op, dev(x), dev(idx), m))
+    for r in range(batch):
+        np.testing.assert_array_equal(h[r], oracle.i32_rbi(op, idx[r], m, x[r]))
+
+
+def test_i32_empty_and_rejects(pcad):
+    y = host(pcad.i32_fwd(pcad.REDUCE, "min", torch.empty((3, 0), dtype=torch.int32, device="cuda")))
+    np.testing.assert_array_equal(y, np.full(3, 2**31 - 1, np.int32))
+    with pytest.raises(pcad.PcadError):
+        pcad.i32_fwd(pcad.SCAN, "linrec", torch.zeros(10, dtype=torch.int32, device="cuda"))
+    with pytest.raises(pcad.PcadError):
+        pcad.i32_fwd(pcad.SCAN, "add", torch.zeros(10, dtype=torch.float32, device="cuda"))
