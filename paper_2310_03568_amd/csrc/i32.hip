@@ -134,18 +134,31 @@ __global__ __launch_bounds__(I_TH) void k_i32_tiles(I32ScanArgs a) {
   }
 }
 
-// pass 2 (one block per row): tile totals -> tile exclusive prefixes, in place
+// pass 2 (one block per row): tile totals -> tile exclusive prefixes, in
+// place; each thread takes TS consecutive tiles per round
 template <int OP>
 __global__ __launch_bounds__(I_TH) void k_i32_tile_scan(I32ScanArgs a) {
+  constexpr int TS = 8;
   __shared__ int32_t s[I_TH];
   const int64_t row = blockIdx.x;
+  int32_t *g = a.agg + row * a.tpr;
   int32_t carry = ineutral<OP>();
-  for (int64_t c0 = 0; c0 < a.tpr; c0 += I_TH) {
-    const int64_t t = c0 + threadIdx.x;
-    const int32_t v = t < a.tpr ? a.agg[row * a.tpr + t] : ineutral<OP>();
+  for (int64_t c0 = 0; c0 < a.tpr; c0 += (int64_t)I_TH * TS) {
+    const int64_t t0 = c0 + (int64_t)threadIdx.x * TS;
+    int32_t v[TS];
+    int32_t acc = ineutral<OP>();
+#pragma unroll
+    for (int j = 0; j < TS; ++j) {
+      v[j] = t0 + j < a.tpr ? g[t0 + j] : ineutral<OP>();
+      acc = icomb<OP>(acc, v[j]);
+    }
     int32_t tot;
-    const int32_t ex = block_excl<OP>(v, s, &tot);
-    if (t < a.tpr) a.agg[row * a.tpr + t] = icomb<OP>(carry, ex);
+    int32_t run = icomb<OP>(carry, block_excl<OP>(acc, s, &tot));
+#pragma unroll
+    for (int j = 0; j < TS; ++j) {
+      if (t0 + j < a.tpr) g[t0 + j] = run;
+      run = icomb<OP>(run, v[j]);
+    }
     carry = icomb<OP>(carry, tot);
   }
 }
@@ -161,11 +174,19 @@ __global__ __launch_bounds__(I_TH) void k_i32_apply(I32ScanArgs a) {
   int32_t *yr = a.y + row * a.n;
   int32_t v[I_EPT];
   int32_t acc = ineutral<OP>();
+  if (((row * a.n) & 3) == 0 && s0 + I_EPT <= a.n) {
+    // 16-byte loads (the row start and s0 are multiples of 4 elements)
 #pragma unroll
-  for (int j = 0; j < I_EPT; ++j) {
-    v[j] = s0 + j < a.n ? xr[s0 + j] : ineutral<OP>();
-    acc = icomb<OP>(acc, v[j]);
+    for (int q = 0; q < I_EPT / 4; ++q) {
+      const int4 w = *reinterpret_cast<const int4 *>(xr + s0 + 4 * q);
+      v[4 * q] = w.x; v[4 * q + 1] = w.y; v[4 * q + 2] = w.z; v[4 * q + 3] = w.w;
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < I_EPT; ++j) v[j] = s0 + j < a.n ? xr[s0 + j] : ineutral<OP>();
   }
+#pragma unroll
+  for (int j = 0; j < I_EPT; ++j) acc = icomb<OP>(acc, v[j]);
   const int32_t pre = a.agg[tile];
   int32_t tot;
   const int32_t ex = block_excl<OP>(acc, s, &tot);
@@ -174,7 +195,17 @@ __global__ __launch_bounds__(I_TH) void k_i32_apply(I32ScanArgs a) {
 #pragma unroll
   for (int j = 0; j < I_EPT; ++j) {
     run = icomb<OP>(run, v[j]);
-    if (s0 + j < a.n) yr[s0 + j] = run;
+    v[j] = run;
+  }
+  if (((row * a.n) & 3) == 0 && s0 + I_EPT <= a.n) {
+#pragma unroll
+    for (int q = 0; q < I_EPT / 4; ++q)
+      *reinterpret_cast<int4 *>(yr + s0 + 4 * q) =
+          make_int4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
+  } else {
+#pragma unroll
+    for (int j = 0; j < I_EPT; ++j)
+      if (s0 + j < a.n) yr[s0 + j] = v[j];
   }
 }
 
