@@ -11,7 +11,9 @@
 //            block per row scanning them, a rescan of every tile from its
 //            exclusive prefix (workspace entries cleared after use);
 //   reduce_by_index : LDS histograms of up to 8192 bins merged with one
-//            atomic per non-neutral bin, global atomics beyond.
+//            atomic per non-neutral bin; one row of up to 131072 bins split
+//            into 128 KB LDS tables, one block per (table, chunk); global
+//            atomics beyond.
 #include "device.hpp"
 #include "internal.hpp"
 
@@ -242,6 +244,40 @@ __global__ __launch_bounds__(I_TH) void k_i32_rbi_global(const int32_t *idx, con
   }
 }
 
+// one row with up to four 128 KB LDS tables' worth of bins: block (part,
+// chunk) keeps the keys of its contiguous bin range in LDS and merges its
+// non-neutral bins with global atomics; the blocks of a chunk sit on one
+// XCD (blocks are dealt to the XCDs round robin), so the chunk is read from
+// HBM about once
+constexpr int I_PARTS_TH = 1024;
+constexpr int kI32PartBins = 32768;  // 128 KB
+constexpr int kI32Xcds = 8;
+
+template <int OP>
+__global__ __launch_bounds__(I_PARTS_TH) void k_i32_rbi_parts(const int32_t *idx, const int32_t *x,
+                                                              int32_t *h, int64_t n, int64_t m,
+                                                              int64_t chunk, int P) {
+  __shared__ int32_t s_h[kI32PartBins];
+  const int b = blockIdx.x;
+  const int xcd = b % kI32Xcds, slot = b / kI32Xcds;
+  const int c = xcd + kI32Xcds * (slot / P), p = slot % P;
+  const int64_t kb0 = (int64_t)p * kI32PartBins;
+  const int lim = (int)(m - kb0 < kI32PartBins ? m - kb0 : kI32PartBins);
+  for (int k = threadIdx.x; k < kI32PartBins; k += I_PARTS_TH) s_h[k] = ineutral<OP>();
+  __syncthreads();
+  const int64_t lo = (int64_t)c * chunk;
+  const int64_t hi = lo + chunk < n ? lo + chunk : n;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += I_PARTS_TH) {
+    const int64_t k = (int64_t)idx[i] - kb0;
+    if (k >= 0 && k < lim) iatomic<OP>(&s_h[k], x[i]);
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < lim; k += I_PARTS_TH) {
+    const int32_t v = s_h[k];
+    if (v != ineutral<OP>()) iatomic<OP>(&h[kb0 + k], v);
+  }
+}
+
 size_t al256(size_t x) { return (x + 255) / 256 * 256; }
 
 unsigned grid_cap(int64_t g, int64_t cap) { return (unsigned)(g < 1 ? 1 : (g > cap ? cap : g)); }
@@ -276,6 +312,16 @@ hipError_t i32_run(int comb, int64_t batch, int64_t n, int64_t m, const int32_t 
         const unsigned bx = grid_cap((n + 16383) / 16384, 2048 / (batch < 2048 ? batch : 2048));
         hipLaunchKernelGGL(k_i32_rbi_lds<OP>, dim3(bx, (unsigned)batch), dim3(I_TH), 0, s, idx, x, y,
                            n, (int)m);
+      } else if (batch == 1 && m <= 4 * kI32PartBins) {
+        const int P = (int)((m + kI32PartBins - 1) / kI32PartBins);
+        int64_t cl = 32 / P;
+        const int64_t want = (n + (int64_t)kI32Xcds * 65536 - 1) / ((int64_t)kI32Xcds * 65536);
+        if (cl > want) cl = want;
+        if (cl < 1) cl = 1;
+        const int64_t C = kI32Xcds * cl;
+        const int64_t chunk = (n + C - 1) / C;
+        hipLaunchKernelGGL(k_i32_rbi_parts<OP>, dim3((unsigned)(C * P)), dim3(I_PARTS_TH), 0, s, idx,
+                           x, y, n, m, chunk, P);
       } else {
         const unsigned bx = grid_cap((n + I_TH * 16 - 1) / (I_TH * 16), 65535 / (batch < 65535 ? batch : 65535));
         hipLaunchKernelGGL(k_i32_rbi_global<OP>, dim3(bx, (unsigned)batch), dim3(I_TH), 0, s, idx, x,

@@ -875,7 +875,8 @@ def test_i32_reduce_and_scan(pcad, op, batch, n):
 
 @pytest.mark.parametrize("op", SCALAR)
 @pytest.mark.parametrize("batch,n,m", [(1, 0, 5), (1, 1, 1), (2, 30_001, 300), (1, 100_000, 8192),
-                                       (1, 100_000, 8193), (1, 60_000, 1 << 20)])
+                                       (1, 100_000, 8193), (1, 700_001, 100_000), (2, 20_000, 9000),
+                                       (1, 60_000, 1 << 20)])
 def test_i32_rbi(pcad, op, batch, n, m):
     rng = np.random.default_rng(n + m + len(op))
     x = _i32_inputs(op, (batch, n), rng)
