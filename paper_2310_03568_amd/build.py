@@ -4,7 +4,7 @@
 
 Each csrc/*.hip file is compiled to an object in _build/ in parallel, then
 linked into paper_2310_03568_amd/libpcad.so.  Compiles every time it is
-called (the driver's "does it build" check).
+called, whether or not a library is already there.
 """
 from __future__ import annotations
 
