@@ -203,6 +203,8 @@ def test_golden(g):
     elif comb == "reduce":
         r = oracle.reduce_fwd(op, np.array(g["x"]))
         np.testing.assert_array_equal(r["y"], g["y"])
+        if "y_signbit" in g:  # -0.0 == +0.0: the bit pattern is checked apart
+            np.testing.assert_array_equal(np.signbit(r["y"]), g["y_signbit"])
         if "k" in g:
             assert r["k"] == g["k"]
         if "n0" in g:
@@ -225,12 +227,16 @@ def test_golden(g):
     elif comb == "scan":
         rs, _ = oracle.scan_fwd(op, np.array(g["x"]))
         np.testing.assert_array_equal(rs[:, 0], g["y"])
+        if "y_signbit" in g:
+            np.testing.assert_array_equal(np.signbit(rs[:, 0]), g["y_signbit"])
         xb, _ = oracle.scan_vjp(op, np.array(g["ybar"]), np.array(g["x"]))
         np.testing.assert_allclose(xb[:, 0], g["xbar"], rtol=1e-15)
     elif comb == "rbi":
         idx = np.array(g["idx"], np.int32)
         r = oracle.rbi_fwd(op, idx, g["m"], np.array(g["v"]))
         np.testing.assert_array_equal(r["hist"][:, 0], _f(g["hist"]))
+        if "hist_signbit" in g:
+            np.testing.assert_array_equal(np.signbit(r["hist"][:, 0]), g["hist_signbit"])
         for key in ("count", "argk", "n0", "ypos"):
             if key in g:
                 np.testing.assert_array_equal(r[key], g[key])
