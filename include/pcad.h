@@ -46,7 +46,8 @@
  * - Workspace: `ws` / `ws_bytes` is caller-owned device scratch of at least
  *   the size pcad_query() reports.  It MUST be zero-filled once before its
  *   first use.  Every call leaves it holding only its control block (the
- *   first 256 bytes), look-back status words tagged with the launch that
+ *   first 256 bytes: rows done, launch epoch, error word -- see
+ *   pcad_ws_status), look-back status words tagged with the launch that
  *   wrote them, and zeros -- scratch data is cleared before a call returns --
  *   so one workspace serves any sequence of calls of this library.  Do not
  *   write other data into it.  Calls that share one workspace must be
@@ -78,7 +79,9 @@ typedef enum {
   PCAD_E_MISALIGNED = 4,  /* a float array is not 16-byte aligned */
   PCAD_E_SIZE = 5,        /* n, m or batch out of the supported range */
   PCAD_E_WORKSPACE = 6,   /* ws_bytes smaller than pcad_query() reports */
-  PCAD_E_HIP = 7          /* a HIP runtime call failed; see pcad_last_hip_error */
+  PCAD_E_HIP = 7,         /* a HIP runtime call failed; see pcad_last_hip_error */
+  PCAD_E_TIMEOUT = 8      /* pcad_ws_status: a look-back wait of an earlier call on the
+                             workspace timed out, so that call's results are invalid */
 } pcad_status;
 
 typedef enum { PCAD_REDUCE = 0, PCAD_SCAN = 1, PCAD_RBI = 2 } pcad_combinator;
@@ -104,6 +107,22 @@ const char *pcad_status_string(int status);
 int pcad_last_hip_error(void);
 /* Library version string. */
 const char *pcad_version(void);
+
+/*
+ * pcad_ws_status -- whether a call on workspace `ws` failed inside its
+ * kernels.  The look-back kernels wait for results of other workgroups of the
+ * same launch; every such wait is bounded (about 2^20 polls), and a wait that
+ * runs out (the grid could not stay resident, e.g. the GPU was shared with
+ * other work) writes the launch's tag into word [2] of the control block,
+ * after which every wait of that launch gives up and its results are invalid.
+ * The word names the failed launch, so later calls on the workspace are not
+ * affected by it.  This call synchronises `stream`, reads the word and
+ * returns PCAD_E_TIMEOUT if it is set (clearing it when `clear` != 0), else
+ * PCAD_OK.  ws must be 256-byte aligned (PCAD_E_NULLPTR / PCAD_E_MISALIGNED);
+ * a HIP failure returns PCAD_E_HIP.  Host only: never call it while a call on
+ * the same workspace is being captured into a graph.
+ */
+int pcad_ws_status(void *ws, int clear, void *stream);
 
 /*
  * pcad_query -- bytes of saved state and workspace for a call.
@@ -427,7 +446,9 @@ int pcad_matd_reduce_vjp(int d, int64_t batch, int64_t n, const float *M, const 
  *       use, same contract as every workspace of this library); others
  *       need none (ws may be NULL).
  * Errors: PCAD_E_UNSUPPORTED for the other operators; PCAD_E_SIZE for
- * batch > 65535 (reduce, reduce-by-index) or the sizes of the float calls;
+ * batch > 65535 (reduce, reduce-by-index), for a scan of more than 2^24 - 1
+ * tiles of 4096 elements in all (batch * ceil(n / 4096)), or the sizes of
+ * the float calls;
  * pointer and workspace errors as for those.
  */
 int pcad_i32_query(int combinator, int op, int64_t batch, int64_t n, int64_t m,

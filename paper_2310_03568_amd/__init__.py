@@ -53,6 +53,7 @@ def lib():
             "pcad_status_string": ([I], ctypes.c_char_p),
             "pcad_last_hip_error": ([], I),
             "pcad_version": ([], ctypes.c_char_p),
+            "pcad_ws_status": ([P, I, P], I),
             "pcad_query": ([I, I, I64, I64, I64, U, PSZ, PSZ], I),
             "pcad_reduce_fwd": ([I, I64, I64, P, P, P, P, U, P, SZ, P], I),
             "pcad_reduce_vjp": ([I, I64, I64, P, P, P, P, P, P, U, P, SZ, P], I),
@@ -102,12 +103,39 @@ def __getattr__(name):
     raise AttributeError(name)
 
 
-def check(status: int, what: str = ""):
+# PCAD_SYNC_CHECK=1: after every call, synchronise its stream and raise if a
+# look-back wait of that call timed out (pcad_ws_status); off by default
+# because it costs a host round trip per call
+SYNC_CHECK = os.environ.get("PCAD_SYNC_CHECK", "0") == "1"
+E_TIMEOUT = 8
+
+
+def check(status: int, what: str = "", ws: Optional[torch.Tensor] = None):
     if status != 0:
         L = lib()
         msg = L.pcad_status_string(status).decode()
         hip = L.pcad_last_hip_error()
         raise PcadError(f"{what}: {msg} (status {status}, hip error {hip})")
+    if SYNC_CHECK and ws is not None:
+        ws_status(ws, what=what)
+
+
+def ws_status(ws: torch.Tensor, clear: bool = True, what: str = "") -> int:
+    """Status of the calls on workspace ``ws`` (synchronises its device's
+    current stream): raises PcadError if a look-back wait timed out, which
+    invalidates that call's results; clears the report when ``clear``."""
+    st = lib().pcad_ws_status(_ptr(ws), 1 if clear else 0, _stream(ws.device))
+    if st == E_TIMEOUT:
+        raise PcadError(f"{what or 'pcad'}: {lib().pcad_status_string(st).decode()}")
+    check(st, "pcad_ws_status")
+    return st
+
+
+def ws_status_all(clear: bool = True) -> int:
+    """ws_status over every cached workspace; 0 when none reports a timeout."""
+    for buf in list(_ws.values()):
+        ws_status(buf, clear)
+    return 0
 
 
 # ---------------------------------------------------------------------------
@@ -208,7 +236,7 @@ def reduce_fwd(op: str, x0: torch.Tensor, x1: Optional[torch.Tensor] = None):
     saved = torch.empty(max(s_b, 16), dtype=torch.uint8, device=dev)
     ws = workspace(w_b, dev)
     check(lib().pcad_reduce_fwd(OPS[op], batch, n, _ptr(x0), _ptr(x1), _ptr(y), _ptr(saved), 0,
-                                _ptr(ws), ws.numel(), _stream(dev)), "pcad_reduce_fwd")
+                                _ptr(ws), ws.numel(), _stream(dev)), "pcad_reduce_fwd", ws=ws)
     return y, saved
 
 
@@ -224,7 +252,7 @@ def reduce_vjp(op: str, x0, x1, saved, ybar, out=None, accumulate: bool = False)
                                 _ptr(ybar.contiguous()), _ptr(out[0]),
                                 _ptr(out[1]) if len(out) > 1 else None,
                                 ACCUMULATE if accumulate else 0, _ptr(ws), ws.numel(),
-                                _stream(dev)), "pcad_reduce_vjp")
+                                _stream(dev)), "pcad_reduce_vjp", ws=ws)
     return out if op == "linrec" else out[0]
 
 
@@ -246,7 +274,7 @@ def scan_fwd(op: str, x0: torch.Tensor, x1: Optional[torch.Tensor] = None, want_
     ws = workspace(w_b, dev)
     check(lib().pcad_scan_fwd(OPS[op], batch, n, _ptr(x0), _ptr(x1), _ptr(y), _ptr(A),
                               _ptr(saved), 0, _ptr(ws), ws.numel(), _stream(dev)),
-          "pcad_scan_fwd")
+          "pcad_scan_fwd", ws=ws)
     return y, A, saved
 
 
@@ -262,7 +290,7 @@ def scan_vjp(op: str, x0, x1, saved, ybar, Abar=None, out=None, accumulate: bool
     check(lib().pcad_scan_vjp(OPS[op], batch, n, _ptr(x0), _ptr(x1), _ptr(saved), _ptr(ybar),
                               _ptr(Abar), _ptr(out[0]), _ptr(out[1]) if len(out) > 1 else None,
                               ACCUMULATE if accumulate else 0, _ptr(ws), ws.numel(),
-                              _stream(dev)), "pcad_scan_vjp")
+                              _stream(dev)), "pcad_scan_vjp", ws=ws)
     return out if op == "linrec" else out[0]
 
 
@@ -281,7 +309,7 @@ def scan_vjp_checkpoint(op: str, x0, x1, y0, y1, ybar, Abar=None, out=None,
                                          _ptr(y1), _ptr(ybar), _ptr(Abar), _ptr(out[0]),
                                          _ptr(out[1]) if len(out) > 1 else None,
                                          ACCUMULATE if accumulate else 0, _ptr(ws), ws.numel(),
-                                         _stream(dev)), "pcad_scan_vjp_checkpoint")
+                                         _stream(dev)), "pcad_scan_vjp_checkpoint", ws=ws)
     return out if op == "linrec" else out[0]
 
 
@@ -320,7 +348,7 @@ def rbi_fwd(op: str, idx: torch.Tensor, v: torch.Tensor, m: int):
     saved = torch.empty(max(s_b, 16), dtype=torch.uint8, device=dev)
     ws = workspace(w_b, dev)
     check(lib().pcad_rbi_fwd(OPS[op], batch, n, m, _ptr(idx), _ptr(v), _ptr(hist), _ptr(saved), 0,
-                             _ptr(ws), ws.numel(), _stream(dev)), "pcad_rbi_fwd")
+                             _ptr(ws), ws.numel(), _stream(dev)), "pcad_rbi_fwd", ws=ws)
     return hist, saved
 
 
@@ -333,7 +361,7 @@ def rbi_vjp(op: str, idx, v, m: int, saved, hbar, out=None, accumulate: bool = F
     ws = workspace(w_b, dev)
     check(lib().pcad_rbi_vjp(OPS[op], batch, n, m, _ptr(idx), _ptr(v), _ptr(saved), _ptr(hbar),
                              _ptr(out), ACCUMULATE if accumulate else 0, _ptr(ws), ws.numel(),
-                             _stream(dev)), "pcad_rbi_vjp")
+                             _stream(dev)), "pcad_rbi_vjp", ws=ws)
     return out
 
 
@@ -396,7 +424,7 @@ def vreduce_fwd(op: str, x: torch.Tensor):
     ws, tmp = workspace(w_b, dev), scratch(t_b, dev)
     check(lib().pcad_vreduce_fwd(OPS[op], batch, n, d, _ptr(x), _ptr(y), _ptr(saved), 0, _ptr(ws),
                                  ws.numel(), _ptr(tmp), tmp.numel(), _stream(dev)),
-          "pcad_vreduce_fwd")
+          "pcad_vreduce_fwd", ws=ws)
     return y, saved
 
 
@@ -409,7 +437,7 @@ def vreduce_vjp(op: str, x, saved, ybar, out=None, accumulate: bool = False):
     ws, tmp = workspace(w_b, dev), scratch(t_b, dev)
     check(lib().pcad_vreduce_vjp(OPS[op], batch, n, d, _ptr(x), _ptr(saved), _ptr(ybar.contiguous()),
                                  _ptr(out), ACCUMULATE if accumulate else 0, _ptr(ws), ws.numel(),
-                                 _ptr(tmp), tmp.numel(), _stream(dev)), "pcad_vreduce_vjp")
+                                 _ptr(tmp), tmp.numel(), _stream(dev)), "pcad_vreduce_vjp", ws=ws)
     return out
 
 
@@ -423,7 +451,7 @@ def vscan_fwd(op: str, x: torch.Tensor):
     saved = torch.empty(max(s_b, 16), dtype=torch.uint8, device=dev)
     ws, tmp = workspace(w_b, dev), scratch(t_b, dev)
     check(lib().pcad_vscan_fwd(OPS[op], batch, n, d, _ptr(x), _ptr(y), _ptr(saved), 0, _ptr(ws),
-                               ws.numel(), _ptr(tmp), tmp.numel(), _stream(dev)), "pcad_vscan_fwd")
+                               ws.numel(), _ptr(tmp), tmp.numel(), _stream(dev)), "pcad_vscan_fwd", ws=ws)
     return y, saved
 
 
@@ -436,7 +464,7 @@ def vscan_vjp(op: str, x, saved, ybar, out=None, accumulate: bool = False):
     ws, tmp = workspace(w_b, dev), scratch(t_b, dev)
     check(lib().pcad_vscan_vjp(OPS[op], batch, n, d, _ptr(x), _ptr(saved), _ptr(ybar.contiguous()),
                                _ptr(out), ACCUMULATE if accumulate else 0, _ptr(ws), ws.numel(),
-                               _ptr(tmp), tmp.numel(), _stream(dev)), "pcad_vscan_vjp")
+                               _ptr(tmp), tmp.numel(), _stream(dev)), "pcad_vscan_vjp", ws=ws)
     return out
 
 
@@ -471,7 +499,7 @@ def matd_scan_fwd(M: torch.Tensor):
     saved = torch.empty(max(s_b, 16), dtype=torch.uint8, device=dev)
     ws = workspace(w_b, dev)
     check(lib().pcad_matd_scan_fwd(d, batch, n, _ptr(M), _ptr(P), _ptr(saved), 0, _ptr(ws),
-                                   ws.numel(), _stream(dev)), "pcad_matd_scan_fwd")
+                                   ws.numel(), _stream(dev)), "pcad_matd_scan_fwd", ws=ws)
     return P, saved
 
 
@@ -486,7 +514,7 @@ def matd_scan_vjp(M, saved, Pbar, out=None, accumulate: bool = False):
     ws = workspace(w_b, dev)
     check(lib().pcad_matd_scan_vjp(d, batch, n, _ptr(M), _ptr(saved), _ptr(Pbar.contiguous()),
                                    _ptr(out), ACCUMULATE if accumulate else 0, _ptr(ws),
-                                   ws.numel(), _stream(dev)), "pcad_matd_scan_vjp")
+                                   ws.numel(), _stream(dev)), "pcad_matd_scan_vjp", ws=ws)
     return out
 
 
@@ -500,7 +528,7 @@ def matd_reduce_fwd(M: torch.Tensor):
     saved = torch.empty(max(s_b, 16), dtype=torch.uint8, device=dev)
     ws = workspace(w_b, dev)
     check(lib().pcad_matd_reduce_fwd(d, batch, n, _ptr(M), _ptr(Y), _ptr(saved), 0, _ptr(ws),
-                                     ws.numel(), _stream(dev)), "pcad_matd_reduce_fwd")
+                                     ws.numel(), _stream(dev)), "pcad_matd_reduce_fwd", ws=ws)
     return Y, saved
 
 
@@ -515,7 +543,7 @@ def matd_reduce_vjp(M, saved, Ybar, out=None, accumulate: bool = False):
     ws = workspace(w_b, dev)
     check(lib().pcad_matd_reduce_vjp(d, batch, n, _ptr(M), _ptr(saved), _ptr(Ybar.contiguous()),
                                      _ptr(out), ACCUMULATE if accumulate else 0, _ptr(ws),
-                                     ws.numel(), _stream(dev)), "pcad_matd_reduce_vjp")
+                                     ws.numel(), _stream(dev)), "pcad_matd_reduce_vjp", ws=ws)
     return out
 
 
@@ -539,7 +567,7 @@ def i32_fwd(comb: int, op: str, x: torch.Tensor, idx: Optional[torch.Tensor] = N
     y = torch.empty(shape, dtype=torch.int32, device=dev)
     ws = workspace(w.value, dev) if w.value else None
     check(lib().pcad_i32_fwd(comb, OPS[op], batch, n, m, _ptr(idx), _ptr(x), _ptr(y), _ptr(ws),
-                             ws.numel() if ws is not None else 0, _stream(dev)), "pcad_i32_fwd")
+                             ws.numel() if ws is not None else 0, _stream(dev)), "pcad_i32_fwd", ws=ws)
     return y
 
 
@@ -554,7 +582,7 @@ def vrbi_fwd(op: str, idx: torch.Tensor, v: torch.Tensor, m: int):
     ws, tmp = workspace(w_b, dev), scratch(t_b, dev)
     check(lib().pcad_vrbi_fwd(OPS[op], batch, n, d, m, _ptr(idx), _ptr(v), _ptr(hist), _ptr(saved),
                               0, _ptr(ws), ws.numel(), _ptr(tmp), tmp.numel(), _stream(dev)),
-          "pcad_vrbi_fwd")
+          "pcad_vrbi_fwd", ws=ws)
     return hist, saved
 
 
@@ -568,7 +596,7 @@ def vrbi_vjp(op: str, idx, v, m: int, saved, hbar, out=None, accumulate: bool = 
     check(lib().pcad_vrbi_vjp(OPS[op], batch, n, d, m, _ptr(idx), _ptr(v), _ptr(saved),
                               _ptr(hbar.contiguous()), _ptr(out), ACCUMULATE if accumulate else 0,
                               _ptr(ws), ws.numel(), _ptr(tmp), tmp.numel(), _stream(dev)),
-          "pcad_vrbi_vjp")
+          "pcad_vrbi_vjp", ws=ws)
     return out
 
 
@@ -640,6 +668,8 @@ class BatchedPlan:
         r = lib().pcad_plan_run(self._h, phase, st)
         if r != 0:
             raise PcadError(f"pcad_plan_run: status {r}, hip {lib().pcad_plan_last_hip_error()}")
+        if SYNC_CHECK:
+            ws_status(self.ws, what="pcad_plan_run")
 
     def run_per_segment(self, phase: int = PHASE_BOTH):
         st = torch.cuda.current_stream(self.device).cuda_stream
@@ -648,7 +678,13 @@ class BatchedPlan:
             raise PcadError(f"pcad_plan_run_per_segment: status {r}, hip {lib().pcad_plan_last_hip_error()}")
 
     def ws_error(self) -> int:
-        return int(self.ws[:16].view(torch.int32)[2].item())
+        """The error word of the plan's workspace (0 when no look-back wait
+        of its launches timed out); see pcad_ws_status."""
+        st = lib().pcad_ws_status(self.ws.data_ptr(), 0,
+                                  torch.cuda.current_stream(self.device).cuda_stream)
+        if st not in (0, E_TIMEOUT):
+            check(st, "pcad_ws_status")
+        return 0 if st == 0 else int(self.ws[:16].view(torch.int32)[2].item())
 
     def close(self):
         if getattr(self, "_h", None):

@@ -170,11 +170,29 @@ const char *pcad_status_string(int status) {
   case PCAD_E_SIZE: return "size out of range";
   case PCAD_E_WORKSPACE: return "workspace too small";
   case PCAD_E_HIP: return "HIP runtime error";
+  case PCAD_E_TIMEOUT: return "a look-back wait timed out: the results of that launch are invalid";
   }
   return "unknown status";
 }
 
 int pcad_last_hip_error(void) { return g_last_hip; }
+
+int pcad_ws_status(void *ws, int clear, void *stream) {
+  if (!ws) return PCAD_E_NULLPTR;
+  if ((uintptr_t)ws & 255u) return PCAD_E_MISALIGNED;
+  hipStream_t s = (hipStream_t)stream;
+  uint32_t *err = reinterpret_cast<uint32_t *>(static_cast<char *>(ws) + 8);
+  uint32_t word = 0;
+  PCAD_TRY(hip_status(hipMemcpyAsync(&word, err, sizeof word, hipMemcpyDeviceToHost, s)));
+  PCAD_TRY(hip_status(hipStreamSynchronize(s)));
+  if (word == 0) return PCAD_OK;
+  if (clear) {
+    const uint32_t zero = 0;
+    PCAD_TRY(hip_status(hipMemcpyAsync(err, &zero, sizeof zero, hipMemcpyHostToDevice, s)));
+    PCAD_TRY(hip_status(hipStreamSynchronize(s)));
+  }
+  return PCAD_E_TIMEOUT;
+}
 
 const char *pcad_version(void) { return "pcad 0.1 gfx950"; }
 
@@ -522,6 +540,9 @@ int check_i32(int comb, int op, int64_t batch, int64_t n, int64_t m) {
   if (op > PCAD_MAX) return PCAD_E_UNSUPPORTED;
   PCAD_TRY(check_common(op, batch, n, 0));
   if (comb != PCAD_SCAN && batch > 65535) return PCAD_E_SIZE;
+  // the scan launches one 256-thread block per tile and per row; a grid
+  // dimension holds fewer than 2^32 threads
+  if (comb == PCAD_SCAN && n > 0 && i32_scan_tiles(batch, n) > kI32MaxScanTiles) return PCAD_E_SIZE;
   if (comb == PCAD_RBI) {
     if (m < 0) return PCAD_E_INVALID_ARG;
     if (m > kMaxBins) return PCAD_E_SIZE;

@@ -622,8 +622,12 @@ __device__ __forceinline__ bool read_words(const uint64_t *w, uint32_t tag, Vec<
 }
 
 // Per-launch control block at the start of every workspace:
-//   [0] rows finished in this launch, [1] launch epoch, [2] error flag
-//       (2 = a look-back wait timed out), [3] unused.
+//   [0] rows finished in this launch, [1] launch epoch, [2] error word: the
+//       tag of the last launch whose look-back wait timed out (0 = none),
+//   [3] unused.
+// The error word names its launch, so only the waits of that same launch give
+// up early on it; a later launch (new tag) waits normally.  The host reads
+// and clears it with pcad_ws_status.
 // Tiles are taken in dispatch order (blockIdx), so no per-tile counter is
 // needed.  The tile that comes last in scan order in a row has, once its
 // look-back is done, seen every tile of its row publish (each publish
@@ -647,12 +651,13 @@ __device__ __forceinline__ unsigned ctl_load(unsigned *p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ void ctl_error(Ctl *ctl, unsigned code) {
-  __hip_atomic_store(&ctl->err, code, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ void ctl_error(Ctl *ctl, uint32_t tag) {
+  __hip_atomic_store(&ctl->err, tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ bool ctl_failed(Ctl *ctl) {
-  return __hip_atomic_load(&ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+// whether a wait of the launch with this tag has already timed out
+__device__ __forceinline__ bool ctl_failed(Ctl *ctl, uint32_t tag) {
+  return __hip_atomic_load(&ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == tag;
 }
 
 // called once per row, by the row's last tile in scan order, after its
@@ -682,9 +687,9 @@ constexpr int lookback_q() {
 // aggregates after it.  When no inclusive prefix lies within dist_max, the
 // result is the combination of the dist_max aggregates and *hit (if given)
 // is set false; the caller then supplies the prefix before the window.
-// Every wait is bounded: after kSpinLimit polls, or as soon as any block has
-// flagged an error, the wave stops waiting (the result is then garbage and
-// the error flag tells the host).
+// Every wait is bounded: after kSpinLimit polls, or as soon as any block of
+// the same launch has flagged a timeout, the wave stops waiting (the result
+// is then garbage and the error word tells the host).
 template <class Tr>
 __device__ typename Tr::T lookback(const uint64_t *st, int64_t tile, int dir, int dist_max,
                                    uint32_t tag, Ctl *ctl, bool *hit = nullptr) {
@@ -742,10 +747,10 @@ __device__ typename Tr::T lookback(const uint64_t *st, int64_t tile, int dir, in
       if (__ballot(missing) == 0) break;
       if ((spin & 255) == 255) {
         if (spin >= kSpinLimit) {
-          ctl_error(ctl, 2u);
+          ctl_error(ctl, tag);
           break;
         }
-        if (ctl_failed(ctl)) break;
+        if (ctl_failed(ctl, tag)) break;
       }
       __builtin_amdgcn_s_sleep(1);
     }

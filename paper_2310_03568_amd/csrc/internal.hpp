@@ -100,6 +100,10 @@ hipError_t matd_reduce_vjp_launch(int d, int64_t batch, int64_t n, const float *
 // int32 forward combinators for + * min max (i32.hip); comb 0 reduce, 1 scan,
 // 2 reduce-by-index
 size_t i32_ws_bytes(int comb, int64_t batch, int64_t n);
+// tiles of an int32 scan over batch rows of n (one block each), at most
+// kI32MaxScanTiles
+int64_t i32_scan_tiles(int64_t batch, int64_t n);
+constexpr int64_t kI32MaxScanTiles = (1LL << 24) - 1;
 hipError_t i32_fwd_launch(int comb, int op, int64_t batch, int64_t n, int64_t m,
                           const int32_t *idx, const int32_t *x, int32_t *y, void *ws,
                           hipStream_t s);

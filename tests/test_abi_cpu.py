@@ -38,6 +38,7 @@ def test_exports_every_declared_symbol(L):
 def test_status_strings(L):
     assert L.pcad_status_string(0) == b"ok"
     assert L.pcad_status_string(6) == b"workspace too small"
+    assert b"timed out" in L.pcad_status_string(8)
     assert L.pcad_status_string(99) == b"unknown status"
     assert L.pcad_version().startswith(b"pcad")
     assert L.pcad_last_hip_error() == 0
@@ -204,7 +205,12 @@ def test_i32_queries_and_validation(L):
     assert iq(3, 0, 1, 10)[0] == 1          # no combinator 3
     assert iq(2, 0, 1, 10, -1)[0] == 1
     assert iq(0, 0, 70_000, 10)[0] == 5     # rows beyond 65535 for reduce
-    assert iq(1, 0, 70_000, 10)[0] == 0     # the scan has no such limit
+    assert iq(1, 0, 70_000, 10)[0] == 0     # the scan has no such limit,
+    # but one block per 4096-element tile and row, fewer than 2^24 blocks
+    assert iq(1, 0, (1 << 24) - 1, 4096)[0] == 0
+    assert iq(1, 0, 1 << 24, 4096)[0] == 5
+    assert iq(1, 0, 1 << 21, 4097 * 8)[0] == 5  # 2^21 rows of 9 tiles
+    assert iq(1, 0, 1 << 30, 0)[0] == 0      # nothing to launch
     assert L.pcad_i32_fwd(0, 0, 1, 10, 0, None, None, None, None, 0, None) == 3
     assert L.pcad_i32_fwd(1, 0, 1, 0, 0, None, None, None, None, 0, None) == 0
     assert L.pcad_i32_fwd(2, 0, 1, 10, 0, None, None, None, None, 0, None) == 0
@@ -212,3 +218,11 @@ def test_i32_queries_and_validation(L):
     p16 = (ctypes.addressof(buf) + 15) & ~15
     assert L.pcad_i32_fwd(1, 0, 1, 10, 0, None, p16, p16, None, 0, None) == 6
     assert L.pcad_i32_fwd(2, 2, 1, 10, 5, None, p16, p16, None, 0, None) == 3
+
+
+def test_ws_status_validation(L):
+    """pcad_ws_status rejects a missing or misaligned workspace on the host."""
+    assert L.pcad_ws_status(None, 1, None) == 3
+    buf = (ctypes.c_uint8 * 1024)()
+    p = (ctypes.addressof(buf) + 255) & ~255
+    assert L.pcad_ws_status(p + 16, 1, None) == 4

@@ -42,8 +42,7 @@ def host(t):
 
 
 def ws_error(p):
-    errs = [int(b[:16].view(torch.int32)[2].item()) for b in p._ws.values()]
-    return max(errs) if errs else 0
+    return p.ws_status_all()  # raises if a look-back wait timed out
 
 
 def test_linrec_scan_2e26(pcad):

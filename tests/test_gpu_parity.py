@@ -39,9 +39,10 @@ def host(t):
 
 
 def ws_error():
+    """0 unless a look-back wait timed out on a cached workspace (then
+    pcad_ws_status reports it and the binding raises)"""
     import paper_2310_03568_amd as p
-    errs = [int(b[:16].view(torch.int32)[2].item()) for b in p._ws.values()]
-    return max(errs) if errs else 0
+    return p.ws_status_all()
 
 
 def make_inputs(op, shape, rng, ties=False):
@@ -183,6 +184,34 @@ def test_scan_signed_zero_ties(pcad):
     np.testing.assert_array_equal(np.signbit(yy), [False, True, True, True, True, True])
     xb = host(pcad.scan_vjp("min", dev(x), None, s, dev(np.ones(6, np.float32))))
     np.testing.assert_array_equal(xb, [1, 5, 0, 0, 0, 0])
+
+
+def test_ws_status_reports_and_clears_a_timeout_word(pcad):
+    """The control block's error word names the launch whose look-back wait
+    timed out.  Planting the tag of the launch that just finished (as if one
+    of its waits had run out) must not disturb the next launches, whose tags
+    differ, and pcad_ws_status reports it once and clears it.  No wait is
+    made to time out here: the word is written from the host."""
+    rng = np.random.default_rng(77)
+    x = rng.integers(-8, 8, 50_000).astype(np.float32)
+    X = dev(x)
+    y, _, s = pcad.scan_fwd("add", X)
+    torch.cuda.synchronize()
+    assert pcad.ws_status_all() == 0
+    key = (X.device.index, torch.cuda.current_stream(X.device).cuda_stream)
+    ws = pcad._ws[key]
+    ctl = ws[:16].view(torch.int32)
+    epoch = int(ctl[1].item())
+    assert epoch != 0
+    ctl[2] = epoch  # the tag of the finished launch
+    torch.cuda.synchronize()
+    for _ in range(3):
+        y, _, s = pcad.scan_fwd("add", X)
+        np.testing.assert_array_equal(host(y), np.cumsum(x.astype(np.float64)).astype(np.float32))
+    with pytest.raises(pcad.PcadError, match="timed out"):
+        pcad.ws_status(ws, clear=True)
+    assert pcad.ws_status(ws) == 0
+    assert int(ws[:16].view(torch.int32)[2].item()) == 0
 
 
 def test_scan_accumulate(pcad):
