@@ -232,6 +232,26 @@ def segmented_fwd(offsets, a, b, idx, m: int):
     return dict(y=y, cy=cy, h=h, ch=ch, argk=argk)
 
 
+def segmented_argmin(offsets, idx, y32, m: int):
+    """Per instance s and bin k, the lowest instance-relative index of the
+    minimum of the float32 values ``y32`` over the positions of s whose key
+    is k (the instance length for an empty bin), and that value: the
+    sequential min-by-index (Section 4 with Section 4.2's lifted min) of the
+    given values, one instance at a time.  Returns (argk (S, m) int64,
+    h (S, m) float64, the winner's value with its sign bit)."""
+    off = np.asarray(offsets, dtype=np.int64)
+    S = off.shape[0] - 1
+    y = np.asarray(y32, dtype=np.float32)
+    argk = np.empty((S, m), np.int64)
+    h = np.empty((S, m))
+    for s in range(S):
+        lo, hi = int(off[s]), int(off[s + 1])
+        r = rbi_fwd("min", idx[lo:hi], m, y[lo:hi])
+        argk[s] = r["argk"]
+        h[s] = r["hist"][:, 0]
+    return argk, h
+
+
 def segmented_vjp(offsets, a, b, idx, m: int, ybar, hbar, argk):
     """Adjoint of the chained workload for a given per-bin decision
     ``argk`` (S, m) (instance-relative, >= length means empty).  The

@@ -85,3 +85,62 @@ def assert_gate(g, r, c, rtol: float, max_range_exceeded=0, what: str = ""):
         assert res["n_range_exceeded"] <= max_range_exceeded, (
             f"{what}: {res['n_range_exceeded']} range-exceeded elements")
     return res
+
+
+def assert_discriminates(g, r, c, rtol: float, start: int = 600, width: int = 1, what: str = ""):
+    """Self-check of a parity test on the CPU: the gate that accepted ``g``
+    must reject a copy of ``g`` whose elements from ``start`` on (``width``
+    floats per element) are zero, i.e. an output that stopped being computed
+    after a few hundred elements.  A gate that lets such a copy through
+    (outputs that under- or overflow, or a companion far above |r|) would
+    make the comparison vacuous."""
+    gz = np.array(g, dtype=np.float64, copy=True).reshape(-1)
+    if gz.size <= start * width:
+        return
+    gz[start * width:] = 0.0
+    res = gate(gz, r, c, rtol)
+    assert not res["ok"], f"{what}: a copy zeroed past element {start} passes the gate"
+    assert res["n_fail"] >= (gz.size - start * width) // 100, (
+        f"{what}: a copy zeroed past element {start} fails only {res['n_fail']} elements")
+
+
+def segmented_decisions(offsets, idx, m: int, y32, h, argk, f=None) -> dict:
+    """Checks of the chained workload's min-by-index decisions, which are
+    taken on the implementation's own float32 y (Section 4.2, Min/Max):
+
+    * argk_ok: every bin's argk is the lowest instance-relative index of the
+      minimum of y32 over the instance's positions with that key (the
+      oracle's min-by-index of y32), the instance length for an empty bin;
+    * h_ok: h is y32 at argk bit for bit (+inf for an empty bin), except that
+      a -0.0 winner may read +0.0;
+    * with ``f`` (the oracle's segmented_fwd on the float64 recurrence):
+      n_diff_oracle counts bins where the float64 decision differs, and
+      diff_ok says every such pair of candidates ties within 1e-4 of their
+      companions.
+    """
+    import oracle
+    off = np.asarray(offsets, dtype=np.int64)
+    S = off.shape[0] - 1
+    lens = np.diff(off)
+    y32 = np.asarray(y32, dtype=np.float32)
+    h = np.asarray(h, dtype=np.float32).reshape(S, m)
+    argk = np.asarray(argk).reshape(S, m)
+    ak_y, h_y = oracle.segmented_argmin(off, idx, y32, m)
+    out = dict(argk_ok=bool(np.array_equal(argk, ak_y)),
+               argk_bad_bins=int(np.count_nonzero(argk != ak_y)))
+    want = h_y.astype(np.float32)
+    neg0 = (want == 0) & np.signbit(want)
+    out["h_ok"] = bool(np.array_equal(h.view(np.uint32)[~neg0], want.view(np.uint32)[~neg0])
+                       and np.all(h[neg0] == 0)
+                       and np.array_equal(argk == lens[:, None], np.isinf(want)))
+    if f is not None:
+        diff = np.argwhere(argk != f["argk"])
+        ok = True
+        for s, k in diff:
+            lo = int(off[s])
+            g, r = int(argk[s, k]), int(f["argk"][s, k])
+            ok = ok and g < lens[s] and r < lens[s] and int(idx[lo + g]) == k and (
+                abs(f["y"][lo + g] - f["y"][lo + r]) <= 1e-4 * (f["cy"][lo + g] + f["cy"][lo + r]))
+        out["n_diff_oracle"] = int(len(diff))
+        out["diff_ok"] = bool(ok)
+    return out

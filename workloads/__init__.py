@@ -20,6 +20,15 @@ Workload names and default sizes:
 * ``rbi``        -- n=2^26 values ~ N(0,1), uniform or Zipf(1.1) keys over m bins.
 * ``segmented``  -- 4096 instances with lognormal lengths (median 4096).
 * ``autograd``   -- 64 sequences of length 2^16 with a 65536-bin histogram.
+
+Parity ensembles (inputs on which every output stays inside the float32
+range, so a comparison with the oracle constrains every element):
+
+* ``mul_finite``     -- multipliers +-(1 + U[-1e-3, 1e-3]), optional exact
+                        zeros past a given position.
+* ``mat2(ensemble="o2")`` -- random orthogonal 2x2 factors.
+* ``segmented_ties`` -- the segmented workload with a = 1 and small integer
+                        offsets, so that equal minima are common.
 """
 from __future__ import annotations
 
@@ -140,6 +149,25 @@ def mat2(n: int = 1 << 24, seed: int = BASE_SEED + 2, ensemble: str = "gauss"):
     return dict(M=M, Pbar=f32(r[1].standard_normal((n, 4))))
 
 
+def mul_finite(shape, seed: int = BASE_SEED + 7, zeros_after: int = -1, n_zeros: int = 0):
+    """Multipliers x = sign * (1 + u) with sign = +-1 equally likely and
+    u ~ U[-1e-3, 1e-3], so prefix products stay finite and non-zero over
+    2^24 and more elements (log |product| drifts by about -u^2/2 per factor
+    with a standard deviation of 5.8e-4 per factor).  With ``n_zeros`` > 0,
+    that many exact zeros at distinct positions >= ``zeros_after`` along the
+    last axis.  Output adjoint y_bar ~ N(0,1) of the same shape."""
+    r = _streams(seed, 4)
+    shape = tuple(shape) if isinstance(shape, (tuple, list)) else (int(shape),)
+    x = r[0].choice([-1.0, 1.0], shape) * (1.0 + r[1].uniform(-1e-3, 1e-3, shape))
+    if n_zeros > 0:
+        n = shape[-1]
+        lo = max(int(zeros_after), 0)
+        flat = x.reshape(-1, n)
+        for row in flat:
+            row[lo + exact_zero_positions(r[2], n - lo, n_zeros)] = 0.0
+    return dict(x=f32(x), ybar=f32(r[3].standard_normal(shape)))
+
+
 # --------------------------------------------------------------------------
 # workload: large reduce-by-index
 # --------------------------------------------------------------------------
@@ -201,6 +229,26 @@ def segmented(S: int = 4096, m: int = 512, seed: int = BASE_SEED + 4,
         idx=r[3].integers(0, m, N, dtype=np.int64).astype(np.int32),
         ybar=f32(r[4].standard_normal(N)),
         hbar=f32(r[5].standard_normal(S * m)),
+    )
+
+
+def segmented_ties(S: int = 64, m: int = 16, seed: int = BASE_SEED + 8, median: int = 700,
+                   cap: int = 30_000):
+    """Like ``segmented`` but with a = 1 and small integer offsets
+    b ~ U{-3..3}: every y is an exact float32 integer (|y| <= 3 * cap), so
+    equal minima occur in most bins and the lowest-index rule decides."""
+    r = _streams(seed, 5)
+    L = segment_lengths(r[0], S, median, cap)
+    off = np.zeros(S + 1, dtype=np.int64)
+    np.cumsum(L, out=off[1:])
+    N = int(off[-1])
+    return dict(
+        offsets=off, lengths=L, m=m, n_total=N,
+        a=np.ones(N, np.float32),
+        b=f32(r[1].integers(-3, 4, N)),
+        idx=r[2].integers(0, m, N, dtype=np.int64).astype(np.int32),
+        ybar=f32(r[3].standard_normal(N)),
+        hbar=f32(r[4].standard_normal(S * m)),
     )
 
 
