@@ -10,7 +10,7 @@
  *   scan (.) e xs, inclusive                           (Section 5)
  *   reduce_by_index hist (.) e ks vs                   (Section 4)
  * Operators are +, *, min, max and two generic associative operators:
- * linear-function composition and the 2x2 matrix product (Section 5.1,
+ * linear-function composition and the 2x2 matrix product (Section 6.1,
  * operator figure), plus the evaluation's sumOfProd (an invertible lifted
  * operator, Section 3.3) and saturated addition (non-invertible).  Further
  * entry points cover scans and reduces of 3x3 and 5x5 matrix products

@@ -10,9 +10,9 @@ arrays through ctypes and composes the C calls for the chained segmented
 workload.  Every function widens its float32 inputs exactly to float64.
 
 Operators (names used throughout): ``add``, ``mul``, ``min``, ``max``,
-``linrec`` (linear-function composition, Section 5.1 operator figure, with
+``linrec`` (linear-function composition, Section 6.1 operator figure, with
 multiplier a and offset b, y_i = a_i*y_{i-1} + b_i), ``mat2`` (row-major
-2x2 matrix product, Section 5.1 operator figure) and ``sumprod`` (the
+2x2 matrix product, Section 6.1 operator figure) and ``sumprod`` (the
 invertible operator sumOfProd of Section 3.3 on lifted pairs (p, s); the
 ``sumprod_*`` functions below take the scalar inputs, lift each a to (0, a)
 and return the p component, as that section composes them) and ``satadd``

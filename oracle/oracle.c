@@ -12,14 +12,14 @@
  * Element types (d = number of float components per element):
  *   ADD, MUL, MIN, MAX : d = 1, a scalar.
  *   LINREC             : d = 2, (multiplier, offset).  The operator is
- *                        linear-function composition (Section 5.1, operator
+ *                        linear-function composition (Section 6.1, operator
  *                        figure): (A1,B1) (.) (a2,b2) = (A1*a2, a2*B1 + b2),
  *                        neutral (1,0).  A scan of (a_i,b_i) therefore yields
  *                        (A_i, y_i) with y_i = a_i*y_{i-1} + b_i, y_{-1}=0, and
  *                        A_i = a_0*...*a_i.
  *   MAT2               : d = 4, a row-major 2x2 matrix (a,b,c,d) =
  *                        [[a,b],[c,d]]; the operator is the matrix product
- *                        P (.) M = P x M (Section 5.1, operator figure),
+ *                        P (.) M = P x M (Section 6.1, operator figure),
  *                        neutral I.
  *   SATADD             : d = 1, saturated addition (the evaluation's operator
  *                        figure): acc (.) x = C if acc + x > C, else acc + x,

@@ -39,7 +39,7 @@ D = oracle.DIM
 
 
 # ---------------------------------------------------------------------------
-# independent operator definitions (Section 5.1 operator figure) and duals
+# independent operator definitions (Section 6.1 operator figure) and duals
 # ---------------------------------------------------------------------------
 class Dual:
     __slots__ = ("v", "t")
