@@ -24,6 +24,9 @@ Workloads:
 `value` is backward elements/s: n / (mean duration of the adjoint kernel,
 HIP events on the stream the kernel runs on).  `roofline` prices that kernel
 against the 8 TB/s HBM peak with the algorithmic bytes of the adjoint.
+`roofline.copy_GBs` is a plain device copy's rate measured in the same run
+and `frac_of_copy` the adjoint's rate over it.  Times are means over the
+timed steps (30 by default), with 95% confidence half-widths and medians.
 `cpu_baseline` is the CPU FP64 oracle timed on the host (1 thread) on the
 same inputs; its outputs also gate the GPU results (`parity`).
 """
@@ -224,8 +227,8 @@ def bench_segmented(args, pcad, torch, np):
 
     return dict(n=N, fwd=fwd, bwd=bwd, plan=plan, inputs=w,
                 # forward reads a, b, idx and writes y (+ h, argk per bin);
-                # adjoint reads a, b, y_bar, idx and writes a_bar, b_bar (+ argk,
-                # h_bar per bin); forward prefixes are recomputed, not stored
+                # adjoint reads a, y, y_bar, idx and writes a_bar, b_bar (+ argk,
+                # h_bar per bin): the prefixes y_{i-1} come from the forward's y
                 bytes_fwd=16 * N + 8 * S * m, bytes_bwd=24 * N + 8 * S * m,
                 kernel="k_seg_bwd", out=lambda: (plan.abar[:N], plan.bbar[:N]),
                 cfg={"workload": f"segmented: {S} instances, lognormal lengths (median 4096, cap 2^20), "
@@ -641,10 +644,53 @@ def autograd_parity(b, torch, np):
     return cpu, dict(ok=ok and rx == 0, max_rel=worst, range_exceeded=rx)
 
 
+def _tune_key(tune, args):
+    """The tuning-cache bucket of the workload (None: apply every entry)."""
+    n = args.n or None
+    if args.workload == "segmented":
+        return tune.key("batched", "linrec+min", n or args.segments * 16384, 512, "lognormal")
+    if args.workload == "linrec":
+        return tune.key("scan", "linrec", n or (1 << 26))
+    if args.workload == "mat2":
+        return tune.key("scan", "mat2", n or (1 << 24))
+    if args.workload == "rbi":
+        return tune.key("rbi", args.op, n or (1 << 26), args.bins, args.dist)
+    return None
+
+
+def _knobs_used(pcad, args):
+    """The knobs that the timed workload reads, as set for the run."""
+    k = pcad.knobs()
+    prefix = {"segmented": ("seg.",), "linrec": ("scan.",), "mat2": ("scan.",),
+              "rbi": ("rbi.",), "vec": ("scan.", "rbi."), "autograd": ("scan.", "rbi."),
+              "matd": ()}[args.workload]
+    return {n: v for n, v in sorted(k.items()) if n.startswith(prefix)}
+
+
+def copy_bandwidth(torch, np, reps=9):
+    """HBM rate of a plain device-to-device copy (torch's copy kernel) of
+    512 MiB into 512 MiB, in GB/s of bytes read + written, median of `reps`
+    timed launches: the practical streaming ceiling beside the 8 TB/s peak."""
+    src = torch.empty(1 << 27, dtype=torch.float32, device="cuda:0").fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1) * 1e-3)
+    del src, dst
+    return 2 * (1 << 27) * 4 / float(np.median(ts)) / 1e9
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="segmented",
                     choices=["segmented", "linrec", "mat2", "rbi", "vec", "autograd", "matd"])
@@ -661,6 +707,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the single-graph and per-instance comparison runs (profiling)")
+    ap.add_argument("--knob", action="append", default=[], metavar="NAME=VALUE",
+                    help="set a tuning knob before the workload is built (repeatable); "
+                         "applied after the tuning cache")
+    ap.add_argument("--tune-cache", default=None,
+                    help="tuning cache to apply (default: the tuner's default path, if present)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after the timed region, run a plain 256 MiB device copy 3 times "
                          "(reference for scaling the HBM byte counters)")
@@ -675,6 +726,11 @@ def main():
     import paper_2310_03568_amd as pcad
 
     pcad.lib()
+    from paper_2310_03568_amd import tune
+    tuned = tune.load(args.tune_cache or tune.DEFAULT_PATH, key=_tune_key(tune, args))
+    for kv in args.knob:
+        name, _, val = kv.partition("=")
+        pcad.set_knob(name, int(val))
     b = {"linrec": bench_linrec, "mat2": bench_mat2, "segmented": bench_segmented,
          "rbi": bench_rbi, "vec": bench_vec, "autograd": bench_autograd,
          "matd": bench_matd}[args.workload](args, pcad, torch, np)
@@ -705,6 +761,7 @@ def main():
     tb = float(t_bwd.mean())
     tf = float(t_fwd.mean())
     achieved = b["bytes_bwd"] / tb / 1e9
+    copy_gbs = copy_bandwidth(torch, np)
 
     if args.calib_copy:
         src = torch.empty(1 << 26, dtype=torch.float32, device="cuda:0").fill_(1.0)
@@ -758,16 +815,20 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": b["cfg"],
+        "config": {**b["cfg"], "tuning": {"cache_applied": tuned, "knobs": _knobs_used(pcad, args)}},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": _traffic(b["kernel"], wl_key)},
+                     "traffic": _traffic(b["kernel"], wl_key),
+                     "copy_GBs": copy_gbs, "frac_of_copy": achieved / copy_gbs},
         "cpu_baseline": cpu,
         "bwd_ms": tb * 1e3,
         "fwd_ms": tf * 1e3,
         "bwd_over_fwd": tb / tf,
         "fwd_GBs": b["bytes_fwd"] / tf / 1e9,
         "bwd_ci95_ms": 1.96 * float(t_bwd.std(ddof=1)) / np.sqrt(len(t_bwd)) * 1e3 if len(t_bwd) > 1 else 0.0,
+        "bwd_median_ms": float(np.median(t_bwd)) * 1e3,
+        "fwd_median_ms": float(np.median(t_fwd)) * 1e3,
+        "fwd_ci95_ms": 1.96 * float(t_fwd.std(ddof=1)) / np.sqrt(len(t_fwd)) * 1e3 if len(t_fwd) > 1 else 0.0,
         "parity": par,
         **extras,
     }

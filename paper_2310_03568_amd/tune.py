@@ -18,10 +18,22 @@ speed.  Each group is searched on the shapes of the workloads it serves:
 * ``rbi.sort_min_bins``: the smallest tested bin count beyond the LDS
   capacity from which sorting by bin (then a segmented scan) beats the LDS
   hash table under both key distributions; 2^26 (never, below that) if it
-  wins at none.
+  wins at none;
+* ``seg.tile`` in {4096, 8192} and ``seg.fwd.threads`` / ``seg.vjp.threads``
+  in {256, 512, 1024}: the batched plan's item size and block sizes, timed
+  on the segmented workload (4096 instances of lognormal length, median
+  4096; 1024 instances with ``quick``): per item size the fastest forward
+  and adjoint block sizes, then the item size with the smaller sum.
 
-The cache records the device it was measured on; ``load`` applies it only on
-the same device name and architecture, otherwise the built-in defaults stay.
+Cache entries are keyed by (combinator, op, n-bucket, m-bucket, skew): the
+buckets are round(log2 n) and round(log2 m) of the shape the entry was
+searched on and the key distribution ("uniform", "zipf", "uniform+zipf" for
+thresholds searched under both, "lognormal" for the batched instance
+lengths).  The cache records the device it was measured on; ``load``
+applies it only on the same device name and architecture, otherwise the
+built-in defaults stay.  ``load(path, key=...)`` applies the entry that
+matches the key's combinator and op (and skew, when both give one) with the
+nearest buckets; without a key every entry is applied.
 """
 from __future__ import annotations
 
@@ -71,7 +83,19 @@ def _scan_inputs(op: str, n: int):
     return x, None, torch.randn(n, device=dev, generator=g)
 
 
-def tune_scan(pcad, timings: dict, quick: bool) -> dict:
+def bucket(x: Optional[int]) -> Optional[int]:
+    """round(log2 x): the n- and m-buckets of cache keys (None stays None)"""
+    import math
+    return None if not x else int(round(math.log2(x)))
+
+
+def key(combinator: str, op: str, n: Optional[int] = None, m: Optional[int] = None,
+        skew: Optional[str] = None) -> dict:
+    return {"combinator": combinator, "op": op, "n_bucket": bucket(n), "m_bucket": bucket(m),
+            "skew": skew}
+
+
+def tune_scan(pcad, timings: dict, quick: bool, entries: list) -> dict:
     best = {}
     ops = ("add", "linrec", "mat2") if quick else SCAN_OPS
     for op in ops:
@@ -92,6 +116,9 @@ def tune_scan(pcad, timings: dict, quick: bool) -> dict:
             pcad.reset_knobs()
             best[name] = min(res, key=res.get)
             timings[name] = {str(k): v for k, v in res.items()}
+        entries.append({"key": key("scan", op, n),
+                        "knobs": {f"scan.{d}.threads.{op}": best[f"scan.{d}.threads.{op}"]
+                                  for d in ("fwd", "vjp")}})
     return best
 
 
@@ -110,7 +137,7 @@ def _rbi_inputs(n: int, m: int, zipf: bool):
     return torch.from_numpy(idx).cuda(), torch.from_numpy(v).cuda()
 
 
-def tune_rbi(pcad, timings: dict, quick: bool) -> dict:
+def tune_rbi(pcad, timings: dict, quick: bool, entries: list) -> dict:
     best = {}
     n = (1 << 22) if quick else (1 << 24)
     for kind, ops, knob in (("f32", ("add",), "rbi.lds_max_bins_f32"),
@@ -160,6 +187,45 @@ def tune_rbi(pcad, timings: dict, quick: bool) -> dict:
             threshold = m
             break
     best["rbi.sort_min_bins"] = threshold
+    # thresholds over m were searched under both key distributions
+    entries.append({"key": key("rbi", "add", n, None, "uniform+zipf"),
+                    "knobs": {k: best[k] for k in ("rbi.lds_max_bins_f32", "rbi.sort_min_bins")}})
+    entries.append({"key": key("rbi", "min", n, None, "uniform+zipf"),
+                    "knobs": {"rbi.lds_max_bins_u64": best["rbi.lds_max_bins_u64"]}})
+    entries.append({"key": key("rbi", "add", n, 256, "uniform"),
+                    "knobs": {"rbi.elems_per_block": best["rbi.elems_per_block"]}})
+    return best
+
+
+def tune_segmented(pcad, timings: dict, quick: bool, entries: list) -> dict:
+    """Item size and block sizes of the batched plan on the segmented
+    workload: per item size the fastest forward and adjoint block sizes, then
+    the item size whose forward + adjoint is smaller."""
+    import numpy as np
+    from workloads import segmented
+    w = segmented(S=1024 if quick else 4096)
+    per_tile = {}
+    for tile in (4096, 8192):
+        tf, tb = {}, {}
+        for th in THREADS:
+            pcad.reset_knobs()
+            pcad.set_knob("seg.tile", tile)
+            pcad.set_knob("seg.fwd.threads", th)
+            pcad.set_knob("seg.vjp.threads", th)
+            plan = pcad.BatchedPlan(w["offsets"], w["m"])
+            plan.load(a=w["a"], b=w["b"], idx=w["idx"], ybar=w["ybar"], hbar=w["hbar"])
+            tf[th] = _time(lambda: plan.run(pcad.PHASE_FWD), 5 if quick else 10)
+            tb[th] = _time(lambda: plan.run(pcad.PHASE_BWD), 5 if quick else 10)
+            plan.close()
+            timings[f"seg@tile={tile},threads={th}"] = {"fwd": tf[th], "vjp": tb[th]}
+        f, b = min(tf, key=tf.get), min(tb, key=tb.get)
+        per_tile[tile] = (tf[f] + tb[b], f, b)
+    pcad.reset_knobs()
+    tile = min(per_tile, key=lambda t: per_tile[t][0])
+    best = {"seg.tile": tile, "seg.fwd.threads": per_tile[tile][1],
+            "seg.vjp.threads": per_tile[tile][2]}
+    entries.append({"key": key("batched", "linrec+min", int(w["n_total"]), w["m"], "lognormal"),
+                    "knobs": dict(best)})
     return best
 
 
@@ -171,11 +237,13 @@ def tune(out: Optional[str] = DEFAULT_PATH, quick: bool = False) -> dict:
     pcad.lib()
     t0 = time.time()
     timings: dict = {}
+    entries: list = []
     best = {}
-    best.update(tune_scan(pcad, timings, quick))
-    best.update(tune_rbi(pcad, timings, quick))
-    cache = {"version": 1, "device": _device_id(), "knobs": best, "timings_s": timings,
-             "quick": quick, "seconds": time.time() - t0}
+    best.update(tune_scan(pcad, timings, quick, entries))
+    best.update(tune_rbi(pcad, timings, quick, entries))
+    best.update(tune_segmented(pcad, timings, quick, entries))
+    cache = {"version": 2, "device": _device_id(), "entries": entries, "knobs": best,
+             "timings_s": timings, "quick": quick, "seconds": time.time() - t0}
     if out:
         os.makedirs(os.path.dirname(os.path.abspath(out)), exist_ok=True)
         with open(out, "w") as f:
@@ -183,24 +251,53 @@ def tune(out: Optional[str] = DEFAULT_PATH, quick: bool = False) -> dict:
     return cache
 
 
-def load(path: str = DEFAULT_PATH, device: Optional[dict] = None) -> bool:
+def _match(entries: list, want: dict) -> Optional[dict]:
+    """The entry for combinator/op (and skew, when both name one) whose
+    buckets are nearest to the wanted ones; None if no entry qualifies."""
+    def dist(a, b):
+        return 0 if a is None or b is None else abs(a - b)
+    best, best_d = None, None
+    for e in entries:
+        k = e.get("key", {})
+        if k.get("combinator") != want.get("combinator") or k.get("op") != want.get("op"):
+            continue
+        ks, ws = k.get("skew"), want.get("skew")
+        if ks is not None and ws is not None and ws not in ks.split("+"):
+            continue
+        d = dist(k.get("n_bucket"), want.get("n_bucket")) + dist(k.get("m_bucket"), want.get("m_bucket"))
+        if best_d is None or d < best_d:
+            best, best_d = e, d
+    return best
+
+
+def load(path: str = DEFAULT_PATH, device: Optional[dict] = None,
+         key: Optional[dict] = None) -> bool:
     """Applies a tuning cache; returns False (built-in defaults kept) when it
-    is missing, unreadable, or was measured on another device."""
+    is missing, unreadable, was measured on another device, or (with
+    ``key``) holds no entry for that combinator and op."""
     import paper_2310_03568_amd as pcad
     try:
         with open(path) as f:
             cache = json.load(f)
     except (OSError, ValueError):
         return False
-    if cache.get("version") != 1 or not isinstance(cache.get("knobs"), dict):
+    if cache.get("version") != 2 or not isinstance(cache.get("entries"), list):
         return False
     if device is None:
         device = _device_id()
     if cache.get("device") != device:
         return False
+    if key is None:
+        chosen = cache["entries"]
+    else:
+        e = _match(cache["entries"], key)
+        if e is None:
+            return False
+        chosen = [e]
     pcad.reset_knobs()
-    for name, value in cache["knobs"].items():
-        pcad.set_knob(name, int(value))
+    for e in chosen:
+        for name, value in e.get("knobs", {}).items():
+            pcad.set_knob(name, int(value))
     return True
 
 
