@@ -165,8 +165,8 @@ def test_scan_function(ag, op, mode):
         x0 = o2_matrices(rng, 2 * n).reshape(2, n, 4)
         x1 = None
     elif op == "mul":
-        # +-(1 + U[-1e-3, 1e-3]): finite, non-zero products over all of n
-        x0 = (rng.choice([-1.0, 1.0], (2, n)) * (1 + rng.uniform(-1e-3, 1e-3, (2, n)))).astype(np.float32)
+        # +-exp(U[-0.01, 0.01]): finite, non-zero products over all of n
+        x0 = (rng.choice([-1.0, 1.0], (2, n)) * np.exp(rng.uniform(-0.01, 0.01, (2, n)))).astype(np.float32)
         x1 = None
     else:
         x0 = rng.uniform(0.5, 2.0, (2, n)).astype(np.float32)
@@ -212,7 +212,7 @@ def test_reduce_function(ag, op):
         x0 = o2_matrices(rng, 3 * n).reshape(3, n, 4)
     elif op == "mul":
         # finite non-zero products; one row with a single exact zero
-        x0 = (rng.choice([-1.0, 1.0], (3, n)) * (1 + rng.uniform(-1e-3, 1e-3, (3, n)))).astype(np.float32)
+        x0 = (rng.choice([-1.0, 1.0], (3, n)) * np.exp(rng.uniform(-0.01, 0.01, (3, n)))).astype(np.float32)
         x0[1, 17] = 0.0
     else:
         x0 = rng.uniform(0.5, 2.0, (3, n)).astype(np.float32)

@@ -16,7 +16,9 @@ every output (the C oracle finishes these sizes in seconds):
     bit-exact), and the ordered 2x2 product per bin (orthogonal factors
     where N(0, 1) ones would overflow float32);
   * the batched segmented workload, 4096 instances (about 2^26 elements),
-    with every bin's arg-minimum checked bit for bit against the GPU's y.
+    with every bin's arg-minimum checked bit for bit against the GPU's y;
+  * int32 reduce and scan of + * min max at n = 2^24 + 13 (more tiles than
+    one block of the tile-carry scan covers), bit-exact.
 
 Where a check could pass vacuously, the test also shows on the CPU that a
 copy of the GPU output zeroed past element 600 fails the same gate.
@@ -28,7 +30,7 @@ import pytest
 import torch
 
 import oracle
-from oracle.gate import RTOL, assert_discriminates, assert_gate, segmented_decisions
+from oracle.gate import RTOL, assert_discriminates, assert_gate, chain_rtol, segmented_decisions
 
 pytestmark = pytest.mark.gpu
 
@@ -89,13 +91,17 @@ def test_mat2_scan_2e24_orthogonal(pcad):
     Mb = pcad.scan_vjp("mat2", M, None, saved, dev(w["Pbar"]))
     Mc = pcad.scan_vjp_checkpoint("mat2", M, None, P, None, dev(w["Pbar"]))
     P, Mb, Mc = host(P), host(Mb), host(Mc)
+    # products of up to 2^24 factors: the tolerance grows with the chain
+    # length as the rounding error of any evaluation does
+    rf = chain_rtol(n, RTOL["mat2"], width=4)
+    rb = chain_rtol(n, RTOL["mat2"], width=4, adjoint=True)
     rs, c = oracle.scan_fwd("mat2", w["M"])
-    assert_gate(P, rs, c, RTOL["mat2"], max_range_exceeded=0, what="O(2) P")
-    assert_discriminates(P, rs, c, RTOL["mat2"], width=4, what="O(2) P")
+    assert_gate(P, rs, c, rf, max_range_exceeded=0, what="O(2) P")
+    assert_discriminates(P, rs, c, rf, width=4, what="O(2) P")
     xb, cx = oracle.scan_vjp("mat2", w["Pbar"], w["M"])
-    assert_gate(Mb, xb, cx, RTOL["mat2"], max_range_exceeded=0, what="O(2) M_bar")
-    assert_gate(Mc, xb, cx, RTOL["mat2"], max_range_exceeded=0, what="O(2) M_bar (checkpoint)")
-    assert_discriminates(Mb, xb, cx, RTOL["mat2"], width=4, what="O(2) M_bar")
+    assert_gate(Mb, xb, cx, rb, max_range_exceeded=0, what="O(2) M_bar")
+    assert_gate(Mc, xb, cx, rb, max_range_exceeded=0, what="O(2) M_bar (checkpoint)")
+    assert_discriminates(Mb, xb, cx, rb, width=4, what="O(2) M_bar")
     assert ws_error(pcad) == 0
 
 
@@ -105,9 +111,17 @@ def _scalar_scan_inputs(op, n):
         w = mul_finite(n, seed=BASE_SEED + 70)
         return w["x"], w["ybar"]
     r = _streams(BASE_SEED + 71 + ["add", "min", "max"].index(op), 2)
-    x = r[0].uniform(0.5, 2.0, n)
     if op in ("min", "max"):
-        x = round_to_grid(x, -6)  # ties
+        # a trend from 2 down to 0.5 (max: up) under U[0, 2e-4] noise on a
+        # 2^-14 grid: the running extremum is renewed about every 700
+        # elements all the way (about 24,500 positions with a non-zero
+        # adjoint) and equals later elements about 3 million times, where
+        # the earlier index must keep it
+        t = np.arange(n) / n
+        noise = r[0].uniform(0.0, 2e-4, n)
+        x = (2.0 - 1.5 * t + noise) if op == "min" else (0.5 + 1.5 * t - noise)
+        return f32(round_to_grid(x, -14)), f32(r[1].standard_normal(n))
+    x = r[0].uniform(0.5, 2.0, n)
     return f32(x), f32(r[1].standard_normal(n))
 
 
@@ -127,22 +141,24 @@ def test_scalar_scan_2e24(pcad, op):
     y, g, gc = host(y), host(g), host(gc)
     rs, c = oracle.scan_fwd(op, x)
     xb, cx = oracle.scan_vjp(op, yb, x)
-    rt = RTOL[op]
+    rt = rtb = RTOL[op]
+    if op == "mul":  # products of up to 2^24 factors
+        rt, rtb = chain_rtol(n, RTOL[op]), chain_rtol(n, RTOL[op], adjoint=True)
     if op in ("min", "max"):
         np.testing.assert_array_equal(y, rs[:, 0].astype(np.float32))
         assert_gate(g, xb[:, 0], cx[:, 0], rt, what=f"scan {op} x_bar")
         assert_gate(gc, xb[:, 0], cx[:, 0], rt, what=f"scan {op} x_bar (checkpoint)")
         # the adjoint sums y_bar over runs of equal prefix minima: non-zero far
         # beyond the first elements
-        assert np.count_nonzero(xb[600:, 0]) > 0
-        assert_discriminates(g, xb[:, 0], cx[:, 0], rt, what=f"scan {op} x_bar")
+        assert np.count_nonzero(xb[600:, 0]) > 10_000
+        assert_discriminates(g, xb[:, 0], cx[:, 0], rt, what=f"scan {op} x_bar", sparse=True)
     else:
         assert np.count_nonzero(rs[:, 0]) == n
         assert_gate(y, rs[:, 0], c[:, 0], rt, what=f"scan {op} y")
         assert_discriminates(y, rs[:, 0], c[:, 0], rt, what=f"scan {op} y")
-        assert_gate(g, xb[:, 0], cx[:, 0], rt, what=f"scan {op} x_bar")
-        assert_gate(gc, xb[:, 0], cx[:, 0], rt, what=f"scan {op} x_bar (checkpoint)")
-        assert_discriminates(g, xb[:, 0], cx[:, 0], rt, what=f"scan {op} x_bar")
+        assert_gate(g, xb[:, 0], cx[:, 0], rtb, what=f"scan {op} x_bar")
+        assert_gate(gc, xb[:, 0], cx[:, 0], rtb, what=f"scan {op} x_bar (checkpoint)")
+        assert_discriminates(g, xb[:, 0], cx[:, 0], rtb, what=f"scan {op} x_bar")
     assert ws_error(pcad) == 0
 
 
@@ -250,3 +266,22 @@ def test_segmented_4096_instances(pcad):
     assert_discriminates(b_bar, bb, cbb, 1e-4, what="segmented b_bar")
     assert plan.ws_error() == 0
     plan.close()
+
+
+@pytest.mark.parametrize("op", ["add", "mul", "min", "max"])
+def test_i32_scan_2e24(pcad, op):
+    """int32 reduce and scan, wrapping mod 2^32, bit for bit against the
+    oracle at a size whose tile carries take several rounds."""
+    rng = np.random.default_rng(231003568 + len(op))
+    n = (1 << 24) + 13
+    if op == "mul":
+        x = rng.choice(np.array([-3, -1, 1, 3, 5, 7], np.int64), size=n).astype(np.int32)
+    else:
+        x = rng.integers(-2**31, 2**31, size=n, dtype=np.int64).astype(np.int32)
+    print(f"i32 {op} n={n}", flush=True)
+    X = dev(x)
+    y = host(pcad.i32_fwd(pcad.REDUCE, op, X))
+    s = host(pcad.i32_fwd(pcad.SCAN, op, X))
+    assert int(y) == oracle.i32_reduce(op, x)
+    np.testing.assert_array_equal(s, oracle.i32_scan(op, x))
+    assert ws_error(pcad) == 0

@@ -13,7 +13,7 @@ import pytest
 import torch
 
 import oracle
-from oracle.gate import RTOL, assert_discriminates, assert_gate
+from oracle.gate import RTOL, assert_discriminates, assert_gate, chain_rtol
 
 pytestmark = pytest.mark.gpu
 
@@ -166,7 +166,7 @@ MUL_TILE = 8192  # elements per tile of the scalar scans
 
 def check_scan_mul_finite(pcad, batch, n, seed, n_zeros=0, ckpt=False):
     """* scans whose prefix products stay finite and non-zero across many
-    tiles (multipliers +-(1 + U[-1e-3, 1e-3])), so that the cross-tile
+    tiles (multipliers +-exp(U[-0.01, 0.01])), so that the cross-tile
     carries of the forward products and of the adjoint maps are compared
     on non-zero values; with ``n_zeros``, exact zeros only past the first
     three tiles (the zero-prefix guard of the adjoint and the three zero
@@ -182,16 +182,18 @@ def check_scan_mul_finite(pcad, batch, n, seed, n_zeros=0, ckpt=False):
     else:
         g = pcad.scan_vjp("mul", X, None, saved, dev(yb))
     y, g = host(y).reshape(batch, n), host(g).reshape(batch, n)
+    # products of up to n factors: the tolerance grows with the chain length
+    rf, rb = chain_rtol(n, RTOL["mul"]), chain_rtol(n, RTOL["mul"], adjoint=True)
     for r in range(batch):
         xr, ybr = x.reshape(batch, n)[r], yb.reshape(batch, n)[r]
         rs, c = oracle.scan_fwd("mul", xr)
         nz = int(np.count_nonzero(rs[:, 0]))
         assert nz >= min(n, 3 * MUL_TILE), nz  # the ensemble does what it claims
-        assert_gate(y[r], rs[:, 0], c[:, 0], RTOL["mul"], what=f"scan mul row {r}")
-        assert_discriminates(y[r], rs[:, 0], c[:, 0], RTOL["mul"], what=f"scan mul row {r}")
+        assert_gate(y[r], rs[:, 0], c[:, 0], rf, what=f"scan mul row {r}")
+        assert_discriminates(y[r], rs[:, 0], c[:, 0], rf, what=f"scan mul row {r}")
         xb, cx = oracle.scan_vjp("mul", ybr, xr)
-        assert_gate(g[r], xb[:, 0], cx[:, 0], RTOL["mul"], what=f"scan_vjp mul row {r}")
-        assert_discriminates(g[r], xb[:, 0], cx[:, 0], RTOL["mul"], what=f"scan_vjp mul row {r}")
+        assert_gate(g[r], xb[:, 0], cx[:, 0], rb, what=f"scan_vjp mul row {r}")
+        assert_discriminates(g[r], xb[:, 0], cx[:, 0], rb, what=f"scan_vjp mul row {r}")
     assert ws_error() == 0
 
 
@@ -361,7 +363,10 @@ def check_reduce(pcad, op, batch, n, seed, ties=False):
         if op == "linrec":
             assert_gate(g[0][sl], xb[:, 0], cx[:, 0], rt, what="reduce_vjp linrec a")
             assert_gate(g[1][sl], xb[:, 1], cx[:, 1], rt, what="reduce_vjp linrec b")
-            assert_discriminates(g[1][sl], xb[:, 1], cx[:, 1], rt, what="reduce_vjp linrec b")
+            # b_bar_i = y_bar times the later multipliers (a < 1): negligible
+            # beyond a few thousand elements from the end
+            assert_discriminates(g[1][sl], xb[:, 1], cx[:, 1], rt, what="reduce_vjp linrec b",
+                                 sparse=True)
         elif op == "mat2":
             mx2 = 0 if mat2_o2(n) else None
             assert_gate(g[sl], xb, cx, rt, max_range_exceeded=mx2, what="reduce_vjp mat2")

@@ -24,10 +24,10 @@ Workload names and default sizes:
 Parity ensembles (inputs on which every output stays inside the float32
 range, so a comparison with the oracle constrains every element):
 
-* ``mul_finite``     -- multipliers +-(1 + U[-1e-3, 1e-3]), optional exact
+* ``mul_finite``     -- multipliers +-exp(U[-0.01, 0.01]), optional exact
                         zeros past a given position.
 * ``mat2(ensemble="o2")`` -- random orthogonal 2x2 factors.
-* ``segmented_ties`` -- the segmented workload with a = 1 and small integer
+* ``segmented_ties`` -- the segmented workload with a in {0, 1} and small integer
                         offsets, so that equal minima are common.
 """
 from __future__ import annotations
@@ -150,15 +150,19 @@ def mat2(n: int = 1 << 24, seed: int = BASE_SEED + 2, ensemble: str = "gauss"):
 
 
 def mul_finite(shape, seed: int = BASE_SEED + 7, zeros_after: int = -1, n_zeros: int = 0):
-    """Multipliers x = sign * (1 + u) with sign = +-1 equally likely and
-    u ~ U[-1e-3, 1e-3], so prefix products stay finite and non-zero over
-    2^24 and more elements (log |product| drifts by about -u^2/2 per factor
-    with a standard deviation of 5.8e-4 per factor).  With ``n_zeros`` > 0,
-    that many exact zeros at distinct positions >= ``zeros_after`` along the
-    last axis.  Output adjoint y_bar ~ N(0,1) of the same shape."""
+    """Multipliers x = sign * exp(v) with sign = +-1 equally likely and
+    v ~ U[-0.01, 0.01]: log |product| is a driftless random walk with a
+    standard deviation of 5.8e-3 per factor, so prefix products stay finite
+    and non-zero over 2^24 and more elements (|log| below about 25 there).
+    Factors much closer to 1 (spread 1e-3) would make float32 products in
+    a tree order drop their second-order terms systematically, an error
+    that grows linearly with the chain instead of as its square root.
+    With ``n_zeros`` > 0, that many exact zeros at distinct positions >=
+    ``zeros_after`` along the last axis.  Output adjoint y_bar ~ N(0,1) of
+    the same shape."""
     r = _streams(seed, 4)
     shape = tuple(shape) if isinstance(shape, (tuple, list)) else (int(shape),)
-    x = r[0].choice([-1.0, 1.0], shape) * (1.0 + r[1].uniform(-1e-3, 1e-3, shape))
+    x = r[0].choice([-1.0, 1.0], shape) * np.exp(r[1].uniform(-0.01, 0.01, shape))
     if n_zeros > 0:
         n = shape[-1]
         lo = max(int(zeros_after), 0)
@@ -234,18 +238,20 @@ def segmented(S: int = 4096, m: int = 512, seed: int = BASE_SEED + 4,
 
 def segmented_ties(S: int = 64, m: int = 16, seed: int = BASE_SEED + 8, median: int = 700,
                    cap: int = 30_000):
-    """Like ``segmented`` but with a = 1 and small integer offsets
-    b ~ U{-3..3}: every y is an exact float32 integer (|y| <= 3 * cap), so
-    equal minima occur in most bins and the lowest-index rule decides."""
-    r = _streams(seed, 5)
+    """Like ``segmented`` but with multipliers a in {0, 1} (each 0 with
+    probability 1/2, which restarts the recurrence at y_i = b_i) and small
+    integer offsets b ~ U{-1, 0, 1}: every y is an exact float32 integer of
+    small magnitude, so equal minima occur in about half of the bins with
+    several elements and the lowest-index rule decides them."""
+    r = _streams(seed, 6)
     L = segment_lengths(r[0], S, median, cap)
     off = np.zeros(S + 1, dtype=np.int64)
     np.cumsum(L, out=off[1:])
     N = int(off[-1])
     return dict(
         offsets=off, lengths=L, m=m, n_total=N,
-        a=np.ones(N, np.float32),
-        b=f32(r[1].integers(-3, 4, N)),
+        a=(r[5].random(N) >= 0.5).astype(np.float32),
+        b=f32(r[1].integers(-1, 2, N)),
         idx=r[2].integers(0, m, N, dtype=np.int64).astype(np.int32),
         ybar=f32(r[3].standard_normal(N)),
         hbar=f32(r[4].standard_normal(S * m)),
