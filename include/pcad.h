@@ -435,6 +435,40 @@ int pcad_matd_reduce_vjp(int d, int64_t batch, int64_t n, const float *M, const 
                          size_t ws_bytes, void *stream);
 
 /*
+ * Scans of block-diagonal matrix products (Section 5.3, Block-Diagonal
+ * Sparsity): every factor is a d x d block-diagonal matrix with k distinct
+ * q x q blocks (d = k q), stored as its k blocks; products keep the shape,
+ * so P_i is block diagonal too and so is the Jacobian of P_{i-1} M_i with
+ * respect to P_{i-1}.  The adjoint therefore runs as k scans, one per block
+ * position, each over q x q adjoint maps (the blocks' own redundant
+ * block-diagonal form), never forming a d x d Jacobian.
+ *   q   : 1, 2, 3 or 5 (block size); k >= 1 blocks, k*q*q <= 4096.
+ *   M   : [batch][n][k][q*q]: block j of element i is a row-major q x q
+ *         matrix; 16-byte aligned.
+ *   P   : same layout; block j of P_i = M_0^j M_1^j ... M_i^j.
+ *   saved: the blocks' tile prefixes (pcad_bds_query), read by the adjoint.
+ *   Pbar / Mbar: adjoints in the layout of P / M (the diagonal blocks of the
+ *         d x d adjoint; entries outside the blocks are structurally zero
+ *         and have none); PCAD_ACCUMULATE adds into Mbar.
+ *   ws  : workspace of pcad_bds_query's size, 256-byte aligned.
+ *   tmp : scratch for the regrouped blocks, 256-byte aligned, of
+ *         tmp_fwd_bytes (forward) or tmp_vjp_bytes (adjoint).
+ * Errors: PCAD_E_INVALID_ARG for another q, k < 1, negative sizes or
+ * unknown flags; PCAD_E_SIZE for k*q*q > 4096, n > 2^31-1 or too many
+ * tiles; PCAD_E_NULLPTR / PCAD_E_MISALIGNED / PCAD_E_WORKSPACE as for the
+ * scans.  No compute happens on an error; batch == 0 or n == 0 is a no-op.
+ */
+int pcad_bds_query(int q, int64_t k, int64_t batch, int64_t n, unsigned flags,
+                   size_t *saved_bytes, size_t *workspace_bytes, size_t *tmp_fwd_bytes,
+                   size_t *tmp_vjp_bytes);
+int pcad_bds_scan_fwd(int q, int64_t k, int64_t batch, int64_t n, const float *M, float *P,
+                      void *saved, unsigned flags, void *ws, size_t ws_bytes, void *tmp,
+                      size_t tmp_bytes, void *stream);
+int pcad_bds_scan_vjp(int q, int64_t k, int64_t batch, int64_t n, const float *M,
+                      const void *saved, const float *Pbar, float *Mbar, unsigned flags, void *ws,
+                      size_t ws_bytes, void *tmp, size_t tmp_bytes, void *stream);
+
+/*
  * int32 forward combinators for ADD, MUL, MIN, MAX (the evaluation's integer
  * element types; integer arithmetic has no adjoint).  ADD and MUL wrap mod
  * 2^32 (two's complement); every result is exact, whatever the order of

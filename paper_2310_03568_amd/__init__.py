@@ -76,6 +76,9 @@ def lib():
             "pcad_vscan_vjp": ([I, I64, I64, I64, P, P, P, P, U, P, SZ, P, SZ, P], I),
             "pcad_vrbi_fwd": ([I, I64, I64, I64, I64, P, P, P, P, U, P, SZ, P, SZ, P], I),
             "pcad_vrbi_vjp": ([I, I64, I64, I64, I64, P, P, P, P, P, U, P, SZ, P, SZ, P], I),
+            "pcad_bds_query": ([I, I64, I64, I64, U, PSZ, PSZ, PSZ, PSZ], I),
+            "pcad_bds_scan_fwd": ([I, I64, I64, I64, P, P, P, U, P, SZ, P, SZ, P], I),
+            "pcad_bds_scan_vjp": ([I, I64, I64, I64, P, P, P, P, U, P, SZ, P, SZ, P], I),
             "pcad_matd_query": ([I, I64, I64, U, PSZ, PSZ], I),
             "pcad_matd_scan_fwd": ([I, I64, I64, P, P, P, U, P, SZ, P], I),
             "pcad_matd_scan_vjp": ([I, I64, I64, P, P, P, P, U, P, SZ, P], I),
@@ -515,6 +518,56 @@ def matd_scan_vjp(M, saved, Pbar, out=None, accumulate: bool = False):
     check(lib().pcad_matd_scan_vjp(d, batch, n, _ptr(M), _ptr(saved), _ptr(Pbar.contiguous()),
                                    _ptr(out), ACCUMULATE if accumulate else 0, _ptr(ws),
                                    ws.numel(), _stream(dev)), "pcad_matd_scan_vjp", ws=ws)
+    return out
+
+
+def _bdsshape(M: torch.Tensor):
+    """M (..., n, k, q, q) -> (q, k, batch, n, lead)"""
+    if M.dim() < 4 or M.shape[-1] != M.shape[-2]:
+        raise PcadError("block-diagonal operands are (..., n, k, q, q)")
+    lead = tuple(M.shape[:-4])
+    batch = 1
+    for t in lead:
+        batch *= t
+    return M.shape[-1], M.shape[-3], batch, M.shape[-4], lead
+
+
+def bds_query(q: int, k: int, batch: int, n: int):
+    s, w, tf, tv = (ctypes.c_size_t(0) for _ in range(4))
+    check(lib().pcad_bds_query(q, k, batch, n, 0, ctypes.byref(s), ctypes.byref(w),
+                               ctypes.byref(tf), ctypes.byref(tv)), "pcad_bds_query")
+    return s.value, w.value, tf.value, tv.value
+
+
+def bds_scan_fwd(M: torch.Tensor):
+    """Scan of block-diagonal matrix products.  M (..., n, k, q, q): element
+    i is the block-diagonal matrix diag(M[i, 0], ..., M[i, k-1]).  Returns
+    (P, saved) with P[i, j] = M[0, j] M[1, j] ... M[i, j]."""
+    _dev_check(M)
+    q, k, batch, n, lead = _bdsshape(M)
+    s_b, w_b, t_b, _ = bds_query(q, k, batch, n)
+    dev = M.device
+    P = torch.empty_like(M)
+    saved = torch.empty(max(s_b, 16), dtype=torch.uint8, device=dev)
+    ws, tmp = workspace(w_b, dev), scratch(t_b, dev)
+    check(lib().pcad_bds_scan_fwd(q, k, batch, n, _ptr(M), _ptr(P), _ptr(saved), 0, _ptr(ws),
+                                  ws.numel(), _ptr(tmp), tmp.numel(), _stream(dev)),
+          "pcad_bds_scan_fwd", ws=ws)
+    return P, saved
+
+
+def bds_scan_vjp(M, saved, Pbar, out=None, accumulate: bool = False):
+    """Adjoint of bds_scan_fwd: returns M_bar (shape of M)."""
+    _dev_check(M, Pbar)
+    q, k, batch, n, lead = _bdsshape(M)
+    s_b, w_b, _, t_b = bds_query(q, k, batch, n)
+    dev = M.device
+    out = torch.empty_like(M) if out is None else out
+    _dev_check(out)
+    ws, tmp = workspace(w_b, dev), scratch(t_b, dev)
+    check(lib().pcad_bds_scan_vjp(q, k, batch, n, _ptr(M), _ptr(saved), _ptr(Pbar.contiguous()),
+                                  _ptr(out), ACCUMULATE if accumulate else 0, _ptr(ws), ws.numel(),
+                                  _ptr(tmp), tmp.numel(), _stream(dev)), "pcad_bds_scan_vjp", ws=ws)
     return out
 
 

@@ -580,3 +580,93 @@ int pcad_i32_fwd(int combinator, int op, int64_t batch, int64_t n, int64_t m,
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// block-diagonal matrix-product scans (k blocks of q x q)
+// ---------------------------------------------------------------------------
+namespace {
+
+int check_bds(int q, int64_t k, int64_t batch, int64_t n, unsigned flags) {
+  if (flags & ~kKnownFlags) return PCAD_E_INVALID_ARG;
+  if (k < 1 || batch < 0 || n < 0) return PCAD_E_INVALID_ARG;
+  if (q != 1 && q != 2 && q != 3 && q != 5) return PCAD_E_INVALID_ARG;
+  if (!bds_supported(q, k)) return PCAD_E_SIZE;
+  if (n > kMaxN) return PCAD_E_SIZE;
+  if (batch > 0 && n > 0 && batch > kMaxTotal / n / k) return PCAD_E_SIZE;
+  const int64_t rows = batch * k;
+  if (q >= 3) {
+    if (matd_tiles(q, rows, n) > 2147483647LL) return PCAD_E_SIZE;
+  } else if (scan_tiles(q == 1 ? PCAD_MUL : PCAD_MAT2, rows, n) > 2147483647LL) {
+    return PCAD_E_SIZE;
+  }
+  return PCAD_OK;
+}
+
+void bds_sizes(int q, int64_t k, int64_t batch, int64_t n, size_t *saved, size_t *ws) {
+  const int64_t rows = batch * k;
+  if (q >= 3) {
+    *saved = matd_saved_bytes(q, rows, n);
+    *ws = matd_ws_bytes(q, rows, n);
+  } else {
+    const int op = q == 1 ? PCAD_MUL : PCAD_MAT2;
+    *saved = scan_saved(op, rows, n);
+    *ws = scan_ws(op, rows, n);
+  }
+}
+
+int check_bds_bufs(int q, int64_t k, int64_t batch, int64_t n, int dir, const void *saved,
+                   const void *ws, size_t ws_bytes, const void *tmp, size_t tmp_bytes) {
+  size_t sv = 0, w = 0;
+  bds_sizes(q, k, batch, n, &sv, &w);
+  if (sv > 0) PCAD_TRY(need(saved));
+  if (ws_bytes < w) return PCAD_E_WORKSPACE;
+  if (!ws) return PCAD_E_NULLPTR;
+  if ((uintptr_t)ws & 255u) return PCAD_E_MISALIGNED;
+  if (tmp_bytes < bds_tmp_bytes(dir, q, k, batch, n)) return PCAD_E_WORKSPACE;
+  if (!tmp) return PCAD_E_NULLPTR;
+  if ((uintptr_t)tmp & 255u) return PCAD_E_MISALIGNED;
+  return PCAD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pcad_bds_query(int q, int64_t k, int64_t batch, int64_t n, unsigned flags,
+                   size_t *saved_bytes, size_t *workspace_bytes, size_t *tmp_fwd_bytes,
+                   size_t *tmp_vjp_bytes) {
+  PCAD_TRY(check_bds(q, k, batch, n, flags));
+  size_t sv = 0, w = 0;
+  bds_sizes(q, k, batch, n, &sv, &w);
+  if (saved_bytes) *saved_bytes = sv;
+  if (workspace_bytes) *workspace_bytes = w;
+  if (tmp_fwd_bytes) *tmp_fwd_bytes = bds_tmp_bytes(0, q, k, batch, n);
+  if (tmp_vjp_bytes) *tmp_vjp_bytes = bds_tmp_bytes(1, q, k, batch, n);
+  return PCAD_OK;
+}
+
+int pcad_bds_scan_fwd(int q, int64_t k, int64_t batch, int64_t n, const float *M, float *P,
+                      void *saved, unsigned flags, void *ws, size_t ws_bytes, void *tmp,
+                      size_t tmp_bytes, void *stream) {
+  PCAD_TRY(check_bds(q, k, batch, n, flags));
+  if (batch == 0 || n == 0) return PCAD_OK;
+  PCAD_TRY(need(M));
+  PCAD_TRY(need(P));
+  PCAD_TRY(check_bds_bufs(q, k, batch, n, 0, saved, ws, ws_bytes, tmp, tmp_bytes));
+  return hip_status(bds_fwd_launch(q, k, batch, n, M, P, saved, ws, tmp, (hipStream_t)stream));
+}
+
+int pcad_bds_scan_vjp(int q, int64_t k, int64_t batch, int64_t n, const float *M,
+                      const void *saved, const float *Pbar, float *Mbar, unsigned flags, void *ws,
+                      size_t ws_bytes, void *tmp, size_t tmp_bytes, void *stream) {
+  PCAD_TRY(check_bds(q, k, batch, n, flags));
+  if (batch == 0 || n == 0) return PCAD_OK;
+  PCAD_TRY(need(M));
+  PCAD_TRY(need(Pbar));
+  PCAD_TRY(need(Mbar));
+  PCAD_TRY(check_bds_bufs(q, k, batch, n, 1, saved, ws, ws_bytes, tmp, tmp_bytes));
+  return hip_status(bds_vjp_launch(q, k, batch, n, M, saved, Pbar, Mbar,
+                                   (flags & PCAD_ACCUMULATE) != 0, ws, tmp, (hipStream_t)stream));
+}
+
+}  // extern "C"

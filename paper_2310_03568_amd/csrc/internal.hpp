@@ -21,6 +21,8 @@ int64_t knob_rbi_elems_per_block();
 int64_t knob_rbi_sort_min_bins();
 bool knob_rbi_partition();
 bool knob_rbi_parts();
+int64_t knob_seg_tile();
+int knob_seg_threads(int dir);
 
 // stable sort of element indices by bin (sort.hip): keys outside [0, m)
 // sort last as m
@@ -96,6 +98,17 @@ hipError_t matd_reduce_fwd_launch(int d, int64_t batch, int64_t n, const float *
 hipError_t matd_reduce_vjp_launch(int d, int64_t batch, int64_t n, const float *x,
                                   const float *saved, const float *ybar, float *xbar,
                                   bool accumulate, void *ws, hipStream_t s);
+
+// block-diagonal matrix-product scans (bds.hip): k blocks of q x q, q in
+// {1, 2, 3, 5}, k*q*q <= kBdsMaxBlockFloats; dir 0 forward, 1 adjoint
+constexpr int64_t kBdsMaxBlockFloats = 4096;
+bool bds_supported(int q, int64_t k);
+size_t bds_tmp_bytes(int dir, int q, int64_t k, int64_t batch, int64_t n);
+hipError_t bds_fwd_launch(int q, int64_t k, int64_t batch, int64_t n, const float *M, float *P,
+                          void *saved, void *ws, void *tmp, hipStream_t s);
+hipError_t bds_vjp_launch(int q, int64_t k, int64_t batch, int64_t n, const float *M,
+                          const void *saved, const float *Pbar, float *Mbar, bool accumulate,
+                          void *ws, void *tmp, hipStream_t s);
 
 // int32 forward combinators for + * min max (i32.hip); comb 0 reduce, 1 scan,
 // 2 reduce-by-index

@@ -50,10 +50,15 @@ Knob g_knobs[] = {
     // 65536), one row: 1 splits the bins into those tables, one block per
     // (table, chunk of elements); 0 leaves them to the partition / hash path
     {"rbi.parts", 1, 0, 1, false, 1},
+    // batched segmented plans (read when a plan is created): elements per
+    // work item, and the block sizes of the forward and adjoint kernels
+    {"seg.tile", 8192, 4096, 8192, true, 8192},
+    {"seg.fwd.threads", 512, 256, 1024, true, 512},
+    {"seg.vjp.threads", 512, 256, 1024, true, 512},
 };
 constexpr int kNumKnobs = (int)(sizeof(g_knobs) / sizeof(g_knobs[0]));
 constexpr int kRbiF32 = 12, kRbiU64 = 13, kRbiEpb = 14, kRbiSort = 15, kRbiPart = 16,
-              kRbiParts = 17;
+              kRbiParts = 17, kSegTile = 18, kSegFwdThreads = 19, kSegVjpThreads = 20;
 
 Knob *find(const char *name) {
   if (!name) return nullptr;
@@ -75,6 +80,8 @@ int64_t knob_rbi_elems_per_block() { return g_knobs[kRbiEpb].value; }
 int64_t knob_rbi_sort_min_bins() { return g_knobs[kRbiSort].value; }
 bool knob_rbi_partition() { return g_knobs[kRbiPart].value != 0; }
 bool knob_rbi_parts() { return g_knobs[kRbiParts].value != 0; }
+int64_t knob_seg_tile() { return g_knobs[kSegTile].value; }
+int knob_seg_threads(int dir) { return (int)g_knobs[dir ? kSegVjpThreads : kSegFwdThreads].value; }
 
 }  // namespace pcad
 

@@ -84,9 +84,38 @@ def test_quick_tune_writes_valid_cache(pcad, tmp_path):
     from paper_2310_03568_amd import tune
     out = tmp_path / "tune.json"
     cache = tune.tune(str(out), quick=True)
-    assert json.loads(out.read_text())["knobs"] == cache["knobs"]
+    assert json.loads(out.read_text())["entries"] == cache["entries"]
     assert tune.load(str(out))
     k = pcad.knobs()
     for name, v in cache["knobs"].items():
         assert k[name] == v
+    seg = tune.key("batched", "linrec+min", 1 << 26, 512, "lognormal")
+    assert tune.load(str(out), key=seg)
+    for name in ("seg.tile", "seg.fwd.threads", "seg.vjp.threads"):
+        assert pcad.knobs()[name] == cache["knobs"][name]
     print(json.dumps(cache["knobs"]), flush=True)
+
+
+@pytest.mark.parametrize("threads", [256, 512, 1024])
+@pytest.mark.parametrize("tile", [4096, 8192])
+def test_segmented_plan_shapes(pcad, tile, threads):
+    """Every item size and block size of the batched plan (each its own
+    kernel instantiation, chosen when the plan is created) against the
+    oracle, forward and adjoint, on ragged instances."""
+    from test_gpu_batched import check_backward, check_forward, ragged_lengths, workload
+    pcad.set_knob("seg.tile", tile)
+    pcad.set_knob("seg.fwd.threads", threads)
+    pcad.set_knob("seg.vjp.threads", 1024 if threads == 256 else threads // 2)
+    print(f"segmented tile {tile} threads {threads}", flush=True)
+    w = workload(ragged_lengths(3), 512, seed=tile + threads)
+    plan = pcad.BatchedPlan(w["offsets"], 512)
+    plan.load(a=w["a"], b=w["b"], idx=w["idx"], ybar=w["ybar"], hbar=w["hbar"])
+    N = plan.n
+    plan.run(pcad.PHASE_BOTH)
+    torch.cuda.synchronize()
+    check_forward(pcad, w, plan.y[:N].cpu().numpy(), plan.h.cpu().numpy(),
+                  plan.argk.cpu().numpy(), f"tile {tile} threads {threads}")
+    check_backward(w, plan.argk.cpu().numpy(), plan.abar[:N].cpu().numpy(),
+                   plan.bbar[:N].cpu().numpy(), f"tile {tile} threads {threads}")
+    assert plan.ws_error() == 0
+    plan.close()

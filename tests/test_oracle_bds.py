@@ -29,7 +29,7 @@ def diag_blocks(M, k, q):
 
 def blocks(rng, n, k, q):
     if q == 1:
-        x = rng.choice([-1.0, 1.0], (n, k)) * (1.0 + rng.uniform(-1e-3, 1e-3, (n, k)))
+        x = rng.choice([-1.0, 1.0], (n, k)) * np.exp(rng.uniform(-0.01, 0.01, (n, k)))
         return x.astype(np.float32).reshape(n, k, 1, 1)
     if q == 2:
         return o2_matrices(rng, n * k).reshape(n, k, 2, 2)
