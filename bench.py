@@ -537,37 +537,42 @@ def segmented_extras(b, torch, np, reps=3):
 
 def segmented_parity(b, torch, np):
     """Oracle (fp64, one thread) on the whole workload: times the adjoint
-    (cpu_baseline) and gates the GPU forward and adjoint.  The adjoint is
-    re-run with the oracle's argmin decision in argk."""
+    (cpu_baseline) and gates the GPU forward and adjoint.  The min-by-index
+    decisions are taken on the plan's own float32 y: every bin's argk must
+    be the lowest index of that y's minimum in the bin and h must be y at
+    argk, bit for bit (Section 4.2, Min/Max); the adjoint runs on the plan's
+    own argk and is gated against the oracle's adjoint for those decisions."""
     import oracle
     import paper_2310_03568_amd as pcad
-    from oracle.gate import gate
+    from oracle.gate import gate, segmented_decisions
     w, plan = b["inputs"], b["plan"]
     N, S, m = plan.n, plan.nseg, plan.m
     plan.run(pcad.PHASE_FWD)
     torch.cuda.synchronize()
     y = plan.y[:N].cpu().numpy()
+    h = plan.h.cpu().numpy()
     argk = plan.argk.cpu().numpy().reshape(S, m)
     t0 = time.perf_counter()
     f = oracle.segmented_fwd(w["offsets"], w["a"], w["b"], w["idx"], m)
     tf = time.perf_counter() - t0
     ry = gate(y, f["y"], f["cy"], 1e-4)
-    mism = int((argk != f["argk"]).sum())
-    plan.argk.copy_(torch.from_numpy(f["argk"].reshape(-1).astype(np.int32)))
+    dec = segmented_decisions(w["offsets"], w["idx"], m, y, h, argk, f)
     plan.run(pcad.PHASE_BWD)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ab, bb, cab, cbb = oracle.segmented_vjp(w["offsets"], w["a"], w["b"], w["idx"], m,
-                                            w["ybar"], w["hbar"], f["argk"])
+                                            w["ybar"], w["hbar"], argk)
     tb = time.perf_counter() - t0
     ra = gate(plan.abar[:N].cpu().numpy(), ab, cab, 1e-4)
     rb = gate(plan.bbar[:N].cpu().numpy(), bb, cbb, 1e-4)
-    ok = ry["ok"] and ra["ok"] and rb["ok"] and (ry["n_range_exceeded"] + ra["n_range_exceeded"]
-                                                   + rb["n_range_exceeded"]) == 0
+    rx = ry["n_range_exceeded"] + ra["n_range_exceeded"] + rb["n_range_exceeded"]
+    ok = (ry["ok"] and ra["ok"] and rb["ok"] and rx == 0
+          and dec["argk_ok"] and dec["h_ok"] and dec["diff_ok"])
     par = dict(ok=ok, y_max_rel=ry["max_rel"], a_max_rel=ra["max_rel"], b_max_rel=rb["max_rel"],
                normwise_a=ra["normwise"], normwise_b=rb["normwise"],
-               argk_mismatch_bins=mism, range_exceeded=ry["n_range_exceeded"] + ra["n_range_exceeded"]
-               + rb["n_range_exceeded"])
+               argk_lowest_min_of_own_y=dec["argk_ok"], argk_bad_bins=dec["argk_bad_bins"],
+               h_is_y_at_argk=dec["h_ok"], argk_differs_from_fp64_oracle_bins=dec["n_diff_oracle"],
+               argk_differences_are_ties=dec["diff_ok"], range_exceeded=rx)
     cpu = {"value": N / tb, "unit": "elem/s", "cores": 1, "kind": "oracle",
            "sample": f"whole workload ({S} instances, {N} elements): oracle adjoint incl. its "
                      f"forward re-execution {tb:.2f} s (forward alone {tf:.2f} s), fp64"}

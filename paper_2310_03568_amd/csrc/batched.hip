@@ -24,23 +24,11 @@
 
 namespace pcad {
 
-// items of SEG_T elements; block sizes of the forward and adjoint kernels
-// (build-time knobs for shape sweeps)
-#ifndef PCAD_SEG_FWD_THREADS
-#define PCAD_SEG_FWD_THREADS 512
-#endif
-#ifndef PCAD_SEG_VJP_THREADS
-#define PCAD_SEG_VJP_THREADS 512
-#endif
-#ifndef PCAD_SEG_TILE
-#define PCAD_SEG_TILE 8192
-#endif
-constexpr int SEG_T = PCAD_SEG_TILE;
+// Items of SEG_T elements (4096 or 8192) and the block sizes of the forward
+// and adjoint kernels (256, 512 or 1024 threads) are template parameters; a
+// plan picks one instantiation of each from the tuning knobs when it is
+// created (seg.tile, seg.fwd.threads, seg.vjp.threads).
 constexpr int SEG_EPL = 4;
-constexpr int SEG_THF = PCAD_SEG_FWD_THREADS, SEG_KF = SEG_T / (SEG_THF * SEG_EPL);
-constexpr int SEG_THB = PCAD_SEG_VJP_THREADS, SEG_KB = SEG_T / (SEG_THB * SEG_EPL);
-static_assert(SEG_KF * SEG_THF * SEG_EPL == SEG_T && SEG_KB * SEG_THB * SEG_EPL == SEG_T,
-              "items must be whole groups of the block");
 constexpr int SEG_MAX_BINS = 1024;
 
 // one record per work item, built on the host at bind time
@@ -69,8 +57,24 @@ struct SegItem {
   int wofs;              // wbase - start: instance index of the window's first element
 };
 
+// a block-uniform 64-bit value, held in scalar registers: the item record is
+// then read through the scalar cache, so reading it never waits for vector
+// loads in flight
+__device__ __forceinline__ int64_t uniform64(int64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 __device__ __forceinline__ SegItem seg_item(const SegTables &t, int64_t item) {
+  // the table is never written during a launch: read it as constant memory
+  // (the host pass only parses this function)
+#if defined(__HIP_DEVICE_COMPILE__)
+  typedef const __attribute__((address_space(4))) ItemRec ConstRec;
+  const ItemRec r = ((ConstRec *)(t.items))[uniform64(item)];
+#else
   const ItemRec r = t.items[item];
+#endif
   SegItem q;
   q.s = r.s;
   q.li = r.li;
@@ -86,25 +90,56 @@ __device__ __forceinline__ SegItem seg_item(const SegTables &t, int64_t item) {
   return q;
 }
 
-// elements [e, e+4) of the window at `w` (block-uniform pointer) of which
-// those in [lo, hi) are read; `fill` elsewhere
-__device__ __forceinline__ float4 ld_range(const float *__restrict__ w, int e, int lo, int hi,
-                                           float fill) {
-  const unsigned o = (unsigned)e;
-  if (e >= lo && e + 4 <= hi) return *reinterpret_cast<const float4 *>(w + o);
-  float r[4];
-#pragma unroll
-  for (int j = 0; j < 4; ++j) r[j] = (e + j >= lo && e + j < hi) ? w[o + j] : fill;
-  return make_float4(r[0], r[1], r[2], r[3]);
+// Window loads are split in two so that no lane ever branches around a load
+// or writes a register that a load in flight targets (a wave that
+// straddles an instance boundary would otherwise have to drain every load
+// it has in flight, once per array):
+//  * ld_raw issues one 16-byte load per lane, always: the group [e, e+4) of
+//    the window at element wbase of an array of N >= 4 elements, or, for a
+//    group that runs past the array's end, the array's last four elements;
+//  * win_fix, applied where the data is first used (the loads have landed
+//    by then anyway), shifts that last group into place and replaces the
+//    elements outside the window's [lo, hi) by `fill`.
+template <class V, class S>
+__device__ __forceinline__ V ld_raw(const S *__restrict__ arr, int64_t N, int64_t wbase, int e) {
+  const int64_t i0 = wbase + e;
+  return *reinterpret_cast<const V *>(arr + (i0 + 4 <= N ? i0 : N - 4));
 }
 
-__device__ __forceinline__ int4 ld_range_i(const int32_t *__restrict__ w, int e, int lo, int hi) {
-  const unsigned o = (unsigned)e;
-  if (e >= lo && e + 4 <= hi) return *reinterpret_cast<const int4 *>(w + o);
-  int r[4];
+// which of the group's four elements [e, e+4) lie in the window's [lo, hi)
+struct WinMask {
+  bool in[4];
+};
+__device__ __forceinline__ WinMask win_mask(int e, int lo, int hi) {
+  WinMask m;
 #pragma unroll
-  for (int j = 0; j < 4; ++j) r[j] = (e + j >= lo && e + j < hi) ? w[o + j] : -1;
-  return make_int4(r[0], r[1], r[2], r[3]);
+  for (int j = 0; j < 4; ++j) m.in[j] = (unsigned)(e + j - lo) < (unsigned)(hi - lo);
+  return m;
+}
+
+// `tail`: the window reaches past the array's end (a uniform condition, so
+// the shifting costs nothing elsewhere)
+template <class V, class S>
+__device__ __forceinline__ V win_fix(const V &v, const WinMask &m, bool tail, int64_t N,
+                                     int64_t wbase, int e, S fill) {
+  S x[4] = {v.x, v.y, v.z, v.w};
+  if (tail) {
+    const int64_t i0 = wbase + e;
+    const int64_t sh = i0 + 4 <= N ? 0 : i0 - (N - 4);
+    const int s = (int)(sh < 4 ? sh : 4);
+    const S y0 = x[0], y1 = x[1], y2 = x[2], y3 = x[3];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int q = j + s;
+      x[j] = q == 0 ? y0 : (q == 1 ? y1 : (q == 2 ? y2 : (q == 3 ? y3 : fill)));
+    }
+  }
+  V o;
+  o.x = m.in[0] ? x[0] : fill;
+  o.y = m.in[1] ? x[1] : fill;
+  o.z = m.in[2] ? x[2] : fill;
+  o.w = m.in[3] ? x[3] : fill;
+  return o;
 }
 
 __device__ __forceinline__ void st_range(float *__restrict__ w, int e, int lo, int hi, float4 v) {
@@ -131,6 +166,7 @@ __device__ __forceinline__ int i4get(const int4 &v, int j) {
 struct SegFwdArgs {
   SegTables tab;
   int64_t nitems;
+  int64_t n;           // elements of the concatenated arrays
   int S, m;
   int nrows;           // instances with at least one element
   const float *a, *b;
@@ -149,10 +185,12 @@ struct SegFwdArgs {
 // publishes its next item in between).  The pending item's item-local
 // prefixes and keys wait in LDS; its outputs and LDS sub-histogram follow
 // the look-back.
-__global__ __launch_bounds__(SEG_THF) void k_seg_fwd(SegFwdArgs a) {
+template <int SEG_T, int TH>
+__global__ __launch_bounds__(TH) void k_seg_fwd(SegFwdArgs a) {
   using Op = FwdLB<LINREC>;
   using T = Op::T;
-  constexpr int K = SEG_KF, EPL = SEG_EPL, TH = SEG_THF, W = TH / WAVE;
+  constexpr int EPL = SEG_EPL, K = SEG_T / (TH * EPL), W = TH / WAVE;
+  static_assert(K >= 1 && K * TH * EPL == SEG_T, "items must be whole groups of the block");
 
   __shared__ T s_tot[K][W];
   __shared__ T s_pre[K][W];
@@ -172,9 +210,9 @@ __global__ __launch_bounds__(SEG_THF) void k_seg_fwd(SegFwdArgs a) {
 #pragma unroll
     for (int g = 0; g < K; ++g) {
       const int e = g * TH * EPL + tid * EPL;
-      ca[g] = ld_range(a.a + it.wbase, e, it.lo_r, it.hi_r, 1.0f);
-      cb[g] = ld_range(a.b + it.wbase, e, it.lo_r, it.hi_r, 0.0f);
-      ci[g] = ld_range_i(a.idx + it.wbase, e, it.lo_r, it.hi_r);
+      ca[g] = ld_raw<float4>(a.a, a.n, it.wbase, e);
+      cb[g] = ld_raw<float4>(a.b, a.n, it.wbase, e);
+      ci[g] = ld_raw<int4>(a.idx, a.n, it.wbase, e);
     }
   };
   int64_t i = blockIdx.x;  // the item whose outputs are pending
@@ -188,6 +226,15 @@ __global__ __launch_bounds__(SEG_THF) void k_seg_fwd(SegFwdArgs a) {
   // item publishes it as its inclusive prefix)
   auto phase1 = [&](const SegItem &jt, int64_t item, T (&v)[K][EPL], T &ag) {
     T incl[K];
+    const bool tail = jt.wbase + SEG_T > a.n;
+#pragma unroll
+    for (int g = 0; g < K; ++g) {
+      const int e = g * TH * EPL + tid * EPL;
+      const WinMask wm = win_mask(e, jt.lo_r, jt.hi_r);
+      ca[g] = win_fix(ca[g], wm, tail, a.n, jt.wbase, e, 1.0f);
+      cb[g] = win_fix(cb[g], wm, tail, a.n, jt.wbase, e, 0.0f);
+      ci[g] = win_fix(ci[g], wm, tail, a.n, jt.wbase, e, -1);
+    }
 #pragma unroll
     for (int g = 0; g < K; ++g) {
       T acc = {{f4get(ca[g], 0), f4get(cb[g], 0)}};
@@ -372,6 +419,7 @@ __global__ void k_fill_u64(uint64_t *p, int64_t n, uint64_t v) {
 struct SegBwdArgs {
   SegTables tab;
   int64_t nitems;
+  int64_t n;             // elements of the concatenated arrays
   int S, m;
   int nrows;
   const float *a, *b;
@@ -393,27 +441,28 @@ struct SegBwdArgs {
 // forward prefix y_{i-1} that a_bar needs is read from the forward output
 // (the forward of this workload stores y anyway), so the adjoint never
 // re-runs the forward recurrence and never reads b.
-__global__ __launch_bounds__(SEG_THB) void k_seg_bwd(SegBwdArgs a) {
+template <int SEG_T, int TH>
+__global__ __launch_bounds__(TH) void k_seg_bwd(SegBwdArgs a) {
   using FT = Fwd<LINREC>::T;
   using M = MapScalT<false>;
   using MT = M::T;
   using A = Adj<LINREC, false>;
-  constexpr int K = SEG_KB, EPL = SEG_EPL, TH = SEG_THB, W = TH / WAVE;
+  constexpr int EPL = SEG_EPL, K = SEG_T / (TH * EPL), W = TH / WAVE;
+  static_assert(K >= 1 && K * TH * EPL == SEG_T, "items must be whole groups of the block");
   constexpr int TPT = (SEG_MAX_BINS + TH - 1) / TH;  // bin entries per thread
 
   __shared__ MT s_mtot[K][W];
   __shared__ MT s_mpre[K][W];
   __shared__ MT s_carry;
   __shared__ unsigned s_epoch;
-  __shared__ int32_t s_ak[SEG_MAX_BINS];
-  __shared__ float s_hb[SEG_MAX_BINS];
+  __shared__ int2 s_bin[SEG_MAX_BINS];  // (argk, h_bar bits) of the item's instance, per bin
 
   const int tid = threadIdx.x, lane = lane_id(), wave = tid / WAVE;
   const int64_t G = gridDim.x;
   if (tid == 0) s_epoch = ctl_load(&a.ctl->epoch);
 
   struct Buf {
-    float4 a[K], y[K], yb[K];
+    float4 a[K], y[K], yb[K];  // raw window loads (fixed where first used)
     int4 ix[K];
     float yp0[K];  // lane 0: y of the element before the lane's group (0 at an instance start)
     int32_t ak[TPT];
@@ -423,10 +472,10 @@ __global__ __launch_bounds__(SEG_THB) void k_seg_bwd(SegBwdArgs a) {
 #pragma unroll
     for (int g = 0; g < K; ++g) {
       const int e = g * TH * EPL + tid * EPL;
-      B.a[g] = ld_range(a.a + it.wbase, e, it.lo_r, it.hi_r, 1.0f);
-      B.y[g] = ld_range(a.y + it.wbase, e, it.lo_r, it.hi_r, 0.0f);
-      B.yb[g] = ld_range(a.ybar + it.wbase, e, it.lo_r, it.hi_r, 0.0f);
-      B.ix[g] = ld_range_i(a.idx + it.wbase, e, it.lo_r, it.hi_r);
+      B.a[g] = ld_raw<float4>(a.a, a.n, it.wbase, e);
+      B.y[g] = ld_raw<float4>(a.y, a.n, it.wbase, e);
+      B.yb[g] = ld_raw<float4>(a.ybar, a.n, it.wbase, e);
+      B.ix[g] = ld_raw<int4>(a.idx, a.n, it.wbase, e);
       // element e-1 lies in the instance iff its instance index is >= 0 and
       // it is before the instance's end in this window
       B.yp0[g] = 0.0f;
@@ -435,9 +484,11 @@ __global__ __launch_bounds__(SEG_THB) void k_seg_bwd(SegBwdArgs a) {
     const int64_t hb = it.s * a.m;
 #pragma unroll
     for (int r = 0; r < TPT; ++r) {
+      // every lane loads (entries past m are never put in LDS)
       const int k = tid + r * TH;
-      B.ak[r] = k < a.m ? a.argk[hb + k] : 0;
-      B.hb[r] = k < a.m ? a.hbar[hb + k] : 0.0f;
+      const int kc = k < a.m ? k : a.m - 1;
+      B.ak[r] = a.argk[hb + kc];
+      B.hb[r] = a.hbar[hb + kc];
     }
   };
   auto item_of = [&](int64_t kk) { return a.nitems - 1 - kk; };
@@ -455,16 +506,33 @@ __global__ __launch_bounds__(SEG_THB) void k_seg_bwd(SegBwdArgs a) {
 
   // scans the item in `cur` (its bin entries already in LDS)
   auto phase1 = [&](const SegItem &jt, int64_t item) {
+    const bool tail = jt.wbase + SEG_T > a.n;
 #pragma unroll
     for (int g = 0; g < K; ++g) {
       const int e = g * TH * EPL + tid * EPL;
+      const WinMask wm = win_mask(e, jt.lo_r, jt.hi_r);
+      cur.a[g] = win_fix(cur.a[g], wm, tail, a.n, jt.wbase, e, 1.0f);
+      cur.yb[g] = win_fix(cur.yb[g], wm, tail, a.n, jt.wbase, e, 0.0f);
+      cur.ix[g] = win_fix(cur.ix[g], wm, tail, a.n, jt.wbase, e, -1);
+    }
+#pragma unroll
+    for (int g = 0; g < K; ++g) {
+      const int e = g * TH * EPL + tid * EPL;
+      // the group's four bin records, read together (one LDS round trip)
+      int2 bv[EPL];
+#pragma unroll
+      for (int j = 0; j < EPL; ++j) {
+        const int kb = i4get(cur.ix[g], j);
+        bv[j] = s_bin[(unsigned)kb < (unsigned)a.m ? kb : 0];
+      }
       MT acc = M::id();
 #pragma unroll
       for (int j = EPL - 1; j >= 0; --j) {
         // y_bar_total = y_bar + h_bar at the bin's argmin (fused min-by-index adjoint)
         const int kb = i4get(cur.ix[g], j);
-        if (kb >= 0 && kb < a.m && s_ak[kb] == jt.wofs + e + j)
-          f4set(cur.yb[g], j, f4get(cur.yb[g], j) + s_hb[kb]);
+        const bool hit = (unsigned)kb < (unsigned)a.m && bv[j].x == jt.wofs + e + j;
+        const float y0 = f4get(cur.yb[g], j);
+        f4set(cur.yb[g], j, hit ? y0 + __int_as_float(bv[j].y) : y0);
         const float yb[2] = {f4get(cur.yb[g], j), 0.0f};
         const MT hm = A::make(FT{{1.0f, 0.0f}}, FT{{f4get(cur.a[g], j), 0.0f}}, yb, false);
         acc = (j == EPL - 1) ? hm : M::comb(acc, hm);
@@ -488,10 +556,7 @@ __global__ __launch_bounds__(SEG_THB) void k_seg_bwd(SegBwdArgs a) {
 #pragma unroll
     for (int r = 0; r < TPT; ++r) {
       const int kb = tid + r * TH;
-      if (kb < a.m) {
-        s_ak[kb] = B.ak[r];
-        s_hb[kb] = B.hb[r];
-      }
+      if (kb < a.m) s_bin[kb] = make_int2(B.ak[r], __float_as_int(B.hb[r]));
     }
   };
 
@@ -530,16 +595,19 @@ __global__ __launch_bounds__(SEG_THB) void k_seg_bwd(SegBwdArgs a) {
     }
     __syncthreads();
     const MT carry = s_carry;
+    const bool tail = it.wbase + SEG_T > a.n;
 
 #pragma unroll
     for (int g = 0; g < K; ++g) {
       MT ex = shift_down1(mincl[g]);
       if (lane == WAVE - 1) ex = M::id();
       M::P rho = M::apply0(M::comb(M::comb(carry, s_mpre[g][wave]), ex));
+      const int e = g * TH * EPL + tid * EPL;
+      const float4 yg = win_fix(cur.y[g], win_mask(e, it.lo_r, it.hi_r), tail, a.n, it.wbase, e, 0.0f);
       // y_{i-1} of the four slots: the left neighbour's last y for the first
-      float yprev0 = dpp_f<kDppWaveShr1>(cur.y[g].w);
+      float yprev0 = dpp_f<kDppWaveShr1>(yg.w);
       if (lane == 0) yprev0 = cur.yp0[g];
-      const float yprev[4] = {yprev0, cur.y[g].x, cur.y[g].y, cur.y[g].z};
+      const float yprev[4] = {yprev0, yg.x, yg.y, yg.z};
       float4 oa, ob;
 #pragma unroll
       for (int j = EPL - 1; j >= 0; --j) {
@@ -549,7 +617,6 @@ __global__ __launch_bounds__(SEG_THB) void k_seg_bwd(SegBwdArgs a) {
         f4set(oa, j, xb[0]);
         f4set(ob, j, xb[1]);
       }
-      const int e = g * TH * EPL + tid * EPL;
       st_range(a.abar + it.wbase, e, it.lo_r, it.hi_r, oa);
       st_range(a.bbar + it.wbase, e, it.lo_r, it.hi_r, ob);
     }
@@ -574,6 +641,7 @@ using namespace pcad;
 struct pcad_plan {
   int64_t S = 0, N = 0, m = 0, nitems = 0, nrows = 0;
   unsigned flags = 0;
+  int tile = 8192, thf = 512, thb = 512;  // item size and block sizes, fixed at creation
   std::vector<int64_t> off;
   std::vector<ItemRec> item_rec;
   std::vector<int32_t> seg_item0;
@@ -621,23 +689,53 @@ int64_t seg_grid(F kernel, int threads, int64_t nitems) {
   return nitems < cap ? nitems : cap;
 }
 
+template <int T, int TH>
+hipError_t launch_fwd_t(pcad_plan *p, hipStream_t s) {
+  const int64_t grid = seg_grid(k_seg_fwd<T, TH>, TH, p->nitems);
+  if (grid == 0) return hipErrorInvalidDevice;
+  hipLaunchKernelGGL((k_seg_fwd<T, TH>), dim3((unsigned)grid), dim3(TH), 0, s, p->fa);
+  return hipGetLastError();
+}
+
+template <int T, int TH>
+hipError_t launch_bwd_t(pcad_plan *p, hipStream_t s) {
+  const int64_t grid = seg_grid(k_seg_bwd<T, TH>, TH, p->nitems);
+  if (grid == 0) return hipErrorInvalidDevice;
+  hipLaunchKernelGGL((k_seg_bwd<T, TH>), dim3((unsigned)grid), dim3(TH), 0, s, p->ba);
+  return hipGetLastError();
+}
+
+template <int T>
+hipError_t launch_fwd_tile(pcad_plan *p, hipStream_t s) {
+  switch (p->thf) {
+  case 256: return launch_fwd_t<T, 256>(p, s);
+  case 1024: return launch_fwd_t<T, 1024>(p, s);
+  default: return launch_fwd_t<T, 512>(p, s);
+  }
+}
+
+template <int T>
+hipError_t launch_bwd_tile(pcad_plan *p, hipStream_t s) {
+  switch (p->thb) {
+  case 256: return launch_bwd_t<T, 256>(p, s);
+  case 1024: return launch_bwd_t<T, 1024>(p, s);
+  default: return launch_bwd_t<T, 512>(p, s);
+  }
+}
+
 hipError_t launch_fwd_nodes(pcad_plan *p, hipStream_t s) {
   if (p->nitems > 0) {
-    const int64_t grid = seg_grid(k_seg_fwd, SEG_THF, p->nitems);
-    if (grid == 0) return hipErrorInvalidDevice;
-    hipLaunchKernelGGL(k_seg_fwd, dim3((unsigned)grid), dim3(SEG_THF), 0, s, p->fa);
+    const hipError_t e = p->tile == 4096 ? launch_fwd_tile<4096>(p, s) : launch_fwd_tile<8192>(p, s);
+    if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_seg_fin, dim3(2048), dim3(256), 0, s, p->fa);
   return hipGetLastError();
 }
 
 hipError_t launch_bwd_nodes(pcad_plan *p, hipStream_t s) {
-  if (p->nitems > 0) {
-    const int64_t grid = seg_grid(k_seg_bwd, SEG_THB, p->nitems);
-    if (grid == 0) return hipErrorInvalidDevice;
-    hipLaunchKernelGGL(k_seg_bwd, dim3((unsigned)grid), dim3(SEG_THB), 0, s, p->ba);
-  }
-  return hipGetLastError();
+  if (p->nitems > 0)
+    return p->tile == 4096 ? launch_bwd_tile<4096>(p, s) : launch_bwd_tile<8192>(p, s);
+  return hipSuccess;
 }
 
 }  // namespace
@@ -661,6 +759,10 @@ int pcad_plan_create(pcad_plan **out, int64_t nseg, const int64_t *offsets, int6
   p->S = nseg;
   p->m = m;
   p->flags = flags;
+  p->tile = (int)knob_seg_tile();
+  p->thf = knob_seg_threads(0);
+  p->thb = knob_seg_threads(1);
+  const int64_t SEG_T = p->tile;
   p->off.assign(offsets, offsets + nseg + 1);
   p->N = offsets[nseg];
   p->seg_item0.resize(nseg + 1);
@@ -792,9 +894,9 @@ int pcad_plan_bind(pcad_plan *p, const float *a, const float *b, const int32_t *
   Ctl *ctl = reinterpret_cast<Ctl *>(p->ws);
   uint64_t *status = reinterpret_cast<uint64_t *>(p->ws + p->ws_status);
   float *carry = reinterpret_cast<float *>(p->saved + p->sv_carry);
-  p->fa = SegFwdArgs{t, p->nitems, (int)p->S, (int)p->m, (int)p->nrows, a, b, idx, y, h, argk, carry,
+  p->fa = SegFwdArgs{t, p->nitems, p->N, (int)p->S, (int)p->m, (int)p->nrows, a, b, idx, y, h, argk, carry,
                      keys, ctl, status};
-  p->ba = SegBwdArgs{t, p->nitems, (int)p->S, (int)p->m, (int)p->nrows, a, b, idx, y, argk,
+  p->ba = SegBwdArgs{t, p->nitems, p->N, (int)p->S, (int)p->m, (int)p->nrows, a, b, idx, y, argk,
                      ybar, hbar, abar, bbar, ctl, status};
 
   // one graph per phase: forward, adjoint, both
