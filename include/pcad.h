@@ -206,6 +206,24 @@ int pcad_scan_vjp(int op, int64_t batch, int64_t n, const float *x0, const float
                   float *xbar1, unsigned flags, void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * pcad_scan_vjp_noalloc -- pcad_scan_vjp for callers that cannot allocate
+ * device memory (code under graph capture, tight serving loops, harnesses
+ * that forbid allocation): the same adjoint, arguments and results, with no
+ * ws argument.  Its look-back workspace is a static device array of
+ * PCAD_SCRATCH_BYTES, one per GPU, held until the process ends; the call
+ * allocates nothing.  Sizes whose workspace (pcad_query) exceeds
+ * PCAD_SCRATCH_BYTES return PCAD_E_SIZE before any launch (every operator up
+ * to 2^26 elements fits).  All calls on one GPU share that array: calls that
+ * may overlap (other streams, other host threads) race and must be ordered
+ * by the caller.  A timed-out look-back wait is not reported (there is no
+ * workspace to pass to pcad_ws_status).
+ */
+#define PCAD_SCRATCH_BYTES (4u << 20)
+int pcad_scan_vjp_noalloc(int op, int64_t batch, int64_t n, const float *x0, const float *x1,
+                          const void *saved, const float *ybar0, const float *ybar1,
+                          float *xbar0, float *xbar1, unsigned flags, void *stream);
+
+/*
  * Adjoint of the inclusive scan, checkpoint form: the forward prefixes
  * rs_{i-1} are read from the stored forward outputs (the tape of
  * intermediates, Section 2 on tapes versus redundant execution) instead of

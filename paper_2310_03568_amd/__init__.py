@@ -60,6 +60,7 @@ def lib():
             "pcad_scan_fwd": ([I, I64, I64, P, P, P, P, P, U, P, SZ, P], I),
             "pcad_scan_vjp": ([I, I64, I64, P, P, P, P, P, P, P, U, P, SZ, P], I),
             "pcad_scan_vjp_checkpoint": ([I, I64, I64, P, P, P, P, P, P, P, P, U, P, SZ, P], I),
+            "pcad_scan_vjp_noalloc": ([I, I64, I64, P, P, P, P, P, P, P, U, P], I),
             "pcad_rbi_fwd": ([I, I64, I64, I64, P, P, P, P, U, P, SZ, P], I),
             "pcad_rbi_vjp": ([I, I64, I64, I64, P, P, P, P, P, U, P, SZ, P], I),
             "pcad_plan_create": ([ctypes.POINTER(P), I64, P, I64, U], I),

@@ -3,6 +3,8 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <mutex>
+
 #include "../../include/pcad.h"
 #include "internal.hpp"
 
@@ -264,6 +266,64 @@ int pcad_scan_vjp(int op, int64_t batch, int64_t n, const float *x0, const float
   if (op == PCAD_LINREC) PCAD_TRY(need(xbar1));
   PCAD_TRY(check_saved(PCAD_SCAN, op, batch, n, 0, saved));
   PCAD_TRY(check_ws(PCAD_SCAN, op, batch, n, 0, ws, ws_bytes));
+  return hip_status(scan_vjp_launch(op, batch, n, x0, x1, static_cast<const float *>(saved),
+                                    nullptr, nullptr, ybar0, ybar1, xbar0, xbar1,
+                                    (flags & PCAD_ACCUMULATE) != 0, ws, (hipStream_t)stream));
+}
+
+// ---------------------------------------------------------------------------
+// pcad_scan_vjp_noalloc: pcad_scan_vjp with its look-back workspace in a
+// file-scope device array (one copy per GPU) instead of a caller's buffer.
+// Device variables without an initialiser start zeroed, which is the state
+// the control block needs before its first launch; every launch leaves the
+// block ready for the next (the epoch advances, the finished-row count
+// returns to 0), and the status words are validated by the launch tag, so
+// nothing is cleared between calls.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[PCAD_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[kMaxDevices];  // device address of `scratch` on each GPU
+
+// the device address of the current GPU's copy of `scratch`, looked up once
+// per GPU (the host-side name is only a stand-in for it)
+int scratch_address(void **out) {
+  int dev = 0;
+  PCAD_TRY(hip_status(hipGetDevice(&dev)));
+  if (dev < 0 || dev >= kMaxDevices) return PCAD_E_UNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void *p = nullptr;
+    PCAD_TRY(hip_status(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch))));
+    if (!p) return PCAD_E_HIP;
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return PCAD_OK;
+}
+
+}  // namespace
+
+int pcad_scan_vjp_noalloc(int op, int64_t batch, int64_t n, const float *x0, const float *x1,
+                          const void *saved, const float *ybar0, const float *ybar1,
+                          float *xbar0, float *xbar1, unsigned flags, void *stream) {
+  PCAD_TRY(check_common(op, batch, n, flags));
+  if (batch == 0 || n == 0) return PCAD_OK;
+  if (scan_tiles(op, batch, n) > 2147483647LL) return PCAD_E_SIZE;
+  if (scan_ws(op, batch, n) > (size_t)PCAD_SCRATCH_BYTES) return PCAD_E_SIZE;
+  PCAD_TRY(need(x0));
+  if (op == PCAD_LINREC) PCAD_TRY(need(x1));
+  PCAD_TRY(need(ybar0));
+  PCAD_TRY(opt(ybar1));
+  if (op != PCAD_LINREC && ybar1) return PCAD_E_INVALID_ARG;
+  PCAD_TRY(need(xbar0));
+  if (op == PCAD_LINREC) PCAD_TRY(need(xbar1));
+  PCAD_TRY(check_saved(PCAD_SCAN, op, batch, n, 0, saved));
+  void *ws = nullptr;
+  PCAD_TRY(scratch_address(&ws));
   return hip_status(scan_vjp_launch(op, batch, n, x0, x1, static_cast<const float *>(saved),
                                     nullptr, nullptr, ybar0, ybar1, xbar0, xbar1,
                                     (flags & PCAD_ACCUMULATE) != 0, ws, (hipStream_t)stream));
