@@ -90,20 +90,28 @@ __device__ __forceinline__ SegItem seg_item(const SegTables &t, int64_t item) {
   return q;
 }
 
-// Window loads are split in two so that no lane ever branches around a load
-// or writes a register that a load in flight targets (a wave that
-// straddles an instance boundary would otherwise have to drain every load
-// it has in flight, once per array):
-//  * ld_raw issues one 16-byte load per lane, always: the group [e, e+4) of
-//    the window at element wbase of an array of N >= 4 elements, or, for a
-//    group that runs past the array's end, the array's last four elements;
+// Window loads are split in two so that no lane ever writes a register
+// that a load in flight targets (a wave that straddles an instance boundary
+// would otherwise have to drain every load it has in flight, once per
+// array):
+//  * ld_raw issues one 16-byte load for a lane whose group [e, e+4) meets
+//    the window's [lo, hi) -- the group of the window at element wbase of an
+//    array of N >= 4 elements, or, for a group that runs past the array's
+//    end, the array's last four elements -- and leaves the other lanes'
+//    registers undefined (no fill is written at load time, and no byte of
+//    another instance is fetched);
 //  * win_fix, applied where the data is first used (the loads have landed
 //    by then anyway), shifts that last group into place and replaces the
-//    elements outside the window's [lo, hi) by `fill`.
+//    elements outside [lo, hi) by `fill`.
 template <class V, class S>
-__device__ __forceinline__ V ld_raw(const S *__restrict__ arr, int64_t N, int64_t wbase, int e) {
-  const int64_t i0 = wbase + e;
-  return *reinterpret_cast<const V *>(arr + (i0 + 4 <= N ? i0 : N - 4));
+__device__ __forceinline__ V ld_raw(const S *__restrict__ arr, int64_t N, int64_t wbase, int e,
+                                    int lo, int hi) {
+  V v;
+  if (e + 4 > lo && e < hi) {
+    const int64_t i0 = wbase + e;
+    v = *reinterpret_cast<const V *>(arr + (i0 + 4 <= N ? i0 : N - 4));
+  }
+  return v;
 }
 
 // which of the group's four elements [e, e+4) lie in the window's [lo, hi)
@@ -210,9 +218,9 @@ __global__ __launch_bounds__(TH) void k_seg_fwd(SegFwdArgs a) {
 #pragma unroll
     for (int g = 0; g < K; ++g) {
       const int e = g * TH * EPL + tid * EPL;
-      ca[g] = ld_raw<float4>(a.a, a.n, it.wbase, e);
-      cb[g] = ld_raw<float4>(a.b, a.n, it.wbase, e);
-      ci[g] = ld_raw<int4>(a.idx, a.n, it.wbase, e);
+      ca[g] = ld_raw<float4>(a.a, a.n, it.wbase, e, it.lo_r, it.hi_r);
+      cb[g] = ld_raw<float4>(a.b, a.n, it.wbase, e, it.lo_r, it.hi_r);
+      ci[g] = ld_raw<int4>(a.idx, a.n, it.wbase, e, it.lo_r, it.hi_r);
     }
   };
   int64_t i = blockIdx.x;  // the item whose outputs are pending
@@ -472,10 +480,10 @@ __global__ __launch_bounds__(TH) void k_seg_bwd(SegBwdArgs a) {
 #pragma unroll
     for (int g = 0; g < K; ++g) {
       const int e = g * TH * EPL + tid * EPL;
-      B.a[g] = ld_raw<float4>(a.a, a.n, it.wbase, e);
-      B.y[g] = ld_raw<float4>(a.y, a.n, it.wbase, e);
-      B.yb[g] = ld_raw<float4>(a.ybar, a.n, it.wbase, e);
-      B.ix[g] = ld_raw<int4>(a.idx, a.n, it.wbase, e);
+      B.a[g] = ld_raw<float4>(a.a, a.n, it.wbase, e, it.lo_r, it.hi_r);
+      B.y[g] = ld_raw<float4>(a.y, a.n, it.wbase, e, it.lo_r, it.hi_r);
+      B.yb[g] = ld_raw<float4>(a.ybar, a.n, it.wbase, e, it.lo_r, it.hi_r);
+      B.ix[g] = ld_raw<int4>(a.idx, a.n, it.wbase, e, it.lo_r, it.hi_r);
       // element e-1 lies in the instance iff its instance index is >= 0 and
       // it is before the instance's end in this window
       B.yp0[g] = 0.0f;
