@@ -469,26 +469,25 @@ __global__ __launch_bounds__(TH) void k_seg_bwd(SegBwdArgs a) {
   const int64_t G = gridDim.x;
   if (tid == 0) s_epoch = ctl_load(&a.ctl->epoch);
 
+  // what the scan of an item reads: raw window loads, fixed where first used
   struct Buf {
-    float4 a[K], y[K], yb[K];  // raw window loads (fixed where first used)
+    float4 a[K], yb[K];
     int4 ix[K];
-    float yp0[K];  // lane 0: y of the element before the lane's group (0 at an instance start)
     int32_t ak[TPT];
     float hb[TPT];
   };
-  auto load = [&](const SegItem &it, Buf &B) {
-#pragma unroll
-    for (int g = 0; g < K; ++g) {
-      const int e = g * TH * EPL + tid * EPL;
-      B.a[g] = ld_raw<float4>(a.a, a.n, it.wbase, e, it.lo_r, it.hi_r);
-      B.y[g] = ld_raw<float4>(a.y, a.n, it.wbase, e, it.lo_r, it.hi_r);
-      B.yb[g] = ld_raw<float4>(a.ybar, a.n, it.wbase, e, it.lo_r, it.hi_r);
-      B.ix[g] = ld_raw<int4>(a.idx, a.n, it.wbase, e, it.lo_r, it.hi_r);
-      // element e-1 lies in the instance iff its instance index is >= 0 and
-      // it is before the instance's end in this window
-      B.yp0[g] = 0.0f;
-      if (lane == 0 && it.wofs + e - 1 >= 0 && e - 1 < it.hi_r) B.yp0[g] = a.y[it.wbase + e - 1];
-    }
+  // what only its sweep reads: the forward output
+  struct YBuf {
+    float4 y[K];
+    float yp0[K];  // lane 0: y of the element before the lane's group (0 at an instance start)
+  };
+  auto load_grp = [&](const SegItem &it, Buf &B, int g) {
+    const int e = g * TH * EPL + tid * EPL;
+    B.a[g] = ld_raw<float4>(a.a, a.n, it.wbase, e, it.lo_r, it.hi_r);
+    B.yb[g] = ld_raw<float4>(a.ybar, a.n, it.wbase, e, it.lo_r, it.hi_r);
+    B.ix[g] = ld_raw<int4>(a.idx, a.n, it.wbase, e, it.lo_r, it.hi_r);
+  };
+  auto load_bins = [&](const SegItem &it, Buf &B) {
     const int64_t hb = it.s * a.m;
 #pragma unroll
     for (int r = 0; r < TPT; ++r) {
@@ -499,52 +498,58 @@ __global__ __launch_bounds__(TH) void k_seg_bwd(SegBwdArgs a) {
       B.hb[r] = a.hbar[hb + kc];
     }
   };
+  auto load_y = [&](const SegItem &it, YBuf &Y) {
+#pragma unroll
+    for (int g = 0; g < K; ++g) {
+      const int e = g * TH * EPL + tid * EPL;
+      Y.y[g] = ld_raw<float4>(a.y, a.n, it.wbase, e, it.lo_r, it.hi_r);
+      // element e-1 lies in the instance iff its instance index is >= 0 and
+      // it is before the instance's end in this window
+      Y.yp0[g] = 0.0f;
+      if (lane == 0 && it.wofs + e - 1 >= 0 && e - 1 < it.hi_r) Y.yp0[g] = a.y[it.wbase + e - 1];
+    }
+  };
   auto item_of = [&](int64_t kk) { return a.nitems - 1 - kk; };
 
-  int64_t k = blockIdx.x;
-  SegItem it = seg_item(a.tab, item_of(k));
-  Buf cur;
-  load(it, cur);
-  __syncthreads();
-  const uint32_t tag = next_tag(s_epoch);
-
+  uint32_t tag = 0;  // this launch's tag, set once the epoch has been read
   MT mincl[K];
   MT agg = M::id();        // wave 0: map aggregate of the current item
   MT prev_incl = M::id();  // wave 0: carry into the block's previous item, combined with it
 
-  // scans the item in `cur` (its bin entries already in LDS)
-  auto phase1 = [&](const SegItem &jt, int64_t item) {
+  // Scans the item in B (its bin entries already in LDS).  After each group,
+  // `after(g)` may issue that group's loads for a later item.
+  auto phase1 = [&](const SegItem &jt, int64_t item, Buf &B, auto &&after) {
     const bool tail = jt.wbase + SEG_T > a.n;
 #pragma unroll
     for (int g = 0; g < K; ++g) {
       const int e = g * TH * EPL + tid * EPL;
       const WinMask wm = win_mask(e, jt.lo_r, jt.hi_r);
-      cur.a[g] = win_fix(cur.a[g], wm, tail, a.n, jt.wbase, e, 1.0f);
-      cur.yb[g] = win_fix(cur.yb[g], wm, tail, a.n, jt.wbase, e, 0.0f);
-      cur.ix[g] = win_fix(cur.ix[g], wm, tail, a.n, jt.wbase, e, -1);
-    }
-#pragma unroll
-    for (int g = 0; g < K; ++g) {
-      const int e = g * TH * EPL + tid * EPL;
+      const float4 av = win_fix(B.a[g], wm, tail, a.n, jt.wbase, e, 1.0f);
+      float4 ybv = win_fix(B.yb[g], wm, tail, a.n, jt.wbase, e, 0.0f);
+      const int4 ixv = win_fix(B.ix[g], wm, tail, a.n, jt.wbase, e, -1);
       // the group's four bin records, read together (one LDS round trip)
       int2 bv[EPL];
 #pragma unroll
       for (int j = 0; j < EPL; ++j) {
-        const int kb = i4get(cur.ix[g], j);
+        const int kb = i4get(ixv, j);
         bv[j] = s_bin[(unsigned)kb < (unsigned)a.m ? kb : 0];
       }
       MT acc = M::id();
 #pragma unroll
       for (int j = EPL - 1; j >= 0; --j) {
         // y_bar_total = y_bar + h_bar at the bin's argmin (fused min-by-index adjoint)
-        const int kb = i4get(cur.ix[g], j);
+        const int kb = i4get(ixv, j);
         const bool hit = (unsigned)kb < (unsigned)a.m && bv[j].x == jt.wofs + e + j;
-        const float y0 = f4get(cur.yb[g], j);
-        f4set(cur.yb[g], j, hit ? y0 + __int_as_float(bv[j].y) : y0);
-        const float yb[2] = {f4get(cur.yb[g], j), 0.0f};
-        const MT hm = A::make(FT{{1.0f, 0.0f}}, FT{{f4get(cur.a[g], j), 0.0f}}, yb, false);
+        const float y0 = f4get(ybv, j);
+        f4set(ybv, j, hit ? y0 + __int_as_float(bv[j].y) : y0);
+        const float yb[2] = {f4get(ybv, j), 0.0f};
+        const MT hm = A::make(FT{{1.0f, 0.0f}}, FT{{f4get(av, j), 0.0f}}, yb, false);
         acc = (j == EPL - 1) ? hm : M::comb(acc, hm);
       }
+      // the sweep reads the fixed values
+      B.a[g] = av;
+      B.yb[g] = ybv;
+      after(g);
       mincl[g] = wave_scan_rev<M>(acc);
       if (lane == 0) s_mtot[g][wave] = mincl[g];
     }
@@ -568,20 +573,37 @@ __global__ __launch_bounds__(TH) void k_seg_bwd(SegBwdArgs a) {
     }
   };
 
-  put_bins(cur);
+  // Two register buffers alternate roles: `cur` holds the scanned item k,
+  // `nxt` the loads of item k+G.  Once item k is swept, the loads of item
+  // k+2G go into `cur` a group at a time while item k+G is scanned, so the
+  // memory requests of the next items are in flight through the scan, the
+  // look-back and the sweep, and no wave stalls issuing a whole item's loads
+  // at once.  The loop is unrolled by two so that no register of a load in
+  // flight is ever copied.  The forward output y, which only the sweep
+  // reads, has one buffer of its own, loaded for item k+G as soon as item k
+  // is swept.
+  int64_t k = blockIdx.x;
+  SegItem it = seg_item(a.tab, item_of(k));
+  Buf b0, b1;
+  YBuf yv;
+#pragma unroll
+  for (int g = 0; g < K; ++g) load_grp(it, b0, g);
+  load_bins(it, b0);
   __syncthreads();
-  phase1(it, item_of(k));
-  for (;;) {
-    const int64_t item = item_of(k);
-    const int64_t kn = k + G;
-    const bool more = kn < a.nitems;
-    SegItem nt = it;
-    Buf nxt;
-    if (more) {
-      nt = seg_item(a.tab, item_of(kn));
-      load(nt, nxt);
-    }
+  tag = next_tag(s_epoch);
+  put_bins(b0);
+  __syncthreads();
+  SegItem nt = it;
+  const bool has1 = k + G < a.nitems;
+  if (has1) nt = seg_item(a.tab, item_of(k + G));
+  phase1(it, item_of(k), b0, [&](int g) {
+    if (has1) load_grp(nt, b1, g);
+  });
+  if (has1) load_bins(nt, b1);
+  load_y(it, yv);
 
+  auto step = [&](Buf &cur, Buf &nxt) -> bool {
+    const int64_t item = item_of(k);
     if (wave == 0) {
       MT c = M::from_pre(M::P{{0.0f}});
       const int dist_max = it.nli - 1 - it.li;
@@ -611,10 +633,10 @@ __global__ __launch_bounds__(TH) void k_seg_bwd(SegBwdArgs a) {
       if (lane == WAVE - 1) ex = M::id();
       M::P rho = M::apply0(M::comb(M::comb(carry, s_mpre[g][wave]), ex));
       const int e = g * TH * EPL + tid * EPL;
-      const float4 yg = win_fix(cur.y[g], win_mask(e, it.lo_r, it.hi_r), tail, a.n, it.wbase, e, 0.0f);
+      const float4 yg = win_fix(yv.y[g], win_mask(e, it.lo_r, it.hi_r), tail, a.n, it.wbase, e, 0.0f);
       // y_{i-1} of the four slots: the left neighbour's last y for the first
       float yprev0 = dpp_f<kDppWaveShr1>(yg.w);
-      if (lane == 0) yprev0 = cur.yp0[g];
+      if (lane == 0) yprev0 = yv.yp0[g];
       const float yprev[4] = {yprev0, yg.x, yg.y, yg.z};
       float4 oa, ob;
 #pragma unroll
@@ -628,14 +650,27 @@ __global__ __launch_bounds__(TH) void k_seg_bwd(SegBwdArgs a) {
       st_range(a.abar + it.wbase, e, it.lo_r, it.hi_r, oa);
       st_range(a.bbar + it.wbase, e, it.lo_r, it.hi_r, ob);
     }
-    if (!more) break;
-    k = kn;
-    it = nt;
-    cur = nxt;
+    if (k + G >= a.nitems) return false;
+    // the next item's forward output first (its sweep comes first)
+    load_y(nt, yv);
+    const bool has2 = k + 2 * G < a.nitems;
+    SegItem nnt = nt;
+    if (has2) nnt = seg_item(a.tab, item_of(k + 2 * G));
     __syncthreads();  // LDS of the finished item is rewritten below
-    put_bins(cur);
+    put_bins(nxt);
     __syncthreads();
-    phase1(it, item_of(k));
+    phase1(nt, item_of(k + G), nxt, [&](int g) {
+      if (has2) load_grp(nnt, cur, g);
+    });
+    if (has2) load_bins(nnt, cur);
+    k += G;
+    it = nt;
+    nt = nnt;
+    return true;
+  };
+  for (;;) {
+    if (!step(b0, b1)) break;
+    if (!step(b1, b0)) break;
   }
 }
 
