@@ -52,6 +52,7 @@ KERNEL_SOURCES = {
     "k_seg_bwd": ("batched.hip", "device.hpp", "adjoint.hpp"),
     "k_scan_vjp": ("scan.hip", "device.hpp", "adjoint.hpp"),
     "k_rbi_vjp": ("rbi.hip", "device.hpp"),
+    "k_part_scatter": ("rbi_part.hip", "device.hpp"),
     "k_md_vapply": ("matd.hip", "device.hpp"),
 }
 
