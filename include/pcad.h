@@ -533,6 +533,21 @@ int pcad_knob_get(const char *name, int64_t *value);
 int pcad_knob_set(const char *name, int64_t value);
 void pcad_knob_reset(void);
 
+/* ---------------------------------------------------------------------------
+ * Streaming copy (a measurement utility, not part of the method): copies
+ * `bytes` bytes from device memory `src` to device memory `dst` on `stream`
+ * (a hipStream_t; NULL for the null stream) with 16-byte nontemporal loads
+ * and stores.  A kernel that reads and writes every byte once cannot stream
+ * faster than this copy of the same bytes, so the benchmark reports its
+ * kernels' rates against it beside the HBM peak.  The caller owns both
+ * buffers; they must not overlap.
+ *   PCAD_OK at once for bytes == 0; PCAD_E_NULLPTR for a NULL pointer;
+ *   PCAD_E_MISALIGNED unless both pointers are 16-byte aligned;
+ *   PCAD_E_INVALID_ARG unless bytes is a multiple of 16; PCAD_E_HIP if the
+ *   launch fails.
+ * ------------------------------------------------------------------------- */
+int pcad_stream_copy(const void *src, void *dst, size_t bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

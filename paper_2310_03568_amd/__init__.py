@@ -92,6 +92,7 @@ def lib():
             "pcad_knob_get": ([ctypes.c_char_p, ctypes.POINTER(I64)], I),
             "pcad_knob_set": ([ctypes.c_char_p, I64], I),
             "pcad_knob_reset": ([], None),
+            "pcad_stream_copy": ([P, P, SZ, P], I),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -163,6 +164,19 @@ def set_knob(name: str, value: int):
 
 def reset_knobs():
     lib().pcad_knob_reset()
+
+
+def stream_copy(dst: torch.Tensor, src: torch.Tensor):
+    """dst <- src byte for byte with the library's streaming copy (both
+    contiguous device tensors of the same byte size, 16-byte aligned)."""
+    if not (src.is_cuda and dst.is_cuda and src.is_contiguous() and dst.is_contiguous()):
+        raise PcadError("stream_copy: contiguous device tensors required")
+    nb = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nb:
+        raise PcadError("stream_copy: byte sizes differ")
+    check(lib().pcad_stream_copy(_ptr(src), _ptr(dst), nb, _stream(src.device)),
+          "pcad_stream_copy")
+    return dst
 
 
 # ---------------------------------------------------------------------------

@@ -109,7 +109,7 @@ __device__ __forceinline__ V ld_raw(const S *__restrict__ arr, int64_t N, int64_
   V v;
   if (e + 4 > lo && e < hi) {
     const int64_t i0 = wbase + e;
-    v = *reinterpret_cast<const V *>(arr + (i0 + 4 <= N ? i0 : N - 4));
+    v = ld_stream<V>(arr + (i0 + 4 <= N ? i0 : N - 4));
   }
   return v;
 }

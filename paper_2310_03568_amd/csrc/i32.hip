@@ -180,7 +180,7 @@ __global__ __launch_bounds__(I_TH) void k_i32_apply(I32ScanArgs a) {
     // 16-byte loads (the row start and s0 are multiples of 4 elements)
 #pragma unroll
     for (int q = 0; q < I_EPT / 4; ++q) {
-      const int4 w = *reinterpret_cast<const int4 *>(xr + s0 + 4 * q);
+      const int4 w = ld_stream<int4>(xr + s0 + 4 * q);
       v[4 * q] = w.x; v[4 * q + 1] = w.y; v[4 * q + 2] = w.z; v[4 * q + 3] = w.w;
     }
   } else {

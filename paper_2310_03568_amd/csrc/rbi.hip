@@ -91,8 +91,8 @@ __device__ __forceinline__ void for_chunk(const RbiArgs &a, int64_t row, F &&f) 
   const bool vec_ok = ((row * a.n) & 3) == 0;
   for (int64_t i = lo + (int64_t)threadIdx.x * 4; i < hi; i += (int64_t)BLOCK * 4) {
     if (vec_ok && i + 4 <= hi) {
-      const int4 k4 = *reinterpret_cast<const int4 *>(ir + i);
-      const float4 v4 = *reinterpret_cast<const float4 *>(vr + i);
+      const int4 k4 = ld_stream<int4>(ir + i);
+      const float4 v4 = ld_stream<float4>(vr + i);
       f(k4.x, v4.x, (uint32_t)i);
       f(k4.y, v4.y, (uint32_t)(i + 1));
       f(k4.z, v4.z, (uint32_t)(i + 2));
@@ -379,10 +379,10 @@ __global__ __launch_bounds__(VJP_BIG_TH) void k_rbi_vjp_big(RbiVjpArgs a, int64_
     int kk[4];
     float vv[4] = {0.0f, 0.0f, 0.0f, 0.0f}, o[4];
     if (full) {
-      const int4 k4 = *reinterpret_cast<const int4 *>(ir + i);
+      const int4 k4 = ld_stream<int4>(ir + i);
       kk[0] = k4.x; kk[1] = k4.y; kk[2] = k4.z; kk[3] = k4.w;
       if (OP == SUMPROD) {
-        const float4 v4 = *reinterpret_cast<const float4 *>(vr + i);
+        const float4 v4 = ld_stream<float4>(vr + i);
         vv[0] = v4.x; vv[1] = v4.y; vv[2] = v4.z; vv[3] = v4.w;
       }
     } else {
@@ -476,10 +476,10 @@ __global__ __launch_bounds__(BLOCK) void k_rbi_vjp(RbiVjpArgs a) {
     int kk[4];
     float vv[4] = {1.0f, 1.0f, 1.0f, 1.0f}, o[4];
     if (full) {
-      const int4 k4 = *reinterpret_cast<const int4 *>(ir + i);
+      const int4 k4 = ld_stream<int4>(ir + i);
       kk[0] = k4.x; kk[1] = k4.y; kk[2] = k4.z; kk[3] = k4.w;
       if (OP == MUL || OP == SUMPROD) {
-        const float4 v4 = *reinterpret_cast<const float4 *>(vr + i);
+        const float4 v4 = ld_stream<float4>(vr + i);
         vv[0] = v4.x; vv[1] = v4.y; vv[2] = v4.z; vv[3] = v4.w;
       }
     } else {
@@ -606,8 +606,8 @@ __global__ __launch_bounds__(PARTS_TH) void k_rbi_parts(PartsArgs a) {
   };
   for (int64_t i = lo + (int64_t)threadIdx.x * 4; i < hi; i += (int64_t)PARTS_TH * 4) {
     if (i + 4 <= hi) {  // lo, chunk and the row start are multiples of 4
-      const int4 k4 = *reinterpret_cast<const int4 *>(a.idx + i);
-      const float4 v4 = *reinterpret_cast<const float4 *>(a.v + i);
+      const int4 k4 = ld_stream<int4>(a.idx + i);
+      const float4 v4 = ld_stream<float4>(a.v + i);
       upd(k4.x, v4.x, (uint32_t)i);
       upd(k4.y, v4.y, (uint32_t)(i + 1));
       upd(k4.z, v4.z, (uint32_t)(i + 2));

@@ -109,10 +109,10 @@ __device__ __forceinline__ uint32_t lds_count(uint32_t *cnt, uint32_t d, bool ok
 __device__ __forceinline__ void load4(const PartArgs &a, int64_t i, int64_t hi, bool with_v,
                                       int32_t k[4], float x[4]) {
   if (a.vec && i + 4 <= hi) {
-    const int4 k4 = *reinterpret_cast<const int4 *>(a.idx + i);
+    const int4 k4 = ld_stream<int4>(a.idx + i);
     k[0] = k4.x; k[1] = k4.y; k[2] = k4.z; k[3] = k4.w;
     if (with_v) {
-      const float4 v4 = *reinterpret_cast<const float4 *>(a.v + i);
+      const float4 v4 = ld_stream<float4>(a.v + i);
       x[0] = v4.x; x[1] = v4.y; x[2] = v4.z; x[3] = v4.w;
     }
   } else {

@@ -124,7 +124,7 @@ __global__ __launch_bounds__(BLOCK) void k_reduce_part(RedArgs a) {
   LV acc = Lift<OP>::id();
   for (int64_t i = lo + (int64_t)tid * 4; i < hi; i += (int64_t)BLOCK * 4) {
     if (vec_ok && i + 4 <= hi) {
-      const float4 v = *reinterpret_cast<const float4 *>(xr + i);
+      const float4 v = ld_stream<float4>(xr + i);
       acc = Lift<OP>::comb(acc, Lift<OP>::elem(v.x, (uint32_t)i));
       acc = Lift<OP>::comb(acc, Lift<OP>::elem(v.y, (uint32_t)(i + 1)));
       acc = Lift<OP>::comb(acc, Lift<OP>::elem(v.z, (uint32_t)(i + 2)));
@@ -227,7 +227,7 @@ __global__ __launch_bounds__(BLOCK) void k_reduce_vjp(const float *x, const void
     const bool full = vec_ok && i + 4 <= n;
     if (OP == MUL || OP == SUMPROD) {
       if (full) {
-        const float4 t = *reinterpret_cast<const float4 *>(xr + i);
+        const float4 t = ld_stream<float4>(xr + i);
         v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
       } else {
         for (int j = 0; j < 4; ++j) v[j] = (i + j < n) ? xr[i + j] : 1.0f;
