@@ -331,19 +331,22 @@ __device__ __forceinline__ V ld_stream(const void *p) {
 // group is whole and the address 16-byte aligned, one dwordx4 load;
 // otherwise element-wise loads of the valid part with `fill` elsewhere.
 // The tile's base pointer is block-uniform and the lane offset 32-bit, so
-// the address is a scalar base plus a vector offset.
-template <int S>
+// the address is a scalar base plus a vector offset.  NT: the nontemporal
+// hint, for groups whose lines no other load instruction reads (off where
+// lanes stride through lines that the next instructions read, as in
+// lane-major tiles, whose fetched bytes grew 10% with it).
+template <int S, bool NT = true>
 __device__ __forceinline__ float4 load_group(const float *__restrict__ p, int64_t base, int el,
                                              int valid, bool vec_ok, float4 fill) {
   const float *__restrict__ q = p + base * S;
   const unsigned o = (unsigned)el * S;
   if (valid >= 4 / S && (S == 4 || vec_ok)) {
-    return ld_stream<float4>(q + o);
+    return NT ? ld_stream<float4>(q + o) : *reinterpret_cast<const float4 *>(q + o);
   }
   float r[4] = {fill.x, fill.y, fill.z, fill.w};
   if (S == 4) {
     if (valid > 0) {
-      float4 t = ld_stream<float4>(q + o);
+      float4 t = NT ? ld_stream<float4>(q + o) : *reinterpret_cast<const float4 *>(q + o);
       r[0] = t.x; r[1] = t.y; r[2] = t.z; r[3] = t.w;
     }
   } else {

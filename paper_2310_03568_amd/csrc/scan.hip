@@ -300,13 +300,13 @@ __global__ __launch_bounds__(TH_) void k_scan_vjp(ScanVjpArgs a) {
       const int v = ti.valid - el;
 #pragma unroll
       for (int s = 0; s < NX; ++s)
-        buf[g][s] = load_group<S>(src[s], ti.base, el, v, ti.vec_ok, Io::fill(s));
-      buf[g][IYB] = load_group<S>(a.yb0, ti.base, el, v, ti.vec_ok, make_float4(0, 0, 0, 0));
+        buf[g][s] = load_group<S, !LM>(src[s], ti.base, el, v, ti.vec_ok, Io::fill(s));
+      buf[g][IYB] = load_group<S, !LM>(a.yb0, ti.base, el, v, ti.vec_ok, make_float4(0, 0, 0, 0));
       if (ABAR)
         buf[g][IAB] = load_group<1>(a.yb1, ti.base, el, v, ti.vec_ok, make_float4(0, 0, 0, 0));
 #pragma unroll
       for (int s = 0; s < NT; ++s) {
-        buf[g][IT + s] = load_group<S>(tp[s], ti.base, el, v, ti.vec_ok, tape_id(s));
+        buf[g][IT + s] = load_group<S, !LM>(tp[s], ti.base, el, v, ti.vec_ok, tape_id(s));
         float4 q = tape_id(s);
         if (lane == 0 && v > 0 && !(ti.lt == 0 && el == 0)) {
           const int64_t e = ti.base + el - 1;
