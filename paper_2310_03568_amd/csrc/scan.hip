@@ -646,6 +646,338 @@ __global__ __launch_bounds__(TH_) void k_scan_vjp(ScanVjpArgs a) {
   }
 }
 
+// The scan adjoint for group-major tiles (every operator but the 2x2
+// product) with a delayed look-back, as in the forward: a tile's look-back
+// runs one iteration after its map aggregate was published, once the block
+// has scanned its next tile, so the aggregates it needs (the other blocks'
+// tiles of the same round) have long been published when it polls, and the
+// predecessor at distance G is this block's previous tile, whose inclusive
+// prefix the block keeps: no persistent round waits on the publish-to-poll
+// latency of the round before.  Three register buffers rotate (the loop is
+// unrolled by three so that no register of a load in flight is copied): the
+// tile being swept, the tile being scanned, and the tile whose loads go out
+// a group at a time during that scan.  What a scanned tile leaves for its
+// sweep (per thread: the forward prefixes and the wave-inclusive map
+// aggregates; per wave: the block prefixes) waits in LDS, in two slots used
+// by alternate tiles.  The per-tile arithmetic is that of k_scan_vjp.
+template <int OP, bool ABAR, bool CKPT, int TH_>
+__global__ __launch_bounds__(TH_) void k_scan_vjp_d(ScanVjpArgs a) {
+  using Op = FwdLB<OP>;
+  using FT = typename Op::T;
+  using A = Adj<OP, ABAR>;
+  using M = typename A::M;
+  using MT = typename M::T;
+  using Io = IO<OP>;
+  using Sh = ShapeT<OP, TH_>;
+  constexpr int EPL = Sh::EPL, K = Sh::K, TILE = Sh::TILE;
+  constexpr int TH = Sh::THREADS, W = Sh::W;
+  constexpr int NIN = Io::NIN, S = Io::S, N = Fwd<OP>::N, NA = M::NA;
+  static_assert(!lane_major<OP, 1>() && IO<OP>::S == 1, "group-major tiles of scalar elements");
+  constexpr bool LM = false;
+  constexpr bool RECOMP = A::NEEDS_PREFIX && !CKPT;
+  constexpr bool TAPE = A::NEEDS_PREFIX && CKPT;
+  // streams per group: x...; y_bar; [A_bar]; [tape y; [tape A]]
+  constexpr int NX = (TAPE && OP == LINREC) ? 1 : NIN;
+  constexpr int IYB = NX, IAB = NX + 1, IT = NX + 1 + (ABAR ? 1 : 0);
+  constexpr int NT = TAPE ? ((OP == LINREC && ABAR) ? 2 : 1) : 0;
+  constexpr int NB = IT + NT;
+  constexpr int NTP = NT > 0 ? NT : 1;
+  using Buf = float4[K][NB];
+  using PBuf = float4[K][NTP];
+
+  __shared__ FT s_ftot[RECOMP ? K : 1][W];
+  __shared__ FT s_fpre[RECOMP ? K : 1][W];
+  __shared__ MT s_mtot[K][W];
+  __shared__ MT s_mpre[2][K][W];
+  // per-thread state of a scanned tile, component-major so that a wave's
+  // accesses are consecutive words
+  __shared__ float s_thr[2][RECOMP ? K * N : 1][TH];
+  __shared__ float s_minc[2][K * NA][TH];
+  __shared__ MT s_carry;
+  __shared__ unsigned s_epoch;
+
+  const int tid = threadIdx.x, lane = lane_id(), wave = tid / WAVE;
+  const int64_t G = gridDim.x;
+  const float *src[2] = {a.x0, a.x1};
+  const float *tp[2] = {a.tp0, a.tp1};
+  // tape value before a row's first element: the neutral prefix component
+  auto tape_id = [&](int s) -> float4 {
+    const FT e = Op::id();
+    const float v = (OP == LINREC) ? (s == 0 ? e.f[1] : e.f[0]) : e.f[0];
+    return make_float4(v, v, v, v);
+  };
+  // group g of tile ti; pv: for lane 0 only, the tape element just before
+  // the group (the other lanes take it from their left neighbour)
+  auto load_grp = [&](const TileInfo &ti, Buf &buf, PBuf &pv, int g) {
+    const int el = group_el<LM, K, TH, EPL>(g, tid);
+    const int v = ti.valid - el;
+#pragma unroll
+    for (int s = 0; s < NX; ++s)
+      buf[g][s] = load_group<S>(src[s], ti.base, el, v, ti.vec_ok, Io::fill(s));
+    buf[g][IYB] = load_group<S>(a.yb0, ti.base, el, v, ti.vec_ok, make_float4(0, 0, 0, 0));
+    if (ABAR)
+      buf[g][IAB] = load_group<1>(a.yb1, ti.base, el, v, ti.vec_ok, make_float4(0, 0, 0, 0));
+#pragma unroll
+    for (int s = 0; s < NT; ++s) {
+      buf[g][IT + s] = load_group<S>(tp[s], ti.base, el, v, ti.vec_ok, tape_id(s));
+      float4 q = tape_id(s);
+      if (lane == 0 && v > 0 && !(ti.lt == 0 && el == 0)) q.x = tp[s][ti.base + el - 1];
+      pv[g][s] = q;
+    }
+  };
+  auto ybar_of = [&](const Buf &buf, int g, int j, float *yb) {
+    yb[0] = f4get(buf[g][IYB], j);
+    yb[1] = ABAR ? f4get(buf[g][IAB], j) : 0.0f;
+  };
+  auto x_of = [&](const Buf &buf, int g, int j) -> FT {
+    float4 in[NIN];
+#pragma unroll
+    for (int s = 0; s < NIN; ++s) in[s] = s < NX ? buf[g][s] : Io::fill(s);
+    return Io::elem(in, j);
+  };
+  // the forward prefixes rs_{i-1} of the EPL slots of group g, ascending;
+  // thr: the forward prefix before the thread's group (recompute)
+  auto prefixes = [&](const Buf &cur, const PBuf &cpv, const FT &thr, int g, FT (&p)[EPL]) {
+    if (TAPE) {
+      float prev[2][4];
+#pragma unroll
+      for (int s = 0; s < NT; ++s) {
+        const float4 q = cur[g][IT + s];
+        float w = dpp_f<kDppWaveShr1>(q.w);
+        if (lane == 0) w = cpv[g][s].x;
+        prev[s][0] = w; prev[s][1] = q.x; prev[s][2] = q.y; prev[s][3] = q.z;
+      }
+#pragma unroll
+      for (int j = 0; j < EPL; ++j) {
+        if (OP == LINREC) {
+          p[j].f[0] = NT == 2 ? prev[NT - 1][j] : 1.0f;  // A_{i-1}: read only with A_bar
+          p[j].f[1] = prev[0][j];
+        } else {
+          p[j].f[0] = prev[0][j];
+        }
+      }
+    } else {
+      FT acc = thr;
+#pragma unroll
+      for (int j = 0; j < EPL; ++j) {
+        p[j] = acc;
+        if (RECOMP && j + 1 < EPL) acc = Op::comb(acc, x_of(cur, g, j));
+      }
+    }
+  };
+
+  if (tid == 0) s_epoch = ctl_load(&a.ctl->epoch);
+  int64_t k = blockIdx.x;
+  uint32_t tag = 0;  // this launch's tag, set once the epoch has been read
+  auto tile_of = [&](int64_t kk) { return a.ntiles - 1 - kk; };  // right to left
+
+  // Scans tile kk (data in cur) up to the wave level: forward prefixes
+  // (recompute) and the adjoint maps' wave scans, kept in LDS slot sl, and
+  // the wave totals in s_mtot.  after(g) runs once group g's data has been
+  // read for the last time before the sweep.  The block level follows in
+  // `resolve`.
+  auto phase1 = [&](int64_t kk, const Buf &cur, const PBuf &cpv, int sl, auto &&after) {
+    const TileInfo ti = tile_info(tile_of(kk), a.n, a.tpr, TILE);
+    FT thr[K];
+    if (RECOMP) {
+      FT fincl[K];
+#pragma unroll
+      for (int g = 0; g < K; ++g) {
+        FT acc = x_of(cur, g, 0);
+#pragma unroll
+        for (int j = 1; j < EPL; ++j) acc = Op::comb(acc, x_of(cur, g, j));
+        fincl[g] = wave_scan_fwd<Op>(acc);
+        if (lane == WAVE - 1) s_ftot[g][wave] = fincl[g];
+      }
+      __syncthreads();
+      if (wave == 0) {
+        FT c;
+#pragma unroll
+        for (int i = 0; i < N; ++i) c.f[i] = a.saved[ti.tile * N + i];
+        wave0_block_prefix<Op, K, W, false>(s_ftot, s_fpre, c);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int g = 0; g < K; ++g) {
+        FT ex = shift_up1(fincl[g]);
+        if (lane == 0) ex = Op::id();
+        thr[g] = Op::comb(s_fpre[g][wave], ex);
+#pragma unroll
+        for (int i = 0; i < N; ++i) s_thr[sl][g * N + i][tid] = thr[g].f[i];
+      }
+    } else {
+#pragma unroll
+      for (int g = 0; g < K; ++g) thr[g] = Op::id();
+    }
+    // adjoint maps: thread aggregate per group = h_0 o h_1 o ... o h_{EPL-1}
+#pragma unroll
+    for (int g = 0; g < K; ++g) {
+      FT p[EPL];
+      prefixes(cur, cpv, thr[g], g, p);
+      MT acc = M::id();
+#pragma unroll
+      for (int j = EPL - 1; j >= 0; --j) {
+        float yb[4];
+        ybar_of(cur, g, j, yb);
+        const bool first = ti.lt == 0 && g == 0 && tid == 0 && j == 0;
+        const MT h = A::make(p[j], x_of(cur, g, j), yb, first);
+        acc = (j == EPL - 1) ? h : M::comb(acc, h);
+      }
+      after(g);
+      const MT mi = wave_scan_rev<M>(acc);
+#pragma unroll
+      for (int i = 0; i < NA; ++i) s_minc[sl][g * NA + i][tid] = mi.f[i];
+      if (lane == 0) s_mtot[g][wave] = mi;
+    }
+  };
+
+  // wave 0: the block prefix of scanned tile kk into slot sl, and the
+  // publication of its aggregate (a row's last tile: its inclusive prefix)
+  auto block_level = [&](int64_t kk, int sl) -> MT {
+    const TileInfo ti = tile_info(tile_of(kk), a.n, a.tpr, TILE);
+    const MT agg = wave0_block_prefix<M, K, W, true>(s_mtot, s_mpre[sl], M::id());
+    uint64_t *st = a.status + ti.tile * (M::NA + M::NP);
+    if (lane == 0) {
+      if (ti.lt == a.tpr - 1) {
+        typename M::P zero;
+#pragma unroll
+        for (int i = 0; i < M::NP; ++i) zero.f[i] = 0.0f;
+        publish<M::NP>(st + M::NA, tag, M::apply0(M::comb(M::from_pre(zero), agg)));
+      } else {
+        publish<M::NA>(st, tag, agg);
+      }
+    }
+    return agg;
+  };
+
+  MT prev_incl = M::id();  // wave 0: inclusive prefix of the block's previous tile
+  // Wave 0: the block level of the scanned tile kp (if `scanned`), then the
+  // look-back of the pending tile ks, whose inclusive prefix is published.
+  auto resolve = [&](int64_t ks, const MT &agg_s, bool scanned, int64_t kp, MT &agg_p, int slp) {
+    __syncthreads();
+    if (wave == 0) {
+      if (scanned) agg_p = block_level(kp, slp);
+      const TileInfo ti = tile_info(tile_of(ks), a.n, a.tpr, TILE);
+      typename M::P zero;
+#pragma unroll
+      for (int i = 0; i < M::NP; ++i) zero.f[i] = 0.0f;
+      MT c = M::from_pre(zero);
+      const int dist_max = a.tpr - 1 - ti.lt;
+      if (dist_max > 0) {
+        // successors at distances 1..G-1 belong to other blocks; the one at
+        // distance G is this block's previous tile, in the same row
+        const int win = dist_max < G ? dist_max : (int)(G - 1);
+        bool hit = false;
+        if (win > 0) c = lookback<M>(a.status, ti.tile, -1, win, tag, a.ctl, &hit);
+        if (!hit) c = win > 0 ? M::comb(prev_incl, c) : prev_incl;
+        if (lane == 0)
+          publish<M::NP>(a.status + ti.tile * (M::NA + M::NP) + M::NA, tag,
+                         M::apply0(M::comb(c, agg_s)));
+      }
+      prev_incl = M::from_pre(M::apply0(M::comb(c, agg_s)));
+      if (lane == 0) {
+        s_carry = c;
+        if (ti.lt == 0) ctl_row_done(a.ctl, (unsigned)(a.ntiles / a.tpr), tag);
+      }
+    }
+    __syncthreads();
+  };
+
+  // thread-serial sweep of tile ks (state in slot sl), right to left
+  auto sweep = [&](int64_t ks, const Buf &cur, const PBuf &cpv, int sl) {
+    const TileInfo ti = tile_info(tile_of(ks), a.n, a.tpr, TILE);
+    const MT carry = s_carry;
+#pragma unroll
+    for (int g = 0; g < K; ++g) {
+      MT mi;
+#pragma unroll
+      for (int i = 0; i < NA; ++i) mi.f[i] = s_minc[sl][g * NA + i][tid];
+      FT thr = Op::id();
+      if (RECOMP) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) thr.f[i] = s_thr[sl][g * N + i][tid];
+      }
+      MT ex = shift_down1(mi);
+      if (lane == WAVE - 1) ex = M::id();
+      typename M::P rho = M::apply0(M::comb(M::comb(carry, s_mpre[sl][g][wave]), ex));
+      FT p[EPL];
+      prefixes(cur, cpv, thr, g, p);
+      float4 o[2];
+      o[0] = make_float4(0, 0, 0, 0);
+      o[1] = make_float4(0, 0, 0, 0);
+#pragma unroll
+      for (int j = EPL - 1; j >= 0; --j) {
+        float yb[4];
+        ybar_of(cur, g, j, yb);
+        const bool first = ti.lt == 0 && g == 0 && tid == 0 && j == 0;
+        float xb[4];
+        A::step(p[j], x_of(cur, g, j), yb, first, rho, xb);
+        f4set(o[0], j, xb[0]);
+        if (A::NXB == 2) f4set(o[1], j, xb[1]);
+      }
+      const int el = group_el<LM, K, TH, EPL>(g, tid);
+      const int v = ti.valid - el;
+      float *dst[2] = {a.xb0, a.xb1};
+#pragma unroll
+      for (int s = 0; s < A::NXB; ++s) {
+        float4 val = o[s];
+        if (a.accumulate) {
+          const float4 old = load_group<S>(dst[s], ti.base, el, v, ti.vec_ok, make_float4(0, 0, 0, 0));
+          val.x += old.x; val.y += old.y; val.z += old.z; val.w += old.w;
+        }
+        store_group<S>(dst[s], ti.base, el, v, ti.vec_ok, val);
+      }
+    }
+  };
+
+  Buf b0, b1, b2;
+  PBuf p0, p1, p2;
+  MT g0 = M::id(), g1 = M::id(), g2 = M::id();  // wave 0: map aggregates
+  int sl = 0;  // LDS slot of the tile being swept
+  {
+    const TileInfo ti = tile_info(tile_of(k), a.n, a.tpr, TILE);
+#pragma unroll
+    for (int g = 0; g < K; ++g) load_grp(ti, b0, p0, g);
+  }
+  __syncthreads();
+  tag = next_tag(s_epoch);
+  {
+    const bool has1 = k + G < a.ntiles;
+    const TileInfo t1 = tile_info(tile_of(has1 ? k + G : k), a.n, a.tpr, TILE);
+    phase1(k, b0, p0, 0, [&](int g) {
+      if (has1) load_grp(t1, b1, p1, g);
+    });
+    // the first tile's block level; nothing is pending yet
+    __syncthreads();
+    if (wave == 0) g0 = block_level(k, 0);
+  }
+
+  // S: tile k, scanned (state in slot sl); P: tile k+G, loaded (or
+  // loading); L: free
+  auto step = [&](Buf &bs, PBuf &ps, MT &gs, Buf &bp, PBuf &pp, MT &gp, Buf &bl,
+                  PBuf &pl) -> bool {
+    const bool scan = k + G < a.ntiles;
+    if (scan) {
+      const bool has2 = k + 2 * G < a.ntiles;
+      const TileInfo t2 = tile_info(tile_of(has2 ? k + 2 * G : k), a.n, a.tpr, TILE);
+      phase1(k + G, bp, pp, sl ^ 1, [&](int g) {
+        if (has2) load_grp(t2, bl, pl, g);
+      });
+    }
+    resolve(k, gs, scan, k + G, gp, sl ^ 1);
+    sweep(k, bs, ps, sl);
+    if (!scan) return false;
+    k += G;
+    sl ^= 1;
+    return true;
+  };
+  for (;;) {
+    if (!step(b0, p0, g0, b1, p1, g1, b2, p2)) break;
+    if (!step(b1, p1, g1, b2, p2, g2, b0, p0)) break;
+    if (!step(b2, p2, g2, b0, p0, g0, b1, p1)) break;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
@@ -713,10 +1045,20 @@ static hipError_t launch_fwd(const ScanFwdArgs &a, hipStream_t s) {
 template <int OP, bool ABAR, bool CKPT, int TH>
 static hipError_t launch_vjp_t(const ScanVjpArgs &a, hipStream_t s) {
   static int64_t cap = 0;
-  if (cap == 0) cap = resident_blocks(k_scan_vjp<OP, ABAR, CKPT, TH>, TH);
-  if (cap == 0) return hipErrorInvalidDevice;
-  const int64_t grid = a.ntiles < cap ? a.ntiles : cap;
-  hipLaunchKernelGGL((k_scan_vjp<OP, ABAR, CKPT, TH>), dim3((unsigned)grid), dim3(TH), 0, s, a);
+  // the delayed form holds three tiles in registers: not for the 2x2
+  // product's lane-major tiles, nor for the recurrence with the adjoint of
+  // its cumulative product, whose four input streams would spill
+  if constexpr (lane_major<OP, 1>() || ABAR) {
+    if (cap == 0) cap = resident_blocks(k_scan_vjp<OP, ABAR, CKPT, TH>, TH);
+    if (cap == 0) return hipErrorInvalidDevice;
+    const int64_t grid = a.ntiles < cap ? a.ntiles : cap;
+    hipLaunchKernelGGL((k_scan_vjp<OP, ABAR, CKPT, TH>), dim3((unsigned)grid), dim3(TH), 0, s, a);
+  } else {
+    if (cap == 0) cap = resident_blocks(k_scan_vjp_d<OP, ABAR, CKPT, TH>, TH);
+    if (cap == 0) return hipErrorInvalidDevice;
+    const int64_t grid = a.ntiles < cap ? a.ntiles : cap;
+    hipLaunchKernelGGL((k_scan_vjp_d<OP, ABAR, CKPT, TH>), dim3((unsigned)grid), dim3(TH), 0, s, a);
+  }
   return hipGetLastError();
 }
 
