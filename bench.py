@@ -53,6 +53,8 @@ METRIC = "backward elems/s + % HBM peak, batched vs per-segment, at 1e-5 rel err
 KERNEL_SOURCES = {
     "k_seg_bwd": ("batched.hip", "device.hpp", "adjoint.hpp"),
     "k_scan_vjp": ("scan.hip", "device.hpp", "adjoint.hpp"),
+    "k_scan_vjp_d": ("scan.hip", "device.hpp", "adjoint.hpp"),
+    "k_scan_vjp_m2d": ("scan.hip", "device.hpp", "adjoint.hpp"),
     "k_rbi_vjp": ("rbi.hip", "device.hpp"),
     "k_part_scatter": ("rbi_part.hip", "device.hpp"),
     "k_md_vapply": ("matd.hip", "device.hpp"),
@@ -104,7 +106,7 @@ def bench_linrec(args, pcad, torch, np):
     # algorithmic bytes: fwd reads a, b and writes y; adjoint reads a, b,
     # ybar and writes a_bar, b_bar (the forward prefixes are recomputed)
     return dict(n=n, fwd=fwd, bwd=bwd, bytes_fwd=12 * n, bytes_bwd=20 * n,
-                kernel="k_scan_vjp<LINREC>", inputs=w,
+                kernel="k_scan_vjp_d<LINREC>", inputs=w,
                 out=lambda: (ab, bb), cfg={"workload": "linrec scan, n=2^26, fp32 (a~U[0.9,1), b~N(0,1))",
                                            "n": n, "op": "linrec", "combinator": "scan"})
 
@@ -125,7 +127,7 @@ def bench_mat2(args, pcad, torch, np):
         pcad.scan_vjp("mat2", M, None, saved, PB, out=(mb,))
 
     return dict(n=n, fwd=fwd, bwd=bwd, bytes_fwd=32 * n, bytes_bwd=48 * n,
-                kernel="k_scan_vjp<MAT2>", inputs=w, out=lambda: (mb,),
+                kernel="k_scan_vjp_m2d<MAT2>", inputs=w, out=lambda: (mb,),
                 cfg={"workload": "2x2 matrix-product scan, n=2^24, fp32 (entries ~N(0,0.5))",
                      "n": n, "op": "mat2", "combinator": "scan"})
 
@@ -399,7 +401,7 @@ def bench_vec(args, pcad, torch, np):
     # 2 x 8 B (forward) and 3 x 8 B (adjoint) per value on top
     per_bwd = 8 if op == "add" else 12
     return dict(n=N, fwd=fwd, bwd=bwd, bytes_fwd=8 * N, bytes_bwd=per_bwd * N,
-                kernel="k_scan_vjp<vec>", inputs={"x": x, "ybar": yb, "n": n, "d": d},
+                kernel="k_scan_vjp_d<vec>", inputs={"x": x, "ybar": yb, "n": n, "d": d},
                 out=lambda: (state["y"], xb),
                 cfg={"workload": f"vectorised scan ({op} over vectors of {d}), {n} rows, fp32",
                      "rows": n, "d": d, "op": op, "combinator": "scan (map2)"})
@@ -488,7 +490,7 @@ def bench_autograd(args, pcad, torch, np):
                 # histogram reads v, idx (+ 12 B per bin); backward: scan
                 # adjoint reads a, b, y_bar, writes a_bar, b_bar; v_bar one-hot
                 bytes_fwd=(12 + 8 + 8) * n, bytes_bwd=(20 + 8) * n,
-                kernel="k_scan_vjp<LINREC>", out=lambda: (a.grad, bb.grad, v.grad),
+                kernel="k_scan_vjp_d<LINREC>", out=lambda: (a.grad, bb.grad, v.grad),
                 cfg={"workload": f"autograd: {B} sequences x {T}, loss = sum log|linrec scan| + "
                                  f"sum of non-empty max-by-index ({m} bins), fwd+bwd, fp32, "
                                  f"saved state: {args.mode}",

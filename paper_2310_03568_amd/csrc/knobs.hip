@@ -31,7 +31,7 @@ Knob g_knobs[] = {
     {"scan.vjp.threads.min", 512, 256, 1024, true, 512},
     {"scan.vjp.threads.max", 512, 256, 1024, true, 512},
     {"scan.vjp.threads.linrec", 512, 256, 1024, true, 512},
-    {"scan.vjp.threads.mat2", 1024, 256, 1024, true, 1024},
+    {"scan.vjp.threads.mat2", 512, 256, 1024, true, 512},
     // bins up to which a block keeps a private LDS histogram (+ and *: float
     // values; min/max: 64-bit keys); above it, global atomics
     {"rbi.lds_max_bins_f32", 8192, 0, 8192, false, 8192},

@@ -978,6 +978,228 @@ __global__ __launch_bounds__(TH_) void k_scan_vjp_d(ScanVjpArgs a) {
   }
 }
 
+// The 2x2-product scan adjoint (recompute form) with the delayed look-back
+// of k_scan_vjp_d, on lane-major tiles: a thread's K groups are consecutive
+// elements (one serial pass and one wave scan each way per thread), three
+// register buffers rotate, and a scanned tile's state (per thread: the
+// forward prefix before its first element and its wave-inclusive map
+// aggregate; per wave: the block prefix) waits in two LDS slots.  The
+// per-tile arithmetic is that of k_scan_vjp.
+template <int TH_>
+__global__ __launch_bounds__(TH_) void k_scan_vjp_m2d(ScanVjpArgs a) {
+  constexpr int OP = MAT2;
+  using Op = FwdLB<OP>;
+  using FT = typename Op::T;
+  using A = Adj<OP, false>;
+  using M = typename A::M;
+  using MT = typename M::T;
+  using Sh = ShapeT<OP, TH_>;
+  constexpr int K = Sh::K, TILE = Sh::TILE, TH = Sh::THREADS, W = Sh::W;
+  constexpr int N = Fwd<OP>::N, NA = M::NA;
+  static_assert(Sh::EPL == 1 && lane_major<OP, 1>(), "lane-major 2x2 tiles");
+  struct Buf {
+    float4 x[K], yb[K];
+  };
+
+  __shared__ FT s_ftot[W];
+  __shared__ FT s_fpre[W];
+  __shared__ MT s_mtot[W];
+  __shared__ MT s_mpre[2][W];
+  __shared__ float s_thr[2][N][TH];
+  __shared__ float s_minc[2][NA][TH];
+  __shared__ MT s_carry;
+  __shared__ unsigned s_epoch;
+
+  const int tid = threadIdx.x, lane = lane_id(), wave = tid / WAVE;
+  const int64_t G = gridDim.x;
+  // group g of tile ti: element tid*K + g (plain loads: the lanes stride
+  // through lines that the next groups' loads read)
+  auto load_grp = [&](const TileInfo &ti, Buf &b, int g) {
+    const int el = group_el<true, K, TH, 1>(g, tid);
+    const int v = ti.valid - el;
+    b.x[g] = load_group<4, false>(a.x0, ti.base, el, v, true, make_float4(1, 0, 0, 1));
+    b.yb[g] = load_group<4, false>(a.yb0, ti.base, el, v, true, make_float4(0, 0, 0, 0));
+  };
+  auto xg = [&](const Buf &b, int g) -> FT { return FT{{b.x[g].x, b.x[g].y, b.x[g].z, b.x[g].w}}; };
+  auto ybg = [&](const Buf &b, int g, float *yb) {
+    yb[0] = b.yb[g].x; yb[1] = b.yb[g].y; yb[2] = b.yb[g].z; yb[3] = b.yb[g].w;
+  };
+
+  if (tid == 0) s_epoch = ctl_load(&a.ctl->epoch);
+  int64_t k = blockIdx.x;
+  uint32_t tag = 0;
+  auto tile_of = [&](int64_t kk) { return a.ntiles - 1 - kk; };  // right to left
+
+  // scans tile kk up to the wave level, state into LDS slot sl
+  auto phase1 = [&](int64_t kk, const Buf &cur, int sl, auto &&after) {
+    const TileInfo ti = tile_info(tile_of(kk), a.n, a.tpr, TILE);
+    FT acc = xg(cur, 0);
+#pragma unroll
+    for (int g = 1; g < K; ++g) acc = Op::comb(acc, xg(cur, g));
+    const FT fin = wave_scan_fwd<Op>(acc);
+    if (lane == WAVE - 1) s_ftot[wave] = fin;
+    __syncthreads();
+    if (wave == 0) {
+      FT c;
+#pragma unroll
+      for (int i = 0; i < N; ++i) c.f[i] = a.saved[ti.tile * N + i];
+      wave0_block_prefix<Op, 1, W, false>(reinterpret_cast<FT (*)[W]>(s_ftot),
+                                          reinterpret_cast<FT (*)[W]>(s_fpre), c);
+    }
+    __syncthreads();
+    FT thr[K];
+    {
+      FT ex = shift_up1(fin);
+      if (lane == 0) ex = Op::id();
+      thr[0] = Op::comb(s_fpre[wave], ex);
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) s_thr[sl][i][tid] = thr[0].f[i];
+#pragma unroll
+    for (int g = 1; g < K; ++g) thr[g] = Op::comb(thr[g - 1], xg(cur, g - 1));
+    MT macc = M::id();
+#pragma unroll
+    for (int g = K - 1; g >= 0; --g) {
+      float yb[4];
+      ybg(cur, g, yb);
+      const MT h = A::make(thr[g], xg(cur, g), yb, false);
+      macc = (g == K - 1) ? h : M::comb(macc, h);
+      after(g);
+    }
+    const MT mi = wave_scan_rev<M>(macc);
+#pragma unroll
+    for (int i = 0; i < NA; ++i) s_minc[sl][i][tid] = mi.f[i];
+    if (lane == 0) s_mtot[wave] = mi;
+  };
+
+  auto block_level = [&](int64_t kk, int sl) -> MT {
+    const TileInfo ti = tile_info(tile_of(kk), a.n, a.tpr, TILE);
+    const MT agg = wave0_block_prefix<M, 1, W, true>(reinterpret_cast<MT (*)[W]>(s_mtot),
+                                                     reinterpret_cast<MT (*)[W]>(s_mpre[sl]),
+                                                     M::id());
+    uint64_t *st = a.status + ti.tile * (M::NA + M::NP);
+    if (lane == 0) {
+      if (ti.lt == a.tpr - 1) {
+        typename M::P zero;
+#pragma unroll
+        for (int i = 0; i < M::NP; ++i) zero.f[i] = 0.0f;
+        publish<M::NP>(st + M::NA, tag, M::apply0(M::comb(M::from_pre(zero), agg)));
+      } else {
+        publish<M::NA>(st, tag, agg);
+      }
+    }
+    return agg;
+  };
+
+  MT prev_incl = M::id();  // wave 0: inclusive prefix of the block's previous tile
+  auto resolve = [&](int64_t ks, const MT &agg_s, bool scanned, int64_t kp, MT &agg_p, int slp) {
+    __syncthreads();
+    if (wave == 0) {
+      if (scanned) agg_p = block_level(kp, slp);
+      const TileInfo ti = tile_info(tile_of(ks), a.n, a.tpr, TILE);
+      typename M::P zero;
+#pragma unroll
+      for (int i = 0; i < M::NP; ++i) zero.f[i] = 0.0f;
+      MT c = M::from_pre(zero);
+      const int dist_max = a.tpr - 1 - ti.lt;
+      if (dist_max > 0) {
+        const int win = dist_max < G ? dist_max : (int)(G - 1);
+        bool hit = false;
+        if (win > 0) c = lookback<M>(a.status, ti.tile, -1, win, tag, a.ctl, &hit);
+        if (!hit) c = win > 0 ? M::comb(prev_incl, c) : prev_incl;
+        if (lane == 0)
+          publish<M::NP>(a.status + ti.tile * (M::NA + M::NP) + M::NA, tag,
+                         M::apply0(M::comb(c, agg_s)));
+      }
+      prev_incl = M::from_pre(M::apply0(M::comb(c, agg_s)));
+      if (lane == 0) {
+        s_carry = c;
+        if (ti.lt == 0) ctl_row_done(a.ctl, (unsigned)(a.ntiles / a.tpr), tag);
+      }
+    }
+    __syncthreads();
+  };
+
+  // thread-serial sweep of tile ks from its last element; the thread's
+  // elements are stored together afterwards with ordinary stores, which L2
+  // merges into whole lines
+  auto sweep = [&](int64_t ks, const Buf &cur, int sl) {
+    const TileInfo ti = tile_info(tile_of(ks), a.n, a.tpr, TILE);
+    MT mi;
+#pragma unroll
+    for (int i = 0; i < NA; ++i) mi.f[i] = s_minc[sl][i][tid];
+    MT ex = shift_down1(mi);
+    if (lane == WAVE - 1) ex = M::id();
+    typename M::P rho = M::apply0(M::comb(M::comb(s_carry, s_mpre[sl][wave]), ex));
+    FT thr[K];
+#pragma unroll
+    for (int i = 0; i < N; ++i) thr[0].f[i] = s_thr[sl][i][tid];
+#pragma unroll
+    for (int g = 1; g < K; ++g) thr[g] = Op::comb(thr[g - 1], xg(cur, g - 1));
+    float4 o[K];
+#pragma unroll
+    for (int g = K - 1; g >= 0; --g) {
+      float yb[4], xb[4];
+      ybg(cur, g, yb);
+      A::step(thr[g], xg(cur, g), yb, false, rho, xb);
+      o[g] = make_float4(xb[0], xb[1], xb[2], xb[3]);
+    }
+#pragma unroll
+    for (int g = 0; g < K; ++g) {
+      const int el = group_el<true, K, TH, 1>(g, tid);
+      if (el >= ti.valid) break;
+      float4 *q = reinterpret_cast<float4 *>(a.xb0 + (ti.base + el) * 4);
+      float4 val = o[g];
+      if (a.accumulate) {
+        const float4 old = *q;
+        val.x += old.x; val.y += old.y; val.z += old.z; val.w += old.w;
+      }
+      *q = val;
+    }
+  };
+
+  Buf b0, b1, b2;
+  MT g0 = M::id(), g1 = M::id(), g2 = M::id();  // wave 0: map aggregates
+  int sl = 0;
+  {
+    const TileInfo ti = tile_info(tile_of(k), a.n, a.tpr, TILE);
+#pragma unroll
+    for (int g = 0; g < K; ++g) load_grp(ti, b0, g);
+  }
+  __syncthreads();
+  tag = next_tag(s_epoch);
+  {
+    const bool has1 = k + G < a.ntiles;
+    const TileInfo t1 = tile_info(tile_of(has1 ? k + G : k), a.n, a.tpr, TILE);
+    phase1(k, b0, 0, [&](int g) {
+      if (has1) load_grp(t1, b1, g);
+    });
+    __syncthreads();
+    if (wave == 0) g0 = block_level(k, 0);
+  }
+  auto step = [&](Buf &bs, MT &gs, Buf &bp, MT &gp, Buf &bl) -> bool {
+    const bool scan = k + G < a.ntiles;
+    if (scan) {
+      const bool has2 = k + 2 * G < a.ntiles;
+      const TileInfo t2 = tile_info(tile_of(has2 ? k + 2 * G : k), a.n, a.tpr, TILE);
+      phase1(k + G, bp, sl ^ 1, [&](int g) {
+        if (has2) load_grp(t2, bl, g);
+      });
+    }
+    resolve(k, gs, scan, k + G, gp, sl ^ 1);
+    sweep(k, bs, sl);
+    if (!scan) return false;
+    k += G;
+    sl ^= 1;
+    return true;
+  };
+  for (;;) {
+    if (!step(b0, g0, b1, g1, b2)) break;
+    if (!step(b1, g1, b2, g2, b0)) break;
+    if (!step(b2, g2, b0, g0, b1)) break;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
@@ -1045,10 +1267,15 @@ static hipError_t launch_fwd(const ScanFwdArgs &a, hipStream_t s) {
 template <int OP, bool ABAR, bool CKPT, int TH>
 static hipError_t launch_vjp_t(const ScanVjpArgs &a, hipStream_t s) {
   static int64_t cap = 0;
-  // the delayed form holds three tiles in registers: not for the 2x2
-  // product's lane-major tiles, nor for the recurrence with the adjoint of
-  // its cumulative product, whose four input streams would spill
-  if constexpr (lane_major<OP, 1>() || ABAR) {
+  // the delayed forms hold three tiles in registers: not for the 2x2
+  // product's checkpoint form, nor for the recurrence with the adjoint of
+  // its cumulative product, whose extra input streams would spill
+  if constexpr (OP == MAT2 && !CKPT) {
+    if (cap == 0) cap = resident_blocks(k_scan_vjp_m2d<TH>, TH);
+    if (cap == 0) return hipErrorInvalidDevice;
+    const int64_t grid = a.ntiles < cap ? a.ntiles : cap;
+    hipLaunchKernelGGL((k_scan_vjp_m2d<TH>), dim3((unsigned)grid), dim3(TH), 0, s, a);
+  } else if constexpr (lane_major<OP, 1>() || ABAR) {
     if (cap == 0) cap = resident_blocks(k_scan_vjp<OP, ABAR, CKPT, TH>, TH);
     if (cap == 0) return hipErrorInvalidDevice;
     const int64_t grid = a.ntiles < cap ? a.ntiles : cap;
