@@ -60,15 +60,16 @@ __global__ __launch_bounds__(TH_) void k_scan_fwd(ScanFwdArgs a) {
 
   const int tid = threadIdx.x, lane = lane_id(), wave = tid / WAVE;
   const float *src[2] = {a.x0, a.x1};
+  auto load_grp = [&](const TileInfo &ti, float4 (&buf)[K][NIN], int g) {
+    const int el = group_el<LM, K, TH, EPL>(g, tid);
+#pragma unroll
+    for (int s = 0; s < NIN; ++s)
+      buf[g][s] = load_group<S>(src[s], ti.base, el, ti.valid - el, ti.vec_ok, Io::fill(s));
+  };
   auto load = [&](int64_t t, float4 (&buf)[K][NIN]) {
     const TileInfo ti = tile_info(t, a.n, a.tpr, TILE);
 #pragma unroll
-    for (int g = 0; g < K; ++g) {
-      const int el = group_el<LM, K, TH, EPL>(g, tid);
-#pragma unroll
-      for (int s = 0; s < NIN; ++s)
-        buf[g][s] = load_group<S>(src[s], ti.base, el, ti.valid - el, ti.vec_ok, Io::fill(s));
-    }
+    for (int g = 0; g < K; ++g) load_grp(ti, buf, g);
   };
 
   if (tid == 0) s_epoch = ctl_load(&a.ctl->epoch);
@@ -82,8 +83,11 @@ __global__ __launch_bounds__(TH_) void k_scan_fwd(ScanFwdArgs a) {
   // Scans the tile in `cur`: thread-serial inclusive values (lc), the
   // exclusive prefix of each thread's group inside the tile (thr), and, in
   // wave 0, the tile aggregate (ag), which is published (a row's first tile
-  // publishes it as its inclusive prefix).
-  auto phase1 = [&](int64_t tt, T (&thr)[K], T (&lc)[K][EPL], T &ag) {
+  // publishes it as its inclusive prefix).  Group-major tiles: after(g) runs
+  // once group g of `cur` has been read for the last time (its registers
+  // may then receive the next tile's loads); lane-major tiles call it for
+  // every group after the serial pass.
+  auto phase1 = [&](int64_t tt, T (&thr)[K], T (&lc)[K][EPL], T &ag, auto &&after) {
     const TileInfo ti = tile_info(tt, a.n, a.tpr, TILE);
     if constexpr (LM) {
       // a thread's K groups are consecutive elements: one serial pass, one
@@ -97,6 +101,8 @@ __global__ __launch_bounds__(TH_) void k_scan_fwd(ScanFwdArgs a) {
           lc[g][j] = acc;
         }
       }
+#pragma unroll
+      for (int g = 0; g < K; ++g) after(g);
       const T inc = wave_scan_fwd<Op>(acc);
       if (lane == WAVE - 1) s_tot[0][wave] = inc;
       __syncthreads();
@@ -123,6 +129,7 @@ __global__ __launch_bounds__(TH_) void k_scan_fwd(ScanFwdArgs a) {
         acc = Op::comb(acc, Io::elem(cur[g], j));
         lc[g][j] = acc;
       }
+      after(g);
       incl[g] = wave_scan_fwd<Op>(acc);
       if (lane == WAVE - 1) s_tot[g][wave] = incl[g];
     }
@@ -148,16 +155,25 @@ __global__ __launch_bounds__(TH_) void k_scan_fwd(ScanFwdArgs a) {
   T pthr[K], ploc[K][EPL];
   T pagg = Op::id();       // wave 0: aggregate of the pending tile
   T prev_incl = Op::id();  // wave 0: inclusive prefix of the block's previous tile
-  phase1(t, pthr, ploc, pagg);
   int64_t tn = t + G;
-  if (tn < a.ntiles) load(tn, cur);
+  {
+    // the next tile's loads go out a group at a time during the scan
+    const bool has = tn < a.ntiles;
+    const TileInfo tin = tile_info(has ? tn : t, a.n, a.tpr, TILE);
+    phase1(t, pthr, ploc, pagg, [&](int g) {
+      if (has) load_grp(tin, cur, g);
+    });
+  }
   for (;;) {
     const bool more = tn < a.ntiles;
     T nthr[K], nloc[K][EPL];
     T nagg = Op::id();
     if (more) {
-      phase1(tn, nthr, nloc, nagg);
-      if (tn + G < a.ntiles) load(tn + G, cur);
+      const bool has = tn + G < a.ntiles;
+      const TileInfo tin = tile_info(has ? tn + G : tn, a.n, a.tpr, TILE);
+      phase1(tn, nthr, nloc, nagg, [&](int g) {
+        if (has) load_grp(tin, cur, g);
+      });
     }
 
     const TileInfo ti = tile_info(t, a.n, a.tpr, TILE);
