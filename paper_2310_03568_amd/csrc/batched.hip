@@ -214,14 +214,15 @@ __global__ __launch_bounds__(TH) void k_seg_fwd(SegFwdArgs a) {
 
   float4 ca[K], cb[K];  // the prefetched item
   int4 ci[K];
+  auto load_grp = [&](const SegItem &it, int g) {
+    const int e = g * TH * EPL + tid * EPL;
+    ca[g] = ld_raw<float4>(a.a, a.n, it.wbase, e, it.lo_r, it.hi_r);
+    cb[g] = ld_raw<float4>(a.b, a.n, it.wbase, e, it.lo_r, it.hi_r);
+    ci[g] = ld_raw<int4>(a.idx, a.n, it.wbase, e, it.lo_r, it.hi_r);
+  };
   auto load = [&](const SegItem &it) {
 #pragma unroll
-    for (int g = 0; g < K; ++g) {
-      const int e = g * TH * EPL + tid * EPL;
-      ca[g] = ld_raw<float4>(a.a, a.n, it.wbase, e, it.lo_r, it.hi_r);
-      cb[g] = ld_raw<float4>(a.b, a.n, it.wbase, e, it.lo_r, it.hi_r);
-      ci[g] = ld_raw<int4>(a.idx, a.n, it.wbase, e, it.lo_r, it.hi_r);
-    }
+    for (int g = 0; g < K; ++g) load_grp(it, g);
   };
   int64_t i = blockIdx.x;  // the item whose outputs are pending
   SegItem it = seg_item(a.tab, i);
@@ -229,10 +230,14 @@ __global__ __launch_bounds__(TH) void k_seg_fwd(SegFwdArgs a) {
   __syncthreads();
   const uint32_t tag = next_tag(s_epoch);
 
-  // scans the prefetched item into item-local inclusive prefixes (v) and, in
-  // wave 0, the item aggregate (ag), which is published (an instance's first
-  // item publishes it as its inclusive prefix)
-  auto phase1 = [&](const SegItem &jt, int64_t item, T (&v)[K][EPL], T &ag) {
+  // scans the prefetched item into item-local inclusive prefixes (v) and its
+  // fixed keys (ix) and, in wave 0, the item aggregate (ag), which is
+  // published (an instance's first item publishes it as its inclusive
+  // prefix).  after(g) runs once group g of the prefetch registers has been
+  // read for the last time: the next item's loads for that group go out
+  // there, a group at a time, instead of all at once after the scan.
+  auto phase1 = [&](const SegItem &jt, int64_t item, T (&v)[K][EPL], int4 (&ix)[K], T &ag,
+                    auto &&after) {
     T incl[K];
     const bool tail = jt.wbase + SEG_T > a.n;
 #pragma unroll
@@ -252,6 +257,8 @@ __global__ __launch_bounds__(TH) void k_seg_fwd(SegFwdArgs a) {
         acc = Op::comb(acc, T{{f4get(ca[g], j), f4get(cb[g], j)}});
         v[g][j] = acc;
       }
+      ix[g] = ci[g];
+      after(g);
       incl[g] = wave_scan_fwd<Op>(acc);
       if (lane == WAVE - 1) s_tot[g][wave] = incl[g];
     }
@@ -284,16 +291,17 @@ __global__ __launch_bounds__(TH) void k_seg_fwd(SegFwdArgs a) {
 
   T pagg = Op::id();       // wave 0: aggregate of the pending item
   T prev_incl = Op::id();  // wave 0: inclusive prefix of the block's previous item
-  {
-    T v[K][EPL];
-    phase1(it, i, v, pagg);
-    put_pending(v, ci);
-  }
   int64_t in = i + G;
   SegItem nt = it;
-  if (in < a.nitems) {
-    nt = seg_item(a.tab, in);
-    load(nt);
+  {
+    const bool has = in < a.nitems;
+    if (has) nt = seg_item(a.tab, in);
+    T v[K][EPL];
+    int4 iv[K];
+    phase1(it, i, v, iv, pagg, [&](int g) {
+      if (has) load_grp(nt, g);
+    });
+    put_pending(v, iv);
   }
   for (;;) {
     const bool more = in < a.nitems;
@@ -302,13 +310,11 @@ __global__ __launch_bounds__(TH) void k_seg_fwd(SegFwdArgs a) {
     T nagg = Op::id();
     SegItem nnt = nt;
     if (more) {
-      phase1(nt, in, nv, nagg);
-#pragma unroll
-      for (int g = 0; g < K; ++g) niv[g] = ci[g];
-      if (in + G < a.nitems) {
-        nnt = seg_item(a.tab, in + G);
-        load(nnt);
-      }
+      const bool has = in + G < a.nitems;
+      if (has) nnt = seg_item(a.tab, in + G);
+      phase1(nt, in, nv, niv, nagg, [&](int g) {
+        if (has) load_grp(nnt, g);
+      });
     }
 
     if (wave == 0) {
