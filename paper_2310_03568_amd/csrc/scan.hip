@@ -2,16 +2,19 @@
 //
 // Both kernels are persistent and software-pipelined.  The grid holds as many
 // blocks as can be resident at once; block b owns tiles b, b+G, b+2G, ... of
-// the scan order.  One iteration of a block:
-//   1. issues the loads of its next tile,
-//   2. resolves the look-back of its current tile (whose aggregate it
-//      published one iteration earlier, as did the predecessors' blocks, so
-//      one poll normally finds everything),
-//   3. writes the current tile's outputs,
-//   4. scans the next tile in registers (thread-serial over 4 elements, wave64
-//      scan, block prefix by wave 0) and publishes its aggregate.
-// The memory pipe keeps streaming while a look-back waits, and a look-back
-// reaches back at most one round of tiles.
+// the scan order.  One iteration of a block scans its next tile in registers
+// (thread-serial over 4 elements, wave64 scan, block prefix by wave 0) and
+// publishes its aggregate, issuing the loads of a later tile a group at a
+// time as the scan frees their registers; only then does it resolve the
+// look-back of its pending tile (whose aggregate, and its predecessors',
+// were published an iteration earlier, so one poll normally finds
+// everything; the predecessor one round back is the block's own previous
+// tile, whose prefix it keeps) and write that tile's outputs.  The memory
+// pipe keeps streaming while a look-back waits, and a look-back reaches back
+// at most one round of tiles.  (k_scan_vjp, kept for the 2x2 product's
+// checkpoint form and the recurrence with the adjoint of its cumulative
+// product, resolves its current tile's look-back before scanning the next
+// tile, whose loads it issues first.)
 //
 // Forward: the exclusive prefix of every tile is saved, so the adjoint can
 // recompute forward prefixes inside a tile without storing y.
