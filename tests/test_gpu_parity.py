@@ -86,7 +86,7 @@ def rows(a, batch):
 SCAN_SIZES = [1, 2, 5, 63, 64, 65, 1023, 1024, 1025, 4095, 4096, 4097, 12293, 100_000]
 
 
-def check_scan(pcad, op, batch, n, seed, ties=False, abar=False, ckpt=False):
+def check_scan(pcad, op, batch, n, seed, ties=False, abar=False, ckpt=False, rt_f=None, rt_b=None):
     rng = np.random.default_rng(seed)
     shape = (batch, n) if batch > 1 else (n,)
     x0, x1 = make_inputs(op, shape, rng, ties)
@@ -105,7 +105,8 @@ def check_scan(pcad, op, batch, n, seed, ties=False, abar=False, ckpt=False):
     y = host(y)
     A = host(A) if A is not None else None
     g = [host(t) for t in g] if op == "linrec" else host(g)
-    rt = RTOL[op]
+    rt = RTOL[op] if rt_f is None else rt_f
+    rtb = rt if rt_b is None else rt_b
     max_rx = n * batch if op == "mul" else 0
     for r in range(batch):
         sl = (r,) if batch > 1 else ()
@@ -134,20 +135,37 @@ def check_scan(pcad, op, batch, n, seed, ties=False, abar=False, ckpt=False):
             ybo = yb[sl]
         xb, cx = oracle.scan_vjp(op, ybo, xr0, xr1)
         if op == "linrec":
-            assert_gate(g[0][sl], xb[:, 0], cx[:, 0], rt, what=f"scan_vjp linrec a_bar row {r}")
-            assert_gate(g[1][sl], xb[:, 1], cx[:, 1], rt, what=f"scan_vjp linrec b_bar row {r}")
-            assert_discriminates(g[0][sl], xb[:, 0], cx[:, 0], rt, what=f"linrec a_bar row {r}")
-            assert_discriminates(g[1][sl], xb[:, 1], cx[:, 1], rt, what=f"linrec b_bar row {r}")
+            assert_gate(g[0][sl], xb[:, 0], cx[:, 0], rtb, what=f"scan_vjp linrec a_bar row {r}")
+            assert_gate(g[1][sl], xb[:, 1], cx[:, 1], rtb, what=f"scan_vjp linrec b_bar row {r}")
+            assert_discriminates(g[0][sl], xb[:, 0], cx[:, 0], rtb, what=f"linrec a_bar row {r}")
+            assert_discriminates(g[1][sl], xb[:, 1], cx[:, 1], rtb, what=f"linrec b_bar row {r}")
         elif op == "mat2":
-            assert_gate(g[sl], xb, cx, rt, max_range_exceeded=mx2, what=f"scan_vjp mat2 row {r}")
+            assert_gate(g[sl], xb, cx, rtb, max_range_exceeded=mx2, what=f"scan_vjp mat2 row {r}")
             if mx2 == 0:
-                assert_discriminates(g[sl], xb, cx, rt, width=4, what=f"scan_vjp mat2 row {r}")
+                assert_discriminates(g[sl], xb, cx, rtb, width=4, what=f"scan_vjp mat2 row {r}")
         else:
-            assert_gate(g[sl], xb[:, 0], cx[:, 0], rt, max_range_exceeded=max_rx,
+            assert_gate(g[sl], xb[:, 0], cx[:, 0], rtb, max_range_exceeded=max_rx,
                         what=f"scan_vjp {op} row {r}")
             if op == "add":
-                assert_discriminates(g[sl], xb[:, 0], cx[:, 0], rt, what=f"scan_vjp add row {r}")
+                assert_discriminates(g[sl], xb[:, 0], cx[:, 0], rtb, what=f"scan_vjp add row {r}")
     assert ws_error() == 0
+
+
+@pytest.mark.parametrize("op,batch,tiles", [("add", 3, 258), ("linrec", 3, 258), ("mat2", 2, 300)])
+def test_scan_rows_past_a_round(pcad, op, batch, tiles):
+    """Rows of more tiles than one round of the persistent grid (about one
+    512-thread block per CU): a tile's look-back then takes the prefix one
+    round back from its block's own previous tile, which has to lie in the
+    same row, and row boundaries fall inside rounds.  The 2x2 products are
+    orthogonal chains of up to 6e5 factors, gated with the chain tolerance."""
+    tile = 2048 if op == "mat2" else 8192
+    n = tiles * tile + 5
+    print(f"scan rows past a round: {op} batch={batch} n={n}", flush=True)
+    kw = {}
+    if op == "mat2":
+        kw = dict(rt_f=chain_rtol(n, RTOL["mat2"], width=4),
+                  rt_b=chain_rtol(n, RTOL["mat2"], width=4, adjoint=True))
+    check_scan(pcad, op, batch, n, 7100 + tiles, **kw)
 
 
 @pytest.mark.parametrize("op", ALL)
