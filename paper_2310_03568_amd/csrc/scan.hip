@@ -966,9 +966,13 @@ __global__ __launch_bounds__(TH_) void k_scan_vjp_d(ScanVjpArgs a) {
     phase1(k, b0, p0, 0, [&](int g) {
       if (has1) load_grp(t1, b1, p1, g);
     });
-    // the first tile's block level; nothing is pending yet
+    // the first tile's block level; nothing is pending yet.  The barrier
+    // after it keeps the next scan's wave totals out of s_mtot until wave 0
+    // has read this tile's (a scan without a forward re-scan has no barrier
+    // before it writes them).
     __syncthreads();
     if (wave == 0) g0 = block_level(k, 0);
+    __syncthreads();
   }
 
   // S: tile k, scanned (state in slot sl); P: tile k+G, loaded (or
@@ -1195,6 +1199,7 @@ __global__ __launch_bounds__(TH_) void k_scan_vjp_m2d(ScanVjpArgs a) {
     });
     __syncthreads();
     if (wave == 0) g0 = block_level(k, 0);
+    __syncthreads();  // s_mtot is rewritten by the next scan
   }
   auto step = [&](Buf &bs, MT &gs, Buf &bp, MT &gp, Buf &bl) -> bool {
     const bool scan = k + G < a.ntiles;
