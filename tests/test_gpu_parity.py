@@ -319,6 +319,39 @@ def test_scan_accumulate(pcad):
     assert_gate(host(out), xb[:, 0] + base, cx[:, 0] + np.abs(base), 1e-5, what="accumulate")
 
 
+@pytest.mark.parametrize("op,n,ckpt", [("add", 100_003, False), ("linrec", 2_500_007, False),
+                                       ("linrec", 300_001, True), ("max", 200_003, True),
+                                       ("mat2", 300_001, False), ("mat2", 100_001, True)])
+def test_scan_vjp_accumulate(pcad, op, n, ckpt):
+    """PCAD_ACCUMULATE (the paper's +=) in every scan-adjoint kernel: the
+    delayed group-major and lane-major kernels (recompute form), and the
+    checkpoint forms, over several tiles and, for LINREC, several rounds."""
+    rng = np.random.default_rng(4000 + n)
+    x0, x1 = make_inputs(op, (n,), rng)
+    yb = rng.standard_normal((n, 4) if op == "mat2" else n).astype(np.float32)
+    X0, X1 = dev(x0), (dev(x1) if x1 is not None else None)
+    y, A, saved = pcad.scan_fwd(op, X0, X1, want_A=(op == "linrec"))
+    k = 2 if op == "linrec" else 1
+    base = [rng.standard_normal(x0.shape).astype(np.float32) for _ in range(k)]
+    out = tuple(dev(b) for b in base)
+    if ckpt:
+        pcad.scan_vjp_checkpoint(op, X0, None, y, None, dev(yb), out=out, accumulate=True)
+    else:
+        pcad.scan_vjp(op, X0, X1, saved, dev(yb), out=out, accumulate=True)
+    ybo = np.stack([np.zeros(n), yb], 1) if op == "linrec" else yb
+    xb, cx = oracle.scan_vjp(op, ybo, x0, x1)
+    rt = RTOL[op]
+    if op == "mat2":
+        rt = chain_rtol(n, RTOL["mat2"], width=4, adjoint=True)
+        assert_gate(host(out[0]), xb + base[0], cx + np.abs(base[0]), rt, max_range_exceeded=0,
+                    what="mat2 accumulate")
+        return
+    for c in range(k):
+        assert_gate(host(out[c]), xb[:, c] + base[c], cx[:, c] + np.abs(base[c]), rt,
+                    what=f"{op} accumulate {c}")
+    assert ws_error() == 0
+
+
 def test_scan_repeat_reuses_workspace(pcad):
     """Self-resetting counters and epoch tags: many launches on one
     workspace, alternating directions and sizes, stay exact."""
